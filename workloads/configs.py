@@ -1,0 +1,84 @@
+"""The five synthetic workloads used by the tests and the benchmark.
+
+Each stands in for a class of matrices the paper factors (Section 6): the
+fractional-Laplacian-like stiffness (s = 0.75) of the headline case, a plain
+FP64 case at two sizes, a batch of uneven small instances, and the random
+field case that differentiates through the solve.  Seeds are fixed so every
+run of every consumer sees the same matrices and right-hand sides.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List
+
+import numpy as np
+
+from .wavelet import WaveletSpec, make_matrix, normal_rhs
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    spec: WaveletSpec
+    nrhs: int
+    seed: int          # base seed S; xi uses S, b uses S+1, y* S+2, z S+3, FD choice S+4
+
+    @property
+    def n(self) -> int:
+        return self.spec.n
+
+    def matrix(self) -> Dict[str, np.ndarray]:
+        return make_matrix(self.spec)
+
+    def rhs(self) -> np.ndarray:
+        return normal_rhs(self.n, self.nrhs, self.seed + 1)
+
+
+def small_fp64() -> Workload:
+    """64x64 grid, levels 0..5, N = 4096, a = 1.5, exp(-|dc|/0.3) values, one RHS."""
+    return Workload("haar64_n4096", WaveletSpec(6, 1.5, 0.5, "exp", 0.3, 1.5, 1000), 1, 1000)
+
+
+def medium_fp64() -> Workload:
+    """256x256 grid, levels 0..7, N = 65536, a = 1.5, one RHS."""
+    return Workload("haar256_n65536", WaveletSpec(8, 1.5, 0.5, "exp", 0.3, 1.5, 2000), 1, 2000)
+
+
+def headline() -> Workload:
+    """512x512 grid, levels 0..8, N = 262144, a = 2, s = 0.75, algebraic decay, 64 RHS."""
+    return Workload("haar512_n262144_s075", WaveletSpec(9, 2.0, 0.75, "alg", 0.3, 1.75, 3000), 64, 3000)
+
+
+def random_field() -> Workload:
+    """Same operator class as the headline case with its own seed, one RHS."""
+    return Workload("haar512_n262144_grf", WaveletSpec(9, 2.0, 0.75, "alg", 0.3, 1.75, 5000), 1, 5000)
+
+
+def tiny(grid_exp: int, a: float = 1.5, s: float = 0.5, seed: int = 7) -> Workload:
+    """Small instances for brute-force checks (N = 4^grid_exp)."""
+    return Workload(f"haar{1 << grid_exp}_n{4 ** grid_exp}", WaveletSpec(grid_exp, a, s, "exp", 0.3, 1.5, seed), 1, seed)
+
+
+def batch_instance(i: int, base_seed: int = 4000) -> Workload:
+    """Instance i of the uneven batch: grid side 2^J with J uniform in {5,6,7},
+    ell ~ U(0.1,0.5), a ~ U(1.2,2.0), s uniform in {1/4,1/2,3/4}; values as in
+    the small case.  The draws come from PCG64(base_seed + 10 + i) in that order."""
+    seed = base_seed + 10 + i
+    g = np.random.Generator(np.random.PCG64(seed))
+    J = int(g.integers(5, 8))
+    ell = float(g.uniform(0.1, 0.5))
+    a = float(g.uniform(1.2, 2.0))
+    s = float(g.choice(np.array([0.25, 0.5, 0.75])))
+    return Workload(f"batch{i}_n{4 ** J}", WaveletSpec(J, a, s, "exp", ell, 1.5, seed), 4, seed)
+
+
+def batch(count: int = 256, base_seed: int = 4000) -> List[Workload]:
+    return [batch_instance(i, base_seed) for i in range(count)]
+
+
+ALL = {
+    "small": small_fp64,
+    "medium": medium_fp64,
+    "headline": headline,
+    "grf": random_field,
+}
