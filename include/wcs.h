@@ -1,0 +1,227 @@
+/*
+ * wcs — sparse Cholesky for compressed wavelet Galerkin matrices on MI355X.
+ *
+ * C ABI of the library.  The operations follow the problem statement of
+ * Harbrecht & Multerer, "A fast direct solver for nonlocal operators in
+ * wavelet coordinates":
+ *   - Section 4: a nested dissection ordering P of the symmetric sparsity
+ *     pattern (computed once per pattern and reusable for every matrix with
+ *     that pattern, as done for V_J and A_J in Section 6.1), then the
+ *     Cholesky factorization P A P^T = L L^T;
+ *   - Section 1 and Section 5: the factor used as an exact inverse of the
+ *     compressed matrix, factored once and applied to many right-hand sides
+ *     (Section 5.1) and many time steps (Section 5.2);
+ *   - Section 5.3: the half solve with L^T alone, used to draw Gaussian
+ *     random field samples (here in precision form, x = P^T L^-T z, whose
+ *     covariance is A^-1).
+ *
+ * Conventions shared by all calls
+ *   Pattern: lower triangle including the diagonal, compressed sparse column,
+ *     colptr int64[n+1] (colptr[0] = 0), rowind int32[colptr[n]], rows strictly
+ *     ascending within a column and the diagonal stored first.  Host memory,
+ *     owned by the caller, copied by wcs_analyze.
+ *   Values: device FP64 array aligned with rowind (one value per stored
+ *     entry), owned by the caller.
+ *   Right-hand sides / solutions: device FP64, column-major n x nrhs with
+ *     leading dimension ld >= n, always in the caller's (original) ordering;
+ *     the permutation is internal.
+ *   Workspace: device memory provided by the caller (the library performs no
+ *     device allocation); its size comes from wcs_workspace_size.
+ *   Streams: every device call is enqueued on the given HIP stream and is
+ *     asynchronous unless stated otherwise.
+ *   Errors: status codes (wcs_status); no C++ exception crosses the ABI.
+ *     wcs_last_error() returns a thread-local human-readable detail.
+ *   Handles are owned by the caller and released only by the *_free calls.
+ */
+#ifndef WCS_H
+#define WCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *wcs_stream; /* a hipStream_t; NULL = the default stream */
+
+typedef struct wcs_symbolic_s *wcs_symbolic; /* host: ordering, trees, supernodes, plan */
+typedef struct wcs_factor_s *wcs_factor;     /* device-resident L plus its plan */
+
+typedef enum {
+    WCS_OK = 0,
+    WCS_EINVAL = -1,    /* malformed argument or pattern */
+    WCS_ENOMEM = -2,    /* workspace too small, or host allocation failed */
+    WCS_EHIP = -3,      /* a HIP runtime call failed */
+    WCS_ENOTSPD = -4,   /* a pivot was not positive (or NaN): matrix not SPD */
+    WCS_ENOTCONV = -5,  /* iterative refinement did not reach the tolerance */
+    WCS_ESTATE = -6     /* call not valid in the handle's current state */
+} wcs_status;
+
+typedef enum {
+    WCS_FP64 = 0,       /* fronts stored and factored in FP64 */
+    WCS_FP32 = 1        /* fronts stored and factored in FP32 (FP64 diagonal
+                           tiles in fronts with at least fp64_diag_min_cols pivots) */
+} wcs_precision;
+
+typedef enum {
+    WCS_SOLVE_FULL = 0, /* X = A^-1 B          = P^T L^-T L^-1 P B */
+    WCS_SOLVE_L = 1,    /* X = L^-1 P B         (result in pivot order) */
+    WCS_SOLVE_LT = 2    /* X = P^T L^-T B       (input in pivot order)  */
+} wcs_part;
+
+typedef struct {
+    int32_t leaf_size;          /* nested dissection stops at <= leaf_size vertices (default 64) */
+    double dense_degree_frac;   /* peel vertices whose degree >= dense_degree_frac * n ... */
+    double dense_degree_min;    /* ... and >= dense_degree_min; peeled vertices join the root separator
+                                   (defaults 0.25 and 1024) */
+    const double *coords;       /* optional n x coord_dim row-major vertex positions used only to
+                                   choose the split of each dissection step; the separator itself
+                                   is always a vertex cover of the cut edges of the graph.
+                                   NULL = graph-only (breadth-first level structure) splits */
+    int32_t coord_dim;          /* 1..3 when coords != NULL */
+    const int32_t *user_perm;   /* optional ordering (perm[k] = original index of pivot k);
+                                   bypasses nested dissection */
+    int32_t relax;              /* 1 = relaxed supernode amalgamation (default), 0 = fundamental only */
+} wcs_analyze_opts;
+
+typedef struct {
+    int32_t n;
+    int64_t nnz_lower;          /* stored entries of the input (lower triangle incl. diagonal) */
+    int64_t nnz_l;              /* nnz(L), lower triangle including the diagonal, from the
+                                   fundamental symbolic structure */
+    int64_t flops;              /* sum over columns of colcount^2 (fundamental structure) */
+    int64_t flops_padded;       /* the same sum over the amalgamated supernodes actually factored */
+    int32_t nsuper_fund;        /* fundamental supernodes */
+    int32_t nsuper;             /* supernodes after amalgamation (= fronts) */
+    int32_t nlevels;            /* levels of the assembly tree (height + 1) */
+    int32_t max_front;          /* largest front order m */
+    int32_t nsep_nodes;         /* nodes of the separator tree */
+    int32_t npeeled;            /* dense vertices moved into the root separator */
+    int64_t front_elems;        /* sum over fronts of m^2 (front storage, elements) */
+    int64_t nnz_l_padded;       /* entries of L as stored by the fronts (explicit zeros included) */
+} wcs_symbolic_info_t;
+
+typedef struct {
+    int32_t iterations;         /* refinement steps taken */
+    double raw_residual;        /* max column relative residual after the first low-precision solve */
+    double final_residual;      /* max column ||b - A x||_2 / ||b||_2 at exit */
+} wcs_ir_report;
+
+/* Status name ("WCS_OK", ...). */
+const char *wcs_status_string(int status);
+/* Detail of the last failing call on this thread (empty string if none). */
+const char *wcs_last_error(void);
+
+/*
+ * Ordering and symbolic analysis (host only, synchronous, deterministic).
+ * Validates the pattern (WCS_EINVAL on any violation of the conventions
+ * above), builds the adjacency graph (Section 4), orders it by nested
+ * dissection (or takes opts->user_perm), and computes the elimination tree,
+ * column counts (Lemma 4.1 pattern), fundamental and amalgamated supernodes,
+ * the assembly tree, extend-add index maps and the level schedule.
+ * opts may be NULL (defaults).  On success *out owns a new handle.
+ */
+int wcs_analyze(int32_t n, const int64_t *colptr, const int32_t *rowind,
+                const wcs_analyze_opts *opts, wcs_symbolic *out);
+
+int wcs_symbolic_info(wcs_symbolic sym, wcs_symbolic_info_t *info);
+
+/*
+ * Copies the symbolic results into caller host arrays (each may be NULL):
+ *   perm[n]              perm[k] = original index of pivot k
+ *   parent[n]            elimination tree, parent[j] = min{i > j : l_ij != 0} or -1
+ *   colcount[n]          nonzeros of column j of L (diagonal included)
+ *   super_ptr[nsuper_fund+1]  first column of each fundamental supernode
+ *   sep_tree[6*nsep_nodes]    nested dissection tree, node t = (lo, mid, sep, hi,
+ *                        child1, child2) in pivot positions: V1 = perm[lo:mid],
+ *                        V2 = perm[mid:sep], S = perm[sep:hi]; leaves have mid = -1
+ */
+int wcs_symbolic_export(wcs_symbolic sym, int32_t *perm, int32_t *parent, int32_t *colcount,
+                        int32_t *super_ptr, int32_t *sep_tree);
+
+/*
+ * Relaxed (factored) supernode partition: relaxed_ptr[nsuper+1] first columns,
+ * and front_order[nsuper] = m (rows of each front).  Either may be NULL.
+ */
+int wcs_symbolic_fronts(wcs_symbolic sym, int32_t *relaxed_ptr, int32_t *front_order);
+
+void wcs_symbolic_free(wcs_symbolic sym);
+
+/*
+ * Device workspace (bytes) needed by wcs_factor for this pattern, precision
+ * and number of right-hand sides solved at once (max_nrhs >= 1).  The same
+ * workspace serves the factor, its solves and the refinement.
+ */
+int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, size_t *bytes);
+
+/*
+ * Numeric factorization P A P^T = L L^T (Section 4) of the matrix with the
+ * analysed pattern and the device FP64 values values_dev.  The factor lives in
+ * the workspace (caller-owned device memory of at least the size from
+ * wcs_workspace_size, 256-byte aligned), which must stay valid until
+ * wcs_factor_free.  values_dev is read during this call's device work only.
+ * If bad_col is non-NULL the call waits for the stream and reports the first
+ * failing pivot (pivot order, -1 if none) and returns WCS_ENOTSPD when one
+ * failed; with bad_col NULL the call is asynchronous and wcs_factor_check
+ * reports the outcome later.
+ */
+int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs,
+                      void *workspace, size_t bytes, wcs_stream stream, wcs_factor *out);
+int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *bad_col);
+/* Waits for the stream; *bad_col = first failing pivot or -1; returns WCS_ENOTSPD if one failed. */
+int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col);
+void wcs_factor_free(wcs_factor f);
+
+/*
+ * Copies columns [j0, j1) (pivot order) of L to host memory in compressed
+ * sparse column form over the stored (amalgamated) pattern, explicit zeros
+ * included: Lp[j1-j0+1] offsets starting at 0, Li row indices (pivot order,
+ * ascending, diagonal first), Lx values as FP64.  The caller sizes Li/Lx from
+ * a first call with Li = Lx = NULL, which fills Lp only.  Synchronous.
+ */
+int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t *Li, double *Lx,
+                      wcs_stream stream);
+
+/*
+ * Triangular solves with the factor (Section 5: factor once, solve many).
+ * B_dev: device FP64, n x nrhs column-major, ld >= n, overwritten in place by
+ * the result (see wcs_part).  1 <= nrhs <= max_nrhs of the factor.
+ * In FP32 factors the solve runs in FP32 on an FP32 copy of B (one rounding
+ * of B to FP32 and of the result back to FP64).
+ */
+int wcs_solve(wcs_factor f, wcs_part part, int32_t nrhs, double *B_dev, int64_t ld, wcs_stream stream);
+
+/*
+ * X = A^-1 B by iterative refinement against the FP64 input matrix:
+ * X0 = solve(B); repeat R = B - A X (FP64), stop when every column has
+ * ||R||_2 / ||B||_2 <= tol, else X += solve(R) — at most max_iter corrections.
+ * values_dev are the FP64 values used by the factorization (same pattern).
+ * Reads the residual norms back to the host once per step (synchronous).
+ * Returns WCS_ENOTCONV (with *rep filled) if tol is not reached.
+ */
+int wcs_solve_refined(wcs_factor f, const double *values_dev, int32_t nrhs, const double *B_dev,
+                      double *X_dev, int64_t ld, double tol, int32_t max_iter, wcs_ir_report *rep,
+                      wcs_stream stream);
+
+/*
+ * Y = A X for the FP64 input matrix (full symmetric A from its stored lower
+ * triangle), device arrays, n x nrhs column-major with leading dimension ld.
+ */
+int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double *X_dev, double *Y_dev,
+             int64_t ld, wcs_stream stream);
+
+/*
+ * Gradient of a scalar loss through x = A^-1 b with respect to the stored
+ * lower entries of A, given lam = A^-1 (dloss/dx): entry (i,j), i > j, gets
+ * -(lam_i x_j + lam_j x_i); a diagonal entry gets -lam_i x_i.  Device arrays:
+ * lam_dev[n], x_dev[n], gA_dev[nnz_lower] (aligned with the pattern).
+ */
+int wcs_grad_pattern(wcs_factor f, const double *lam_dev, const double *x_dev, double *gA_dev,
+                     wcs_stream stream);
+
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WCS_H */

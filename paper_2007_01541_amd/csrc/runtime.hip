@@ -1,0 +1,637 @@
+// Device runtime: static launch plan, workspace layout, launch sequences for
+// the numeric factorization, the solves, iterative refinement and the
+// pattern gradient, and their C ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.hip"
+
+namespace wcs {
+const Symbolic &symbolic_of(wcs_symbolic h);
+
+namespace {
+
+using namespace dev;
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            set_error(std::string(#expr) + ": " + hipGetErrorString(e_));               \
+            return WCS_EHIP;                                                            \
+        }                                                                               \
+    } while (0)
+
+constexpr int32_t kFp64DiagMinCols = 1024;   // FP32 fronts with >= this many pivots factor diagonal blocks in FP64
+
+size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Static schedule derived from the symbolic structure only.
+struct Step {
+    int32_t k0;
+    int64_t pan_lo_off, pan_lo_cnt;    // panel tasks of fronts with p < kFp64DiagMinCols
+    int64_t pan_hi_off, pan_hi_cnt;    // ... with p >= kFp64DiagMinCols
+    int64_t syrk_off, syrk_cnt;
+};
+struct Level {
+    std::vector<Step> steps;
+    std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds (offset, count)
+    int64_t fl_off = 0, fl_cnt = 0;                // fronts of this level in flist
+};
+
+struct Plan {
+    std::vector<Level> levels;
+    std::vector<int2> pan_tasks;
+    std::vector<int4> syrk_tasks;
+    std::vector<int2> ea_tasks;
+    std::vector<int32_t> flist;
+    std::vector<int32_t> mfront, pfront, first;
+    std::vector<int64_t> woff;                    // per front: row offset of its solve buffer
+    int64_t wrows = 0;
+    std::vector<int32_t> child_ptr, child_list;
+    std::vector<int32_t> colof;                   // column of each stored entry
+
+    void build(const Symbolic &S)
+    {
+        int32_t ns = S.ns;
+        mfront.resize(ns);
+        pfront.resize(ns);
+        first.resize(ns);
+        woff.resize(ns);
+        wrows = 0;
+        for (int32_t s = 0; s < ns; s++) {
+            mfront[s] = S.m_of(s);
+            pfront[s] = S.p_of(s);
+            first[s] = S.sptr[s];
+            woff[s] = wrows;
+            wrows += mfront[s];
+        }
+        child_ptr.assign((size_t)ns + 1, 0);
+        for (int32_t s = 0; s < ns; s++)
+            if (S.sparent[s] >= 0) child_ptr[S.sparent[s] + 1]++;
+        for (int32_t s = 0; s < ns; s++) child_ptr[s + 1] += child_ptr[s];
+        child_list.resize(child_ptr[ns]);
+        {
+            std::vector<int32_t> fill(child_ptr.begin(), child_ptr.end() - 1);
+            for (int32_t s = 0; s < ns; s++)
+                if (S.sparent[s] >= 0) child_list[fill[S.sparent[s]]++] = s;   // ascending
+        }
+        int32_t H = S.nlevels;
+        std::vector<std::vector<int32_t>> bylev(H);
+        for (int32_t s = 0; s < ns; s++) bylev[S.height[s]].push_back(s);
+        levels.assign(H, Level());
+        flist.clear();
+        pan_tasks.clear();
+        syrk_tasks.clear();
+        ea_tasks.clear();
+        for (int32_t h = 0; h < H; h++) {
+            Level &L = levels[h];
+            const std::vector<int32_t> &fr = bylev[h];
+            L.fl_off = (int64_t)flist.size();
+            flist.insert(flist.end(), fr.begin(), fr.end());
+            L.fl_cnt = (int64_t)fr.size();
+            // extend-add rounds: round r adds the r-th child of every parent
+            int32_t maxk = 0;
+            for (int32_t s : fr) maxk = std::max(maxk, child_ptr[s + 1] - child_ptr[s]);
+            for (int32_t r = 0; r < maxk; r++) {
+                int64_t off = (int64_t)ea_tasks.size();
+                for (int32_t s : fr) {
+                    if (child_ptr[s] + r >= child_ptr[s + 1]) continue;
+                    int32_t c = child_list[child_ptr[s] + r];
+                    int32_t nu = mfront[c] - pfront[c];
+                    for (int32_t c0 = 0; c0 < nu; c0 += EA_COLS) ea_tasks.push_back(make_int2(c, c0));
+                }
+                int64_t cnt = (int64_t)ea_tasks.size() - off;
+                if (cnt) L.ea.push_back({off, cnt});
+            }
+            int32_t maxp = 0;
+            for (int32_t s : fr) maxp = std::max(maxp, pfront[s]);
+            for (int32_t k0 = 0; k0 < maxp; k0 += NB) {
+                Step st;
+                st.k0 = k0;
+                for (int pass = 0; pass < 2; pass++) {
+                    int64_t off = (int64_t)pan_tasks.size();
+                    for (int32_t s : fr) {
+                        int32_t p = pfront[s], m = mfront[s];
+                        if (p <= k0) continue;
+                        if ((p >= kFp64DiagMinCols) != (pass == 1)) continue;
+                        int32_t nb = std::min(NB, p - k0);
+                        int32_t below = m - k0 - nb;
+                        int32_t nt = (below + TR - 1) / TR;
+                        for (int32_t t = 0; t <= nt; t++) pan_tasks.push_back(make_int2(s, t));
+                    }
+                    if (pass == 0) { st.pan_lo_off = off; st.pan_lo_cnt = (int64_t)pan_tasks.size() - off; }
+                    else { st.pan_hi_off = off; st.pan_hi_cnt = (int64_t)pan_tasks.size() - off; }
+                }
+                st.syrk_off = (int64_t)syrk_tasks.size();
+                for (int32_t s : fr) {
+                    int32_t p = pfront[s], m = mfront[s];
+                    if (p <= k0) continue;
+                    int32_t nb = std::min(NB, p - k0);
+                    int32_t below = m - k0 - nb;
+                    int32_t nt = (below + TS - 1) / TS;
+                    for (int32_t ti = 0; ti < nt; ti++)
+                        for (int32_t tj = 0; tj <= ti; tj++) syrk_tasks.push_back(make_int4(s, ti, tj, 0));
+                }
+                st.syrk_cnt = (int64_t)syrk_tasks.size() - st.syrk_off;
+                L.steps.push_back(st);
+            }
+        }
+        colof.resize((size_t)S.nnz);
+        for (int32_t j = 0; j < S.n; j++)
+            for (int64_t p = S.colptr[j]; p < S.colptr[j + 1]; p++) colof[p] = j;
+    }
+};
+
+// Workspace layout (byte offsets), all segments 256-byte aligned.
+struct Layout {
+    size_t fronts, W, Y, Xr, Rr, Br, vec, bad;
+    size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list;
+    size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof;
+    size_t pan, syrk, ea, flist;
+    size_t total;
+
+    void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
+    {
+        size_t o = 0;
+        auto seg = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+        size_t n = (size_t)S.n, ns = (size_t)S.ns;
+        fronts = seg((size_t)S.front_off.back() * esz);
+        W = seg((size_t)P.wrows * k * esz);
+        Y = seg(n * k * esz);
+        Xr = seg(n * k * 8);
+        Rr = seg(n * k * 8);
+        Br = seg(n * k * 8);
+        vec = seg((size_t)4 * k * 8 + 64);
+        bad = seg(64);
+        front_off = seg((ns + 1) * 8);
+        mfront = seg(ns * 4);
+        pfront = seg(ns * 4);
+        first = seg(ns * 4);
+        sparent = seg(ns * 4);
+        rptr = seg((ns + 1) * 8);
+        rows = seg(S.rows.size() * 4);
+        rel = seg(S.rel.size() * 4);
+        amap = seg((size_t)S.nnz * 8);
+        woff = seg(ns * 8);
+        child_ptr = seg((ns + 1) * 4);
+        child_list = seg(std::max<size_t>(1, P.child_list.size()) * 4);
+        perm = seg(n * 4);
+        csr_ptr = seg((n + 1) * 8);
+        csr_col = seg(S.csr_col.size() * 4);
+        csr_src = seg(S.csr_src.size() * 8);
+        csr_val = seg(S.csr_col.size() * 8);
+        rowind = seg((size_t)S.nnz * 4);
+        colof = seg((size_t)S.nnz * 4);
+        pan = seg(std::max<size_t>(1, P.pan_tasks.size()) * sizeof(int2));
+        syrk = seg(std::max<size_t>(1, P.syrk_tasks.size()) * sizeof(int4));
+        ea = seg(std::max<size_t>(1, P.ea_tasks.size()) * sizeof(int2));
+        flist = seg(std::max<size_t>(1, P.flist.size()) * 4);
+        total = o;
+    }
+};
+
+size_t elem_size(wcs_precision p) { return p == WCS_FP64 ? 8 : 4; }
+
+int grid_for(int64_t work, int threads = 256)
+{
+    int64_t g = (work + threads - 1) / threads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1 << 16));
+}
+
+}  // namespace
+}  // namespace wcs
+
+struct wcs_factor_s {
+    const wcs::Symbolic *S = nullptr;
+    wcs::Plan plan;
+    wcs::Layout lay;
+    wcs_precision prec = WCS_FP64;
+    int32_t max_nrhs = 1;
+    char *ws = nullptr;
+    size_t bytes = 0;
+    bool have_values = false;
+    const double *csr_values_from = nullptr;   // values pointer the expanded CSR values were built from
+
+    template <typename P> P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
+};
+
+namespace wcs {
+namespace {
+
+template <typename T>
+int launch_factor(wcs_factor f, const double *values, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    const Plan &P = f->plan;
+    const Symbolic &S = *f->S;
+    T *fronts = f->at<T>(Lo.fronts);
+    int64_t nel = S.front_off.back();
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nel)), dim3(256), 0, st, fronts, nel, (T)0);
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, f->at<int32_t>(Lo.bad), (int64_t)1, INT32_MAX);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(S.nnz)), dim3(256), 0, st, values, f->at<int64_t>(Lo.amap),
+                       S.nnz, fronts);
+    const int64_t *fo = f->at<int64_t>(Lo.front_off);
+    const int32_t *mf = f->at<int32_t>(Lo.mfront);
+    const int32_t *pf = f->at<int32_t>(Lo.pfront);
+    const int32_t *fi = f->at<int32_t>(Lo.first);
+    const int32_t *sp = f->at<int32_t>(Lo.sparent);
+    const int64_t *rp = f->at<int64_t>(Lo.rptr);
+    const int32_t *rl = f->at<int32_t>(Lo.rel);
+    const int2 *pan = f->at<int2>(Lo.pan);
+    const int4 *syrk = f->at<int4>(Lo.syrk);
+    const int2 *ea = f->at<int2>(Lo.ea);
+    int32_t *bad = f->at<int32_t>(Lo.bad);
+    for (const Level &L : P.levels) {
+        for (auto &r : L.ea)
+            hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)r.second), dim3(256), 0, st, ea + r.first, fo, mf,
+                               pf, sp, rp, rl, fronts);
+        for (const Step &s : L.steps) {
+            if (s.pan_lo_cnt)
+                hipLaunchKernelGGL((k_panel<T, T>), dim3((unsigned)s.pan_lo_cnt), dim3(THREADS), 0, st,
+                                   pan + s.pan_lo_off, s.k0, fo, mf, pf, fi, fronts, bad);
+            if (s.pan_hi_cnt)
+                hipLaunchKernelGGL((k_panel<T, double>), dim3((unsigned)s.pan_hi_cnt), dim3(THREADS), 0, st,
+                                   pan + s.pan_hi_off, s.k0, fo, mf, pf, fi, fronts, bad);
+            if (s.syrk_cnt)
+                hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)s.syrk_cnt), dim3(THREADS), 0, st, syrk + s.syrk_off,
+                                   s.k0, fo, mf, pf, fronts);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+// Y (row-major, pivot order, n x k) := L^-1 Y and/or L^-T Y
+template <typename T>
+int launch_solve_internal(wcs_factor f, int part, int k, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    const Plan &P = f->plan;
+    T *fronts = f->at<T>(Lo.fronts);
+    T *W = f->at<T>(Lo.W);
+    T *Y = f->at<T>(Lo.Y);
+    const int64_t *fo = f->at<int64_t>(Lo.front_off);
+    const int32_t *mf = f->at<int32_t>(Lo.mfront);
+    const int32_t *pf = f->at<int32_t>(Lo.pfront);
+    const int32_t *fi = f->at<int32_t>(Lo.first);
+    const int64_t *wo = f->at<int64_t>(Lo.woff);
+    const int32_t *cp = f->at<int32_t>(Lo.child_ptr);
+    const int32_t *cl = f->at<int32_t>(Lo.child_list);
+    const int64_t *rp = f->at<int64_t>(Lo.rptr);
+    const int32_t *rl = f->at<int32_t>(Lo.rel);
+    const int32_t *rw = f->at<int32_t>(Lo.rows);
+    const int32_t *fl = f->at<int32_t>(Lo.flist);
+    if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_L) {
+        for (const Level &L : P.levels)
+            hipLaunchKernelGGL(k_fwd_front<T>, dim3((unsigned)L.fl_cnt), dim3(THREADS), 0, st, fl + L.fl_off, fo, mf,
+                               pf, fi, wo, cp, cl, rp, rl, fronts, W, Y, k);
+    }
+    if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_LT) {
+        for (size_t h = P.levels.size(); h-- > 0;) {
+            const Level &L = P.levels[h];
+            hipLaunchKernelGGL(k_bwd_front<T>, dim3((unsigned)L.fl_cnt), dim3(THREADS), 0, st, fl + L.fl_off, fo, mf,
+                               pf, fi, wo, rp, rw, fronts, W, Y, k);
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+template <typename T>
+int launch_solve(wcs_factor f, int part, int k, double *B, int64_t ld, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    int n = f->S->n;
+    T *Y = f->at<T>(Lo.Y);
+    const int32_t *perm = f->at<int32_t>(Lo.perm);
+    int64_t nk = (int64_t)n * k;
+    if (part == WCS_SOLVE_LT)
+        hipLaunchKernelGGL(k_rows_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, n, k, Y);
+    else
+        hipLaunchKernelGGL(k_perm_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Y,
+                           (const double *)nullptr);
+    int rc = launch_solve_internal<T>(f, part, k, st);
+    if (rc) return rc;
+    if (part == WCS_SOLVE_L)
+        hipLaunchKernelGGL(k_rows_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, n, k, B, ld);
+    else
+        hipLaunchKernelGGL(k_perm_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k, B, ld,
+                           (const double *)nullptr, 0);
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st)
+{
+    const Symbolic &S = *f->S;
+    int64_t nz = (int64_t)S.csr_col.size();
+    hipLaunchKernelGGL(k_expand_values, dim3(grid_for(nz)), dim3(256), 0, st, values,
+                       f->at<int64_t>(f->lay.csr_src), nz, f->at<double>(f->lay.csr_val));
+    HIP_TRY(hipGetLastError());
+    f->csr_values_from = values;
+    return WCS_OK;
+}
+
+// Y = A X or R = B - A X, column-major with leading dimension ld
+int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R, int64_t ld, hipStream_t st)
+{
+    const Symbolic &S = *f->S;
+    int n = S.n;
+    hipLaunchKernelGGL(k_spmv_colmajor, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st,
+                       f->at<int64_t>(f->lay.csr_ptr), f->at<int32_t>(f->lay.csr_col), f->at<double>(f->lay.csr_val),
+                       n, k, X, B, R, ld);
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+template <typename T>
+int solve_refined(wcs_factor f, const double *values, int k, const double *B, double *X, int64_t ld, double tol,
+                  int max_iter, wcs_ir_report *rep, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    int n = f->S->n;
+    int rc = ensure_csr_values(f, values, st);
+    if (rc) return rc;
+    double *R = f->at<double>(Lo.Rr);       // column-major n x k, ld = n
+    double *vec = f->at<double>(Lo.vec);    // [0,k): |B|^2, [k,2k): |R|^2, [2k,3k): amax, [3k,4k): scale
+    T *Y = f->at<T>(Lo.Y);
+    const int32_t *perm = f->at<int32_t>(Lo.perm);
+    int64_t nk = (int64_t)n * k;
+    hipLaunchKernelGGL(k_colnorm2, dim3(k), dim3(THREADS), 0, st, B, n, k, ld, vec);
+    // X0 = solve(B)
+    hipLaunchKernelGGL(k_perm_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Y,
+                       (const double *)nullptr);
+    rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_perm_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k, X, ld,
+                       (const double *)nullptr, 0);
+    std::vector<double> h((size_t)2 * k);
+    rep->iterations = 0;
+    rep->raw_residual = -1;
+    rep->final_residual = -1;
+    for (int it = 0;; it++) {
+        rc = launch_spmv(f, k, X, B, R, ld, st);
+        if (rc) return rc;
+        // R is stored with leading dimension ld as well
+        hipLaunchKernelGGL(k_colnorm2, dim3(k), dim3(THREADS), 0, st, R, n, k, ld, vec + k);
+        HIP_TRY(hipMemcpyAsync(h.data(), vec, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        double worst = 0;
+        for (int c = 0; c < k; c++) {
+            double bn = std::sqrt(h[c]), rn = std::sqrt(h[k + c]);
+            double rel = bn > 0 ? rn / bn : rn;
+            if (!(rel <= worst)) worst = rel;   // NaN propagates as worst
+        }
+        if (it == 0) rep->raw_residual = worst;
+        rep->final_residual = worst;
+        if (worst <= tol) return WCS_OK;
+        if (it >= max_iter) break;
+        // D = solve(R * s) / s, X += D
+        hipLaunchKernelGGL(k_colamax, dim3(k), dim3(THREADS), 0, st, R, n, k, ld, vec + 2 * k);
+        hipLaunchKernelGGL(k_inv_scale, dim3(1), dim3(64 * ((k + 63) / 64)), 0, st, vec + 2 * k, k, vec + 3 * k);
+        hipLaunchKernelGGL(k_perm_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, R, ld, perm, n, k, Y,
+                           (const double *)(vec + 3 * k));
+        rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_perm_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k, X, ld,
+                           (const double *)(vec + 3 * k), 1);
+        rep->iterations = it + 1;
+    }
+    set_error("iterative refinement stopped at relative residual " + std::to_string(rep->final_residual));
+    return WCS_ENOTCONV;
+}
+
+template <typename V>
+int upload(wcs_factor f, size_t off, const std::vector<V> &v, hipStream_t st)
+{
+    if (v.empty()) return WCS_OK;
+    HIP_TRY(hipMemcpyAsync(f->ws + off, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, st));
+    return WCS_OK;
+}
+
+}  // namespace
+}  // namespace wcs
+
+using namespace wcs;
+
+extern "C" {
+
+int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, size_t *bytes)
+{
+    if (!sym || !bytes || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32)) {
+        set_error("invalid argument to wcs_workspace_size");
+        return WCS_EINVAL;
+    }
+    try {
+        Plan P;
+        P.build(symbolic_of(sym));
+        Layout L;
+        L.compute(symbolic_of(sym), P, elem_size(prec), max_nrhs);
+        *bytes = L.total;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return WCS_ENOMEM;
+    }
+    return WCS_OK;
+}
+
+int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, void *workspace, size_t bytes,
+                      wcs_stream stream, wcs_factor *out)
+{
+    if (!sym || !out || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32) || !workspace) {
+        set_error("invalid argument to wcs_factor_create");
+        return WCS_EINVAL;
+    }
+    if (((uintptr_t)workspace) % 256) {
+        set_error("workspace must be 256-byte aligned");
+        return WCS_EINVAL;
+    }
+    *out = nullptr;
+    wcs_factor f = new (std::nothrow) wcs_factor_s;
+    if (!f) return WCS_ENOMEM;
+    try {
+        f->S = &symbolic_of(sym);
+        f->prec = prec;
+        f->max_nrhs = max_nrhs;
+        f->plan.build(*f->S);
+        f->lay.compute(*f->S, f->plan, elem_size(prec), max_nrhs);
+    } catch (const std::bad_alloc &) {
+        delete f;
+        set_error("host allocation failed");
+        return WCS_ENOMEM;
+    }
+    if (bytes < f->lay.total) {
+        set_error("workspace too small: need " + std::to_string(f->lay.total) + " bytes, got " + std::to_string(bytes));
+        delete f;
+        return WCS_ENOMEM;
+    }
+    f->ws = (char *)workspace;
+    f->bytes = bytes;
+    hipStream_t st = (hipStream_t)stream;
+    const Symbolic &S = *f->S;
+    const Plan &P = f->plan;
+    const Layout &L = f->lay;
+    int rc = WCS_OK;
+    std::vector<int64_t> fo(S.front_off.begin(), S.front_off.end());
+    rc = rc ? rc : upload(f, L.front_off, S.front_off, st);
+    rc = rc ? rc : upload(f, L.mfront, P.mfront, st);
+    rc = rc ? rc : upload(f, L.pfront, P.pfront, st);
+    rc = rc ? rc : upload(f, L.first, P.first, st);
+    rc = rc ? rc : upload(f, L.sparent, S.sparent, st);
+    rc = rc ? rc : upload(f, L.rptr, S.rptr, st);
+    rc = rc ? rc : upload(f, L.rows, S.rows, st);
+    rc = rc ? rc : upload(f, L.rel, S.rel, st);
+    rc = rc ? rc : upload(f, L.amap, S.amap, st);
+    rc = rc ? rc : upload(f, L.woff, P.woff, st);
+    rc = rc ? rc : upload(f, L.child_ptr, P.child_ptr, st);
+    rc = rc ? rc : upload(f, L.child_list, P.child_list, st);
+    rc = rc ? rc : upload(f, L.perm, S.perm, st);
+    rc = rc ? rc : upload(f, L.csr_ptr, S.csr_ptr, st);
+    rc = rc ? rc : upload(f, L.csr_col, S.csr_col, st);
+    rc = rc ? rc : upload(f, L.csr_src, S.csr_src, st);
+    rc = rc ? rc : upload(f, L.rowind, S.rowind, st);
+    rc = rc ? rc : upload(f, L.colof, P.colof, st);
+    rc = rc ? rc : upload(f, L.pan, P.pan_tasks, st);
+    rc = rc ? rc : upload(f, L.syrk, P.syrk_tasks, st);
+    rc = rc ? rc : upload(f, L.ea, P.ea_tasks, st);
+    rc = rc ? rc : upload(f, L.flist, P.flist, st);
+    if (rc == WCS_OK) {
+        hipError_t e = hipStreamSynchronize(st);   // host vectors are pageable: finish the copies
+        if (e != hipSuccess) {
+            set_error(std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+            rc = WCS_EHIP;
+        }
+    }
+    if (rc) { delete f; return rc; }
+    *out = f;
+    return WCS_OK;
+}
+
+int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *bad_col)
+{
+    if (!f || !values_dev) { set_error("invalid argument to wcs_factor_numeric"); return WCS_EINVAL; }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st) : launch_factor<float>(f, values_dev, st);
+    if (rc) return rc;
+    f->have_values = true;
+    f->csr_values_from = nullptr;
+    if (bad_col) return wcs_factor_check(f, stream, bad_col);
+    return WCS_OK;
+}
+
+int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col)
+{
+    if (!f || !bad_col) { set_error("invalid argument to wcs_factor_check"); return WCS_EINVAL; }
+    if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
+    int32_t h = INT32_MAX;
+    HIP_TRY(hipMemcpyAsync(&h, f->ws + f->lay.bad, sizeof(int32_t), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    if (h != INT32_MAX) {
+        *bad_col = h;
+        set_error("matrix is not positive definite: pivot " + std::to_string(h) + " (original index " +
+                  std::to_string(f->S->perm[h]) + ")");
+        return WCS_ENOTSPD;
+    }
+    *bad_col = -1;
+    return WCS_OK;
+}
+
+void wcs_factor_free(wcs_factor f) { delete f; }
+
+int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t *Li, double *Lx, wcs_stream stream)
+{
+    if (!f || !Lp || j0 < 0 || j1 < j0 || j1 > f->S->n || ((Li == nullptr) != (Lx == nullptr))) {
+        set_error("invalid argument to wcs_factor_export");
+        return WCS_EINVAL;
+    }
+    const Symbolic &S = *f->S;
+    Lp[0] = 0;
+    for (int32_t j = j0; j < j1; j++) {
+        int32_t s = S.snode_of[j];
+        Lp[j - j0 + 1] = Lp[j - j0] + (S.m_of(s) - (j - S.sptr[s]));
+    }
+    if (!Li) return WCS_OK;
+    if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    size_t esz = elem_size(f->prec);
+    std::vector<char> buf;
+    for (int32_t j = j0; j < j1; j++) {
+        int32_t s = S.snode_of[j];
+        int32_t m = S.m_of(s), t = j - S.sptr[s];
+        int32_t cnt = m - t;
+        buf.resize((size_t)cnt * esz);
+        size_t off = f->lay.fronts + ((size_t)S.front_off[s] + (size_t)t * m + t) * esz;
+        HIP_TRY(hipMemcpy(buf.data(), f->ws + off, (size_t)cnt * esz, hipMemcpyDeviceToHost));
+        int64_t o = Lp[j - j0];
+        for (int32_t r = 0; r < cnt; r++) {
+            Li[o + r] = S.rows[S.rptr[s] + t + r];
+            Lx[o + r] = esz == 8 ? ((const double *)buf.data())[r] : (double)((const float *)buf.data())[r];
+        }
+    }
+    return WCS_OK;
+}
+
+int wcs_solve(wcs_factor f, wcs_part part, int32_t nrhs, double *B_dev, int64_t ld, wcs_stream stream)
+{
+    if (!f || !B_dev || nrhs < 1 || nrhs > f->max_nrhs || ld < f->S->n || part < 0 || part > 2) {
+        set_error("invalid argument to wcs_solve");
+        return WCS_EINVAL;
+    }
+    if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
+    hipStream_t st = (hipStream_t)stream;
+    return f->prec == WCS_FP64 ? launch_solve<double>(f, part, nrhs, B_dev, ld, st)
+                               : launch_solve<float>(f, part, nrhs, B_dev, ld, st);
+}
+
+int wcs_solve_refined(wcs_factor f, const double *values_dev, int32_t nrhs, const double *B_dev, double *X_dev,
+                      int64_t ld, double tol, int32_t max_iter, wcs_ir_report *rep, wcs_stream stream)
+{
+    if (!f || !values_dev || !B_dev || !X_dev || !rep || nrhs < 1 || nrhs > f->max_nrhs || ld < f->S->n ||
+        max_iter < 0 || !(tol >= 0)) {
+        set_error("invalid argument to wcs_solve_refined");
+        return WCS_EINVAL;
+    }
+    if (ld != f->S->n) {
+        set_error("wcs_solve_refined requires ld == n");
+        return WCS_EINVAL;
+    }
+    if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
+    hipStream_t st = (hipStream_t)stream;
+    return f->prec == WCS_FP64
+               ? solve_refined<double>(f, values_dev, nrhs, B_dev, X_dev, ld, tol, max_iter, rep, st)
+               : solve_refined<float>(f, values_dev, nrhs, B_dev, X_dev, ld, tol, max_iter, rep, st);
+}
+
+int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double *X_dev, double *Y_dev, int64_t ld,
+             wcs_stream stream)
+{
+    if (!f || !values_dev || !X_dev || !Y_dev || nrhs < 1 || ld < f->S->n) {
+        set_error("invalid argument to wcs_spmv");
+        return WCS_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = ensure_csr_values(f, values_dev, st);
+    if (rc) return rc;
+    return launch_spmv(f, nrhs, X_dev, nullptr, Y_dev, ld, st);
+}
+
+int wcs_grad_pattern(wcs_factor f, const double *lam_dev, const double *x_dev, double *gA_dev, wcs_stream stream)
+{
+    if (!f || !lam_dev || !x_dev || !gA_dev) { set_error("invalid argument to wcs_grad_pattern"); return WCS_EINVAL; }
+    const Symbolic &S = *f->S;
+    hipLaunchKernelGGL(k_grad_pattern, dim3(grid_for(S.nnz)), dim3(256), 0, (hipStream_t)stream,
+                       f->at<int32_t>(f->lay.rowind), f->at<int32_t>(f->lay.colof), S.nnz, lam_dev, x_dev, gA_dev);
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+}  // extern "C"

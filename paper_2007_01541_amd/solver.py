@@ -1,0 +1,269 @@
+"""Python binding of the wcs C ABI.
+
+Argument marshalling only: every step of analyze/factor/solve runs inside
+libwcs.so (host analysis in C++, numerics in gfx950 kernels).  PyTorch
+provides the device memory (the caller-owned workspace and vectors) and the
+stream.  There is no fallback: without the compiled library every call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional
+
+import numpy as np
+
+from . import capi
+from .capi import AnalyzeOpts, IRReport, SymbolicInfo, check, lib
+
+FP64 = 0
+FP32 = 1
+SOLVE_FULL = 0
+SOLVE_L = 1
+SOLVE_LT = 2
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class Symbolic:
+    """Ordering + symbolic analysis of one pattern (host, deterministic)."""
+
+    def __init__(self, n: int, colptr: np.ndarray, rowind: np.ndarray, coords: Optional[np.ndarray] = None,
+                 leaf_size: int = 64, dense_degree_frac: float = 0.25, dense_degree_min: float = 1024.0,
+                 user_perm: Optional[np.ndarray] = None, relax: bool = True):
+        self._keep = []
+        cp = np.ascontiguousarray(colptr, np.int64)
+        ri = np.ascontiguousarray(rowind, np.int32)
+        o = AnalyzeOpts()
+        o.leaf_size = leaf_size
+        o.dense_degree_frac = dense_degree_frac
+        o.dense_degree_min = dense_degree_min
+        o.relax = 1 if relax else 0
+        if coords is not None:
+            cc = np.ascontiguousarray(coords, np.float64)
+            o.coords = cc.ctypes.data
+            o.coord_dim = 1 if cc.ndim == 1 else cc.shape[1]
+            self._keep.append(cc)
+        if user_perm is not None:
+            up = np.ascontiguousarray(user_perm, np.int32)
+            o.user_perm = up.ctypes.data
+            self._keep.append(up)
+        h = C.c_void_p()
+        check(lib().wcs_analyze(int(n), cp.ctypes.data, ri.ctypes.data, C.byref(o), C.byref(h)), "wcs_analyze")
+        self._keep = []
+        self.handle = h
+        self.n = int(n)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                lib().wcs_symbolic_free(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def info(self) -> dict:
+        inf = SymbolicInfo()
+        check(lib().wcs_symbolic_info(self.handle, C.byref(inf)), "wcs_symbolic_info")
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def export(self) -> dict:
+        inf = self.info
+        n = self.n
+        perm = np.empty(n, np.int32)
+        parent = np.empty(n, np.int32)
+        cc = np.empty(n, np.int32)
+        sp = np.empty(inf["nsuper_fund"] + 1, np.int32)
+        tree = np.empty(6 * inf["nsep_nodes"], np.int32)
+        check(lib().wcs_symbolic_export(self.handle, perm.ctypes.data, parent.ctypes.data, cc.ctypes.data,
+                                        sp.ctypes.data, tree.ctypes.data), "wcs_symbolic_export")
+        rp = np.empty(inf["nsuper"] + 1, np.int32)
+        fo = np.empty(inf["nsuper"], np.int32)
+        check(lib().wcs_symbolic_fronts(self.handle, rp.ctypes.data, fo.ctypes.data), "wcs_symbolic_fronts")
+        return {"perm": perm, "parent": parent, "colcount": cc, "super_ptr": sp, "sep_tree": tree.reshape(-1, 6),
+                "relaxed_ptr": rp, "front_order": fo}
+
+    def workspace_size(self, precision: int = FP64, max_nrhs: int = 1) -> int:
+        b = C.c_size_t()
+        check(lib().wcs_workspace_size(self.handle, precision, max_nrhs, C.byref(b)), "wcs_workspace_size")
+        return int(b.value)
+
+
+class Factor:
+    """A device factor P A P^T = L L^T living in a torch-owned workspace."""
+
+    def __init__(self, sym: Symbolic, precision: int = FP64, max_nrhs: int = 1, device=None, stream=None):
+        torch = _torch()
+        self.sym = sym
+        self.n = sym.n
+        self.precision = precision
+        self.max_nrhs = max_nrhs
+        self.device = torch.device(device if device is not None else "cuda")
+        nbytes = sym.workspace_size(precision, max_nrhs)
+        # 256-byte aligned by the caching allocator
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        check(lib().wcs_factor_create(sym.handle, precision, max_nrhs, _dptr(self.workspace), nbytes,
+                                      _stream_ptr(stream), C.byref(h)), "wcs_factor_create")
+        self.handle = h
+        self.values = None
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                lib().wcs_factor_free(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def numeric(self, values, check_pivots: bool = True, stream=None) -> None:
+        """Factor the matrix with device FP64 values (aligned with the pattern)."""
+        torch = _torch()
+        assert values.dtype == torch.float64 and values.is_cuda and values.is_contiguous()
+        self.values = values
+        if check_pivots:
+            bad = C.c_int32(-1)
+            rc = lib().wcs_factor_numeric(self.handle, _dptr(values), _stream_ptr(stream), C.byref(bad))
+            check(rc, "wcs_factor_numeric", bad.value)
+        else:
+            check(lib().wcs_factor_numeric(self.handle, _dptr(values), _stream_ptr(stream), None),
+                  "wcs_factor_numeric")
+
+    def pivot_check(self, stream=None) -> int:
+        bad = C.c_int32(-1)
+        rc = lib().wcs_factor_check(self.handle, _stream_ptr(stream), C.byref(bad))
+        if rc not in (0, -4):
+            check(rc, "wcs_factor_check")
+        return bad.value
+
+    def solve_(self, B, part: int = SOLVE_FULL, stream=None):
+        """In-place solve on a device FP64 tensor B of shape (n,) or (n, k) (column-major view is made)."""
+        torch = _torch()
+        Bm = B if B.dim() == 2 else B.view(-1, 1)
+        k = Bm.shape[1]
+        # column-major n x k with ld = n == a contiguous (k, n) tensor transposed
+        cm = Bm.t().contiguous()
+        check(lib().wcs_solve(self.handle, part, k, _dptr(cm), self.n, _stream_ptr(stream)), "wcs_solve")
+        Bm.copy_(cm.t())
+        return B
+
+    def solve(self, B, part: int = SOLVE_FULL, stream=None):
+        return self.solve_(B.clone(), part, stream)
+
+    def solve_refined(self, B, values=None, tol: float = 1e-10, max_iter: int = 10, stream=None):
+        """X = A^-1 B by iterative refinement; returns (X, report dict)."""
+        torch = _torch()
+        vals = values if values is not None else self.values
+        Bm = B if B.dim() == 2 else B.view(-1, 1)
+        k = Bm.shape[1]
+        bc = Bm.t().contiguous()
+        xc = torch.empty_like(bc)
+        rep = IRReport()
+        rc = lib().wcs_solve_refined(self.handle, _dptr(vals), k, _dptr(bc), _dptr(xc), self.n, tol, max_iter,
+                                     C.byref(rep), _stream_ptr(stream))
+        report = {"iterations": rep.iterations, "raw_residual": rep.raw_residual,
+                  "final_residual": rep.final_residual}
+        if rc != 0:
+            err = capi.WcsError(rc, "wcs_solve_refined", lib().wcs_last_error().decode(errors="replace"))
+            err.report = report
+            raise err
+        X = xc.t().contiguous()
+        return (X if B.dim() == 2 else X.view(-1)), report
+
+    def spmv(self, X, values=None, stream=None):
+        torch = _torch()
+        vals = values if values is not None else self.values
+        Xm = X if X.dim() == 2 else X.view(-1, 1)
+        xc = Xm.t().contiguous()
+        yc = torch.empty_like(xc)
+        check(lib().wcs_spmv(self.handle, _dptr(vals), Xm.shape[1], _dptr(xc), _dptr(yc), self.n,
+                             _stream_ptr(stream)), "wcs_spmv")
+        Y = yc.t().contiguous()
+        return Y if X.dim() == 2 else Y.view(-1)
+
+    def grad_pattern(self, lam, x, stream=None):
+        torch = _torch()
+        nnz = self.sym.info["nnz_lower"]
+        g = torch.empty(nnz, dtype=torch.float64, device=lam.device)
+        check(lib().wcs_grad_pattern(self.handle, _dptr(lam.contiguous()), _dptr(x.contiguous()), _dptr(g),
+                                     _stream_ptr(stream)), "wcs_grad_pattern")
+        return g
+
+    def export_L(self, j0: int = 0, j1: Optional[int] = None):
+        """Columns [j0, j1) of L in pivot order as host CSC (stored pattern, explicit zeros kept)."""
+        j1 = self.n if j1 is None else j1
+        Lp = np.empty(j1 - j0 + 1, np.int64)
+        check(lib().wcs_factor_export(self.handle, j0, j1, Lp.ctypes.data, None, None, _stream_ptr()),
+              "wcs_factor_export")
+        Li = np.empty(int(Lp[-1]), np.int32)
+        Lx = np.empty(int(Lp[-1]), np.float64)
+        check(lib().wcs_factor_export(self.handle, j0, j1, Lp.ctypes.data, Li.ctypes.data, Lx.ctypes.data,
+                                      _stream_ptr()), "wcs_factor_export")
+        return Lp, Li, Lx
+
+
+def _solve_op():
+    torch = _torch()
+
+    class SparseCholeskySolve(torch.autograd.Function):
+        """y = A^-1 b with A given by its stored lower entries (values).
+
+        Forward factors nothing: it uses a prepared Factor of A.  Backward reuses
+        the same factor: lam = A^-1 gy, gb = lam, and the gradient with respect
+        to the stored entries is -(lam_i y_j + lam_j y_i) off the diagonal and
+        -lam_i y_i on it.  Only the factor and y are kept between the passes.
+        """
+
+        @staticmethod
+        def forward(ctx, values, b, factor, refine, tol, max_iter):
+            if refine:
+                y, _ = factor.solve_refined(b.detach(), values.detach(), tol=tol, max_iter=max_iter)
+            else:
+                y = factor.solve(b.detach())
+            ctx.factor = factor
+            ctx.refine = refine
+            ctx.tol = tol
+            ctx.max_iter = max_iter
+            ctx.save_for_backward(values, y)
+            return y
+
+        @staticmethod
+        def backward(ctx, gy):
+            values, y = ctx.saved_tensors
+            f = ctx.factor
+            if ctx.refine:
+                lam, _ = f.solve_refined(gy.contiguous(), values, tol=ctx.tol, max_iter=ctx.max_iter)
+            else:
+                lam = f.solve(gy.contiguous())
+            gvals = f.grad_pattern(lam, y) if ctx.needs_input_grad[0] else None
+            gb = lam if ctx.needs_input_grad[1] else None
+            return gvals, gb, None, None, None, None
+
+    return SparseCholeskySolve
+
+
+_OP = None
+
+
+def cholesky_solve(values, b, factor: Factor, refine: bool = False, tol: float = 1e-10, max_iter: int = 10):
+    """Differentiable x = A^-1 b (b a 1-D device FP64 tensor) through a prepared Factor."""
+    global _OP
+    if _OP is None:
+        _OP = _solve_op()
+    return _OP.apply(values, b, factor, refine, tol, max_iter)

@@ -1,0 +1,195 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Sizes here run through several tiles, ragged tails and multi-level trees
+while the oracle finishes in seconds."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import small_fp64, tiny, WaveletSpec, make_matrix, normal_rhs
+from tests.helpers import EPS32, EPS64, compare_columns, factor_tol, gershgorin_kappa
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_2007_01541_amd import FP32, FP64, SOLVE_FULL, SOLVE_L, SOLVE_LT, Factor, Symbolic, cholesky_solve  # noqa: E402
+from paper_2007_01541_amd.capi import WcsError  # noqa: E402
+
+
+def instance(kind):
+    if kind == "small":
+        return small_fp64().matrix()
+    if kind == "g5a13":
+        return tiny(5, 1.3, seed=21).matrix()
+    if kind == "g4a2":
+        return tiny(4, 2.0, seed=22).matrix()
+    if kind == "g6alg":
+        return make_matrix(WaveletSpec(6, 2.0, 0.75, "alg", 0.3, 1.75, 23))
+    raise KeyError(kind)
+
+
+_CACHE = {}
+
+
+def prepared(kind, leaf=64, coords=True):
+    key = (kind, leaf, coords)
+    if key not in _CACHE:
+        m = instance(kind)
+        sym = Symbolic(m["n"], m["colptr"], m["rowind"], coords=m["coords"] if coords else None, leaf_size=leaf,
+                       dense_degree_min=64 if m["n"] < 4096 else 1024)
+        perm = sym.export()["perm"]
+        orc = oracle.factorize(m, perm)
+        _CACHE[key] = (m, sym, orc)
+    return _CACHE[key]
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+
+
+CASES = [("small", 64, True), ("g5a13", 16, True), ("g4a2", 8, False), ("g6alg", 32, True)]
+
+
+@pytest.mark.parametrize("kind,leaf,coords", CASES)
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_factor_matches_oracle(kind, leaf, coords, prec):
+    m, sym, orc = prepared(kind, leaf, coords)
+    print(f"case {kind} leaf={leaf} prec={prec} n={m['n']} fronts={sym.info['nsuper']}", flush=True)
+    f = Factor(sym, prec)
+    f.numeric(dev(m["values"]))
+    Lp, Li, Lx = f.export_L()
+    worst, scale = compare_columns(Lp, Li, Lx, orc)
+    tol = factor_tol(m, int(orc.colcount.max()), EPS64 if prec == FP64 else EPS32)
+    assert worst <= tol * scale, (worst / scale, tol)
+
+
+@pytest.mark.parametrize("kind,leaf,coords", CASES)
+@pytest.mark.parametrize("k", [1, 3, 64])
+def test_fp64_solve(kind, leaf, coords, k):
+    m, sym, orc = prepared(kind, leaf, coords)
+    n = m["n"]
+    B = normal_rhs(n, k, 77)
+    f = Factor(sym, FP64, max_nrhs=k)
+    f.numeric(dev(m["values"]))
+    X = f.solve(dev(B)).cpu().numpy()
+    res = oracle.residual(n, m["colptr"], m["rowind"], m["values"], X, B)
+    assert res.max() <= 1e-12
+    Xo = orc.solve(B)
+    tol = factor_tol(m, int(orc.colcount.max()), EPS64)
+    assert np.abs(X - Xo).max() <= tol * np.abs(Xo).max()
+
+
+@pytest.mark.parametrize("part", [SOLVE_L, SOLVE_LT])
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_half_solves(part, prec):
+    m, sym, orc = prepared("small")
+    n = m["n"]
+    B = normal_rhs(n, 2, 5)
+    f = Factor(sym, prec, max_nrhs=2)
+    f.numeric(dev(m["values"]))
+    X = f.solve(dev(B), part).cpu().numpy()
+    Xo = orc.solve(B, part)
+    tol = factor_tol(m, int(orc.colcount.max()), EPS64 if prec == FP64 else EPS32)
+    assert np.abs(X - Xo).max() <= tol * np.abs(Xo).max()
+
+
+@pytest.mark.parametrize("kind,leaf,coords", CASES)
+@pytest.mark.parametrize("k", [1, 64])
+def test_fp32_refined_reaches_1e10(kind, leaf, coords, k):
+    m, sym, orc = prepared(kind, leaf, coords)
+    n = m["n"]
+    B = normal_rhs(n, k, 9)
+    f = Factor(sym, FP32, max_nrhs=k)
+    vals = dev(m["values"])
+    f.numeric(vals)
+    X, rep = f.solve_refined(dev(B), vals, tol=1e-10, max_iter=10)
+    X = X.cpu().numpy()
+    res = oracle.residual(n, m["colptr"], m["rowind"], m["values"], X, B)
+    print(f"{kind} k={k}: iterations={rep['iterations']} raw={rep['raw_residual']:.3e} final={res.max():.3e}")
+    assert res.max() <= 1e-10
+    assert rep["final_residual"] <= 1e-10
+    assert rep["raw_residual"] > rep["final_residual"] or rep["iterations"] == 0
+    Xo = orc.solve(B)
+    assert np.abs(X - Xo).max() <= 1e-10 * gershgorin_kappa(m) * np.abs(Xo).max()
+
+
+def test_fp64_refined_no_iterations_needed():
+    m, sym, _ = prepared("small")
+    B = normal_rhs(m["n"], 1, 3)
+    f = Factor(sym, FP64)
+    vals = dev(m["values"])
+    f.numeric(vals)
+    X, rep = f.solve_refined(dev(B), vals, tol=1e-12, max_iter=0)
+    assert rep["iterations"] == 0 and rep["final_residual"] <= 1e-12
+
+
+def test_refinement_not_converged_reports():
+    m, sym, _ = prepared("small")
+    B = normal_rhs(m["n"], 1, 3)
+    f = Factor(sym, FP32)
+    vals = dev(m["values"])
+    f.numeric(vals)
+    with pytest.raises(WcsError) as e:
+        f.solve_refined(dev(B), vals, tol=1e-30, max_iter=0)
+    assert e.value.code == -5 and e.value.report["iterations"] == 0
+
+
+def test_spmv_matches_oracle():
+    m, sym, _ = prepared("small")
+    X = normal_rhs(m["n"], 3, 4)
+    f = Factor(sym, FP64, max_nrhs=3)
+    Y = f.spmv(dev(X), dev(m["values"])).cpu().numpy()
+    Yo = oracle.symv(m["n"], m["colptr"], m["rowind"], m["values"], X)
+    assert np.abs(Y - Yo).max() <= 1e-13 * np.abs(Yo).max()
+
+
+@pytest.mark.parametrize("kind", ["small", "g5a13"])
+def test_gradient_matches_oracle(kind):
+    m, sym, orc = prepared(kind, *{"small": (64, True), "g5a13": (16, True)}[kind])
+    n = m["n"]
+    g = np.random.default_rng(3)
+    b = g.standard_normal(n)
+    ystar = g.standard_normal(n)
+    f = Factor(sym, FP64)
+    vals = dev(m["values"]).requires_grad_(True)
+    f.numeric(vals.detach())
+    bt = dev(b).requires_grad_(True)
+    y = cholesky_solve(vals, bt, f)
+    loss = 0.5 * ((y - dev(ystar)) ** 2).sum()
+    loss.backward()
+    x = orc.solve(b)
+    lam = orc.solve(x - ystar)
+    gA = oracle.grad(n, m["colptr"], m["rowind"], lam, x)
+    assert np.abs(vals.grad.cpu().numpy() - gA).max() <= 1e-10 * np.abs(gA).max()
+    assert np.abs(bt.grad.cpu().numpy() - lam).max() <= 1e-10 * np.abs(lam).max()
+
+
+def test_not_spd_reports_first_pivot():
+    m, sym, _ = prepared("g5a13", 16, True)
+    perm = sym.export()["perm"]
+    iperm = np.empty_like(perm); iperm[perm] = np.arange(perm.size)
+    col = int(perm[perm.size // 3])
+    v = m["values"].copy()
+    v[m["colptr"][col]] = -1.0
+    f = Factor(sym, FP64)
+    with pytest.raises(WcsError) as e:
+        f.numeric(dev(v))
+    assert e.value.code == -4 and e.value.bad_col == iperm[col]
+    v[m["colptr"][col]] = np.nan
+    with pytest.raises(WcsError) as e:
+        f.numeric(dev(v))
+    assert e.value.code == -4 and e.value.bad_col <= iperm[col]
+
+
+def test_refactor_and_determinism():
+    m, sym, _ = prepared("small")
+    f = Factor(sym, FP64)
+    f.numeric(dev(m["values"]))
+    a = f.export_L()[2].copy()
+    f.numeric(dev(m["values"] * 2.0))
+    b = f.export_L()[2].copy()
+    f.numeric(dev(m["values"]))
+    c = f.export_L()[2]
+    assert np.array_equal(a, c)                      # bitwise reproducible
+    # L(2A) = sqrt(2) L(A): exact up to rounding, measured against max |L|
+    assert np.abs(b - a * np.sqrt(2.0)).max() <= 1e-13 * np.abs(b).max()
