@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the sparse Cholesky hot path on one MI355X.
+
+Workload (default): the 512 x 512 Haar grid, N = 2^18, a = 2, s = 0.75,
+algebraic decay, 64 right-hand sides.  One step is the whole path on inputs
+already resident in HBM: value load into the fronts, numeric factorization,
+and the solve of all 64 right-hand sides to relative residual 1e-10 — in
+FP32 on the matrix cores with FP64 iterative refinement (the measured path),
+and the same step with the plain FP64 factor for comparison.  The ordering
+and symbolic analysis (host, once per pattern) are outside the timed region.
+
+Prints one JSON line (metric, value = factor TFLOP/s of the FP32+IR path from
+the symbolic flop count sum(colcount^2), ...), with a roofline object for the
+dominant kernel (per-launch HIP events on the launch stream) and the CPU
+oracle timed on a bounded sample of the same factorization.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma_tflops": 157.3, "fp64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
+METRIC = "factor TFLOP/s + % MFMA peak, N=2^18: FP32+IR vs FP64 at resid 1e-10"
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def sample_flops(Lp, Li, ncols: int) -> float:
+    """Exact flops the left-looking oracle performs for its first ncols columns
+    (sqrt and divisions of those columns, 2 per multiply-add of every update
+    they receive), in the same counting as sum(colcount^2)."""
+    import numpy as np
+    total = float(Lp[ncols] - Lp[0])              # one sqrt or division per entry of the sample columns
+    for k in range(ncols):
+        rows = Li[Lp[k] + 1:Lp[k + 1]]
+        c = rows.size
+        t = np.searchsorted(rows, ncols)          # off-diagonal rows that are sample columns
+        # an update into column rows[i] touches the c - i rows at or below it
+        total += 2.0 * float(np.sum(c - np.arange(t)))
+    return total
+
+
+def cpu_baseline(m, perm, target_seconds: float) -> dict:
+    import numpy as np
+    import oracle
+    n = m["n"]
+    t0 = time.perf_counter()
+    parent, cc, nnzL, flops = oracle.symbolic(n, m["colptr"], m["rowind"], perm)
+    Lp, Li = oracle.pattern(n, m["colptr"], m["rowind"], perm, parent, cc)
+    log(f"oracle symbolic+pattern {time.perf_counter() - t0:.1f}s")
+    # first a short calibration, then a sample sized for the target time
+    cum = np.cumsum(cc.astype(np.float64) ** 2)
+    k_cal = int(np.searchsorted(cum, 2e9)) + 1
+    t0 = time.perf_counter()
+    oracle.factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp, Li, ncols=min(k_cal, n))
+    t_cal = time.perf_counter() - t0
+    rate = sample_flops(Lp, Li, min(k_cal, n)) / max(t_cal, 1e-3)
+    k = int(np.searchsorted(cum, rate * target_seconds)) + 1
+    k = min(max(k, k_cal), n)
+    t0 = time.perf_counter()
+    oracle.factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp, Li, ncols=k)
+    t = time.perf_counter() - t0
+    fl = sample_flops(Lp, Li, k)
+    log(f"oracle sample: {k} leading pivot columns, {fl / 1e9:.1f} GFLOP in {t:.1f}s")
+    return {"value": fl / t / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"left-looking FP64 factorization of the first {k} of {n} pivot columns "
+                      f"(nested dissection order) of the same matrix: {fl:.4g} flops in {t:.2f} s, "
+                      f"single thread"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the elimination-tree sharding across GPUs is described in DESIGN.md only).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2007_01541_amd import FP32, FP64, Factor, Symbolic
+
+    w = {"headline": workloads.headline, "medium": workloads.medium_fp64, "small": workloads.small_fp64}[args.workload]()
+    nrhs = 64 if args.workload == "headline" else w.nrhs
+    t0 = time.perf_counter()
+    m = w.matrix()
+    B = workloads.normal_rhs(w.n, nrhs, w.seed + 1)
+    log(f"generated {w.name}: n={m['n']} nnz_lower={m['colptr'][-1]} in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    sym = Symbolic(m["n"], m["colptr"], m["rowind"], coords=m["coords"])
+    info = sym.info
+    t_analyze = time.perf_counter() - t0
+    log(f"analyze {t_analyze:.1f}s: nnz(L)={info['nnz_l']} flops={info['flops']:.4e} fronts={info['nsuper']} "
+        f"max front={info['max_front']}")
+    F = float(info["flops"])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    vals = torch.as_tensor(m["values"], device=dev)
+    Bd = torch.as_tensor(B, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def run_path(prec, refine):
+        f = Factor(sym, prec, max_nrhs=nrhs, device=dev)
+        log(f"{'FP32' if prec == FP32 else 'FP64'} workspace {f.workspace.numel() / 2**30:.1f} GiB")
+        reports = []
+
+        def step():
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            f.numeric(vals, check_pivots=False)
+            e1.record(stream)
+            if refine:
+                X, rep = f.solve_refined(Bd, vals, tol=args.tol, max_iter=10)
+            else:
+                X, rep = f.solve_refined(Bd, vals, tol=args.tol, max_iter=0)
+            reports.append(rep)
+            return e0, e1, X
+
+        for i in range(args.warmup):
+            step()
+            torch.cuda.synchronize()
+            log(f"  warmup {i} done: {reports[-1]}")
+        reports.clear()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        evs = []
+        for i in range(args.steps):
+            e0, e1, X = step()
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t0
+        fact_ms = [a.elapsed_time(b) for a, b in evs]
+        bad = f.pivot_check()
+        assert bad == -1, f"pivot {bad} failed"
+        log(f"  {args.steps} steps: {t_total * 1e3 / args.steps:.1f} ms/step, factor {np.mean(fact_ms):.2f} ms; "
+            f"last report {reports[-1]}")
+        return f, t_total / args.steps, float(np.mean(fact_ms)), reports[-1]
+
+    f32, step32, fact32, rep32 = run_path(FP32, True)
+    prof = f32.profile(vals)
+    torch.cuda.synchronize()
+    for nm, st in prof.items():
+        log(f"  kernel class {nm}: {st['launches']} launches, {st['ms']:.2f} ms, "
+            f"{st['flops'] / 1e9:.1f} GFLOP, {st['bytes'] / 1e9:.2f} GB")
+    dom = max(prof, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    del f32
+    torch.cuda.empty_cache()
+    fp64 = None
+    if not args.no_fp64:
+        f64, step64, fact64, rep64 = run_path(FP64, False)
+        fp64 = {"ms_per_step": step64 * 1e3, "factor_ms": fact64, "factor_tflops": F / fact64 / 1e9,
+                "pct_fp64_mfma_peak": 100 * F / fact64 / 1e9 / PEAK["fp64_mfma_tflops"],
+                "final_residual": rep64["final_residual"]}
+        del f64
+        torch.cuda.empty_cache()
+
+    if d["flops"] > 0:
+        achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK["fp32_mfma_tflops"], "traffic": None, "kernel": dom,
+                "launches": d["launches"], "avg_launch_us": d["ms"] * 1e3 / max(1, d["launches"])}
+    else:
+        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                "frac": achieved / PEAK["hbm_gbs"], "traffic": None, "kernel": dom,
+                "launches": d["launches"], "avg_launch_us": d["ms"] * 1e3 / max(1, d["launches"])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        perm = sym.export()["perm"]
+        cpu = cpu_baseline(m, perm, args.cpu_seconds)
+
+    value = F / fact32 / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": int(m["n"]), "nnz_lower": int(m["colptr"][-1]), "nrhs": nrhs,
+                   "nnz_l": int(info["nnz_l"]), "flops": int(info["flops"]), "fronts": int(info["nsuper"]),
+                   "max_front": int(info["max_front"]), "analyze_s": round(t_analyze, 2)},
+        "pct_fp32_mfma_peak": 100 * value / PEAK["fp32_mfma_tflops"],
+        "factor_ms": fact32,
+        "ir": rep32,
+        "fp64": fp64,
+        "speedup_e2e_vs_fp64": (fp64["ms_per_step"] / (step32 * 1e3)) if fp64 else None,
+        "kernels": prof,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

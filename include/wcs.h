@@ -174,6 +174,26 @@ int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col);
 void wcs_factor_free(wcs_factor f);
 
 /*
+ * Diagnostic: performs one numeric factorization (as wcs_factor_numeric with
+ * bad_col NULL) with a HIP event pair around every kernel launch on `stream`,
+ * waits for it, and fills stats[WCS_NKCLASS], one entry per kernel class:
+ *   0 front zero-fill, 1 value scatter, 2 extend-add, 3 panel (diagonal block
+ *   factor + triangular solve), 4 panel with FP64 diagonal blocks (FP32
+ *   factors), 5 trailing update on the matrix cores.
+ * Each entry holds the launch count, the summed event time and the
+ * algorithmic work of those launches (flops: multiply-add = 2; bytes: data the
+ * operation must move once).  The events add a little time between launches.
+ */
+#define WCS_NKCLASS 6
+typedef struct {
+    int32_t launches;
+    double ms;
+    double flops;
+    double bytes;
+} wcs_kernel_stat;
+int wcs_factor_profile(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *stats);
+
+/*
  * Copies columns [j0, j1) (pivot order) of L to host memory in compressed
  * sparse column form over the stored (amalgamated) pattern, explicit zeros
  * included: Lp[j1-j0+1] offsets starting at 0, Li row indices (pivot order,

@@ -43,6 +43,13 @@ class SymbolicInfo(C.Structure):
     ]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("launches", c_i32), ("ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+KERNEL_CLASSES = ["fill", "scatter", "extend_add", "panel", "panel_fp64diag", "update"]
+
+
 class IRReport(C.Structure):
     _fields_ = [("iterations", c_i32), ("raw_residual", C.c_double), ("final_residual", C.c_double)]
 
@@ -61,6 +68,7 @@ SIGNATURES = [
     ("wcs_factor_numeric", C.c_int, [c_p, c_p, c_p, C.POINTER(c_i32)]),
     ("wcs_factor_check", C.c_int, [c_p, c_p, C.POINTER(c_i32)]),
     ("wcs_factor_free", None, [c_p]),
+    ("wcs_factor_profile", C.c_int, [c_p, c_p, c_p, c_p]),
     ("wcs_factor_export", C.c_int, [c_p, c_i32, c_i32, c_p, c_p, c_p, c_p]),
     ("wcs_solve", C.c_int, [c_p, C.c_int, c_i32, c_p, c_i64, c_p]),
     ("wcs_solve_refined", C.c_int, [c_p, c_p, c_i32, c_p, c_p, c_i64, C.c_double, c_i32,

@@ -16,8 +16,6 @@ namespace wcs {
 namespace dev {
 
 constexpr int NB = 64;        // panel width
-constexpr int TS = 64;        // trailing-update tile (TS x TS per workgroup)
-constexpr int TR = 64;        // rows per triangular-solve tile
 constexpr int EA_COLS = 8;    // update-matrix columns per extend-add task
 constexpr int THREADS = 256;
 
@@ -95,137 +93,358 @@ __global__ void k_extend_add(const int2 *__restrict__ tasks, const int64_t *__re
 }
 
 // ---------------------------------------------------------------- panel
-// task = (front, tile).  Every workgroup factors the diagonal block
-// F[k0:k0+nb, k0:k0+nb] in LDS (in precision TD); tile 0 writes it back, tile
-// t >= 1 solves rows [k0+nb+(t-1)*TR, ...) of the panel: X = B * L_kk^-T.
-// A non-positive (or NaN) pivot is reported through atomicMin on *bad (in
-// global pivot numbering) and replaced by 1 so the rest stays finite.
+// Broadcast of lane `l` (a compile-time constant after unrolling) to the wave.
+__device__ __forceinline__ float readlane(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l)
+{
+    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// 16 x 16 x 16 product on one wave: acc += X * Y with X(r, k) = fx(r, k),
+// Y(k, n) = fy(k, n); the caller maps acc element e of lane l to
+// C(Mfma<TD>::row(l/16, e), l%16).
+template <typename TD, typename FX, typename FY>
+__device__ __forceinline__ typename Mfma<TD>::V mm16(typename Mfma<TD>::V acc, FX fx, FY fy)
+{
+    int lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) acc = Mfma<TD>::mma(fx(ln, kk + kq), fy(kk + kq, ln), acc);
+    return acc;
+}
+
+// task = (front, tile).  Wave 0 of every workgroup factors the diagonal
+// block A = F[k0:k0+nb, k0:k0+nb] (still unfactored in the front), padded to
+// NB x NB with the identity, by 16-column blocks: the 16 x 16 diagonal
+// sub-block with one lane per row in registers (l_jj = sqrt(a_jj),
+// l_rj = a_rj / l_jj, a_rc -= l_rj l_cj, l_cj broadcast from lane c), its
+// inverse by forward substitution, the sub-panel below it as X = A L_kk^-T
+// and the trailing update A -= X X^T as 16x16x16 matrix-core products.  The
+// inverse of the whole block is then assembled blockwise:
+// (L^-1)_ik = -L_ii^-1 sum_{k<=j<i} L_ij (L^-1)_jk.  Meanwhile waves 1..3 load
+// their 64-row slabs of the panel below the block; afterwards they solve them
+// as X = B L^-T on the matrix cores (rows [k0+nb+t*TRW, +TRW)).
+// Tile 0 writes the factored block to `dscr` (the front must keep the
+// unfactored block readable for the other workgroups of this launch, and a
+// later launch copies it into place) and the block's inverse to `dinv`, which
+// the triangular solves use.
+// A non-positive (or NaN) pivot is reported through atomicMin on *bad (global
+// pivot numbering) and replaced by 1 so the rest stays finite.
+constexpr int TRW = THREADS - 64;   // panel rows per workgroup (waves 1..3)
+
 template <typename T, typename TD>
 __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ tasks, int k0,
                                                    const int64_t *__restrict__ front_off,
                                                    const int32_t *__restrict__ mfront,
                                                    const int32_t *__restrict__ pfront,
-                                                   const int32_t *__restrict__ first, T *__restrict__ fronts,
+                                                   const int32_t *__restrict__ first,
+                                                   const int64_t *__restrict__ dscr_off, T *__restrict__ fronts,
+                                                   T *__restrict__ dscr, T *__restrict__ dinv,
                                                    int32_t *__restrict__ bad)
 {
-    __shared__ TD D[NB][NB + 1];     // D[c][r] = L(k0+r, k0+c)
-    __shared__ TD X[NB][TR + 1];     // X[c][r] = panel(row r of tile, column c)
+    typedef typename Mfma<TD>::V VD;
+    __shared__ TD A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L
+    __shared__ TD Iv[NB][NB + 1];    // column-major: Iv[c][r] = L^-1(r, c)
+    __shared__ T Li[NB][NB + 1];     // row-major copy of L^-1 in the panel precision
     int2 t = tasks[blockIdx.x];
     int f = t.x;
     int m = mfront[f], p = pfront[f];
     int nb = min(NB, p - k0);
     T *F = fronts + front_off[f];
     int tid = threadIdx.x;
-    for (int idx = tid; idx < NB * NB; idx += THREADS) {
-        int c = idx / NB, r = idx % NB;
-        TD v = 0;
-        if (c < nb && r < nb && r >= c) v = (TD)F[(int64_t)(k0 + c) * m + k0 + r];
-        D[c][r] = v;
-    }
-    __syncthreads();
-    for (int j = 0; j < nb; j++) {
-        if (tid == 0) {
-            TD d = D[j][j];
-            if (!(d > (TD)0)) {
-                atomicMin(bad, first[f] + k0 + j);
-                d = (TD)1;
+    int wave = tid / 64, lane = tid % 64;
+    int kq = lane / 16, ln = lane % 16;
+    int row0 = k0 + nb + t.y * TRW + (wave - 1) * 64;
+    T bv[NB / 4][4];                 // waves 1..3: the slab in MFMA A-operand order
+    if (wave == 0) {
+        {
+            const int r = lane;
+            TD col[NB];
+#pragma unroll
+            for (int c = 0; c < NB; c++)
+                col[c] = (r < nb && c < nb && c <= r) ? (TD)F[(int64_t)(k0 + c) * m + k0 + r]
+                                                      : (c == r ? (TD)1 : (TD)0);
+#pragma unroll
+            for (int c = 0; c < NB; c++) {
+                A[c][r] = col[c];
+                Iv[c][r] = 0;
             }
-            D[j][j] = sqrt(d);
         }
-        __syncthreads();
-        TD djj = D[j][j];
-        for (int r = j + 1 + tid; r < nb; r += THREADS) D[j][r] /= djj;
-        __syncthreads();
-        int w = nb - j - 1;
-        for (int idx = tid; idx < w * w; idx += THREADS) {
-            int c = j + 1 + idx / w, r = j + 1 + idx % w;
-            if (r >= c) D[c][r] -= D[j][r] * D[j][c];
+        for (int kb = 0; kb < NB; kb += 16) {
+            __builtin_amdgcn_wave_barrier();
+            // (1) diagonal 16 x 16 sub-block, lanes 0..15 own its rows
+            if (lane < 16) {
+                const int r = kb + lane;
+                TD a[16];
+#pragma unroll
+                for (int u = 0; u < 16; u++) a[u] = A[kb + u][r];
+#pragma unroll
+                for (int u = 0; u < 16; u++) {
+                    TD d = readlane(a[u], u);
+                    if (!(d > (TD)0)) {
+                        if (lane == 0 && t.y == 0 && kb + u < nb) atomicMin(bad, first[f] + k0 + kb + u);
+                        d = (TD)1;
+                    }
+                    TD piv = sqrt(d);
+                    TD l = (lane == u) ? piv : a[u] / piv;
+                    a[u] = l;
+#pragma unroll
+                    for (int v = u + 1; v < 16; v++) a[v] -= l * readlane(l, v);
+                }
+#pragma unroll
+                for (int u = 0; u < 16; u++) A[kb + u][r] = (u <= lane) ? a[u] : (TD)0;
+            }
+            __builtin_amdgcn_wave_barrier();
+            // (2) its inverse: lane c < 16 solves L_kk y = e_c
+            if (lane < 16) {
+                const int c = lane;
+                TD y[16];
+#pragma unroll
+                for (int rr = 0; rr < 16; rr++) {
+                    TD s2 = (rr == c) ? (TD)1 : (TD)0;
+#pragma unroll
+                    for (int q = 0; q < rr; q++) s2 -= A[kb + q][kb + rr] * y[q];
+                    y[rr] = s2 / A[kb + rr][kb + rr];
+                }
+#pragma unroll
+                for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
+            }
+            __builtin_amdgcn_wave_barrier();
+            // (3) sub-panel below: X(i, n) = sum_k A(i, kb+k) L_kk^-1(n, k)
+            for (int ib = kb + 16; ib < NB; ib += 16) {
+                VD acc = {0, 0, 0, 0};
+                acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
+                               [&](int k, int n) { return Iv[kb + k][kb + n]; });
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int e = 0; e < 4; e++) A[kb + ln][ib + Mfma<TD>::row(kq, e)] = acc[e];
+                __builtin_amdgcn_wave_barrier();
+            }
+            // (4) trailing update: A(i, j) -= X_i X_j^T for kb < j <= i
+            for (int ib = kb + 16; ib < NB; ib += 16)
+                for (int jb = kb + 16; jb <= ib; jb += 16) {
+                    VD acc = {0, 0, 0, 0};
+                    acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
+                                   [&](int k, int n) { return A[kb + k][jb + n]; });
+#pragma unroll
+                    for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<TD>::row(kq, e)] -= acc[e];
+                }
         }
-        __syncthreads();
-    }
-    if (t.y == 0) {
-        for (int idx = tid; idx < nb * nb; idx += THREADS) {
-            int c = idx / nb, r = idx % nb;
-            if (r >= c) F[(int64_t)(k0 + c) * m + k0 + r] = (T)D[c][r];
+        __builtin_amdgcn_wave_barrier();
+        // block inverse: (L^-1)_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij (L^-1)_jk
+        for (int ib = 16; ib < NB; ib += 16)
+            for (int kb = 0; kb < ib; kb += 16) {
+                VD acc = {0, 0, 0, 0};
+                for (int jb = kb; jb < ib; jb += 16)
+                    acc = mm16<TD>(acc, [&](int r, int k) { return A[jb + k][ib + r]; },
+                                   [&](int k, int n) { return Iv[kb + n][jb + k]; });
+                __builtin_amdgcn_wave_barrier();
+                // stage T = acc in the upper (unused) part of A: A[ib + col][kb + row] for the product
+                // with L_ii^-1 (rows ib.., cols kb..): T(row, col) stored at A[kb + col][... ] is busy,
+                // so use the 16 x 16 block of Iv above the diagonal, Iv[ib + col][kb + row] (row < 16).
+#pragma unroll
+                for (int e = 0; e < 4; e++) Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = acc[e];
+                __builtin_amdgcn_wave_barrier();
+                VD res = {0, 0, 0, 0};
+                res = mm16<TD>(res, [&](int r, int k) { return Iv[ib + k][ib + r]; },
+                               [&](int k, int n) { return Iv[ib + n][kb + k]; });
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    Iv[kb + ln][ib + Mfma<TD>::row(kq, e)] = -res[e];
+                    Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = 0;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        __builtin_amdgcn_wave_barrier();
+        {
+            const int r = lane;
+            if (t.y == 0) {
+                int64_t o = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
+                T *D = dscr + o;
+                T *DI = dinv + o;
+#pragma unroll
+                for (int c = 0; c < NB; c++) {
+                    if (c <= r) D[c * NB + r] = (T)A[c][r];
+                    DI[c * NB + r] = (T)Iv[c][r];     // column-major L^-1 of the padded block
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < NB; c++) Li[r][c] = (T)Iv[c][r];
         }
-        return;
-    }
-    int r0 = k0 + nb + (t.y - 1) * TR;
-    int nr = min(TR, m - r0);
-    for (int idx = tid; idx < NB * TR; idx += THREADS) {
-        int c = idx / TR, r = idx % TR;
-        X[c][r] = (c < nb && r < nr) ? (TD)F[(int64_t)(k0 + c) * m + r0 + r] : (TD)0;
+    } else if (row0 < m) {
+#pragma unroll
+        for (int ks = 0; ks < NB / 4; ks++) {
+            int k = ks * 4 + kq;
+#pragma unroll
+            for (int rb = 0; rb < 4; rb++) {
+                int row = row0 + rb * 16 + ln;
+                bv[ks][rb] = (row < m && k < nb) ? F[(int64_t)(k0 + k) * m + row] : (T)0;
+            }
+        }
     }
     __syncthreads();
-    // X := X * L^-T, column by column: x_c = (b_c - sum_{t<c} x_t L(c,t)) / L(c,c)
-    for (int c = 0; c < nb; c++) {
-        if (tid < TR) X[c][tid] /= D[c][c];
-        __syncthreads();
-        int w = nb - c - 1;
-        for (int idx = tid; idx < w * TR; idx += THREADS) {
-            int cc = c + 1 + idx / TR, r = idx % TR;
-            X[cc][r] -= X[c][r] * D[c][cc];
-        }
-        __syncthreads();
+    if (wave == 0 || row0 >= m) return;
+    typedef typename Mfma<T>::V V;
+    V acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+    // X(i, n) = sum_k B(i, k) L^-1(n, k): A operand from the panel, B operand L^-T
+#pragma unroll
+    for (int ks = 0; ks < NB / 4; ks++) {
+        int k = ks * 4 + kq;
+        T lv[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) lv[cb] = Li[cb * 16 + ln][k];
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++) acc[rb][cb] = Mfma<T>::mma(bv[ks][rb], lv[cb], acc[rb][cb]);
     }
-    for (int idx = tid; idx < nb * TR; idx += THREADS) {
-        int c = idx / TR, r = idx % TR;
-        if (r < nr) F[(int64_t)(k0 + c) * m + r0 + r] = (T)X[c][r];
+#pragma unroll
+    for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) {
+            int n = cb * 16 + ln;
+            if (n >= nb) continue;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int row = row0 + rb * 16 + Mfma<T>::row(kq, e);
+                if (row < m) F[(int64_t)(k0 + n) * m + row] = acc[rb][cb][e];
+            }
+        }
+}
+
+// Copies the factored diagonal blocks of every listed front from the scratch
+// area into the lower triangle of the front's pivot columns.
+template <typename T>
+__global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *__restrict__ front_off,
+                             const int32_t *__restrict__ mfront, const int32_t *__restrict__ pfront,
+                             const int64_t *__restrict__ dscr_off, const T *__restrict__ dscr,
+                             T *__restrict__ fronts)
+{
+    int f = flist[blockIdx.x];
+    int m = mfront[f], p = pfront[f];
+    T *F = fronts + front_off[f];
+    const T *D = dscr + dscr_off[f];
+    int nblk = (p + NB - 1) / NB;
+    for (int64_t idx = threadIdx.x; idx < (int64_t)nblk * NB * NB; idx += blockDim.x) {
+        int b = (int)(idx / (NB * NB)), e = (int)(idx % (NB * NB));
+        int c = e / NB, r = e % NB;
+        int k0 = b * NB;
+        int nb = min(NB, p - k0);
+        if (c < nb && r < nb && r >= c) F[(int64_t)(k0 + c) * m + k0 + r] = D[idx];
     }
 }
 
 // ---------------------------------------------------------------- trailing update
-// task = (front, ti, tj): C = F[i0:i0+TS, j0:j0+TS] -= A * B^T with
-// A = F[i0:, k0:k0+nb], B = F[j0:, k0:k0+nb], i0 = k0+nb+ti*TS, j0 = k0+nb+tj*TS.
-// Four waves, each a 32 x 32 quarter of the tile as 2 x 2 MFMA 16x16 blocks.
+// task = (front, i0, j0, jend): C = F[i0:i0+UT, j0:min(j0+UT, jend)] -= A B^T
+// on the lower part (row >= column), with A = F[i0:, ka:ka+K], B = F[j0:, ka:ka+K]
+// and K = min(kw, p - ka) for the front's p.  The workgroup's four waves
+// own 64 x 64 quarters (4 x 4 MFMA 16x16 blocks each); K advances in chunks
+// of KC staged through double-buffered LDS.
+constexpr int UT = 128;
+
+template <typename T> struct UpdCfg;
+template <> struct UpdCfg<float> { static constexpr int KC = 32; };
+template <> struct UpdCfg<double> { static constexpr int KC = 16; };
+
 template <typename T>
-__global__ __launch_bounds__(THREADS) void k_syrk(const int4 *__restrict__ tasks, int k0,
-                                                  const int64_t *__restrict__ front_off,
-                                                  const int32_t *__restrict__ mfront,
-                                                  const int32_t *__restrict__ pfront, T *__restrict__ fronts)
+__global__ __launch_bounds__(THREADS) void k_update(const int4 *__restrict__ tasks, int ka, int kw,
+                                                    const int64_t *__restrict__ front_off,
+                                                    const int32_t *__restrict__ mfront,
+                                                    const int32_t *__restrict__ pfront, T *__restrict__ fronts)
 {
-    __shared__ T As[NB][TS + 4];
-    __shared__ T Bs[NB][TS + 4];
+    constexpr int KC = UpdCfg<T>::KC;
+    constexpr int LD = UT + 4;
+    __shared__ T As[2][KC][LD];
+    __shared__ T Bs[2][KC][LD];
+    constexpr int PER = KC * UT / THREADS;     // elements of each operand per thread per chunk
     int4 t = tasks[blockIdx.x];
-    int f = t.x;
+    int f = t.x, i0 = t.y, j0 = t.z, jend = t.w;
     int m = mfront[f], p = pfront[f];
-    int nb = min(NB, p - k0);
-    int i0 = k0 + nb + t.y * TS, j0 = k0 + nb + t.z * TS;
+    int K = min(kw, p - ka);
     T *F = fronts + front_off[f];
     int tid = threadIdx.x;
-    for (int idx = tid; idx < NB * TS; idx += THREADS) {
-        int k = idx / TS, r = idx % TS;
-        bool ok = k < nb;
-        As[k][r] = (ok && i0 + r < m) ? F[(int64_t)(k0 + k) * m + i0 + r] : (T)0;
-        Bs[k][r] = (ok && j0 + r < m) ? F[(int64_t)(k0 + k) * m + j0 + r] : (T)0;
-    }
-    __syncthreads();
     int wave = tid / 64, lane = tid % 64;
-    int wr = (wave / 2) * 32, wc = (wave % 2) * 32;
-    typedef typename Mfma<T>::V V;
-    V acc[2][2];
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++)
-            for (int e = 0; e < 4; e++) acc[a][b][e] = 0;
+    int wr = (wave / 2) * 64, wc = (wave % 2) * 64;
     int kq = lane / 16, ln = lane % 16;
-    int kmax = (nb + 3) & ~3;
-    for (int kk = 0; kk < kmax; kk += 4) {
-        T a0 = As[kk + kq][wr + ln], a1 = As[kk + kq][wr + 16 + ln];
-        T b0 = Bs[kk + kq][wc + ln], b1 = Bs[kk + kq][wc + 16 + ln];
-        acc[0][0] = Mfma<T>::mma(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::mma(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::mma(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::mma(a1, b1, acc[1][1]);
+    // a wave whose quarter lies entirely above the diagonal (or right of jend) has nothing to do
+    bool active = (i0 + wr + 63 >= j0 + wc) && (j0 + wc < jend) && (i0 + wr < m);
+    T ra[PER], rb[PER];
+    auto gload = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            int idx = tid + q * THREADS;
+            int k = idx / UT, r = idx % UT;
+            bool kok = kc + k < K;
+            int64_t col = (int64_t)(ka + kc + k) * m;
+            ra[q] = (kok && i0 + r < m) ? F[col + i0 + r] : (T)0;
+            rb[q] = (kok && j0 + r < m) ? F[col + j0 + r] : (T)0;
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            int idx = tid + q * THREADS;
+            int k = idx / UT, r = idx % UT;
+            As[buf][k][r] = ra[q];
+            Bs[buf][k][r] = rb[q];
+        }
+    };
+    typedef typename Mfma<T>::V V;
+    V acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+    int nchunk = (K + KC - 1) / KC;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; c++) {
+        int buf = c & 1;
+        if (c + 1 < nchunk) gload((c + 1) * KC);
+        if (active) {
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 4) {
+                T av[4], bv[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    av[q] = As[buf][kk + kq][wr + q * 16 + ln];
+                    bv[q] = Bs[buf][kk + kq][wc + q * 16 + ln];
+                }
+#pragma unroll
+                for (int x = 0; x < 4; x++)
+#pragma unroll
+                    for (int y = 0; y < 4; y++) acc[x][y] = Mfma<T>::mma(av[x], bv[y], acc[x][y]);
+            }
+        }
+        if (c + 1 < nchunk) sstore(buf ^ 1);
+        __syncthreads();
     }
-    bool diag = t.y == t.z;
-    for (int a = 0; a < 2; a++)
-        for (int b = 0; b < 2; b++) {
-            int col = wc + b * 16 + ln;
-            if (j0 + col >= m) continue;
+    if (!active) return;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) {
+            int col = j0 + wc + y * 16 + ln;
+            if (col >= jend) continue;
+            T *Cc = F + (int64_t)col * m;
+#pragma unroll
             for (int e = 0; e < 4; e++) {
-                int row = wr + a * 16 + Mfma<T>::row(kq, e);
-                if (i0 + row >= m || (diag && row < col)) continue;
-                F[(int64_t)(j0 + col) * m + i0 + row] -= acc[a][b][e];
+                int row = i0 + wr + x * 16 + Mfma<T>::row(kq, e);
+                if (row < m && row >= col) Cc[row] -= acc[x][y][e];
             }
         }
 }
@@ -290,115 +509,6 @@ __global__ void k_rows_out(const T *__restrict__ Y, int n, int k, double *__rest
     }
 }
 
-// Forward substitution of one front (multifrontal): W = [Y(pivots); 0] plus
-// the children's update vectors, then W[0:p] := L11^-1 W[0:p] and
-// W[p:m] -= L21 W[0:p]; the pivots' part goes back to Y, W[p:m] stays for
-// the parent.
-template <typename T>
-__global__ __launch_bounds__(THREADS) void k_fwd_front(const int32_t *__restrict__ flist,
-                                                       const int64_t *__restrict__ front_off,
-                                                       const int32_t *__restrict__ mfront,
-                                                       const int32_t *__restrict__ pfront,
-                                                       const int32_t *__restrict__ first,
-                                                       const int64_t *__restrict__ woff,
-                                                       const int32_t *__restrict__ child_ptr,
-                                                       const int32_t *__restrict__ child_list,
-                                                       const int64_t *__restrict__ rptr,
-                                                       const int32_t *__restrict__ rel,
-                                                       const T *__restrict__ fronts, T *__restrict__ W,
-                                                       T *__restrict__ Y, int k)
-{
-    int f = flist[blockIdx.x];
-    int m = mfront[f], p = pfront[f], f0 = first[f];
-    const T *L = fronts + front_off[f];
-    T *w = W + woff[f] * k;
-    int tid = threadIdx.x;
-    int64_t mk = (int64_t)m * k, pk = (int64_t)p * k;
-    for (int64_t idx = tid; idx < mk; idx += THREADS) w[idx] = idx < pk ? Y[(int64_t)f0 * k + idx] : (T)0;
-    __syncthreads();
-    for (int q = child_ptr[f]; q < child_ptr[f + 1]; q++) {
-        int c = child_list[q];
-        int mc = mfront[c], pc = pfront[c];
-        const T *wc = W + woff[c] * k + (int64_t)pc * k;
-        const int32_t *rl = rel + rptr[c] + pc;
-        int64_t nu = (int64_t)(mc - pc) * k;
-        for (int64_t idx = tid; idx < nu; idx += THREADS) {
-            int r = (int)(idx / k), cc = (int)(idx % k);
-            w[(int64_t)rl[r] * k + cc] += wc[idx];
-        }
-        __syncthreads();
-    }
-    for (int j = 0; j < p; j++) {
-        const T *col = L + (int64_t)j * m;
-        T ljj = col[j];
-        // every thread reads w[j] before anyone overwrites it: scale in registers
-        int64_t n_upd = (int64_t)(m - j - 1) * k;
-        for (int64_t idx = tid; idx < n_upd; idx += THREADS) {
-            int r = j + 1 + (int)(idx / k), cc = (int)(idx % k);
-            w[(int64_t)r * k + cc] -= col[r] * (w[(int64_t)j * k + cc] / ljj);
-        }
-        __syncthreads();
-        for (int cc = tid; cc < k; cc += THREADS) w[(int64_t)j * k + cc] /= ljj;
-        __syncthreads();
-    }
-    for (int64_t idx = tid; idx < pk; idx += THREADS) Y[(int64_t)f0 * k + idx] = w[idx];
-}
-
-// Backward substitution of one front: x_j = (y_j - sum_{i>j} L(i,j) x_i) / L(j,j)
-// for the pivots j from last to first, with x of the update rows already
-// final (they belong to ancestor fronts).  Reads and writes Y in place.
-template <typename T>
-__global__ __launch_bounds__(THREADS) void k_bwd_front(const int32_t *__restrict__ flist,
-                                                       const int64_t *__restrict__ front_off,
-                                                       const int32_t *__restrict__ mfront,
-                                                       const int32_t *__restrict__ pfront,
-                                                       const int32_t *__restrict__ first,
-                                                       const int64_t *__restrict__ woff,
-                                                       const int64_t *__restrict__ rptr,
-                                                       const int32_t *__restrict__ rows,
-                                                       const T *__restrict__ fronts, T *__restrict__ W,
-                                                       T *__restrict__ Y, int k)
-{
-    __shared__ double red[THREADS];
-    int f = flist[blockIdx.x];
-    int m = mfront[f], p = pfront[f], f0 = first[f];
-    const T *L = fronts + front_off[f];
-    T *x = W + woff[f] * k;                 // local copy of x over the front's rows
-    const int32_t *rw = rows + rptr[f];
-    int tid = threadIdx.x;
-    int64_t mk = (int64_t)m * k;
-    for (int64_t idx = tid; idx < mk; idx += THREADS) {
-        int r = (int)(idx / k), cc = (int)(idx % k);
-        x[idx] = Y[(int64_t)rw[r] * k + cc];
-    }
-    __syncthreads();
-    // lane groups: g = tid / k handles rows g, g + G, ...; cc = tid % k
-    int kk = k < THREADS ? k : THREADS;
-    int G = THREADS / kk;
-    for (int j = p - 1; j >= 0; j--) {
-        const T *col = L + (int64_t)j * m;
-        for (int c0 = 0; c0 < k; c0 += kk) {
-            int cc = c0 + tid % kk;
-            int g = tid / kk;
-            double s = 0;
-            if (g < G && cc < k)
-                for (int r = j + 1 + g; r < m; r += G) s += (double)col[r] * (double)x[(int64_t)r * k + cc];
-            red[tid] = s;
-            __syncthreads();
-            if (tid < kk && c0 + tid < k) {
-                double tot = 0;
-                for (int gg = 0; gg < G; gg++) tot += red[gg * kk + tid];
-                int c = c0 + tid;
-                T v = (T)(((double)x[(int64_t)j * k + c] - tot) / (double)col[j]);
-                x[(int64_t)j * k + c] = v;
-            }
-            __syncthreads();
-        }
-    }
-    int64_t pk = (int64_t)p * k;
-    for (int64_t idx = tid; idx < pk; idx += THREADS) Y[(int64_t)f0 * k + idx] = x[idx];
-}
-
 // ---------------------------------------------------------------- A * X (FP64)
 // Full symmetric CSR in the original order; values expanded from the stored
 // lower entries by k_expand_values.
@@ -409,80 +519,144 @@ __global__ void k_expand_values(const double *__restrict__ values, const int64_t
         out[i] = values[src[i]];
 }
 
-// R = B - A X  (or Y = A X when B is null), column-major n x k with ld.
-// One wave per row; lanes split the row's entries (k columns one after another).
-__global__ void k_spmv_colmajor(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                const double *__restrict__ v, int n, int k, const double *__restrict__ X,
-                                const double *__restrict__ B, double *__restrict__ R, int64_t ld)
+// R = B - A X (or Y = A X when B is null).  Element (row i, column c) of X,
+// B and R sits at i * sx + c * sc (row-major: sx = k, sc = 1; column-major:
+// sx = 1, sc = ld).  Narrow form: one wave per row, lanes split the row's
+// entries, one pass per column.  Wide form: one wave per row, lanes are the
+// columns (up to 64 per pass), so every matrix entry is read once per pass.
+__global__ void k_spmv_narrow(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                              const double *__restrict__ v, int n, int k, const double *__restrict__ X,
+                              const double *__restrict__ B, double *__restrict__ R, int64_t sx, int64_t sc)
 {
-    int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64);
+    int row = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64);
     int lane = threadIdx.x % 64;
-    if (wave >= n) return;
-    int64_t a = rp[wave], b = rp[wave + 1];
+    if (row >= n) return;
+    int64_t a = rp[row], b = rp[row + 1];
     for (int c = 0; c < k; c++) {
-        const double *x = X + (int64_t)c * ld;
+        const double *x = X + (int64_t)c * sc;
         double s = 0;
-        for (int64_t q = a + lane; q < b; q += 64) s += v[q] * x[ci[q]];
+        for (int64_t q = a + lane; q < b; q += 64) s += v[q] * x[(int64_t)ci[q] * sx];
         for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
         if (lane == 0) {
-            int64_t o = (int64_t)c * ld + wave;
+            int64_t o = (int64_t)row * sx + (int64_t)c * sc;
             R[o] = B ? B[o] - s : s;
         }
     }
 }
 
-// Row-major variant for many right-hand sides: one wave per row, lanes over
-// the k columns (k <= 64 per pass), X and R row-major (ld = k).
-__global__ void k_spmm_rowmajor(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                const double *__restrict__ v, int n, int k, const double *__restrict__ X,
-                                const double *__restrict__ B, double *__restrict__ R)
+__global__ void k_spmv_wide(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                            const double *__restrict__ v, int n, int k, const double *__restrict__ X,
+                            const double *__restrict__ B, double *__restrict__ R, int64_t sx, int64_t sc)
 {
-    int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64);
+    int row = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64);
     int lane = threadIdx.x % 64;
-    if (wave >= n) return;
-    int64_t a = rp[wave], b = rp[wave + 1];
+    if (row >= n) return;
+    int64_t a = rp[row], b = rp[row + 1];
     for (int c0 = 0; c0 < k; c0 += 64) {
         int c = c0 + lane;
         if (c >= k) break;
         double s = 0;
-        for (int64_t q = a; q < b; q++) s += v[q] * X[(int64_t)ci[q] * k + c];
-        int64_t o = (int64_t)wave * k + c;
+        for (int64_t q = a; q < b; q++) s += v[q] * X[(int64_t)ci[q] * sx + (int64_t)c * sc];
+        int64_t o = (int64_t)row * sx + (int64_t)c * sc;
         R[o] = B ? B[o] - s : s;
     }
 }
 
-// per-column sum of squares of a column-major block (k columns, ld) -> out[c]
-__global__ void k_colnorm2(const double *__restrict__ A, int n, int k, int64_t ld, double *__restrict__ out)
+// Column reductions of a row-major n x k block in two passes with a fixed
+// order (deterministic): part[b * k + c] over the rows of block b, then
+// out[c] over the blocks.  op 0: sum of squares, op 1: max |a|.
+__global__ void k_colred_part(const double *__restrict__ A, int n, int k, int op, double *__restrict__ part)
 {
     __shared__ double red[THREADS];
-    int c = blockIdx.x;
-    const double *a = A + (int64_t)c * ld;
-    double s = 0;
-    for (int i = threadIdx.x; i < n; i += THREADS) s += a[i] * a[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    int nb = gridDim.x;
+    int64_t r0 = (int64_t)n * blockIdx.x / nb, r1 = (int64_t)n * (blockIdx.x + 1) / nb;
+    int kc = k < THREADS ? k : THREADS;
+    int groups = THREADS / kc;
+    for (int c0 = 0; c0 < k; c0 += kc) {
+        int c = c0 + threadIdx.x % kc, g = threadIdx.x / kc;
+        double s = 0;
+        if (g < groups && c < k)
+            for (int64_t r = r0 + g; r < r1; r += groups) {
+                double x = A[r * k + c];
+                s = op == 0 ? s + x * x : fmax(s, fabs(x));
+            }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        if ((int)threadIdx.x < kc && c < k) {
+            double t = 0;
+            for (int gg = 0; gg < groups; gg++) {
+                double x = red[gg * kc + threadIdx.x];
+                t = op == 0 ? t + x : fmax(t, x);
+            }
+            part[(int64_t)blockIdx.x * k + c] = t;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[c] = red[0];
 }
 
-// per-column max |a| of a column-major block
-__global__ void k_colamax(const double *__restrict__ A, int n, int k, int64_t ld, double *__restrict__ out)
+__global__ void k_colred_final(const double *__restrict__ part, int nb, int k, int op, double *__restrict__ out)
 {
-    __shared__ double red[THREADS];
-    int c = blockIdx.x;
-    const double *a = A + (int64_t)c * ld;
-    double s = 0;
-    for (int i = threadIdx.x; i < n; i += THREADS) s = fmax(s, fabs(a[i]));
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = THREADS / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        double t = 0;
+        for (int b = 0; b < nb; b++) {
+            double x = part[(int64_t)b * k + c];
+            t = op == 0 ? t + x : fmax(t, x);
+        }
+        out[c] = t;
     }
-    if (threadIdx.x == 0) out[c] = red[0];
+}
+
+// column-major (ld) <-> row-major (n x k)
+__global__ void k_cm2rm(const double *__restrict__ A, int64_t ld, int n, int k, double *__restrict__ B)
+{
+    int64_t total = (int64_t)n * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx / k), c = (int)(idx % k);
+        B[idx] = A[(int64_t)c * ld + i];
+    }
+}
+
+__global__ void k_rm2cm(const double *__restrict__ B, int n, int k, double *__restrict__ A, int64_t ld)
+{
+    int64_t total = (int64_t)n * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx / k), c = (int)(idx % k);
+        A[(int64_t)c * ld + i] = B[idx];
+    }
+}
+
+// Y(pivot i, c) = (T)(Xr[perm[i] * k + c] * scale[c])  (row-major in and out)
+template <typename T>
+__global__ void k_perm_in_rm(const double *__restrict__ Xr, const int32_t *__restrict__ perm, int n, int k,
+                             const double *__restrict__ scale, T *__restrict__ Y)
+{
+    int64_t total = (int64_t)n * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx / k), c = (int)(idx % k);
+        double v = Xr[(int64_t)perm[i] * k + c];
+        if (scale) v *= scale[c];
+        Y[idx] = (T)v;
+    }
+}
+
+// Xr[perm[i] * k + c] (+)= Y(i, c) / scale[c]
+template <typename T>
+__global__ void k_perm_out_rm(const T *__restrict__ Y, const int32_t *__restrict__ perm, int n, int k,
+                              const double *__restrict__ scale, int accumulate, double *__restrict__ Xr)
+{
+    int64_t total = (int64_t)n * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx / k), c = (int)(idx % k);
+        double v = (double)Y[idx];
+        if (scale) v /= scale[c];
+        double *d = Xr + (int64_t)perm[i] * k + c;
+        if (accumulate) *d += v;
+        else *d = v;
+    }
 }
 
 // scale[c] = amax[c] > 0 ? 1 / amax[c] : 1

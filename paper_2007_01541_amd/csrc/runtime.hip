@@ -12,6 +12,7 @@
 
 #include "internal.h"
 #include "kernels.hip"
+#include "solve.hip"
 
 namespace wcs {
 const Symbolic &symbolic_of(wcs_symbolic h);
@@ -33,15 +34,31 @@ constexpr int32_t kFp64DiagMinCols = 1024;   // FP32 fronts with >= this many pi
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
-// Static schedule derived from the symbolic structure only.
-struct Step {
-    int32_t k0;
-    int64_t pan_lo_off, pan_lo_cnt;    // panel tasks of fronts with p < kFp64DiagMinCols
-    int64_t pan_hi_off, pan_hi_cnt;    // ... with p >= kFp64DiagMinCols
-    int64_t syrk_off, syrk_cnt;
+constexpr int32_t NBO = 256;   // outer block: trailing updates use K = NBO columns at once
+constexpr int32_t kSolveStepMinCols = 512;   // fronts with at least this many pivots solve block by block over many workgroups
+constexpr int kPartBlocks = 512;             // blocks of the two-pass column reductions
+
+// Static schedule derived from the symbolic structure only.  Inside every
+// front: for each outer block of NBO pivot columns, for each NB-wide panel in
+// it, factor the panel (diagonal block + rows below) and update the rest of
+// the outer block's columns; then update the trailing matrix with the whole
+// outer block (K = NBO).
+enum OpKind { OP_PANEL = 0, OP_PANEL_FP64DIAG = 1, OP_UPDATE = 2 };
+struct Op {
+    int32_t kind;
+    int32_t ka, kw;      // panel: ka = k0; update: columns [ka, ka + min(kw, p - ka)) form K
+    int64_t off, cnt;
+};
+struct SolveLevel {
+    int64_t fused_off = 0, fused_cnt = 0;          // fronts solved by one workgroup each (in slist)
+    int64_t step_off = 0, step_cnt = 0;            // fronts solved block by block (in slist)
+    std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> fwd;   // (kb, tasks)
+    std::pair<int64_t, int64_t> below{0, 0};                            // backward update-row tasks
+    std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> bwd;   // (block b, tasks), b descending
 };
 struct Level {
-    std::vector<Step> steps;
+    SolveLevel sv;
+    std::vector<Op> ops;
     std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds (offset, count)
     int64_t fl_off = 0, fl_cnt = 0;                // fronts of this level in flist
 };
@@ -49,14 +66,19 @@ struct Level {
 struct Plan {
     std::vector<Level> levels;
     std::vector<int2> pan_tasks;
-    std::vector<int4> syrk_tasks;
+    std::vector<int4> upd_tasks;
     std::vector<int2> ea_tasks;
     std::vector<int32_t> flist;
     std::vector<int32_t> mfront, pfront, first;
     std::vector<int64_t> woff;                    // per front: row offset of its solve buffer
     int64_t wrows = 0;
+    std::vector<int64_t> dscr_off;                // per front: element offset of its diagonal-block scratch
+    int64_t dscr_elems = 0;
+    std::vector<int32_t> all_fronts;
     std::vector<int32_t> child_ptr, child_list;
     std::vector<int32_t> colof;                   // column of each stored entry
+    std::vector<int32_t> slist;                   // fronts per level for the solves (fused first, then stepped)
+    std::vector<int2> sfwd_tasks, sbelow_tasks, sbwd_tasks;
 
     void build(const Symbolic &S)
     {
@@ -65,13 +87,19 @@ struct Plan {
         pfront.resize(ns);
         first.resize(ns);
         woff.resize(ns);
+        dscr_off.resize(ns);
+        all_fronts.resize(ns);
         wrows = 0;
+        dscr_elems = 0;
         for (int32_t s = 0; s < ns; s++) {
             mfront[s] = S.m_of(s);
             pfront[s] = S.p_of(s);
             first[s] = S.sptr[s];
             woff[s] = wrows;
             wrows += mfront[s];
+            dscr_off[s] = dscr_elems;
+            dscr_elems += (int64_t)((pfront[s] + NB - 1) / NB) * NB * NB;
+            all_fronts[s] = s;
         }
         child_ptr.assign((size_t)ns + 1, 0);
         for (int32_t s = 0; s < ns; s++)
@@ -89,7 +117,7 @@ struct Plan {
         levels.assign(H, Level());
         flist.clear();
         pan_tasks.clear();
-        syrk_tasks.clear();
+        upd_tasks.clear();
         ea_tasks.clear();
         for (int32_t h = 0; h < H; h++) {
             Level &L = levels[h];
@@ -113,35 +141,89 @@ struct Plan {
             }
             int32_t maxp = 0;
             for (int32_t s : fr) maxp = std::max(maxp, pfront[s]);
-            for (int32_t k0 = 0; k0 < maxp; k0 += NB) {
-                Step st;
-                st.k0 = k0;
-                for (int pass = 0; pass < 2; pass++) {
-                    int64_t off = (int64_t)pan_tasks.size();
-                    for (int32_t s : fr) {
-                        int32_t p = pfront[s], m = mfront[s];
-                        if (p <= k0) continue;
-                        if ((p >= kFp64DiagMinCols) != (pass == 1)) continue;
-                        int32_t nb = std::min(NB, p - k0);
-                        int32_t below = m - k0 - nb;
-                        int32_t nt = (below + TR - 1) / TR;
-                        for (int32_t t = 0; t <= nt; t++) pan_tasks.push_back(make_int2(s, t));
+            auto tiles = [&](int32_t s, int32_t clo, int32_t jend) {
+                int32_t m = mfront[s];
+                for (int32_t j0 = clo; j0 < jend; j0 += UT)
+                    for (int32_t i0 = j0; i0 < m; i0 += UT) upd_tasks.push_back(make_int4(s, i0, j0, jend));
+            };
+            for (int32_t K0 = 0; K0 < maxp; K0 += NBO) {
+                for (int32_t k0 = K0; k0 < std::min(K0 + NBO, maxp); k0 += NB) {
+                    for (int pass = 0; pass < 2; pass++) {
+                        Op op{pass ? OP_PANEL_FP64DIAG : OP_PANEL, k0, NB, (int64_t)pan_tasks.size(), 0};
+                        for (int32_t s : fr) {
+                            int32_t p = pfront[s], m = mfront[s];
+                            if (p <= k0 || (p >= kFp64DiagMinCols) != (pass == 1)) continue;
+                            int32_t nb = std::min(NB, p - k0);
+                            int32_t nt = std::max(1, (m - k0 - nb + TRW - 1) / TRW);
+                            for (int32_t t = 0; t < nt; t++) pan_tasks.push_back(make_int2(s, t));
+                        }
+                        op.cnt = (int64_t)pan_tasks.size() - op.off;
+                        if (op.cnt) L.ops.push_back(op);
                     }
-                    if (pass == 0) { st.pan_lo_off = off; st.pan_lo_cnt = (int64_t)pan_tasks.size() - off; }
-                    else { st.pan_hi_off = off; st.pan_hi_cnt = (int64_t)pan_tasks.size() - off; }
+                    Op up{OP_UPDATE, k0, NB, (int64_t)upd_tasks.size(), 0};
+                    for (int32_t s : fr) {
+                        int32_t p = pfront[s];
+                        if (p <= k0) continue;
+                        int32_t nb = std::min(NB, p - k0);
+                        int32_t kend = K0 + std::min(NBO, p - K0);
+                        if (k0 + nb < kend) tiles(s, k0 + nb, kend);
+                    }
+                    up.cnt = (int64_t)upd_tasks.size() - up.off;
+                    if (up.cnt) L.ops.push_back(up);
                 }
-                st.syrk_off = (int64_t)syrk_tasks.size();
+                Op up{OP_UPDATE, K0, NBO, (int64_t)upd_tasks.size(), 0};
                 for (int32_t s : fr) {
                     int32_t p = pfront[s], m = mfront[s];
-                    if (p <= k0) continue;
-                    int32_t nb = std::min(NB, p - k0);
-                    int32_t below = m - k0 - nb;
-                    int32_t nt = (below + TS - 1) / TS;
-                    for (int32_t ti = 0; ti < nt; ti++)
-                        for (int32_t tj = 0; tj <= ti; tj++) syrk_tasks.push_back(make_int4(s, ti, tj, 0));
+                    if (p <= K0) continue;
+                    int32_t kend = K0 + std::min(NBO, p - K0);
+                    if (kend < m) tiles(s, kend, m);
                 }
-                st.syrk_cnt = (int64_t)syrk_tasks.size() - st.syrk_off;
-                L.steps.push_back(st);
+                up.cnt = (int64_t)upd_tasks.size() - up.off;
+                if (up.cnt) L.ops.push_back(up);
+            }
+        }
+        // solve schedule
+        slist.clear();
+        sfwd_tasks.clear();
+        sbelow_tasks.clear();
+        sbwd_tasks.clear();
+        for (int32_t h = 0; h < H; h++) {
+            SolveLevel &V = levels[h].sv;
+            std::vector<int32_t> big;
+            V.fused_off = (int64_t)slist.size();
+            for (int32_t s : bylev[h]) {
+                if (pfront[s] >= kSolveStepMinCols) big.push_back(s);
+                else slist.push_back(s);
+            }
+            V.fused_cnt = (int64_t)slist.size() - V.fused_off;
+            V.step_off = (int64_t)slist.size();
+            slist.insert(slist.end(), big.begin(), big.end());
+            V.step_cnt = (int64_t)big.size();
+            int32_t maxp = 0;
+            for (int32_t s : big) maxp = std::max(maxp, pfront[s]);
+            for (int32_t kb = 0; kb < maxp; kb += SB) {
+                int64_t off = (int64_t)sfwd_tasks.size();
+                for (int32_t s : big) {
+                    if (pfront[s] <= kb) continue;
+                    int32_t nbk = std::min(SB, pfront[s] - kb);
+                    int32_t rows = mfront[s] - kb - nbk;
+                    int32_t nt = std::max(1, (rows + SROWS - 1) / SROWS);
+                    for (int32_t t = 0; t < nt; t++) sfwd_tasks.push_back(make_int2(s, t));
+                }
+                V.fwd.push_back({kb, {off, (int64_t)sfwd_tasks.size() - off}});
+            }
+            V.below.first = (int64_t)sbelow_tasks.size();
+            for (int32_t s : big)
+                for (int32_t a = 0; a < (pfront[s] + SB - 1) / SB; a++) sbelow_tasks.push_back(make_int2(s, a));
+            V.below.second = (int64_t)sbelow_tasks.size() - V.below.first;
+            int32_t maxb = (maxp + SB - 1) / SB;
+            for (int32_t b = maxb - 1; b >= 0; b--) {
+                int64_t off = (int64_t)sbwd_tasks.size();
+                for (int32_t s : big) {
+                    if ((pfront[s] + SB - 1) / SB <= b) continue;
+                    for (int32_t a = 0; a <= b; a++) sbwd_tasks.push_back(make_int2(s, a));
+                }
+                V.bwd.push_back({b, {off, (int64_t)sbwd_tasks.size() - off}});
             }
         }
         colof.resize((size_t)S.nnz);
@@ -155,7 +237,7 @@ struct Layout {
     size_t fronts, W, Y, Xr, Rr, Br, vec, bad;
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof;
-    size_t pan, syrk, ea, flist;
+    size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, part;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -191,9 +273,18 @@ struct Layout {
         rowind = seg((size_t)S.nnz * 4);
         colof = seg((size_t)S.nnz * 4);
         pan = seg(std::max<size_t>(1, P.pan_tasks.size()) * sizeof(int2));
-        syrk = seg(std::max<size_t>(1, P.syrk_tasks.size()) * sizeof(int4));
+        upd = seg(std::max<size_t>(1, P.upd_tasks.size()) * sizeof(int4));
         ea = seg(std::max<size_t>(1, P.ea_tasks.size()) * sizeof(int2));
         flist = seg(std::max<size_t>(1, P.flist.size()) * 4);
+        dscr = seg((size_t)P.dscr_elems * esz);
+        dinv = seg((size_t)P.dscr_elems * esz);
+        slist = seg(std::max<size_t>(1, P.slist.size()) * 4);
+        sfwd = seg(std::max<size_t>(1, P.sfwd_tasks.size()) * sizeof(int2));
+        sbelow = seg(std::max<size_t>(1, P.sbelow_tasks.size()) * sizeof(int2));
+        sbwd = seg(std::max<size_t>(1, P.sbwd_tasks.size()) * sizeof(int2));
+        part = seg((size_t)kPartBlocks * k * 8 * 2);
+        dscr_off = seg(ns * 8);
+        all_fronts = seg(ns * 4);
         total = o;
     }
 };
@@ -226,18 +317,96 @@ struct wcs_factor_s {
 namespace wcs {
 namespace {
 
+// Optional per-kernel-class timing with HIP events on the launch stream,
+// plus the algorithmic work of every launch (for roofline accounting).
+enum KClass { KC_FILL = 0, KC_SCATTER, KC_EXTEND_ADD, KC_PANEL, KC_PANEL_FP64DIAG, KC_UPDATE, KC_COUNT };
+
+struct Prof {
+    hipStream_t st;
+    std::vector<hipEvent_t> ev[KC_COUNT];
+    double flops[KC_COUNT] = {0};
+    double bytes[KC_COUNT] = {0};
+    int begin(int c)
+    {
+        hipEvent_t a;
+        HIP_TRY(hipEventCreate(&a));
+        ev[c].push_back(a);
+        HIP_TRY(hipEventRecord(a, st));
+        return WCS_OK;
+    }
+    int end(int c)
+    {
+        hipEvent_t b;
+        HIP_TRY(hipEventCreate(&b));
+        ev[c].push_back(b);
+        HIP_TRY(hipEventRecord(b, st));
+        return WCS_OK;
+    }
+    int collect(wcs_kernel_stat *out)
+    {
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int c = 0; c < KC_COUNT; c++) {
+            double ms = 0;
+            for (size_t i = 0; i + 1 < ev[c].size(); i += 2) {
+                float t = 0;
+                HIP_TRY(hipEventElapsedTime(&t, ev[c][i], ev[c][i + 1]));
+                ms += t;
+            }
+            out[c].launches = (int32_t)(ev[c].size() / 2);
+            out[c].ms = ms;
+            out[c].flops = flops[c];
+            out[c].bytes = bytes[c];
+        }
+        return WCS_OK;
+    }
+    ~Prof()
+    {
+        for (int c = 0; c < KC_COUNT; c++)
+            for (hipEvent_t e : ev[c]) (void)hipEventDestroy(e);
+    }
+};
+
+#define PROF_BEGIN(c) do { if (prof) { int r_ = prof->begin(c); if (r_) return r_; } } while (0)
+#define PROF_END(c) do { if (prof) { int r_ = prof->end(c); if (r_) return r_; } } while (0)
+
+// algorithmic work (host accounting only)
+double panel_flops(const Plan &P, int32_t s, int32_t k0)
+{
+    double nb = std::min(NB, P.pfront[s] - k0);
+    double below = P.mfront[s] - k0 - nb;
+    return nb * nb * nb / 3.0 + below * nb * nb;
+}
+double update_flops(const Plan &P, const int4 &t, int32_t ka, int32_t kw)
+{
+    int32_t m = P.mfront[t.x], p = P.pfront[t.x];
+    double K = std::min(kw, p - ka);
+    double cnt = 0;
+    for (int32_t col = t.z; col < std::min(t.z + UT, t.w); col++)
+        cnt += std::max(0, std::min(t.y + UT, m) - std::max(t.y, col));
+    return 2.0 * K * cnt;
+}
+
 template <typename T>
-int launch_factor(wcs_factor f, const double *values, hipStream_t st)
+int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof)
 {
     const Layout &Lo = f->lay;
     const Plan &P = f->plan;
     const Symbolic &S = *f->S;
+    const size_t esz = sizeof(T);
     T *fronts = f->at<T>(Lo.fronts);
     int64_t nel = S.front_off.back();
-    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nel)), dim3(256), 0, st, fronts, nel, (T)0);
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, f->at<int32_t>(Lo.bad), (int64_t)1, INT32_MAX);
+    PROF_BEGIN(KC_FILL);
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nel)), dim3(256), 0, st, fronts, nel, (T)0);
+    PROF_END(KC_FILL);
+    PROF_BEGIN(KC_SCATTER);
     hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(S.nnz)), dim3(256), 0, st, values, f->at<int64_t>(Lo.amap),
                        S.nnz, fronts);
+    PROF_END(KC_SCATTER);
+    if (prof) {
+        prof->bytes[KC_FILL] += (double)nel * esz;
+        prof->bytes[KC_SCATTER] += (double)S.nnz * (8 + 8 + esz);
+    }
     const int64_t *fo = f->at<int64_t>(Lo.front_off);
     const int32_t *mf = f->at<int32_t>(Lo.mfront);
     const int32_t *pf = f->at<int32_t>(Lo.pfront);
@@ -246,63 +415,126 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st)
     const int64_t *rp = f->at<int64_t>(Lo.rptr);
     const int32_t *rl = f->at<int32_t>(Lo.rel);
     const int2 *pan = f->at<int2>(Lo.pan);
-    const int4 *syrk = f->at<int4>(Lo.syrk);
+    const int4 *upd = f->at<int4>(Lo.upd);
     const int2 *ea = f->at<int2>(Lo.ea);
     int32_t *bad = f->at<int32_t>(Lo.bad);
+    const int64_t *dso = f->at<int64_t>(Lo.dscr_off);
+    T *dscr = f->at<T>(Lo.dscr);
+    T *dinv = f->at<T>(Lo.dinv);
     for (const Level &L : P.levels) {
-        for (auto &r : L.ea)
+        for (auto &r : L.ea) {
+            PROF_BEGIN(KC_EXTEND_ADD);
             hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)r.second), dim3(256), 0, st, ea + r.first, fo, mf,
                                pf, sp, rp, rl, fronts);
-        for (const Step &s : L.steps) {
-            if (s.pan_lo_cnt)
-                hipLaunchKernelGGL((k_panel<T, T>), dim3((unsigned)s.pan_lo_cnt), dim3(THREADS), 0, st,
-                                   pan + s.pan_lo_off, s.k0, fo, mf, pf, fi, fronts, bad);
-            if (s.pan_hi_cnt)
-                hipLaunchKernelGGL((k_panel<T, double>), dim3((unsigned)s.pan_hi_cnt), dim3(THREADS), 0, st,
-                                   pan + s.pan_hi_off, s.k0, fo, mf, pf, fi, fronts, bad);
-            if (s.syrk_cnt)
-                hipLaunchKernelGGL(k_syrk<T>, dim3((unsigned)s.syrk_cnt), dim3(THREADS), 0, st, syrk + s.syrk_off,
-                                   s.k0, fo, mf, pf, fronts);
+            PROF_END(KC_EXTEND_ADD);
+            if (prof)
+                for (int64_t t = r.first; t < r.first + r.second; t++) {
+                    int2 task = P.ea_tasks[t];
+                    double nu = P.mfront[task.x] - P.pfront[task.x];
+                    double c1 = std::min<double>(task.y + EA_COLS, nu);
+                    for (double col = task.y; col < c1; col++) prof->bytes[KC_EXTEND_ADD] += (nu - col) * (3 * esz + 4);
+                }
+        }
+        for (const Op &op : L.ops) {
+            if (op.kind == OP_UPDATE) {
+                PROF_BEGIN(KC_UPDATE);
+                hipLaunchKernelGGL(k_update<T>, dim3((unsigned)op.cnt), dim3(THREADS), 0, st, upd + op.off, op.ka,
+                                   op.kw, fo, mf, pf, fronts);
+                PROF_END(KC_UPDATE);
+                if (prof)
+                    for (int64_t q = op.off; q < op.off + op.cnt; q++)
+                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], op.ka, op.kw);
+            } else {
+                int c = op.kind == OP_PANEL ? KC_PANEL : KC_PANEL_FP64DIAG;
+                PROF_BEGIN(c);
+                if (op.kind == OP_PANEL)
+                    hipLaunchKernelGGL((k_panel<T, T>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
+                                       pan + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr, dinv, bad);
+                else
+                    hipLaunchKernelGGL((k_panel<T, double>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
+                                       pan + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr, dinv, bad);
+                PROF_END(c);
+                if (prof)
+                    for (int64_t q = op.off; q < op.off + op.cnt; q++)
+                        if (P.pan_tasks[q].y == 0) prof->flops[c] += panel_flops(P, P.pan_tasks[q].x, op.ka);
+            }
+        }
+    }
+    PROF_BEGIN(KC_FILL);
+    hipLaunchKernelGGL(k_diag_fixup<T>, dim3((unsigned)S.ns), dim3(256), 0, st, f->at<int32_t>(Lo.all_fronts), fo, mf,
+                       pf, dso, dscr, fronts);
+    PROF_END(KC_FILL);
+    if (prof) prof->bytes[KC_FILL] += (double)P.dscr_elems * esz * 2;
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+// Y (row-major, pivot order, n x k) := L^-1 Y and/or L^-T Y
+template <typename T, int KT>
+int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    const Plan &P = f->plan;
+    SolveArgs<T> a;
+    a.front_off = f->at<int64_t>(Lo.front_off);
+    a.mfront = f->at<int32_t>(Lo.mfront);
+    a.pfront = f->at<int32_t>(Lo.pfront);
+    a.first = f->at<int32_t>(Lo.first);
+    a.woff = f->at<int64_t>(Lo.woff);
+    a.child_ptr = f->at<int32_t>(Lo.child_ptr);
+    a.child_list = f->at<int32_t>(Lo.child_list);
+    a.rptr = f->at<int64_t>(Lo.rptr);
+    a.rel = f->at<int32_t>(Lo.rel);
+    a.rows = f->at<int32_t>(Lo.rows);
+    a.dscr_off = f->at<int64_t>(Lo.dscr_off);
+    a.fronts = f->at<T>(Lo.fronts);
+    a.dinv = f->at<T>(Lo.dinv);
+    a.W = f->at<T>(Lo.W);
+    a.Y = f->at<T>(Lo.Y);
+    a.k = k;
+    const int32_t *sl = f->at<int32_t>(Lo.slist);
+    const int2 *tf = f->at<int2>(Lo.sfwd);
+    const int2 *tb = f->at<int2>(Lo.sbelow);
+    const int2 *ts = f->at<int2>(Lo.sbwd);
+    if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_L) {
+        for (const Level &L : P.levels) {
+            const SolveLevel &V = L.sv;
+            if (V.fused_cnt)
+                hipLaunchKernelGGL((k_fwd_fused<T, KT>), dim3((unsigned)V.fused_cnt), dim3(THREADS), 0, st,
+                                   sl + V.fused_off, a);
+            if (V.step_cnt) {
+                hipLaunchKernelGGL(k_fwd_init<T>, dim3((unsigned)V.step_cnt), dim3(THREADS), 0, st, sl + V.step_off, a);
+                for (auto &s : V.fwd)
+                    hipLaunchKernelGGL((k_fwd_step<T, KT>), dim3((unsigned)s.second.second), dim3(THREADS), 0, st,
+                                       tf + s.second.first, s.first, a);
+            }
+        }
+    }
+    if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_LT) {
+        for (size_t h = P.levels.size(); h-- > 0;) {
+            const SolveLevel &V = P.levels[h].sv;
+            if (V.fused_cnt)
+                hipLaunchKernelGGL((k_bwd_fused<T, KT>), dim3((unsigned)V.fused_cnt), dim3(THREADS), 0, st,
+                                   sl + V.fused_off, a);
+            if (V.step_cnt) {
+                hipLaunchKernelGGL((k_bwd_below<T, KT>), dim3((unsigned)V.below.second), dim3(THREADS), 0, st,
+                                   tb + V.below.first, a);
+                for (auto &s : V.bwd)
+                    hipLaunchKernelGGL((k_bwd_step<T, KT>), dim3((unsigned)s.second.second), dim3(THREADS), 0, st,
+                                       ts + s.second.first, s.first, a);
+            }
         }
     }
     HIP_TRY(hipGetLastError());
     return WCS_OK;
 }
 
-// Y (row-major, pivot order, n x k) := L^-1 Y and/or L^-T Y
 template <typename T>
 int launch_solve_internal(wcs_factor f, int part, int k, hipStream_t st)
 {
-    const Layout &Lo = f->lay;
-    const Plan &P = f->plan;
-    T *fronts = f->at<T>(Lo.fronts);
-    T *W = f->at<T>(Lo.W);
-    T *Y = f->at<T>(Lo.Y);
-    const int64_t *fo = f->at<int64_t>(Lo.front_off);
-    const int32_t *mf = f->at<int32_t>(Lo.mfront);
-    const int32_t *pf = f->at<int32_t>(Lo.pfront);
-    const int32_t *fi = f->at<int32_t>(Lo.first);
-    const int64_t *wo = f->at<int64_t>(Lo.woff);
-    const int32_t *cp = f->at<int32_t>(Lo.child_ptr);
-    const int32_t *cl = f->at<int32_t>(Lo.child_list);
-    const int64_t *rp = f->at<int64_t>(Lo.rptr);
-    const int32_t *rl = f->at<int32_t>(Lo.rel);
-    const int32_t *rw = f->at<int32_t>(Lo.rows);
-    const int32_t *fl = f->at<int32_t>(Lo.flist);
-    if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_L) {
-        for (const Level &L : P.levels)
-            hipLaunchKernelGGL(k_fwd_front<T>, dim3((unsigned)L.fl_cnt), dim3(THREADS), 0, st, fl + L.fl_off, fo, mf,
-                               pf, fi, wo, cp, cl, rp, rl, fronts, W, Y, k);
-    }
-    if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_LT) {
-        for (size_t h = P.levels.size(); h-- > 0;) {
-            const Level &L = P.levels[h];
-            hipLaunchKernelGGL(k_bwd_front<T>, dim3((unsigned)L.fl_cnt), dim3(THREADS), 0, st, fl + L.fl_off, fo, mf,
-                               pf, fi, wo, rp, rw, fronts, W, Y, k);
-        }
-    }
-    HIP_TRY(hipGetLastError());
-    return WCS_OK;
+    if (k <= 4) return launch_sweeps<T, 4>(f, part, k, st);
+    if (k <= 16) return launch_sweeps<T, 16>(f, part, k, st);
+    return launch_sweeps<T, 64>(f, part, k, st);
 }
 
 template <typename T>
@@ -340,16 +572,31 @@ int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st)
     return WCS_OK;
 }
 
-// Y = A X or R = B - A X, column-major with leading dimension ld
-int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R, int64_t ld, hipStream_t st)
+// R = B - A X or Y = A X (B null); element (i, c) at i * sx + c * sc
+int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R, int64_t sx, int64_t sc,
+                hipStream_t st)
 {
     const Symbolic &S = *f->S;
     int n = S.n;
-    hipLaunchKernelGGL(k_spmv_colmajor, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st,
-                       f->at<int64_t>(f->lay.csr_ptr), f->at<int32_t>(f->lay.csr_col), f->at<double>(f->lay.csr_val),
-                       n, k, X, B, R, ld);
+    const int64_t *rp = f->at<int64_t>(f->lay.csr_ptr);
+    const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
+    const double *v = f->at<double>(f->lay.csr_val);
+    if (k >= 8)
+        hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R, sx,
+                           sc);
+    else
+        hipLaunchKernelGGL(k_spmv_narrow, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R,
+                           sx, sc);
     HIP_TRY(hipGetLastError());
     return WCS_OK;
+}
+
+// out[c] = column reduction (op 0: sum of squares, op 1: max |a|) of row-major A
+void launch_colred(wcs_factor f, const double *A, int n, int k, int op, double *out, hipStream_t st)
+{
+    double *part = f->at<double>(f->lay.part);
+    hipLaunchKernelGGL(k_colred_part, dim3(kPartBlocks), dim3(THREADS), 0, st, A, n, k, op, part);
+    hipLaunchKernelGGL(k_colred_final, dim3(1), dim3(256), 0, st, part, kPartBlocks, k, op, out);
 }
 
 template <typename T>
@@ -360,28 +607,31 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     int n = f->S->n;
     int rc = ensure_csr_values(f, values, st);
     if (rc) return rc;
-    double *R = f->at<double>(Lo.Rr);       // column-major n x k, ld = n
+    double *Br = f->at<double>(Lo.Br);      // row-major n x k copies
+    double *Xr = f->at<double>(Lo.Xr);
+    double *Rr = f->at<double>(Lo.Rr);
     double *vec = f->at<double>(Lo.vec);    // [0,k): |B|^2, [k,2k): |R|^2, [2k,3k): amax, [3k,4k): scale
     T *Y = f->at<T>(Lo.Y);
     const int32_t *perm = f->at<int32_t>(Lo.perm);
     int64_t nk = (int64_t)n * k;
-    hipLaunchKernelGGL(k_colnorm2, dim3(k), dim3(THREADS), 0, st, B, n, k, ld, vec);
+    hipLaunchKernelGGL(k_cm2rm, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, n, k, Br);
+    launch_colred(f, Br, n, k, 0, vec, st);
     // X0 = solve(B)
-    hipLaunchKernelGGL(k_perm_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Y,
-                       (const double *)nullptr);
+    hipLaunchKernelGGL(k_perm_in_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Br, perm, n, k, (const double *)nullptr,
+                       Y);
     rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_perm_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k, X, ld,
-                       (const double *)nullptr, 0);
+    hipLaunchKernelGGL(k_perm_out_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k,
+                       (const double *)nullptr, 0, Xr);
     std::vector<double> h((size_t)2 * k);
     rep->iterations = 0;
     rep->raw_residual = -1;
     rep->final_residual = -1;
+    int status = WCS_ENOTCONV;
     for (int it = 0;; it++) {
-        rc = launch_spmv(f, k, X, B, R, ld, st);
+        rc = launch_spmv(f, k, Xr, Br, Rr, k, 1, st);
         if (rc) return rc;
-        // R is stored with leading dimension ld as well
-        hipLaunchKernelGGL(k_colnorm2, dim3(k), dim3(THREADS), 0, st, R, n, k, ld, vec + k);
+        launch_colred(f, Rr, n, k, 0, vec + k, st);
         HIP_TRY(hipMemcpyAsync(h.data(), vec, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         double worst = 0;
@@ -392,21 +642,24 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
         }
         if (it == 0) rep->raw_residual = worst;
         rep->final_residual = worst;
-        if (worst <= tol) return WCS_OK;
+        if (worst <= tol) { status = WCS_OK; break; }
         if (it >= max_iter) break;
-        // D = solve(R * s) / s, X += D
-        hipLaunchKernelGGL(k_colamax, dim3(k), dim3(THREADS), 0, st, R, n, k, ld, vec + 2 * k);
+        // D = solve(R * s) / s, X += D with s = 1 / max|R| per column (keeps R in the FP32 range)
+        launch_colred(f, Rr, n, k, 1, vec + 2 * k, st);
         hipLaunchKernelGGL(k_inv_scale, dim3(1), dim3(64 * ((k + 63) / 64)), 0, st, vec + 2 * k, k, vec + 3 * k);
-        hipLaunchKernelGGL(k_perm_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, R, ld, perm, n, k, Y,
-                           (const double *)(vec + 3 * k));
+        hipLaunchKernelGGL(k_perm_in_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Rr, perm, n, k,
+                           (const double *)(vec + 3 * k), Y);
         rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_perm_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k, X, ld,
-                           (const double *)(vec + 3 * k), 1);
+        hipLaunchKernelGGL(k_perm_out_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k,
+                           (const double *)(vec + 3 * k), 1, Xr);
         rep->iterations = it + 1;
     }
-    set_error("iterative refinement stopped at relative residual " + std::to_string(rep->final_residual));
-    return WCS_ENOTCONV;
+    hipLaunchKernelGGL(k_rm2cm, dim3(grid_for(nk)), dim3(256), 0, st, Xr, n, k, X, ld);
+    HIP_TRY(hipGetLastError());
+    if (status != WCS_OK)
+        set_error("iterative refinement stopped at relative residual " + std::to_string(rep->final_residual));
+    return status;
 }
 
 template <typename V>
@@ -500,9 +753,15 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.rowind, S.rowind, st);
     rc = rc ? rc : upload(f, L.colof, P.colof, st);
     rc = rc ? rc : upload(f, L.pan, P.pan_tasks, st);
-    rc = rc ? rc : upload(f, L.syrk, P.syrk_tasks, st);
+    rc = rc ? rc : upload(f, L.upd, P.upd_tasks, st);
     rc = rc ? rc : upload(f, L.ea, P.ea_tasks, st);
     rc = rc ? rc : upload(f, L.flist, P.flist, st);
+    rc = rc ? rc : upload(f, L.dscr_off, P.dscr_off, st);
+    rc = rc ? rc : upload(f, L.all_fronts, P.all_fronts, st);
+    rc = rc ? rc : upload(f, L.slist, P.slist, st);
+    rc = rc ? rc : upload(f, L.sfwd, P.sfwd_tasks, st);
+    rc = rc ? rc : upload(f, L.sbelow, P.sbelow_tasks, st);
+    rc = rc ? rc : upload(f, L.sbwd, P.sbwd_tasks, st);
     if (rc == WCS_OK) {
         hipError_t e = hipStreamSynchronize(st);   // host vectors are pageable: finish the copies
         if (e != hipSuccess) {
@@ -519,12 +778,27 @@ int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream
 {
     if (!f || !values_dev) { set_error("invalid argument to wcs_factor_numeric"); return WCS_EINVAL; }
     hipStream_t st = (hipStream_t)stream;
-    int rc = f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st) : launch_factor<float>(f, values_dev, st);
+    int rc = f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st, nullptr)
+                                 : launch_factor<float>(f, values_dev, st, nullptr);
     if (rc) return rc;
     f->have_values = true;
     f->csr_values_from = nullptr;
     if (bad_col) return wcs_factor_check(f, stream, bad_col);
     return WCS_OK;
+}
+
+int wcs_factor_profile(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *stats)
+{
+    if (!f || !values_dev || !stats) { set_error("invalid argument to wcs_factor_profile"); return WCS_EINVAL; }
+    hipStream_t st = (hipStream_t)stream;
+    Prof prof;
+    prof.st = st;
+    int rc = f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st, &prof)
+                                 : launch_factor<float>(f, values_dev, st, &prof);
+    if (rc) return rc;
+    f->have_values = true;
+    f->csr_values_from = nullptr;
+    return prof.collect(stats);
 }
 
 int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col)
@@ -600,10 +874,6 @@ int wcs_solve_refined(wcs_factor f, const double *values_dev, int32_t nrhs, cons
         set_error("invalid argument to wcs_solve_refined");
         return WCS_EINVAL;
     }
-    if (ld != f->S->n) {
-        set_error("wcs_solve_refined requires ld == n");
-        return WCS_EINVAL;
-    }
     if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
     hipStream_t st = (hipStream_t)stream;
     return f->prec == WCS_FP64
@@ -621,7 +891,7 @@ int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double 
     hipStream_t st = (hipStream_t)stream;
     int rc = ensure_csr_values(f, values_dev, st);
     if (rc) return rc;
-    return launch_spmv(f, nrhs, X_dev, nullptr, Y_dev, ld, st);
+    return launch_spmv(f, nrhs, X_dev, nullptr, Y_dev, 1, ld, st);
 }
 
 int wcs_grad_pattern(wcs_factor f, const double *lam_dev, const double *x_dev, double *gA_dev, wcs_stream stream)

@@ -145,6 +145,15 @@ class Factor:
             check(lib().wcs_factor_numeric(self.handle, _dptr(values), _stream_ptr(stream), None),
                   "wcs_factor_numeric")
 
+    def profile(self, values, stream=None) -> dict:
+        """One factorization with HIP events around every launch; per kernel class
+        {launches, ms, flops, bytes} (algorithmic work)."""
+        stats = (capi.KernelStat * len(capi.KERNEL_CLASSES))()
+        self.values = values
+        check(lib().wcs_factor_profile(self.handle, _dptr(values), _stream_ptr(stream), stats), "wcs_factor_profile")
+        return {nm: {"launches": st.launches, "ms": st.ms, "flops": st.flops, "bytes": st.bytes}
+                for nm, st in zip(capi.KERNEL_CLASSES, stats)}
+
     def pivot_check(self, stream=None) -> int:
         bad = C.c_int32(-1)
         rc = lib().wcs_factor_check(self.handle, _stream_ptr(stream), C.byref(bad))
