@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -35,7 +36,12 @@ constexpr int32_t kFp64DiagMinCols = 1024;   // FP32 fronts with >= this many pi
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 constexpr int32_t NBO = 256;   // outer block: trailing updates use K = NBO columns at once
-constexpr int32_t kSolveStepMinCols = 512;   // fronts with at least this many pivots solve block by block over many workgroups
+// fronts with more rows solve block by block over many workgroups (tuning knob WCS_SOLVE_STEP_ROWS)
+int32_t solve_step_min_rows()
+{
+    const char *e = std::getenv("WCS_SOLVE_STEP_ROWS");
+    return e ? std::atoi(e) : 512;
+}
 constexpr int kPartBlocks = 512;             // blocks of the two-pass column reductions
 
 // Static schedule derived from the symbolic structure only.  Inside every
@@ -52,6 +58,7 @@ struct Op {
 struct SolveLevel {
     int64_t fused_off = 0, fused_cnt = 0;          // fronts solved by one workgroup each (in slist)
     int64_t step_off = 0, step_cnt = 0;            // fronts solved block by block (in slist)
+    std::pair<int64_t, int64_t> assemble{0, 0};                         // forward assembly tasks
     std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> fwd;   // (kb, tasks)
     std::pair<int64_t, int64_t> below{0, 0};                            // backward update-row tasks
     std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> bwd;   // (block b, tasks), b descending
@@ -78,7 +85,7 @@ struct Plan {
     std::vector<int32_t> child_ptr, child_list;
     std::vector<int32_t> colof;                   // column of each stored entry
     std::vector<int32_t> slist;                   // fronts per level for the solves (fused first, then stepped)
-    std::vector<int2> sfwd_tasks, sbelow_tasks, sbwd_tasks;
+    std::vector<int2> sfwd_tasks, sbelow_tasks, sbwd_tasks, sasm_tasks;
 
     void build(const Symbolic &S)
     {
@@ -187,12 +194,14 @@ struct Plan {
         sfwd_tasks.clear();
         sbelow_tasks.clear();
         sbwd_tasks.clear();
+        sasm_tasks.clear();
+        const int32_t step_rows = solve_step_min_rows();
         for (int32_t h = 0; h < H; h++) {
             SolveLevel &V = levels[h].sv;
             std::vector<int32_t> big;
             V.fused_off = (int64_t)slist.size();
             for (int32_t s : bylev[h]) {
-                if (pfront[s] >= kSolveStepMinCols) big.push_back(s);
+                if (mfront[s] > step_rows) big.push_back(s);
                 else slist.push_back(s);
             }
             V.fused_cnt = (int64_t)slist.size() - V.fused_off;
@@ -201,6 +210,10 @@ struct Plan {
             V.step_cnt = (int64_t)big.size();
             int32_t maxp = 0;
             for (int32_t s : big) maxp = std::max(maxp, pfront[s]);
+            V.assemble.first = (int64_t)sasm_tasks.size();
+            for (int32_t s : big)
+                for (int32_t t = 0; t < (mfront[s] + SROWS - 1) / SROWS; t++) sasm_tasks.push_back(make_int2(s, t));
+            V.assemble.second = (int64_t)sasm_tasks.size() - V.assemble.first;
             for (int32_t kb = 0; kb < maxp; kb += SB) {
                 int64_t off = (int64_t)sfwd_tasks.size();
                 for (int32_t s : big) {
@@ -237,7 +250,7 @@ struct Layout {
     size_t fronts, W, Y, Xr, Rr, Br, vec, bad;
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof;
-    size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, part;
+    size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -282,6 +295,7 @@ struct Layout {
         sfwd = seg(std::max<size_t>(1, P.sfwd_tasks.size()) * sizeof(int2));
         sbelow = seg(std::max<size_t>(1, P.sbelow_tasks.size()) * sizeof(int2));
         sbwd = seg(std::max<size_t>(1, P.sbwd_tasks.size()) * sizeof(int2));
+        sasm = seg(std::max<size_t>(1, P.sasm_tasks.size()) * sizeof(int2));
         part = seg((size_t)kPartBlocks * k * 8 * 2);
         dscr_off = seg(ns * 8);
         all_fronts = seg(ns * 4);
@@ -496,6 +510,7 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
     const int2 *tf = f->at<int2>(Lo.sfwd);
     const int2 *tb = f->at<int2>(Lo.sbelow);
     const int2 *ts = f->at<int2>(Lo.sbwd);
+    const int2 *tas = f->at<int2>(Lo.sasm);
     if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_L) {
         for (const Level &L : P.levels) {
             const SolveLevel &V = L.sv;
@@ -503,7 +518,8 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
                 hipLaunchKernelGGL((k_fwd_fused<T, KT>), dim3((unsigned)V.fused_cnt), dim3(THREADS), 0, st,
                                    sl + V.fused_off, a);
             if (V.step_cnt) {
-                hipLaunchKernelGGL(k_fwd_init<T>, dim3((unsigned)V.step_cnt), dim3(THREADS), 0, st, sl + V.step_off, a);
+                hipLaunchKernelGGL(k_fwd_assemble<T>, dim3((unsigned)V.assemble.second), dim3(THREADS), 0, st,
+                                   tas + V.assemble.first, a);
                 for (auto &s : V.fwd)
                     hipLaunchKernelGGL((k_fwd_step<T, KT>), dim3((unsigned)s.second.second), dim3(THREADS), 0, st,
                                        tf + s.second.first, s.first, a);
@@ -762,6 +778,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.sfwd, P.sfwd_tasks, st);
     rc = rc ? rc : upload(f, L.sbelow, P.sbelow_tasks, st);
     rc = rc ? rc : upload(f, L.sbwd, P.sbwd_tasks, st);
+    rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
     if (rc == WCS_OK) {
         hipError_t e = hipStreamSynchronize(st);   // host vectors are pageable: finish the copies
         if (e != hipSuccess) {

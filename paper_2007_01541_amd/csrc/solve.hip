@@ -8,9 +8,10 @@
 //   forward  (y = L^-1 b):   z_b = L_bb^-1 w_b,  w_rows_below -= L_rows_below,b z_b
 //   backward (x = L^-T y):   v = y_pivots - L_update,:^T x_update, then from the last
 //                            block down: x_b = L_bb^-T v_b,  v_a -= L_b,a^T x_b (a < b).
-// Fronts with few pivots run one workgroup per front for the whole sweep
-// ("fused"); fronts with many pivots run one launch per 64-column block with
-// the rows (forward) or column blocks (backward) spread over workgroups.
+// Fronts with few rows run one workgroup per front for the whole sweep
+// ("fused"); larger fronts run one launch per 64-column block with the rows
+// (forward) or column blocks (backward) spread over workgroups.  With 64
+// right-hand sides at a time the block products run on the matrix cores.
 // Summation order is fixed everywhere, so results are deterministic.
 
 namespace wcs {
@@ -58,6 +59,132 @@ __device__ void fwd_assemble(const SolveArgs<T> &a, int f)
     }
 }
 
+// ---- matrix-core forms for 64 right-hand sides at a time
+
+// Zs = op(Linv) * Ss (64 x 64 each); wave w produces output rows [16w, 16w+16)
+template <typename T>
+__device__ void blk_mfma(T (*Ds)[SB + 1], T (*Ss)[64], T (*Zs)[64])
+{
+    typedef typename Mfma<T>::V V;
+    int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+    V acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc[cb][e] = 0;
+#pragma unroll
+    for (int kk = 0; kk < SB; kk += 4) {
+        T av = Ds[kk + kq][wave * 16 + ln];          // op(Linv)(row, j) = Ds[j][row]
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) acc[cb] = Mfma<T>::mma(av, Ss[kk + kq][cb * 16 + ln], acc[cb]);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) Zs[wave * 16 + Mfma<T>::row(kq, e)][cb * 16 + ln] = acc[cb][e];
+}
+
+// rows [r0, r1) of w:  w[r][c0 + n] -= sum_j L(r, kb + j) Zs[j][n]; waves take 64-row slabs
+template <typename T>
+__device__ void fwd_rows_mfma(const T *__restrict__ L, int m, int kb, int nbk, T *__restrict__ w, int k, int c0,
+                              int r0, int r1, T (*Zs)[64])
+{
+    typedef typename Mfma<T>::V V;
+    int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+    int nw = blockDim.x / 64;
+    for (int s0 = r0 + wave * 64; s0 < r1; s0 += nw * 64) {
+        V acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+        T av[SB / 4][4];
+#pragma unroll
+        for (int ks = 0; ks < SB / 4; ks++) {
+            int j = ks * 4 + kq;
+#pragma unroll
+            for (int rb = 0; rb < 4; rb++) {
+                int r = s0 + rb * 16 + ln;
+                av[ks][rb] = (r < r1 && j < nbk) ? L[(int64_t)(kb + j) * m + r] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int ks = 0; ks < SB / 4; ks++) {
+            T bv[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++) bv[cb] = Zs[ks * 4 + kq][cb * 16 + ln];
+#pragma unroll
+            for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++) acc[rb][cb] = Mfma<T>::mma(av[ks][rb], bv[cb], acc[rb][cb]);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int r = s0 + rb * 16 + Mfma<T>::row(kq, e);
+                if (r >= r1) continue;
+                T *wr = w + (int64_t)r * k + c0;
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++) {
+                    int n = cb * 16 + ln;
+                    if (c0 + n < k) wr[n] -= acc[rb][cb][e];
+                }
+            }
+    }
+}
+
+// v[c][c0 + n] -= sum_{r in [r0, r1)} L(r, a + c) X[r][n]  (c < na, n < 64);
+// wave w owns output rows c in [16w, 16w+16)
+template <typename T, typename XR>
+__device__ void bwd_cols_mfma(const T *__restrict__ L, int m, int a, int na, int r0, int r1, XR xrow, int k, int c0,
+                              T *__restrict__ v, T (*Ls)[SB + 1], T (*Xs)[64])
+{
+    typedef typename Mfma<T>::V V;
+    int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+    // v may have just been written by other waves: order those writes before
+    // the read-modify-write below even when there are no rows to sum over
+    __syncthreads();
+    if (r0 >= r1) return;
+    V acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) acc[cb][e] = 0;
+    for (int rb = r0; rb < r1; rb += SB) {
+        int nr = min(SB, r1 - rb);
+        __syncthreads();
+        for (int i = tid; i < SB * SB; i += blockDim.x) {
+            int cc = i / SB, rr = i % SB;
+            Ls[cc][rr] = (cc < na && rr < nr) ? L[(int64_t)(a + cc) * m + rb + rr] : (T)0;
+        }
+        for (int i = tid; i < SB * 64; i += blockDim.x) {
+            int rr = i / 64, cc = i % 64;
+            Xs[rr][cc] = (rr < nr && c0 + cc < k) ? xrow(rb + rr)[c0 + cc] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < SB; kk += 4) {
+            T av = Ls[wave * 16 + ln][kk + kq];
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++) acc[cb] = Mfma<T>::mma(av, Xs[kk + kq][cb * 16 + ln], acc[cb]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        int c = wave * 16 + Mfma<T>::row(kq, e);
+        if (c >= na) continue;
+#pragma unroll
+        for (int cb = 0; cb < 4; cb++) {
+            int n = cb * 16 + ln;
+            if (c0 + n < k) v[(int64_t)c * k + c0 + n] -= acc[cb][e];
+        }
+    }
+    __syncthreads();
+}
+
 // Zs[i][c] = sum_j Linv(i, j) * src_j[c] for the block starting at pivot kb
 // (src rows given by a row pointer of stride k).  Stages L^-1 and the block
 // rows in LDS.  For the transposed form Zs = Linv^T src set trans = true.
@@ -75,12 +202,16 @@ __device__ void block_apply(const T *__restrict__ Dinv, const T *__restrict__ sr
         Ss[r][c] = (r < nbk && c0 + c < k) ? src[(int64_t)r * k + c0 + c] : (T)0;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < SB * KT; i += blockDim.x) {
-        int r = i / KT, c = i % KT;
-        T s = 0;
+    if constexpr (KT == 64) {
+        blk_mfma<T>(Ds, Ss, Zs);
+    } else {
+        for (int i = threadIdx.x; i < SB * KT; i += blockDim.x) {
+            int r = i / KT, c = i % KT;
+            T s = 0;
 #pragma unroll 8
-        for (int j = 0; j < SB; j++) s += Ds[j][r] * Ss[j][c];
-        Zs[r][c] = s;
+            for (int j = 0; j < SB; j++) s += Ds[j][r] * Ss[j][c];
+            Zs[r][c] = s;
+        }
     }
     __syncthreads();
 }
@@ -115,6 +246,10 @@ __device__ void bwd_cols(const T *__restrict__ L, int m, int a, int na, int r0, 
 {
     int tid = threadIdx.x, c = tid % SB, g = tid / SB;
     constexpr int PG = (KT + 3) / 4;
+    // v may have just been written by other waves: order those writes before
+    // the read-modify-write below even when there are no rows to sum over
+    __syncthreads();
+    if (r0 >= r1) return;
     T acc[PG];
 #pragma unroll
     for (int q = 0; q < PG; q++) acc[q] = 0;
@@ -151,6 +286,22 @@ __device__ void bwd_cols(const T *__restrict__ L, int m, int a, int na, int r0, 
     __syncthreads();
 }
 
+template <typename T, int KT>
+__device__ __forceinline__ void fwd_rows_any(const T *L, int m, int kb, int nbk, T *w, int k, int c0, int r0, int r1,
+                                             T (*Zs)[KT])
+{
+    if constexpr (KT == 64) fwd_rows_mfma<T>(L, m, kb, nbk, w, k, c0, r0, r1, Zs);
+    else fwd_rows<T, KT>(L, m, kb, nbk, w, k, c0, r0, r1, Zs);
+}
+
+template <typename T, int KT, typename XR>
+__device__ __forceinline__ void bwd_cols_any(const T *L, int m, int a, int na, int r0, int r1, XR xrow, int k, int c0,
+                                             T *v, T (*Ls)[SB + 1], T (*Xs)[KT])
+{
+    if constexpr (KT == 64) bwd_cols_mfma<T>(L, m, a, na, r0, r1, xrow, k, c0, v, Ls, Xs);
+    else bwd_cols<T, KT>(L, m, a, na, r0, r1, xrow, k, c0, v, Ls, Xs);
+}
+
 template <typename T, int KT> struct SolveLds {
     T Ds[SB][SB + 1];
     T Ss[SB][KT];
@@ -178,15 +329,45 @@ __global__ __launch_bounds__(THREADS) void k_fwd_fused(const int32_t *__restrict
                 int r = i / KT, c = i % KT;
                 if (c0 + c < k) a.Y[(int64_t)(f0 + kb + r) * k + c0 + c] = sh.Zs[r][c];
             }
-            fwd_rows<T, KT>(L, m, kb, nbk, w, k, c0, kb + nbk, m, sh.Zs);
+            fwd_rows_any<T, KT>(L, m, kb, nbk, w, k, c0, kb + nbk, m, sh.Zs);
         }
     }
 }
 
+// task = (front, row slab of SROWS rows): w rows of the slab = [Y(pivots); 0]
+// plus the update rows of every child that land in the slab.  The index map
+// of a child is increasing, so those rows are one contiguous run found by
+// binary search; children are visited in a fixed order (deterministic).
 template <typename T>
-__global__ __launch_bounds__(THREADS) void k_fwd_init(const int32_t *__restrict__ flist, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS) void k_fwd_assemble(const int2 *__restrict__ tasks, SolveArgs<T> a)
 {
-    fwd_assemble(a, flist[blockIdx.x]);
+    int2 t = tasks[blockIdx.x];
+    int f = t.x;
+    int m = a.mfront[f], p = a.pfront[f], k = a.k;
+    int r0 = t.y * SROWS, r1 = min(m, r0 + SROWS);
+    T *w = a.W + a.woff[f] * k;
+    const T *y = a.Y + (int64_t)a.first[f] * k;
+    for (int64_t i = (int64_t)r0 * k + threadIdx.x; i < (int64_t)r1 * k; i += blockDim.x)
+        w[i] = i < (int64_t)p * k ? y[i] : (T)0;
+    __syncthreads();
+    for (int q = a.child_ptr[f]; q < a.child_ptr[f + 1]; q++) {
+        int c = a.child_list[q];
+        int mc = a.mfront[c], pc = a.pfront[c];
+        const int32_t *rl = a.rel + a.rptr[c] + pc;
+        int nu = mc - pc;
+        int lo = 0, hi = nu;
+        while (lo < hi) { int md = (lo + hi) / 2; if (rl[md] < r0) lo = md + 1; else hi = md; }
+        int t0 = lo;
+        hi = nu;
+        while (lo < hi) { int md = (lo + hi) / 2; if (rl[md] < r1) lo = md + 1; else hi = md; }
+        int t1 = lo;
+        const T *wc = a.W + a.woff[c] * k + (int64_t)pc * k;
+        for (int64_t i = (int64_t)t0 * k + threadIdx.x; i < (int64_t)t1 * k; i += blockDim.x) {
+            int r = (int)(i / k), cc = (int)(i % k);
+            w[(int64_t)rl[r] * k + cc] += wc[i];
+        }
+        __syncthreads();
+    }
 }
 
 // task = (front, row slab) for block kb; slab 0 also stores z_b into Y.  The
@@ -212,7 +393,7 @@ __global__ __launch_bounds__(THREADS) void k_fwd_step(const int2 *__restrict__ t
                 int r = i / KT, c = i % KT;
                 if (c0 + c < k) a.Y[(int64_t)(f0 + kb + r) * k + c0 + c] = sh.Zs[r][c];
             }
-        if (r0 < r1) fwd_rows<T, KT>(L, m, kb, nbk, w, k, c0, r0, r1, sh.Zs);
+        if (r0 < r1) fwd_rows_any<T, KT>(L, m, kb, nbk, w, k, c0, r0, r1, sh.Zs);
     }
 }
 
@@ -238,7 +419,7 @@ __device__ void bwd_below(const SolveArgs<T> &a, int f, int ab, T (*Ls)[SB + 1],
     const int32_t *rw = a.rows + a.rptr[f];
     const T *Y = a.Y;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
-    for (int c0 = 0; c0 < k; c0 += KT) bwd_cols<T, KT>(L, m, ab, na, p, m, xrow, k, c0, w + (int64_t)ab * k, Ls, Xs);
+    for (int c0 = 0; c0 < k; c0 += KT) bwd_cols_any<T, KT>(L, m, ab, na, p, m, xrow, k, c0, w + (int64_t)ab * k, Ls, Xs);
 }
 
 template <typename T, int KT>
@@ -266,8 +447,8 @@ __global__ __launch_bounds__(THREADS) void k_bwd_fused(const int32_t *__restrict
             for (int ab = 0; ab < kb; ab += SB) {
                 T(*Zs)[KT] = sh.Zs;
                 auto xrow = [&](int r) { return &Zs[r - kb][0] - c0; };
-                bwd_cols<T, KT>(L, a.mfront[f], ab, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)ab * k, sh.Ls,
-                                sh.Ss);
+                bwd_cols_any<T, KT>(L, a.mfront[f], ab, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)ab * k, sh.Ls,
+                                    sh.Ss);
             }
         }
     }
@@ -306,8 +487,8 @@ __global__ __launch_bounds__(THREADS) void k_bwd_step(const int2 *__restrict__ t
         } else {
             T(*Zs)[KT] = sh.Zs;
             auto xrow = [&](int r) { return &Zs[r - kb][0] - c0; };
-            bwd_cols<T, KT>(L, a.mfront[f], t.y * SB, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)t.y * SB * k,
-                            sh.Ls, sh.Ss);
+            bwd_cols_any<T, KT>(L, a.mfront[f], t.y * SB, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)t.y * SB * k,
+                                sh.Ls, sh.Ss);
         }
     }
 }

@@ -64,7 +64,7 @@ def test_factor_matches_oracle(kind, leaf, coords, prec):
 
 
 @pytest.mark.parametrize("kind,leaf,coords", CASES)
-@pytest.mark.parametrize("k", [1, 3, 64])
+@pytest.mark.parametrize("k", [1, 3, 9, 64, 70])
 def test_fp64_solve(kind, leaf, coords, k):
     m, sym, orc = prepared(kind, leaf, coords)
     n = m["n"]
