@@ -649,31 +649,42 @@ int analyze(int32_t n, const int64_t *colptr, const int32_t *rowind, const wcs_a
             }
         }
     }
-    // full symmetric CSR in the original order for A * x
+    // full symmetric CSR of C = P A P^T (pivot order, columns ascending) for
+    // the refinement residual; csr_src names the stored entry of each value
     S.csr_ptr.assign((size_t)n + 1, 0);
     for (int32_t j = 0; j < n; j++)
         for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
             int32_t i = rowind[p];
-            S.csr_ptr[i + 1]++;
-            if (i != j) S.csr_ptr[j + 1]++;
+            S.csr_ptr[S.iperm[i] + 1]++;
+            if (i != j) S.csr_ptr[S.iperm[j] + 1]++;
         }
     for (int32_t i = 0; i < n; i++) S.csr_ptr[i + 1] += S.csr_ptr[i];
     S.csr_col.resize((size_t)S.csr_ptr[n]);
     S.csr_src.resize((size_t)S.csr_ptr[n]);
     {
         std::vector<int64_t> fill(S.csr_ptr.begin(), S.csr_ptr.end() - 1);
-        // row i: first the entries (i, j) with j < i (from columns j ascending), then column i itself
-        for (int32_t j = 0; j < n; j++)
-            for (int64_t p = colptr[j] + 1; p < colptr[j + 1]; p++) {
-                int32_t i = rowind[p];
-                S.csr_col[fill[i]] = j;
-                S.csr_src[fill[i]++] = p;
-            }
         for (int32_t j = 0; j < n; j++)
             for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
-                S.csr_col[fill[j]] = rowind[p];
-                S.csr_src[fill[j]++] = p;
+                int32_t i = rowind[p];
+                int32_t a = S.iperm[i], b = S.iperm[j];
+                S.csr_col[fill[a]] = b;
+                S.csr_src[fill[a]++] = p;
+                if (i != j) {
+                    S.csr_col[fill[b]] = a;
+                    S.csr_src[fill[b]++] = p;
+                }
             }
+        std::vector<std::pair<int32_t, int64_t>> tmp2;
+        for (int32_t r = 0; r < n; r++) {
+            int64_t a = S.csr_ptr[r], b = S.csr_ptr[r + 1];
+            tmp2.resize((size_t)(b - a));
+            for (int64_t q = a; q < b; q++) tmp2[q - a] = {S.csr_col[q], S.csr_src[q]};
+            std::sort(tmp2.begin(), tmp2.end());
+            for (int64_t q = a; q < b; q++) {
+                S.csr_col[q] = tmp2[q - a].first;
+                S.csr_src[q] = tmp2[q - a].second;
+            }
+        }
     }
     return WCS_OK;
 }

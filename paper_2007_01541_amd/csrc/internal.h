@@ -42,8 +42,8 @@ struct Symbolic {
     std::vector<int64_t> front_off;  // ns + 1 element offsets of the m x m front buffers
     std::vector<int64_t> amap;       // per stored entry: element offset inside the fronts
 
-    // full symmetric CSR of A in the original order (for A*x), with the
-    // stored-entry index each CSR entry takes its value from
+    // full symmetric CSR of P A P^T in pivot order (for the residual), with
+    // the stored-entry index each CSR entry takes its value from
     std::vector<int64_t> csr_ptr;
     std::vector<int32_t> csr_col;
     std::vector<int64_t> csr_src;

@@ -544,21 +544,100 @@ __global__ void k_spmv_narrow(const int64_t *__restrict__ rp, const int32_t *__r
     }
 }
 
-__global__ void k_spmv_wide(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                            const double *__restrict__ v, int n, int k, const double *__restrict__ X,
-                            const double *__restrict__ B, double *__restrict__ R, int64_t sx, int64_t sc)
+// Wide form for row-major X (sx = k, sc = 1): one wave per row, lanes are
+// the columns (64 per pass); each wave loads 64 (column, value) pairs at a
+// time and broadcasts them, so the gathers of X rows stay in flight.  Rows
+// go to XCDs in contiguous ranges (block b runs on XCD b % 8), which keeps
+// the gathered X rows of neighbouring rows in the same L2.
+__global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                   const double *__restrict__ v, int n, int k,
+                                                   const double *__restrict__ X, const double *__restrict__ B,
+                                                   double *__restrict__ R, int64_t sx, int64_t sc)
 {
-    int row = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64);
+    int nrb = (n + 3) / 4;                       // row blocks of 4 rows
+    int per = (nrb + 7) / 8;
+    int rb = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+    if (rb >= nrb) return;
+    int row = rb * 4 + (int)threadIdx.x / 64;
     int lane = threadIdx.x % 64;
     if (row >= n) return;
     int64_t a = rp[row], b = rp[row + 1];
     for (int c0 = 0; c0 < k; c0 += 64) {
         int c = c0 + lane;
-        if (c >= k) break;
+        bool on = c < k;
+        const double *xc = X + (int64_t)(on ? c : 0) * sc;
         double s = 0;
-        for (int64_t q = a; q < b; q++) s += v[q] * X[(int64_t)ci[q] * sx + (int64_t)c * sc];
-        int64_t o = (int64_t)row * sx + (int64_t)c * sc;
-        R[o] = B ? B[o] - s : s;
+        for (int64_t q0 = a; q0 < b; q0 += 64) {
+            int cnt = (int)min((int64_t)64, b - q0);
+            int myc = lane < cnt ? ci[q0 + lane] : 0;
+            double myv = lane < cnt ? v[q0 + lane] : 0.0;
+            int t = 0;
+            for (; t + 4 <= cnt; t += 4) {
+                int j0 = __shfl(myc, t), j1 = __shfl(myc, t + 1), j2 = __shfl(myc, t + 2), j3 = __shfl(myc, t + 3);
+                double v0 = __shfl(myv, t), v1 = __shfl(myv, t + 1), v2 = __shfl(myv, t + 2), v3 = __shfl(myv, t + 3);
+                double x0 = xc[(int64_t)j0 * sx], x1 = xc[(int64_t)j1 * sx], x2 = xc[(int64_t)j2 * sx],
+                       x3 = xc[(int64_t)j3 * sx];
+                s += v0 * x0;
+                s += v1 * x1;
+                s += v2 * x2;
+                s += v3 * x3;
+            }
+            for (; t < cnt; t++) s += __shfl(myv, t) * xc[(int64_t)__shfl(myc, t) * sx];
+        }
+        if (on) {
+            int64_t o = (int64_t)row * sx + (int64_t)c * sc;
+            R[o] = B ? B[o] - s : s;
+        }
+    }
+}
+
+// Xp[i * k + c] = X[perm[i] + c * ld]  (caller column-major -> row-major pivot order)
+__global__ void k_gather_rows(const double *__restrict__ X, int64_t ld, const int32_t *__restrict__ perm, int n, int k,
+                              double *__restrict__ Xp)
+{
+    int64_t total = (int64_t)n * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx / k), c = (int)(idx % k);
+        Xp[idx] = X[(int64_t)c * ld + perm[i]];
+    }
+}
+
+// X[perm[i] + c * ld] = Xp[i * k + c]
+__global__ void k_scatter_rows(const double *__restrict__ Xp, const int32_t *__restrict__ perm, int n, int k,
+                               double *__restrict__ X, int64_t ld)
+{
+    int64_t total = (int64_t)n * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx / k), c = (int)(idx % k);
+        X[(int64_t)c * ld + perm[i]] = Xp[idx];
+    }
+}
+
+// Y = (T)(R * scale[c])  (same row-major layout)
+template <typename T>
+__global__ void k_cast_scaled(const double *__restrict__ R, int64_t total, int k, const double *__restrict__ scale,
+                              T *__restrict__ Y)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        double x = R[idx];
+        if (scale) x *= scale[idx % k];
+        Y[idx] = (T)x;
+    }
+}
+
+// X (+)= Y / scale[c]
+template <typename T>
+__global__ void k_add_unscaled(const T *__restrict__ Y, int64_t total, int k, const double *__restrict__ scale,
+                               int accumulate, double *__restrict__ X)
+{
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        double y = (double)Y[idx];
+        if (scale) y /= scale[idx % k];
+        X[idx] = accumulate ? X[idx] + y : y;
     }
 }
 
@@ -603,59 +682,6 @@ __global__ void k_colred_final(const double *__restrict__ part, int nb, int k, i
             t = op == 0 ? t + x : fmax(t, x);
         }
         out[c] = t;
-    }
-}
-
-// column-major (ld) <-> row-major (n x k)
-__global__ void k_cm2rm(const double *__restrict__ A, int64_t ld, int n, int k, double *__restrict__ B)
-{
-    int64_t total = (int64_t)n * k;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int i = (int)(idx / k), c = (int)(idx % k);
-        B[idx] = A[(int64_t)c * ld + i];
-    }
-}
-
-__global__ void k_rm2cm(const double *__restrict__ B, int n, int k, double *__restrict__ A, int64_t ld)
-{
-    int64_t total = (int64_t)n * k;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int i = (int)(idx / k), c = (int)(idx % k);
-        A[(int64_t)c * ld + i] = B[idx];
-    }
-}
-
-// Y(pivot i, c) = (T)(Xr[perm[i] * k + c] * scale[c])  (row-major in and out)
-template <typename T>
-__global__ void k_perm_in_rm(const double *__restrict__ Xr, const int32_t *__restrict__ perm, int n, int k,
-                             const double *__restrict__ scale, T *__restrict__ Y)
-{
-    int64_t total = (int64_t)n * k;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int i = (int)(idx / k), c = (int)(idx % k);
-        double v = Xr[(int64_t)perm[i] * k + c];
-        if (scale) v *= scale[c];
-        Y[idx] = (T)v;
-    }
-}
-
-// Xr[perm[i] * k + c] (+)= Y(i, c) / scale[c]
-template <typename T>
-__global__ void k_perm_out_rm(const T *__restrict__ Y, const int32_t *__restrict__ perm, int n, int k,
-                              const double *__restrict__ scale, int accumulate, double *__restrict__ Xr)
-{
-    int64_t total = (int64_t)n * k;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        int i = (int)(idx / k), c = (int)(idx % k);
-        double v = (double)Y[idx];
-        if (scale) v /= scale[c];
-        double *d = Xr + (int64_t)perm[i] * k + c;
-        if (accumulate) *d += v;
-        else *d = v;
     }
 }
 

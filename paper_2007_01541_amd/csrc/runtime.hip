@@ -588,7 +588,8 @@ int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st)
     return WCS_OK;
 }
 
-// R = B - A X or Y = A X (B null); element (i, c) at i * sx + c * sc
+// R = B - C X or Y = C X (B null) with C = P A P^T in pivot order; element
+// (i, c) at i * sx + c * sc
 int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R, int64_t sx, int64_t sc,
                 hipStream_t st)
 {
@@ -597,12 +598,13 @@ int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R
     const int64_t *rp = f->at<int64_t>(f->lay.csr_ptr);
     const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
     const double *v = f->at<double>(f->lay.csr_val);
-    if (k >= 8)
-        hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R, sx,
-                           sc);
-    else
+    if (k >= 8 && sc == 1) {
+        int nrb = (n + 3) / 4, per = (nrb + 7) / 8;
+        hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)(8 * per)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R, sx, sc);
+    } else {
         hipLaunchKernelGGL(k_spmv_narrow, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R,
                            sx, sc);
+    }
     HIP_TRY(hipGetLastError());
     return WCS_OK;
 }
@@ -615,6 +617,9 @@ void launch_colred(wcs_factor f, const double *A, int n, int k, int op, double *
     hipLaunchKernelGGL(k_colred_final, dim3(1), dim3(256), 0, st, part, kPartBlocks, k, op, out);
 }
 
+// Refinement in pivot order: Bp = P B, Xp = solve(Bp), then while any
+// column has ||Bp - C Xp|| > tol ||Bp||: Xp += solve(R s) / s with the
+// per-column scale s = 1 / max|R| (keeps R inside the FP32 range); X = P^T Xp.
 template <typename T>
 int solve_refined(wcs_factor f, const double *values, int k, const double *B, double *X, int64_t ld, double tol,
                   int max_iter, wcs_ir_report *rep, hipStream_t st)
@@ -623,31 +628,29 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     int n = f->S->n;
     int rc = ensure_csr_values(f, values, st);
     if (rc) return rc;
-    double *Br = f->at<double>(Lo.Br);      // row-major n x k copies
-    double *Xr = f->at<double>(Lo.Xr);
-    double *Rr = f->at<double>(Lo.Rr);
+    double *Bp = f->at<double>(Lo.Br);      // row-major n x k, pivot order
+    double *Xp = f->at<double>(Lo.Xr);
+    double *Rp = f->at<double>(Lo.Rr);
     double *vec = f->at<double>(Lo.vec);    // [0,k): |B|^2, [k,2k): |R|^2, [2k,3k): amax, [3k,4k): scale
     T *Y = f->at<T>(Lo.Y);
     const int32_t *perm = f->at<int32_t>(Lo.perm);
     int64_t nk = (int64_t)n * k;
-    hipLaunchKernelGGL(k_cm2rm, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, n, k, Br);
-    launch_colred(f, Br, n, k, 0, vec, st);
-    // X0 = solve(B)
-    hipLaunchKernelGGL(k_perm_in_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Br, perm, n, k, (const double *)nullptr,
-                       Y);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Bp);
+    launch_colred(f, Bp, n, k, 0, vec, st);
+    hipLaunchKernelGGL(k_cast_scaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Bp, nk, k, (const double *)nullptr, Y);
     rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_perm_out_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k,
-                       (const double *)nullptr, 0, Xr);
+    hipLaunchKernelGGL(k_add_unscaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, nk, k, (const double *)nullptr, 0,
+                       Xp);
     std::vector<double> h((size_t)2 * k);
     rep->iterations = 0;
     rep->raw_residual = -1;
     rep->final_residual = -1;
     int status = WCS_ENOTCONV;
     for (int it = 0;; it++) {
-        rc = launch_spmv(f, k, Xr, Br, Rr, k, 1, st);
+        rc = launch_spmv(f, k, Xp, Bp, Rp, k, 1, st);
         if (rc) return rc;
-        launch_colred(f, Rr, n, k, 0, vec + k, st);
+        launch_colred(f, Rp, n, k, 0, vec + k, st);
         HIP_TRY(hipMemcpyAsync(h.data(), vec, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         double worst = 0;
@@ -660,18 +663,17 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
         rep->final_residual = worst;
         if (worst <= tol) { status = WCS_OK; break; }
         if (it >= max_iter) break;
-        // D = solve(R * s) / s, X += D with s = 1 / max|R| per column (keeps R in the FP32 range)
-        launch_colred(f, Rr, n, k, 1, vec + 2 * k, st);
+        launch_colred(f, Rp, n, k, 1, vec + 2 * k, st);
         hipLaunchKernelGGL(k_inv_scale, dim3(1), dim3(64 * ((k + 63) / 64)), 0, st, vec + 2 * k, k, vec + 3 * k);
-        hipLaunchKernelGGL(k_perm_in_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Rr, perm, n, k,
+        hipLaunchKernelGGL(k_cast_scaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Rp, nk, k,
                            (const double *)(vec + 3 * k), Y);
         rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_perm_out_rm<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k,
-                           (const double *)(vec + 3 * k), 1, Xr);
+        hipLaunchKernelGGL(k_add_unscaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, nk, k,
+                           (const double *)(vec + 3 * k), 1, Xp);
         rep->iterations = it + 1;
     }
-    hipLaunchKernelGGL(k_rm2cm, dim3(grid_for(nk)), dim3(256), 0, st, Xr, n, k, X, ld);
+    hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, Xp, perm, n, k, X, ld);
     HIP_TRY(hipGetLastError());
     if (status != WCS_OK)
         set_error("iterative refinement stopped at relative residual " + std::to_string(rep->final_residual));
@@ -905,10 +907,20 @@ int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double 
         set_error("invalid argument to wcs_spmv");
         return WCS_EINVAL;
     }
+    if (nrhs > f->max_nrhs) { set_error("wcs_spmv: nrhs exceeds the factor's max_nrhs"); return WCS_EINVAL; }
     hipStream_t st = (hipStream_t)stream;
     int rc = ensure_csr_values(f, values_dev, st);
     if (rc) return rc;
-    return launch_spmv(f, nrhs, X_dev, nullptr, Y_dev, 1, ld, st);
+    int n = f->S->n;
+    int64_t nk = (int64_t)n * nrhs;
+    double *Xp = f->at<double>(f->lay.Xr), *Yp = f->at<double>(f->lay.Rr);
+    const int32_t *perm = f->at<int32_t>(f->lay.perm);
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, X_dev, ld, perm, n, nrhs, Xp);
+    rc = launch_spmv(f, nrhs, Xp, nullptr, Yp, nrhs, 1, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, Yp, perm, n, nrhs, Y_dev, ld);
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
 }
 
 int wcs_grad_pattern(wcs_factor f, const double *lam_dev, const double *x_dev, double *gA_dev, wcs_stream stream)
