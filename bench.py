@@ -160,6 +160,17 @@ def main() -> int:
     for nm, st in prof.items():
         log(f"  kernel class {nm}: {st['launches']} launches, {st['ms']:.2f} ms, "
             f"{st['flops'] / 1e9:.1f} GFLOP, {st['bytes'] / 1e9:.2f} GB")
+    levels = f32.profile_levels(vals)
+    torch.cuda.synchronize()
+    top = levels[-3:]
+    root_ms = sum(l["ms"] for l in top)
+    root_flops = sum(l["flops"] for l in top)
+    root = {"levels": len(top), "ms": root_ms, "tflops": root_flops / root_ms / 1e9,
+            "pct_fp32_mfma_peak": 100 * root_flops / root_ms / 1e9 / PEAK["fp32_mfma_tflops"],
+            "per_level": [{"ms": round(l["ms"], 3), "tflops": round(l["flops"] / max(l["ms"], 1e-9) / 1e9, 2)}
+                          for l in levels]}
+    log(f"  root-level fronts (top 3 levels): {root_ms:.2f} ms, {root['tflops']:.1f} TFLOP/s "
+        f"({root['pct_fp32_mfma_peak']:.1f}% of FP32 MFMA peak)")
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]
     del f32
@@ -207,6 +218,7 @@ def main() -> int:
                    "nnz_l": int(info["nnz_l"]), "flops": int(info["flops"]), "fronts": int(info["nsuper"]),
                    "max_front": int(info["max_front"]), "analyze_s": round(t_analyze, 2)},
         "pct_fp32_mfma_peak": 100 * value / PEAK["fp32_mfma_tflops"],
+        "root_fronts": root,
         "factor_ms": fact32,
         "ir": rep32,
         "fp64": fp64,

@@ -194,6 +194,15 @@ typedef struct {
 int wcs_factor_profile(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *stats);
 
 /*
+ * Diagnostic: as wcs_factor_profile, but timing whole levels of the assembly
+ * tree (level 0 = leaves, nlevels-1 = root) with one event pair around all
+ * launches of a level (extend-add and dense steps).  levels[h] gets the
+ * level's time and the algorithmic flops of its fronts (sum over pivots of
+ * the squared column length of the factored front).  nlevels entries.
+ */
+int wcs_factor_profile_levels(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *levels);
+
+/*
  * Copies columns [j0, j1) (pivot order) of L to host memory in compressed
  * sparse column form over the stored (amalgamated) pattern, explicit zeros
  * included: Lp[j1-j0+1] offsets starting at 0, Li row indices (pivot order,

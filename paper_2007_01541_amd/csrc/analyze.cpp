@@ -613,9 +613,10 @@ int analyze(int32_t n, const int64_t *colptr, const int32_t *rowind, const wcs_a
         if (S.sparent[s] != -1) S.height[S.sparent[s]] = std::max(S.height[S.sparent[s]], S.height[s] + 1);
         S.nlevels = std::max(S.nlevels, S.height[s] + 1);
     }
-    // front buffers: m x m column-major, one after another
+    // front buffers: m x m column-major with leading dimension front_ld_host(m), one after another
     S.front_off.assign((size_t)ns + 1, 0);
-    for (int32_t s = 0; s < ns; s++) S.front_off[s + 1] = S.front_off[s] + (int64_t)S.m_of(s) * S.m_of(s);
+    for (int32_t s = 0; s < ns; s++)
+        S.front_off[s + 1] = S.front_off[s] + (int64_t)front_ld_host(S.m_of(s)) * S.m_of(s);
     // stored entries of A -> front offsets: entry (i, j) lands in the front
     // owning column min(pi(i), pi(j)) at row max(pi(i), pi(j))
     S.amap.assign((size_t)S.nnz, 0);
@@ -639,7 +640,7 @@ int analyze(int32_t n, const int64_t *colptr, const int32_t *rowind, const wcs_a
         for (int32_t j = 0; j < n; j++)
             for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) colof[p] = j;
         for (int32_t s = 0; s < ns; s++) {
-            int32_t m = S.m_of(s);
+            int32_t m = front_ld_host(S.m_of(s));
             for (int64_t q = S.rptr[s]; q < S.rptr[s + 1]; q++) pos[S.rows[q]] = (int32_t)(q - S.rptr[s]);
             for (int64_t t = cnt[s]; t < cnt[s + 1]; t++) {
                 int64_t p = ent[t];

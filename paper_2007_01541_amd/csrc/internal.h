@@ -11,6 +11,10 @@ namespace wcs {
 
 void set_error(const std::string &msg);
 
+// Leading dimension of an m x m front buffer: m rounded up to 8 elements, so
+// every column starts 32-byte (FP32) / 64-byte (FP64) aligned.
+inline int32_t front_ld_host(int32_t m) { return (m + 7) & ~7; }
+
 // Result of the ordering + symbolic analysis, plus the static plan derived
 // from it (everything here is host memory and independent of the values).
 struct Symbolic {
@@ -39,7 +43,7 @@ struct Symbolic {
     std::vector<int32_t> sparent;    // parent front or -1
     std::vector<int32_t> height;     // 0 for leaves
     int32_t nlevels = 0;
-    std::vector<int64_t> front_off;  // ns + 1 element offsets of the m x m front buffers
+    std::vector<int64_t> front_off;  // ns + 1 element offsets of the front buffers (ld x m, ld = front_ld_host(m))
     std::vector<int64_t> amap;       // per stored entry: element offset inside the fronts
 
     // full symmetric CSR of P A P^T in pivot order (for the residual), with

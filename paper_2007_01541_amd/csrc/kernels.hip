@@ -45,12 +45,29 @@ template <> struct Mfma<double> {
 
 // ---------------------------------------------------------------- utilities
 
+// leading dimension of an m x m front (m rounded up to 8 elements)
+__device__ __forceinline__ int front_ld(int m) { return (m + 7) & ~7; }
+
 template <typename T>
 __global__ void k_fill(T *__restrict__ p, int64_t n, T v)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (; i < n; i += stride) p[i] = v;
+}
+
+// zero the lower triangle of columns [c0, c0 + ZCOLS) of a front (task = (front, c0))
+constexpr int ZCOLS = 16;
+template <typename T>
+__global__ void k_zero_lower(const int2 *__restrict__ tasks, const int64_t *__restrict__ front_off,
+                             const int32_t *__restrict__ mfront, T *__restrict__ fronts)
+{
+    int2 t = tasks[blockIdx.x];
+    int m = mfront[t.x], ld = front_ld(m);
+    T *F = fronts + front_off[t.x];
+    int c1 = min(t.y + ZCOLS, m);
+    for (int c = t.y; c < c1; c++)
+        for (int r = c + threadIdx.x; r < m; r += blockDim.x) F[(int64_t)c * ld + r] = (T)0;
 }
 
 // fronts[amap[e]] = values[e]: the stored entries of A into their fronts
@@ -80,14 +97,15 @@ __global__ void k_extend_add(const int2 *__restrict__ tasks, const int64_t *__re
     int nu = mc - pc;
     int par = sparent[c];
     int mp = mfront[par];
-    const T *U = fronts + front_off[c] + (int64_t)pc * mc + pc;
+    int ldc = front_ld(mc), ldp = front_ld(mp);
+    const T *U = fronts + front_off[c] + (int64_t)pc * ldc + pc;
     T *Fp = fronts + front_off[par];
     const int32_t *rl = rel + rptr[c] + pc;
     int c1 = min(t.y + EA_COLS, nu);
     for (int col = t.y; col < c1; col++) {
         int pcol = rl[col];
-        const T *u = U + (int64_t)col * mc;
-        T *dst = Fp + (int64_t)pcol * mp;
+        const T *u = U + (int64_t)col * ldc;
+        T *dst = Fp + (int64_t)pcol * ldp;
         for (int r = col + threadIdx.x; r < nu; r += blockDim.x) dst[rl[r]] += u[r];
     }
 }
@@ -152,7 +170,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
     __shared__ T Li[NB][NB + 1];     // row-major copy of L^-1 in the panel precision
     int2 t = tasks[blockIdx.x];
     int f = t.x;
-    int m = mfront[f], p = pfront[f];
+    int m = mfront[f], p = pfront[f], ld = front_ld(m);
     int nb = min(NB, p - k0);
     T *F = fronts + front_off[f];
     int tid = threadIdx.x;
@@ -166,7 +184,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
             TD col[NB];
 #pragma unroll
             for (int c = 0; c < NB; c++)
-                col[c] = (r < nb && c < nb && c <= r) ? (TD)F[(int64_t)(k0 + c) * m + k0 + r]
+                col[c] = (r < nb && c < nb && c <= r) ? (TD)F[(int64_t)(k0 + c) * ld + k0 + r]
                                                       : (c == r ? (TD)1 : (TD)0);
 #pragma unroll
             for (int c = 0; c < NB; c++) {
@@ -283,7 +301,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
 #pragma unroll
             for (int rb = 0; rb < 4; rb++) {
                 int row = row0 + rb * 16 + ln;
-                bv[ks][rb] = (row < m && k < nb) ? F[(int64_t)(k0 + k) * m + row] : (T)0;
+                bv[ks][rb] = (row < m && k < nb) ? F[(int64_t)(k0 + k) * ld + row] : (T)0;
             }
         }
     }
@@ -318,7 +336,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 int row = row0 + rb * 16 + Mfma<T>::row(kq, e);
-                if (row < m) F[(int64_t)(k0 + n) * m + row] = acc[rb][cb][e];
+                if (row < m) F[(int64_t)(k0 + n) * ld + row] = acc[rb][cb][e];
             }
         }
 }
@@ -332,7 +350,7 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
                              T *__restrict__ fronts)
 {
     int f = flist[blockIdx.x];
-    int m = mfront[f], p = pfront[f];
+    int m = mfront[f], p = pfront[f], ld = front_ld(m);
     T *F = fronts + front_off[f];
     const T *D = dscr + dscr_off[f];
     int nblk = (p + NB - 1) / NB;
@@ -341,7 +359,7 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
         int c = e / NB, r = e % NB;
         int k0 = b * NB;
         int nb = min(NB, p - k0);
-        if (c < nb && r < nb && r >= c) F[(int64_t)(k0 + c) * m + k0 + r] = D[idx];
+        if (c < nb && r < nb && r >= c) F[(int64_t)(k0 + c) * ld + k0 + r] = D[idx];
     }
 }
 
@@ -357,6 +375,16 @@ template <typename T> struct UpdCfg;
 template <> struct UpdCfg<float> { static constexpr int KC = 32; };
 template <> struct UpdCfg<double> { static constexpr int KC = 16; };
 
+// LDS position of logical tile row r (0..UT-1) in "fragment order": within
+// each 64-row wave block, row q*16 + l goes to l*4 + q, so the four operands a
+// lane needs for its four 16-row MFMA blocks are adjacent (one 16-byte read
+// for FP32, two for FP64).
+__device__ __forceinline__ int frag_pos(int r) { return (r & ~63) + (r & 15) * 4 + ((r >> 4) & 3); }
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
 template <typename T>
 __global__ __launch_bounds__(THREADS) void k_update(const int4 *__restrict__ tasks, int ka, int kw,
                                                     const int64_t *__restrict__ front_off,
@@ -364,43 +392,48 @@ __global__ __launch_bounds__(THREADS) void k_update(const int4 *__restrict__ tas
                                                     const int32_t *__restrict__ pfront, T *__restrict__ fronts)
 {
     constexpr int KC = UpdCfg<T>::KC;
-    constexpr int LD = UT + 4;
-    __shared__ T As[2][KC][LD];
-    __shared__ T Bs[2][KC][LD];
-    constexpr int PER = KC * UT / THREADS;     // elements of each operand per thread per chunk
+    constexpr int LD = UT + (sizeof(T) == 4 ? 4 : 2);
+    __shared__ __align__(16) T As[2][KC][LD];
+    __shared__ __align__(16) T Bs[2][KC][LD];
+    constexpr int KSTEP = THREADS / UT;        // k rows covered by one pass of the block (2)
+    constexpr int PER = KC / KSTEP;            // elements of each operand per thread per chunk
     int4 t = tasks[blockIdx.x];
     int f = t.x, i0 = t.y, j0 = t.z, jend = t.w;
-    int m = mfront[f], p = pfront[f];
+    int m = mfront[f], p = pfront[f], ld = front_ld(m);
     int K = min(kw, p - ka);
+    const T *F0 = fronts + front_off[f];
     T *F = fronts + front_off[f];
     int tid = threadIdx.x;
     int wave = tid / 64, lane = tid % 64;
     int wr = (wave / 2) * 64, wc = (wave % 2) * 64;
     int kq = lane / 16, ln = lane % 16;
-    // a wave whose quarter lies entirely above the diagonal (or right of jend) has nothing to do
     bool active = (i0 + wr + 63 >= j0 + wc) && (j0 + wc < jend) && (i0 + wr < m);
+    // staging: thread loads tile row r for k = k_first + KSTEP*q
+    const int r = tid % UT, k_first = tid / UT;
+    const int rpos = frag_pos(r);
+    const bool arow = i0 + r < m, brow = j0 + r < m;
+    const T *pa = F0 + (int64_t)(ka + k_first) * ld + i0 + r;
+    const T *pb = F0 + (int64_t)(ka + k_first) * ld + j0 + r;
+    const int64_t kstride = (int64_t)KSTEP * ld;
     T ra[PER], rb[PER];
     auto gload = [&](int kc) {
+        const T *qa = pa + (int64_t)kc * ld, *qb = pb + (int64_t)kc * ld;
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            int idx = tid + q * THREADS;
-            int k = idx / UT, r = idx % UT;
-            bool kok = kc + k < K;
-            int64_t col = (int64_t)(ka + kc + k) * m;
-            ra[q] = (kok && i0 + r < m) ? F[col + i0 + r] : (T)0;
-            rb[q] = (kok && j0 + r < m) ? F[col + j0 + r] : (T)0;
+            bool kok = kc + k_first + q * KSTEP < K;
+            ra[q] = (kok && arow) ? qa[q * kstride] : (T)0;
+            rb[q] = (kok && brow) ? qb[q * kstride] : (T)0;
         }
     };
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            int idx = tid + q * THREADS;
-            int k = idx / UT, r = idx % UT;
-            As[buf][k][r] = ra[q];
-            Bs[buf][k][r] = rb[q];
+            As[buf][k_first + q * KSTEP][rpos] = ra[q];
+            Bs[buf][k_first + q * KSTEP][rpos] = rb[q];
         }
     };
     typedef typename Mfma<T>::V V;
+    typedef typename Vec4<T>::type V4;
     V acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; i++)
@@ -418,12 +451,10 @@ __global__ __launch_bounds__(THREADS) void k_update(const int4 *__restrict__ tas
         if (active) {
 #pragma unroll
             for (int kk = 0; kk < KC; kk += 4) {
-                T av[4], bv[4];
-#pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    av[q] = As[buf][kk + kq][wr + q * 16 + ln];
-                    bv[q] = Bs[buf][kk + kq][wc + q * 16 + ln];
-                }
+                V4 a4 = *reinterpret_cast<const V4 *>(&As[buf][kk + kq][wr + ln * 4]);
+                V4 b4 = *reinterpret_cast<const V4 *>(&Bs[buf][kk + kq][wc + ln * 4]);
+                T av[4] = {a4.x, a4.y, a4.z, a4.w};
+                T bv[4] = {b4.x, b4.y, b4.z, b4.w};
 #pragma unroll
                 for (int x = 0; x < 4; x++)
 #pragma unroll
@@ -440,7 +471,7 @@ __global__ __launch_bounds__(THREADS) void k_update(const int4 *__restrict__ tas
         for (int y = 0; y < 4; y++) {
             int col = j0 + wc + y * 16 + ln;
             if (col >= jend) continue;
-            T *Cc = F + (int64_t)col * m;
+            T *Cc = F + (int64_t)col * ld;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 int row = i0 + wr + x * 16 + Mfma<T>::row(kq, e);
@@ -544,17 +575,18 @@ __global__ void k_spmv_narrow(const int64_t *__restrict__ rp, const int32_t *__r
     }
 }
 
-// Wide form for row-major X (sx = k, sc = 1): one wave per row, lanes are
-// the columns (64 per pass); each wave loads 64 (column, value) pairs at a
-// time and broadcasts them, so the gathers of X rows stay in flight.  Rows
-// go to XCDs in contiguous ranges (block b runs on XCD b % 8), which keeps
-// the gathered X rows of neighbouring rows in the same L2.
+// Wide form for row-major X (k columns, leading dimension k): one wave per
+// row, lanes are the columns (64 per pass).  Each wave loads 64 (column,
+// value) pairs at once with non-temporal loads (the matrix is streamed once
+// and should not evict X from the caches) and broadcasts them, keeping eight
+// gathers of X rows in flight.  Rows go to XCDs in contiguous ranges (block b
+// runs on XCD b % 8), so rows of one subtree of the dissection share an L2.
 __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                    const double *__restrict__ v, int n, int k,
                                                    const double *__restrict__ X, const double *__restrict__ B,
-                                                   double *__restrict__ R, int64_t sx, int64_t sc)
+                                                   double *__restrict__ R)
 {
-    int nrb = (n + 3) / 4;                       // row blocks of 4 rows
+    int nrb = (n + 3) / 4;
     int per = (nrb + 7) / 8;
     int rb = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
     if (rb >= nrb) return;
@@ -565,28 +597,31 @@ __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ r
     for (int c0 = 0; c0 < k; c0 += 64) {
         int c = c0 + lane;
         bool on = c < k;
-        const double *xc = X + (int64_t)(on ? c : 0) * sc;
-        double s = 0;
+        const double *xc = X + (on ? c : 0);
+        double s0 = 0, s1 = 0;
         for (int64_t q0 = a; q0 < b; q0 += 64) {
             int cnt = (int)min((int64_t)64, b - q0);
-            int myc = lane < cnt ? ci[q0 + lane] : 0;
-            double myv = lane < cnt ? v[q0 + lane] : 0.0;
+            int myc = lane < cnt ? __builtin_nontemporal_load(ci + q0 + lane) : 0;
+            double myv = lane < cnt ? __builtin_nontemporal_load(v + q0 + lane) : 0.0;
             int t = 0;
-            for (; t + 4 <= cnt; t += 4) {
-                int j0 = __shfl(myc, t), j1 = __shfl(myc, t + 1), j2 = __shfl(myc, t + 2), j3 = __shfl(myc, t + 3);
-                double v0 = __shfl(myv, t), v1 = __shfl(myv, t + 1), v2 = __shfl(myv, t + 2), v3 = __shfl(myv, t + 3);
-                double x0 = xc[(int64_t)j0 * sx], x1 = xc[(int64_t)j1 * sx], x2 = xc[(int64_t)j2 * sx],
-                       x3 = xc[(int64_t)j3 * sx];
-                s += v0 * x0;
-                s += v1 * x1;
-                s += v2 * x2;
-                s += v3 * x3;
+            for (; t + 8 <= cnt; t += 8) {
+                double x[8], w[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    x[u] = xc[(int64_t)__shfl(myc, t + u) * k];
+                    w[u] = __shfl(myv, t + u);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    s0 += w[u] * x[u];
+                    s1 += w[u + 1] * x[u + 1];
+                }
             }
-            for (; t < cnt; t++) s += __shfl(myv, t) * xc[(int64_t)__shfl(myc, t) * sx];
+            for (; t < cnt; t++) s0 += __shfl(myv, t) * xc[(int64_t)__shfl(myc, t) * k];
         }
         if (on) {
-            int64_t o = (int64_t)row * sx + (int64_t)c * sc;
-            R[o] = B ? B[o] - s : s;
+            int64_t o = (int64_t)row * k + c;
+            R[o] = B ? B[o] - (s0 + s1) : (s0 + s1);
         }
     }
 }

@@ -82,6 +82,8 @@ struct Plan {
     std::vector<int64_t> dscr_off;                // per front: element offset of its diagonal-block scratch
     int64_t dscr_elems = 0;
     std::vector<int32_t> all_fronts;
+    std::vector<int2> zero_tasks;                 // (front, first column) chunks of ZCOLS columns
+    int64_t lower_elems = 0;
     std::vector<int32_t> child_ptr, child_list;
     std::vector<int32_t> colof;                   // column of each stored entry
     std::vector<int32_t> slist;                   // fronts per level for the solves (fused first, then stepped)
@@ -239,6 +241,12 @@ struct Plan {
                 V.bwd.push_back({b, {off, (int64_t)sbwd_tasks.size() - off}});
             }
         }
+        zero_tasks.clear();
+        lower_elems = 0;
+        for (int32_t s = 0; s < ns; s++) {
+            for (int32_t c0 = 0; c0 < mfront[s]; c0 += ZCOLS) zero_tasks.push_back(make_int2(s, c0));
+            lower_elems += (int64_t)mfront[s] * (mfront[s] + 1) / 2;
+        }
         colof.resize((size_t)S.nnz);
         for (int32_t j = 0; j < S.n; j++)
             for (int64_t p = S.colptr[j]; p < S.colptr[j + 1]; p++) colof[p] = j;
@@ -250,7 +258,7 @@ struct Layout {
     size_t fronts, W, Y, Xr, Rr, Br, vec, bad;
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof;
-    size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part;
+    size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -297,6 +305,7 @@ struct Layout {
         sbwd = seg(std::max<size_t>(1, P.sbwd_tasks.size()) * sizeof(int2));
         sasm = seg(std::max<size_t>(1, P.sasm_tasks.size()) * sizeof(int2));
         part = seg((size_t)kPartBlocks * k * 8 * 2);
+        ztasks = seg(std::max<size_t>(1, P.zero_tasks.size()) * sizeof(int2));
         dscr_off = seg(ns * 8);
         all_fronts = seg(ns * 4);
         total = o;
@@ -337,11 +346,36 @@ enum KClass { KC_FILL = 0, KC_SCATTER, KC_EXTEND_ADD, KC_PANEL, KC_PANEL_FP64DIA
 
 struct Prof {
     hipStream_t st;
+    bool levels = false;                 // time levels instead of kernel classes
+    std::vector<hipEvent_t> lev;         // begin/end per level
+    std::vector<double> lev_flops;
     std::vector<hipEvent_t> ev[KC_COUNT];
     double flops[KC_COUNT] = {0};
     double bytes[KC_COUNT] = {0};
+    int mark(std::vector<hipEvent_t> &v)
+    {
+        hipEvent_t a;
+        HIP_TRY(hipEventCreate(&a));
+        v.push_back(a);
+        HIP_TRY(hipEventRecord(a, st));
+        return WCS_OK;
+    }
+    int collect_levels(wcs_kernel_stat *out)
+    {
+        HIP_TRY(hipStreamSynchronize(st));
+        for (size_t h = 0; h + 1 < lev.size() + 1 && 2 * h + 1 < lev.size(); h++) {
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, lev[2 * h], lev[2 * h + 1]));
+            out[h].launches = 0;
+            out[h].ms = t;
+            out[h].flops = lev_flops[h];
+            out[h].bytes = 0;
+        }
+        return WCS_OK;
+    }
     int begin(int c)
     {
+        if (levels) return WCS_OK;
         hipEvent_t a;
         HIP_TRY(hipEventCreate(&a));
         ev[c].push_back(a);
@@ -350,6 +384,7 @@ struct Prof {
     }
     int end(int c)
     {
+        if (levels) return WCS_OK;
         hipEvent_t b;
         HIP_TRY(hipEventCreate(&b));
         ev[c].push_back(b);
@@ -377,6 +412,7 @@ struct Prof {
     {
         for (int c = 0; c < KC_COUNT; c++)
             for (hipEvent_t e : ev[c]) (void)hipEventDestroy(e);
+        for (hipEvent_t e : lev) (void)hipEventDestroy(e);
     }
 };
 
@@ -411,14 +447,15 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     int64_t nel = S.front_off.back();
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, f->at<int32_t>(Lo.bad), (int64_t)1, INT32_MAX);
     PROF_BEGIN(KC_FILL);
-    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(nel)), dim3(256), 0, st, fronts, nel, (T)0);
+    hipLaunchKernelGGL(k_zero_lower<T>, dim3((unsigned)std::min<int64_t>(P.zero_tasks.size(), 1 << 30)), dim3(256), 0,
+                       st, f->at<int2>(Lo.ztasks), f->at<int64_t>(Lo.front_off), f->at<int32_t>(Lo.mfront), fronts);
     PROF_END(KC_FILL);
     PROF_BEGIN(KC_SCATTER);
     hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(S.nnz)), dim3(256), 0, st, values, f->at<int64_t>(Lo.amap),
                        S.nnz, fronts);
     PROF_END(KC_SCATTER);
     if (prof) {
-        prof->bytes[KC_FILL] += (double)nel * esz;
+        prof->bytes[KC_FILL] += (double)P.lower_elems * esz;
         prof->bytes[KC_SCATTER] += (double)S.nnz * (8 + 8 + esz);
     }
     const int64_t *fo = f->at<int64_t>(Lo.front_off);
@@ -435,7 +472,18 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     const int64_t *dso = f->at<int64_t>(Lo.dscr_off);
     T *dscr = f->at<T>(Lo.dscr);
     T *dinv = f->at<T>(Lo.dinv);
-    for (const Level &L : P.levels) {
+    for (size_t h = 0; h < P.levels.size(); h++) {
+        const Level &L = P.levels[h];
+        if (prof && prof->levels) {
+            int r_ = prof->mark(prof->lev);
+            if (r_) return r_;
+            double fl = 0;
+            for (int64_t q = L.fl_off; q < L.fl_off + L.fl_cnt; q++) {
+                int32_t s = P.flist[q];
+                for (int32_t t = 0; t < P.pfront[s]; t++) fl += (double)(P.mfront[s] - t) * (P.mfront[s] - t);
+            }
+            prof->lev_flops.push_back(fl);
+        }
         for (auto &r : L.ea) {
             PROF_BEGIN(KC_EXTEND_ADD);
             hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)r.second), dim3(256), 0, st, ea + r.first, fo, mf,
@@ -472,6 +520,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                     for (int64_t q = op.off; q < op.off + op.cnt; q++)
                         if (P.pan_tasks[q].y == 0) prof->flops[c] += panel_flops(P, P.pan_tasks[q].x, op.ka);
             }
+        }
+        if (prof && prof->levels) {
+            int r_ = prof->mark(prof->lev);
+            if (r_) return r_;
         }
     }
     PROF_BEGIN(KC_FILL);
@@ -598,9 +650,9 @@ int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R
     const int64_t *rp = f->at<int64_t>(f->lay.csr_ptr);
     const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
     const double *v = f->at<double>(f->lay.csr_val);
-    if (k >= 8 && sc == 1) {
+    if (k >= 8 && sx == k && sc == 1) {
         int nrb = (n + 3) / 4, per = (nrb + 7) / 8;
-        hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)(8 * per)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R, sx, sc);
+        hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)(8 * per)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R);
     } else {
         hipLaunchKernelGGL(k_spmv_narrow, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R,
                            sx, sc);
@@ -781,6 +833,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.sbelow, P.sbelow_tasks, st);
     rc = rc ? rc : upload(f, L.sbwd, P.sbwd_tasks, st);
     rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
+    rc = rc ? rc : upload(f, L.ztasks, P.zero_tasks, st);
     if (rc == WCS_OK) {
         hipError_t e = hipStreamSynchronize(st);   // host vectors are pageable: finish the copies
         if (e != hipSuccess) {
@@ -837,6 +890,21 @@ int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col)
     return WCS_OK;
 }
 
+int wcs_factor_profile_levels(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *levels)
+{
+    if (!f || !values_dev || !levels) { set_error("invalid argument to wcs_factor_profile_levels"); return WCS_EINVAL; }
+    hipStream_t st = (hipStream_t)stream;
+    Prof prof;
+    prof.st = st;
+    prof.levels = true;
+    int rc = f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st, &prof)
+                                 : launch_factor<float>(f, values_dev, st, &prof);
+    if (rc) return rc;
+    f->have_values = true;
+    f->csr_values_from = nullptr;
+    return prof.collect_levels(levels);
+}
+
 void wcs_factor_free(wcs_factor f) { delete f; }
 
 int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t *Li, double *Lx, wcs_stream stream)
@@ -862,7 +930,7 @@ int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t
         int32_t m = S.m_of(s), t = j - S.sptr[s];
         int32_t cnt = m - t;
         buf.resize((size_t)cnt * esz);
-        size_t off = f->lay.fronts + ((size_t)S.front_off[s] + (size_t)t * m + t) * esz;
+        size_t off = f->lay.fronts + ((size_t)S.front_off[s] + (size_t)t * front_ld_host(m) + t) * esz;
         HIP_TRY(hipMemcpy(buf.data(), f->ws + off, (size_t)cnt * esz, hipMemcpyDeviceToHost));
         int64_t o = Lp[j - j0];
         for (int32_t r = 0; r < cnt; r++) {

@@ -86,7 +86,7 @@ __device__ void blk_mfma(T (*Ds)[SB + 1], T (*Ss)[64], T (*Zs)[64])
 
 // rows [r0, r1) of w:  w[r][c0 + n] -= sum_j L(r, kb + j) Zs[j][n]; waves take 64-row slabs
 template <typename T>
-__device__ void fwd_rows_mfma(const T *__restrict__ L, int m, int kb, int nbk, T *__restrict__ w, int k, int c0,
+__device__ void fwd_rows_mfma(const T *__restrict__ L, int ld, int kb, int nbk, T *__restrict__ w, int k, int c0,
                               int r0, int r1, T (*Zs)[64])
 {
     typedef typename Mfma<T>::V V;
@@ -107,7 +107,7 @@ __device__ void fwd_rows_mfma(const T *__restrict__ L, int m, int kb, int nbk, T
 #pragma unroll
             for (int rb = 0; rb < 4; rb++) {
                 int r = s0 + rb * 16 + ln;
-                av[ks][rb] = (r < r1 && j < nbk) ? L[(int64_t)(kb + j) * m + r] : (T)0;
+                av[ks][rb] = (r < r1 && j < nbk) ? L[(int64_t)(kb + j) * ld + r] : (T)0;
             }
         }
 #pragma unroll
@@ -139,7 +139,7 @@ __device__ void fwd_rows_mfma(const T *__restrict__ L, int m, int kb, int nbk, T
 // v[c][c0 + n] -= sum_{r in [r0, r1)} L(r, a + c) X[r][n]  (c < na, n < 64);
 // wave w owns output rows c in [16w, 16w+16)
 template <typename T, typename XR>
-__device__ void bwd_cols_mfma(const T *__restrict__ L, int m, int a, int na, int r0, int r1, XR xrow, int k, int c0,
+__device__ void bwd_cols_mfma(const T *__restrict__ L, int ld, int a, int na, int r0, int r1, XR xrow, int k, int c0,
                               T *__restrict__ v, T (*Ls)[SB + 1], T (*Xs)[64])
 {
     typedef typename Mfma<T>::V V;
@@ -158,7 +158,7 @@ __device__ void bwd_cols_mfma(const T *__restrict__ L, int m, int a, int na, int
         __syncthreads();
         for (int i = tid; i < SB * SB; i += blockDim.x) {
             int cc = i / SB, rr = i % SB;
-            Ls[cc][rr] = (cc < na && rr < nr) ? L[(int64_t)(a + cc) * m + rb + rr] : (T)0;
+            Ls[cc][rr] = (cc < na && rr < nr) ? L[(int64_t)(a + cc) * ld + rb + rr] : (T)0;
         }
         for (int i = tid; i < SB * 64; i += blockDim.x) {
             int rr = i / 64, cc = i % 64;
@@ -218,7 +218,7 @@ __device__ void block_apply(const T *__restrict__ Dinv, const T *__restrict__ sr
 
 // rows [r0, r1) of w:  w[r][c] -= sum_j L(r, kb + j) Zs[j][c], one thread per row
 template <typename T, int KT>
-__device__ void fwd_rows(const T *__restrict__ L, int m, int kb, int nbk, T *__restrict__ w, int k, int c0, int r0,
+__device__ void fwd_rows(const T *__restrict__ L, int ld, int kb, int nbk, T *__restrict__ w, int k, int c0, int r0,
                          int r1, T (*Zs)[KT])
 {
     for (int r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
@@ -226,7 +226,7 @@ __device__ void fwd_rows(const T *__restrict__ L, int m, int kb, int nbk, T *__r
 #pragma unroll
         for (int c = 0; c < KT; c++) acc[c] = 0;
         for (int j = 0; j < nbk; j++) {
-            T l = L[(int64_t)(kb + j) * m + r];
+            T l = L[(int64_t)(kb + j) * ld + r];
 #pragma unroll
             for (int c = 0; c < KT; c++) acc[c] += l * Zs[j][c];
         }
@@ -241,7 +241,7 @@ __device__ void fwd_rows(const T *__restrict__ L, int m, int kb, int nbk, T *__r
 // front; X rows come from xrow(r) (a row pointer with stride k).  Thread
 // (c = tid % 64, g = tid / 64) owns columns cc = g, g + 4, ...
 template <typename T, int KT, typename XR>
-__device__ void bwd_cols(const T *__restrict__ L, int m, int a, int na, int r0, int r1, XR xrow, int k, int c0,
+__device__ void bwd_cols(const T *__restrict__ L, int ld, int a, int na, int r0, int r1, XR xrow, int k, int c0,
                          T *__restrict__ v, T (*Ls)[SB + 1], T (*Xs)[KT])
 {
     int tid = threadIdx.x, c = tid % SB, g = tid / SB;
@@ -258,7 +258,7 @@ __device__ void bwd_cols(const T *__restrict__ L, int m, int a, int na, int r0, 
         __syncthreads();
         for (int i = tid; i < SB * SB; i += blockDim.x) {
             int cc = i / SB, rr = i % SB;
-            Ls[cc][rr] = (cc < na && rr < nr) ? L[(int64_t)(a + cc) * m + rb + rr] : (T)0;
+            Ls[cc][rr] = (cc < na && rr < nr) ? L[(int64_t)(a + cc) * ld + rb + rr] : (T)0;
         }
         for (int i = tid; i < SB * KT; i += blockDim.x) {
             int rr = i / KT, cc = i % KT;
@@ -287,19 +287,19 @@ __device__ void bwd_cols(const T *__restrict__ L, int m, int a, int na, int r0, 
 }
 
 template <typename T, int KT>
-__device__ __forceinline__ void fwd_rows_any(const T *L, int m, int kb, int nbk, T *w, int k, int c0, int r0, int r1,
+__device__ __forceinline__ void fwd_rows_any(const T *L, int ld, int kb, int nbk, T *w, int k, int c0, int r0, int r1,
                                              T (*Zs)[KT])
 {
-    if constexpr (KT == 64) fwd_rows_mfma<T>(L, m, kb, nbk, w, k, c0, r0, r1, Zs);
-    else fwd_rows<T, KT>(L, m, kb, nbk, w, k, c0, r0, r1, Zs);
+    if constexpr (KT == 64) fwd_rows_mfma<T>(L, ld, kb, nbk, w, k, c0, r0, r1, Zs);
+    else fwd_rows<T, KT>(L, ld, kb, nbk, w, k, c0, r0, r1, Zs);
 }
 
 template <typename T, int KT, typename XR>
-__device__ __forceinline__ void bwd_cols_any(const T *L, int m, int a, int na, int r0, int r1, XR xrow, int k, int c0,
+__device__ __forceinline__ void bwd_cols_any(const T *L, int ld, int a, int na, int r0, int r1, XR xrow, int k, int c0,
                                              T *v, T (*Ls)[SB + 1], T (*Xs)[KT])
 {
-    if constexpr (KT == 64) bwd_cols_mfma<T>(L, m, a, na, r0, r1, xrow, k, c0, v, Ls, Xs);
-    else bwd_cols<T, KT>(L, m, a, na, r0, r1, xrow, k, c0, v, Ls, Xs);
+    if constexpr (KT == 64) bwd_cols_mfma<T>(L, ld, a, na, r0, r1, xrow, k, c0, v, Ls, Xs);
+    else bwd_cols<T, KT>(L, ld, a, na, r0, r1, xrow, k, c0, v, Ls, Xs);
 }
 
 template <typename T, int KT> struct SolveLds {
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(THREADS) void k_fwd_fused(const int32_t *__restrict
                 int r = i / KT, c = i % KT;
                 if (c0 + c < k) a.Y[(int64_t)(f0 + kb + r) * k + c0 + c] = sh.Zs[r][c];
             }
-            fwd_rows_any<T, KT>(L, m, kb, nbk, w, k, c0, kb + nbk, m, sh.Zs);
+            fwd_rows_any<T, KT>(L, front_ld(m), kb, nbk, w, k, c0, kb + nbk, m, sh.Zs);
         }
     }
 }
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(THREADS) void k_fwd_step(const int2 *__restrict__ t
                 int r = i / KT, c = i % KT;
                 if (c0 + c < k) a.Y[(int64_t)(f0 + kb + r) * k + c0 + c] = sh.Zs[r][c];
             }
-        if (r0 < r1) fwd_rows_any<T, KT>(L, m, kb, nbk, w, k, c0, r0, r1, sh.Zs);
+        if (r0 < r1) fwd_rows_any<T, KT>(L, front_ld(m), kb, nbk, w, k, c0, r0, r1, sh.Zs);
     }
 }
 
@@ -419,7 +419,8 @@ __device__ void bwd_below(const SolveArgs<T> &a, int f, int ab, T (*Ls)[SB + 1],
     const int32_t *rw = a.rows + a.rptr[f];
     const T *Y = a.Y;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
-    for (int c0 = 0; c0 < k; c0 += KT) bwd_cols_any<T, KT>(L, m, ab, na, p, m, xrow, k, c0, w + (int64_t)ab * k, Ls, Xs);
+    for (int c0 = 0; c0 < k; c0 += KT)
+        bwd_cols_any<T, KT>(L, front_ld(m), ab, na, p, m, xrow, k, c0, w + (int64_t)ab * k, Ls, Xs);
 }
 
 template <typename T, int KT>
@@ -447,7 +448,7 @@ __global__ __launch_bounds__(THREADS) void k_bwd_fused(const int32_t *__restrict
             for (int ab = 0; ab < kb; ab += SB) {
                 T(*Zs)[KT] = sh.Zs;
                 auto xrow = [&](int r) { return &Zs[r - kb][0] - c0; };
-                bwd_cols_any<T, KT>(L, a.mfront[f], ab, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)ab * k, sh.Ls,
+                bwd_cols_any<T, KT>(L, front_ld(a.mfront[f]), ab, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)ab * k, sh.Ls,
                                     sh.Ss);
             }
         }
@@ -487,7 +488,7 @@ __global__ __launch_bounds__(THREADS) void k_bwd_step(const int2 *__restrict__ t
         } else {
             T(*Zs)[KT] = sh.Zs;
             auto xrow = [&](int r) { return &Zs[r - kb][0] - c0; };
-            bwd_cols_any<T, KT>(L, a.mfront[f], t.y * SB, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)t.y * SB * k,
+            bwd_cols_any<T, KT>(L, front_ld(a.mfront[f]), t.y * SB, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)t.y * SB * k,
                                 sh.Ls, sh.Ss);
         }
     }

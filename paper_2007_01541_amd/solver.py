@@ -154,6 +154,15 @@ class Factor:
         return {nm: {"launches": st.launches, "ms": st.ms, "flops": st.flops, "bytes": st.bytes}
                 for nm, st in zip(capi.KERNEL_CLASSES, stats)}
 
+    def profile_levels(self, values, stream=None) -> list:
+        """One factorization timed per assembly-tree level: [{ms, flops}] from the leaves up."""
+        nl = self.sym.info["nlevels"]
+        stats = (capi.KernelStat * nl)()
+        self.values = values
+        check(lib().wcs_factor_profile_levels(self.handle, _dptr(values), _stream_ptr(stream), stats),
+              "wcs_factor_profile_levels")
+        return [{"ms": st.ms, "flops": st.flops} for st in stats]
+
     def pivot_check(self, stream=None) -> int:
         bad = C.c_int32(-1)
         rc = lib().wcs_factor_check(self.handle, _stream_ptr(stream), C.byref(bad))
