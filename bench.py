@@ -56,18 +56,29 @@ def cpu_baseline(m, perm, target_seconds: float) -> dict:
     parent, cc, nnzL, flops = oracle.symbolic(n, m["colptr"], m["rowind"], perm)
     Lp, Li = oracle.pattern(n, m["colptr"], m["rowind"], perm, parent, cc)
     log(f"oracle symbolic+pattern {time.perf_counter() - t0:.1f}s")
-    # first a short calibration, then a sample sized for the target time
+    # first a short calibration, then a sample sized for the target time from
+    # the flops the oracle actually performs on a leading block of columns
     cum = np.cumsum(cc.astype(np.float64) ** 2)
-    k_cal = int(np.searchsorted(cum, 2e9)) + 1
+    k_cal = min(int(np.searchsorted(cum, 2e9)) + 1, n)
     t0 = time.perf_counter()
-    oracle.factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp, Li, ncols=min(k_cal, n))
+    oracle.factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp, Li, ncols=k_cal)
     t_cal = time.perf_counter() - t0
-    rate = sample_flops(Lp, Li, min(k_cal, n)) / max(t_cal, 1e-3)
-    k = int(np.searchsorted(cum, rate * target_seconds)) + 1
-    k = min(max(k, k_cal), n)
-    t0 = time.perf_counter()
-    oracle.factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp, Li, ncols=k)
-    t = time.perf_counter() - t0
+    k, t = k_cal, t_cal
+    for _ in range(3):                            # re-size from the last measured rate until the sample is long enough
+        if t >= 0.6 * target_seconds or k == n:
+            break
+        want = sample_flops(Lp, Li, k) / max(t, 1e-3) * target_seconds
+        lo, hi = k, n
+        while lo < hi:                            # smallest k whose sample reaches the target flops
+            mid = (lo + hi) // 2
+            if sample_flops(Lp, Li, mid) >= want:
+                hi = mid
+            else:
+                lo = mid + 1
+        k = lo
+        t0 = time.perf_counter()
+        oracle.factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp, Li, ncols=k)
+        t = time.perf_counter() - t0
     fl = sample_flops(Lp, Li, k)
     log(f"oracle sample: {k} leading pivot columns, {fl / 1e9:.1f} GFLOP in {t:.1f}s")
     return {"value": fl / t / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
@@ -84,7 +95,7 @@ def main() -> int:
     ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tol", type=float, default=1e-10)
     args = ap.parse_args()
     if args.gpus != 1:

@@ -98,8 +98,9 @@ typedef struct {
     int32_t max_front;          /* largest front order m */
     int32_t nsep_nodes;         /* nodes of the separator tree */
     int32_t npeeled;            /* dense vertices moved into the root separator */
-    int64_t front_elems;        /* sum over fronts of m^2 (front storage, elements) */
+    int64_t front_elems;        /* sum over fronts of ld*m, ld = m rounded up to 8 (front storage, elements) */
     int64_t nnz_l_padded;       /* entries of L as stored by the fronts (explicit zeros included) */
+    int32_t nseg;               /* independent diagonal blocks: 1, or the instances of a batch */
 } wcs_symbolic_info_t;
 
 typedef struct {
@@ -146,6 +147,27 @@ int wcs_symbolic_export(wcs_symbolic sym, int32_t *perm, int32_t *parent, int32_
  */
 int wcs_symbolic_fronts(wcs_symbolic sym, int32_t *relaxed_ptr, int32_t *front_order);
 
+/*
+ * Batch of independent systems (many uneven instances at once).  Combines the
+ * analyses parts[0..count-1] (each from wcs_analyze, unchanged and still owned
+ * by the caller) into one handle for the block-diagonal matrix
+ * diag(A_0, ..., A_{count-1}): instance b occupies the unknowns
+ * [seg_ptr[b], seg_ptr[b+1]) in both the original and the pivot order, its
+ * stored entries follow those of instance b-1 (values of the batch = the
+ * instances' value arrays concatenated in order, rows shifted by seg_ptr[b]),
+ * and right-hand sides stack the instances' rows.  The assembly forest is the
+ * union of the instances' trees, so a factorization, solve or refinement of
+ * the batch handle runs the fronts of equal tree height of every instance in
+ * the same launches: the leaf fronts of all instances together first, then
+ * each level above across all instances.  Each instance's factor is exactly
+ * the one its own handle would give.  Refinement tests the tolerance per
+ * instance and column (wcs_factor_residuals).  Host only; *out owns a new
+ * handle independent of the parts.
+ */
+int wcs_symbolic_batch(int32_t count, const wcs_symbolic *parts, wcs_symbolic *out);
+/* seg_ptr[nseg+1]: first unknown of every instance (nseg from wcs_symbolic_info; 1 for a single matrix). */
+int wcs_symbolic_segments(wcs_symbolic sym, int32_t *seg_ptr);
+
 void wcs_symbolic_free(wcs_symbolic sym);
 
 /*
@@ -172,6 +194,39 @@ int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream
 /* Waits for the stream; *bad_col = first failing pivot or -1; returns WCS_ENOTSPD if one failed. */
 int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col);
 void wcs_factor_free(wcs_factor f);
+/*
+ * Relative residuals ||b - A x||_2 / ||b||_2 of the last wcs_solve_refined on
+ * this factor, per instance and column: rel[b * nrhs + c] for instance b of
+ * nseg (nseg = 1 for a single matrix).  count = capacity of rel (>= nseg*nrhs).
+ * WCS_ESTATE if no refinement has run.  Host memory; synchronous.
+ */
+int wcs_factor_residuals(wcs_factor f, double *rel, int64_t count);
+
+/*
+ * Replay mode.  With enable != 0, wcs_factor_numeric records its whole launch
+ * sequence into a HIP graph the first time it runs with a given values_dev
+ * pointer and replays that graph afterwards (a different pointer records
+ * again); the triangular sweeps of wcs_solve and wcs_solve_refined are
+ * recorded once per (part, nrhs) the same way.  The recorded sequences hold
+ * kernel launches only.  Recording needs a created stream: calls on the NULL
+ * stream run their launches directly.  enable = 0 drops the recorded graphs.
+ * Host only (the recorded graph is replayed on the call's stream).
+ */
+int wcs_factor_use_graphs(wcs_factor f, int enable);
+
+/*
+ * Autotuner for the trailing-update tile shape.  Factors values_dev (which
+ * leaves a valid factor, as wcs_factor_numeric does) four times on the
+ * stream: a warm-up and a timed run with 128 x 128 tiles on every level, the
+ * same with 64 x 64 tiles, timing each level of the assembly tree with HIP
+ * events; then keeps, per level, the faster tile.  Synchronous.  tiles
+ * (nlevels entries, may be NULL) receives the choice per level, ms (2
+ * entries, may be NULL) the summed level times with 128 x 128 tiles only and
+ * with the chosen tiles.  Drops a recorded factorization graph.
+ */
+int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *tiles, double *ms);
+/* Sets the update tile per level (nlevels entries, each 128 or 64), e.g. from an earlier autotune. */
+int wcs_factor_set_tiles(wcs_factor f, const int32_t *tiles);
 
 /*
  * Diagnostic: performs one numeric factorization (as wcs_factor_numeric with

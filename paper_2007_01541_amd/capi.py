@@ -40,6 +40,7 @@ class SymbolicInfo(C.Structure):
         ("npeeled", c_i32),
         ("front_elems", c_i64),
         ("nnz_l_padded", c_i64),
+        ("nseg", c_i32),
     ]
 
 
@@ -62,12 +63,18 @@ SIGNATURES = [
     ("wcs_symbolic_info", C.c_int, [c_p, C.POINTER(SymbolicInfo)]),
     ("wcs_symbolic_export", C.c_int, [c_p, c_p, c_p, c_p, c_p, c_p]),
     ("wcs_symbolic_fronts", C.c_int, [c_p, c_p, c_p]),
+    ("wcs_symbolic_batch", C.c_int, [c_i32, c_p, C.POINTER(c_p)]),
+    ("wcs_symbolic_segments", C.c_int, [c_p, c_p]),
     ("wcs_symbolic_free", None, [c_p]),
     ("wcs_workspace_size", C.c_int, [c_p, C.c_int, c_i32, C.POINTER(C.c_size_t)]),
     ("wcs_factor_create", C.c_int, [c_p, C.c_int, c_i32, c_p, C.c_size_t, c_p, C.POINTER(c_p)]),
     ("wcs_factor_numeric", C.c_int, [c_p, c_p, c_p, C.POINTER(c_i32)]),
     ("wcs_factor_check", C.c_int, [c_p, c_p, C.POINTER(c_i32)]),
     ("wcs_factor_free", None, [c_p]),
+    ("wcs_factor_residuals", C.c_int, [c_p, c_p, c_i64]),
+    ("wcs_factor_use_graphs", C.c_int, [c_p, C.c_int]),
+    ("wcs_factor_autotune", C.c_int, [c_p, c_p, c_p, c_p, c_p]),
+    ("wcs_factor_set_tiles", C.c_int, [c_p, c_p]),
     ("wcs_factor_profile", C.c_int, [c_p, c_p, c_p, c_p]),
     ("wcs_factor_profile_levels", C.c_int, [c_p, c_p, c_p, c_p]),
     ("wcs_factor_export", C.c_int, [c_p, c_i32, c_i32, c_p, c_p, c_p, c_p]),

@@ -687,6 +687,84 @@ int analyze(int32_t n, const int64_t *colptr, const int32_t *rowind, const wcs_a
             }
         }
     }
+    S.seg_ptr = {0, n};
+    return WCS_OK;
+}
+
+// Block-diagonal union: the matrix diag(A_0, ..., A_{count-1}) ordered block by
+// block, each block with its own ordering.  Its elimination tree is the forest
+// of the parts' trees, so every symbolic quantity is the concatenation of the
+// parts' with indices shifted; the level schedule then runs the fronts of equal
+// height of all parts together.
+int combine(int32_t count, const Symbolic *const *parts, Symbolic &S)
+{
+    if (count <= 0) { set_error("batch needs at least one part"); return WCS_EINVAL; }
+    int64_t n_tot = 0;
+    for (int32_t b = 0; b < count; b++) {
+        if (!parts[b]) { set_error("null part in batch"); return WCS_EINVAL; }
+        n_tot += parts[b]->n;
+    }
+    if (n_tot > INT32_MAX) { set_error("batch too large for 32-bit indices"); return WCS_EINVAL; }
+    S = Symbolic();
+    S.n = (int32_t)n_tot;
+    S.colptr.push_back(0);
+    S.fund_ptr.push_back(0);
+    S.sptr.push_back(0);
+    S.rptr.push_back(0);
+    S.front_off.push_back(0);
+    S.csr_ptr.push_back(0);
+    S.seg_ptr.push_back(0);
+    int32_t noff = 0, soff = 0, toff = 0;
+    int64_t zoff = 0, roff = 0, foff = 0, coff = 0;
+    auto shift = [](std::vector<int32_t> &dst, const std::vector<int32_t> &src, int32_t d, bool keep_neg) {
+        for (int32_t v : src) dst.push_back(keep_neg && v < 0 ? v : v + d);
+    };
+    for (int32_t b = 0; b < count; b++) {
+        const Symbolic &P = *parts[b];
+        for (int32_t j = 0; j < P.n; j++) S.colptr.push_back(P.colptr[j + 1] + zoff);
+        shift(S.rowind, P.rowind, noff, false);
+        shift(S.perm, P.perm, noff, false);
+        shift(S.iperm, P.iperm, noff, false);
+        for (size_t q = 0; q < P.sep_tree.size(); q += 6) {
+            const int32_t *nd = &P.sep_tree[q];
+            S.sep_tree.push_back(nd[0] + noff);
+            S.sep_tree.push_back(nd[1] < 0 ? -1 : nd[1] + noff);
+            S.sep_tree.push_back(nd[2] + noff);
+            S.sep_tree.push_back(nd[3] + noff);
+            S.sep_tree.push_back(nd[4] < 0 ? -1 : nd[4] + toff);
+            S.sep_tree.push_back(nd[5] < 0 ? -1 : nd[5] + toff);
+        }
+        S.npeeled += P.npeeled;
+        shift(S.parent, P.parent, noff, true);
+        S.colcount.insert(S.colcount.end(), P.colcount.begin(), P.colcount.end());
+        for (size_t q = 1; q < P.fund_ptr.size(); q++) S.fund_ptr.push_back(P.fund_ptr[q] + noff);
+        S.nnz_l += P.nnz_l;
+        S.flops += P.flops;
+        S.flops_padded += P.flops_padded;
+        for (int32_t q = 1; q <= P.ns; q++) S.sptr.push_back(P.sptr[q] + noff);
+        shift(S.snode_of, P.snode_of, soff, false);
+        for (int32_t q = 1; q <= P.ns; q++) S.rptr.push_back(P.rptr[q] + roff);
+        shift(S.rows, P.rows, noff, false);
+        S.rel.insert(S.rel.end(), P.rel.begin(), P.rel.end());
+        shift(S.sparent, P.sparent, soff, true);
+        S.height.insert(S.height.end(), P.height.begin(), P.height.end());
+        S.nlevels = std::max(S.nlevels, P.nlevels);
+        for (int32_t q = 1; q <= P.ns; q++) S.front_off.push_back(P.front_off[q] + foff);
+        for (int64_t v : P.amap) S.amap.push_back(v + foff);
+        for (int32_t r = 0; r < P.n; r++) S.csr_ptr.push_back(P.csr_ptr[r + 1] + coff);
+        shift(S.csr_col, P.csr_col, noff, false);
+        for (int64_t v : P.csr_src) S.csr_src.push_back(v + zoff);
+        noff += P.n;
+        soff += P.ns;
+        toff += (int32_t)(P.sep_tree.size() / 6);
+        zoff += P.nnz;
+        roff += (int64_t)P.rows.size();
+        foff += P.front_off.back();
+        coff += P.csr_ptr.back();
+        S.seg_ptr.push_back(noff);
+    }
+    S.nnz = zoff;
+    S.ns = soff;
     return WCS_OK;
 }
 

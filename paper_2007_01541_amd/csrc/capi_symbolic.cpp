@@ -2,6 +2,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "internal.h"
 
@@ -81,6 +82,7 @@ int wcs_symbolic_info(wcs_symbolic sym, wcs_symbolic_info_t *info)
         pad += p * m - p * (p - 1) / 2;
     }
     info->nnz_l_padded = pad;
+    info->nseg = S.seg_ptr.size() >= 2 ? (int32_t)S.seg_ptr.size() - 1 : 1;
     return WCS_OK;
 }
 
@@ -105,6 +107,39 @@ int wcs_symbolic_fronts(wcs_symbolic sym, int32_t *relaxed_ptr, int32_t *front_o
     if (relaxed_ptr) std::memcpy(relaxed_ptr, S.sptr.data(), S.sptr.size() * sizeof(int32_t));
     if (front_order)
         for (int32_t s = 0; s < S.ns; s++) front_order[s] = S.m_of(s);
+    return WCS_OK;
+}
+
+int wcs_symbolic_batch(int32_t count, const wcs_symbolic *parts, wcs_symbolic *out)
+{
+    if (!out || !parts || count <= 0) { wcs::set_error("invalid argument to wcs_symbolic_batch"); return WCS_EINVAL; }
+    *out = nullptr;
+    wcs_symbolic h = new (std::nothrow) wcs_symbolic_s;
+    if (!h) return WCS_ENOMEM;
+    int rc;
+    try {
+        std::vector<const wcs::Symbolic *> ps((size_t)count);
+        for (int32_t b = 0; b < count; b++) ps[b] = parts[b] ? &parts[b]->s : nullptr;
+        rc = wcs::combine(count, ps.data(), h->s);
+    } catch (const std::bad_alloc &) {
+        wcs::set_error("host allocation failed in wcs_symbolic_batch");
+        rc = WCS_ENOMEM;
+    }
+    if (rc != WCS_OK) { delete h; return rc; }
+    *out = h;
+    return WCS_OK;
+}
+
+int wcs_symbolic_segments(wcs_symbolic sym, int32_t *seg_ptr)
+{
+    if (!sym || !seg_ptr) { wcs::set_error("null argument"); return WCS_EINVAL; }
+    const wcs::Symbolic &S = sym->s;
+    if (S.seg_ptr.size() >= 2)
+        std::memcpy(seg_ptr, S.seg_ptr.data(), S.seg_ptr.size() * sizeof(int32_t));
+    else {
+        seg_ptr[0] = 0;
+        seg_ptr[1] = S.n;
+    }
     return WCS_OK;
 }
 

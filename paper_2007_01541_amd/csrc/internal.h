@@ -52,11 +52,18 @@ struct Symbolic {
     std::vector<int32_t> csr_col;
     std::vector<int64_t> csr_src;
 
+    // independent diagonal blocks (instances of a batch): block b holds the
+    // unknowns [seg_ptr[b], seg_ptr[b+1]) in both the original and the pivot
+    // order; a single matrix has one block
+    std::vector<int32_t> seg_ptr;
+
     int32_t m_of(int32_t s) const { return (int32_t)(rptr[s + 1] - rptr[s]); }
     int32_t p_of(int32_t s) const { return sptr[s + 1] - sptr[s]; }
 };
 
 int analyze(int32_t n, const int64_t *colptr, const int32_t *rowind, const wcs_analyze_opts *opts,
             Symbolic &out);
+// block-diagonal union of independent analyses (one block per part, in order)
+int combine(int32_t count, const Symbolic *const *parts, Symbolic &out);
 
 }  // namespace wcs

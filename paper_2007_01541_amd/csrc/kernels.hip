@@ -366,9 +366,11 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
 // ---------------------------------------------------------------- trailing update
 // task = (front, i0, j0, jend): C = F[i0:i0+UT, j0:min(j0+UT, jend)] -= A B^T
 // on the lower part (row >= column), with A = F[i0:, ka:ka+K], B = F[j0:, ka:ka+K]
-// and K = min(kw, p - ka) for the front's p.  The workgroup's four waves
-// own 64 x 64 quarters (4 x 4 MFMA 16x16 blocks each); K advances in chunks
-// of KC staged through double-buffered LDS.
+// and K = min(kw, p - ka) for the front's p.  Tiles are TW x TW (128 or 64):
+// one wave per 64 x 64 quarter (4 x 4 MFMA 16x16 blocks each); K advances in
+// chunks of KC staged through double-buffered LDS.  The 64 x 64 variant gives
+// four times as many workgroups for the same front, which pays on mid-size
+// fronts; the autotuner picks the tile per level.
 constexpr int UT = 128;
 
 template <typename T> struct UpdCfg;
@@ -385,17 +387,18 @@ template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
 
-template <typename T>
-__global__ __launch_bounds__(THREADS) void k_update(const int4 *__restrict__ tasks, int ka, int kw,
+template <typename T, int TW>
+__global__ __launch_bounds__(TW * TW / 64) void k_update(const int4 *__restrict__ tasks, int ka, int kw,
                                                     const int64_t *__restrict__ front_off,
                                                     const int32_t *__restrict__ mfront,
                                                     const int32_t *__restrict__ pfront, T *__restrict__ fronts)
 {
     constexpr int KC = UpdCfg<T>::KC;
-    constexpr int LD = UT + (sizeof(T) == 4 ? 4 : 2);
+    constexpr int NTH = TW * TW / 64;          // one wave per 64 x 64 quarter
+    constexpr int LD = TW + (sizeof(T) == 4 ? 4 : 2);
     __shared__ __align__(16) T As[2][KC][LD];
     __shared__ __align__(16) T Bs[2][KC][LD];
-    constexpr int KSTEP = THREADS / UT;        // k rows covered by one pass of the block (2)
+    constexpr int KSTEP = NTH / TW;            // k rows covered by one pass of the block
     constexpr int PER = KC / KSTEP;            // elements of each operand per thread per chunk
     int4 t = tasks[blockIdx.x];
     int f = t.x, i0 = t.y, j0 = t.z, jend = t.w;
@@ -405,11 +408,11 @@ __global__ __launch_bounds__(THREADS) void k_update(const int4 *__restrict__ tas
     T *F = fronts + front_off[f];
     int tid = threadIdx.x;
     int wave = tid / 64, lane = tid % 64;
-    int wr = (wave / 2) * 64, wc = (wave % 2) * 64;
+    int wr = (wave / (TW / 64)) * 64, wc = (wave % (TW / 64)) * 64;
     int kq = lane / 16, ln = lane % 16;
     bool active = (i0 + wr + 63 >= j0 + wc) && (j0 + wc < jend) && (i0 + wr < m);
     // staging: thread loads tile row r for k = k_first + KSTEP*q
-    const int r = tid % UT, k_first = tid / UT;
+    const int r = tid % TW, k_first = tid / TW;
     const int rpos = frag_pos(r);
     const bool arow = i0 + r < m, brow = j0 + r < m;
     const T *pa = F0 + (int64_t)(ka + k_first) * ld + i0 + r;
@@ -679,11 +682,19 @@ __global__ void k_add_unscaled(const T *__restrict__ Y, int64_t total, int k, co
 // Column reductions of a row-major n x k block in two passes with a fixed
 // order (deterministic): part[b * k + c] over the rows of block b, then
 // out[c] over the blocks.  op 0: sum of squares, op 1: max |a|.
-__global__ void k_colred_part(const double *__restrict__ A, int n, int k, int op, double *__restrict__ part)
+// Column reductions of a row-major n x k array, per segment of rows: op 0 sum
+// of squares, op 1 max |a|.  seg_ptr (nseg + 1 row offsets) splits the rows
+// into independent blocks; null means one segment [0, n).  Each segment gets
+// gridDim.x / nseg blocks, each reducing a fixed contiguous row range; the
+// final pass adds the partials in block order, so the result is deterministic.
+__global__ void k_colred_part(const double *__restrict__ A, int n, int k, int op, const int32_t *__restrict__ seg_ptr,
+                              int nseg, double *__restrict__ part)
 {
     __shared__ double red[THREADS];
-    int nb = gridDim.x;
-    int64_t r0 = (int64_t)n * blockIdx.x / nb, r1 = (int64_t)n * (blockIdx.x + 1) / nb;
+    int bps = gridDim.x / nseg;
+    int sg = blockIdx.x / bps, sub = blockIdx.x % bps;
+    int64_t s0 = seg_ptr ? seg_ptr[sg] : 0, s1 = seg_ptr ? seg_ptr[sg + 1] : n;
+    int64_t r0 = s0 + (s1 - s0) * sub / bps, r1 = s0 + (s1 - s0) * (sub + 1) / bps;
     int kc = k < THREADS ? k : THREADS;
     int groups = THREADS / kc;
     for (int c0 = 0; c0 < k; c0 += kc) {
@@ -708,15 +719,17 @@ __global__ void k_colred_part(const double *__restrict__ A, int n, int k, int op
     }
 }
 
-__global__ void k_colred_final(const double *__restrict__ part, int nb, int k, int op, double *__restrict__ out)
+// out[sg * k + c] = reduction over the bps partials of segment sg (grid: one block per segment)
+__global__ void k_colred_final(const double *__restrict__ part, int bps, int k, int op, double *__restrict__ out)
 {
+    int sg = blockIdx.x;
     for (int c = threadIdx.x; c < k; c += blockDim.x) {
         double t = 0;
-        for (int b = 0; b < nb; b++) {
-            double x = part[(int64_t)b * k + c];
+        for (int b = 0; b < bps; b++) {
+            double x = part[((int64_t)sg * bps + b) * k + c];
             t = op == 0 ? t + x : fmax(t, x);
         }
-        out[c] = t;
+        out[(int64_t)sg * k + c] = t;
     }
 }
 

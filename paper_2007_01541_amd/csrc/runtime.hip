@@ -35,6 +35,9 @@ constexpr int32_t kFp64DiagMinCols = 1024;   // FP32 fronts with >= this many pi
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
+// independent diagonal blocks of the matrix (1 unless it is a batch)
+size_t nseg_of(const Symbolic &S) { return S.seg_ptr.size() >= 2 ? S.seg_ptr.size() - 1 : 1; }
+
 constexpr int32_t NBO = 256;   // outer block: trailing updates use K = NBO columns at once
 // fronts with more rows solve block by block over many workgroups (tuning knob WCS_SOLVE_STEP_ROWS)
 int32_t solve_step_min_rows()
@@ -53,7 +56,8 @@ enum OpKind { OP_PANEL = 0, OP_PANEL_FP64DIAG = 1, OP_UPDATE = 2 };
 struct Op {
     int32_t kind;
     int32_t ka, kw;      // panel: ka = k0; update: columns [ka, ka + min(kw, p - ka)) form K
-    int64_t off, cnt;
+    int64_t off, cnt;    // tasks (update: 128 x 128 tiles)
+    int64_t off64 = 0, cnt64 = 0;   // update: the same work as 64 x 64 tiles
 };
 struct SolveLevel {
     int64_t fused_off = 0, fused_cnt = 0;          // fronts solved by one workgroup each (in slist)
@@ -65,6 +69,7 @@ struct SolveLevel {
 };
 struct Level {
     SolveLevel sv;
+    int32_t upd_tile = UT;                         // update tile of this level (128 or 64; autotuned)
     std::vector<Op> ops;
     std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds (offset, count)
     int64_t fl_off = 0, fl_cnt = 0;                // fronts of this level in flist
@@ -150,10 +155,11 @@ struct Plan {
             }
             int32_t maxp = 0;
             for (int32_t s : fr) maxp = std::max(maxp, pfront[s]);
+            int32_t tw = UT;
             auto tiles = [&](int32_t s, int32_t clo, int32_t jend) {
                 int32_t m = mfront[s];
-                for (int32_t j0 = clo; j0 < jend; j0 += UT)
-                    for (int32_t i0 = j0; i0 < m; i0 += UT) upd_tasks.push_back(make_int4(s, i0, j0, jend));
+                for (int32_t j0 = clo; j0 < jend; j0 += tw)
+                    for (int32_t i0 = j0; i0 < m; i0 += tw) upd_tasks.push_back(make_int4(s, i0, j0, jend));
             };
             for (int32_t K0 = 0; K0 < maxp; K0 += NBO) {
                 for (int32_t k0 = K0; k0 < std::min(K0 + NBO, maxp); k0 += NB) {
@@ -169,25 +175,35 @@ struct Plan {
                         op.cnt = (int64_t)pan_tasks.size() - op.off;
                         if (op.cnt) L.ops.push_back(op);
                     }
-                    Op up{OP_UPDATE, k0, NB, (int64_t)upd_tasks.size(), 0};
-                    for (int32_t s : fr) {
-                        int32_t p = pfront[s];
-                        if (p <= k0) continue;
-                        int32_t nb = std::min(NB, p - k0);
-                        int32_t kend = K0 + std::min(NBO, p - K0);
-                        if (k0 + nb < kend) tiles(s, k0 + nb, kend);
+                    Op up{OP_UPDATE, k0, NB, 0, 0};
+                    for (int v = 0; v < 2; v++) {
+                        tw = v == 0 ? UT : 64;
+                        int64_t o = (int64_t)upd_tasks.size();
+                        for (int32_t s : fr) {
+                            int32_t p = pfront[s];
+                            if (p <= k0) continue;
+                            int32_t nb = std::min(NB, p - k0);
+                            int32_t kend = K0 + std::min(NBO, p - K0);
+                            if (k0 + nb < kend) tiles(s, k0 + nb, kend);
+                        }
+                        (v == 0 ? up.off : up.off64) = o;
+                        (v == 0 ? up.cnt : up.cnt64) = (int64_t)upd_tasks.size() - o;
                     }
-                    up.cnt = (int64_t)upd_tasks.size() - up.off;
                     if (up.cnt) L.ops.push_back(up);
                 }
-                Op up{OP_UPDATE, K0, NBO, (int64_t)upd_tasks.size(), 0};
-                for (int32_t s : fr) {
-                    int32_t p = pfront[s], m = mfront[s];
-                    if (p <= K0) continue;
-                    int32_t kend = K0 + std::min(NBO, p - K0);
-                    if (kend < m) tiles(s, kend, m);
+                Op up{OP_UPDATE, K0, NBO, 0, 0};
+                for (int v = 0; v < 2; v++) {
+                    tw = v == 0 ? UT : 64;
+                    int64_t o = (int64_t)upd_tasks.size();
+                    for (int32_t s : fr) {
+                        int32_t p = pfront[s], m = mfront[s];
+                        if (p <= K0) continue;
+                        int32_t kend = K0 + std::min(NBO, p - K0);
+                        if (kend < m) tiles(s, kend, m);
+                    }
+                    (v == 0 ? up.off : up.off64) = o;
+                    (v == 0 ? up.cnt : up.cnt64) = (int64_t)upd_tasks.size() - o;
                 }
-                up.cnt = (int64_t)upd_tasks.size() - up.off;
                 if (up.cnt) L.ops.push_back(up);
             }
         }
@@ -257,7 +273,7 @@ struct Plan {
 struct Layout {
     size_t fronts, W, Y, Xr, Rr, Br, vec, bad;
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list;
-    size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof;
+    size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t total;
 
@@ -272,7 +288,8 @@ struct Layout {
         Xr = seg(n * k * 8);
         Rr = seg(n * k * 8);
         Br = seg(n * k * 8);
-        vec = seg((size_t)4 * k * 8 + 64);
+        size_t nseg = nseg_of(S);
+        vec = seg((2 * nseg * k + 2 * (size_t)k) * 8 + 64);
         bad = seg(64);
         front_off = seg((ns + 1) * 8);
         mfront = seg(ns * 4);
@@ -304,7 +321,8 @@ struct Layout {
         sbelow = seg(std::max<size_t>(1, P.sbelow_tasks.size()) * sizeof(int2));
         sbwd = seg(std::max<size_t>(1, P.sbwd_tasks.size()) * sizeof(int2));
         sasm = seg(std::max<size_t>(1, P.sasm_tasks.size()) * sizeof(int2));
-        part = seg((size_t)kPartBlocks * k * 8 * 2);
+        part = seg(std::max<size_t>(kPartBlocks, nseg) * k * 8 * 2);
+        segp = seg((nseg + 1) * 4);
         ztasks = seg(std::max<size_t>(1, P.zero_tasks.size()) * sizeof(int2));
         dscr_off = seg(ns * 8);
         all_fronts = seg(ns * 4);
@@ -333,6 +351,27 @@ struct wcs_factor_s {
     size_t bytes = 0;
     bool have_values = false;
     const double *csr_values_from = nullptr;   // values pointer the expanded CSR values were built from
+    std::vector<double> last_rel;              // last refinement residuals per (segment, column)
+
+    // replay of recorded launch sequences (wcs_factor_use_graphs)
+    bool graphs = false;
+    hipGraphExec_t fgraph = nullptr;           // numeric factorization, recorded for fgraph_values
+    const double *fgraph_values = nullptr;
+    struct SweepGraph {
+        int part, k;
+        hipGraphExec_t exec;
+    };
+    std::vector<SweepGraph> sgraphs;           // triangular sweeps per (part, nrhs)
+
+    void drop_graphs()
+    {
+        if (fgraph) (void)hipGraphExecDestroy(fgraph);
+        fgraph = nullptr;
+        fgraph_values = nullptr;
+        for (auto &g : sgraphs) (void)hipGraphExecDestroy(g.exec);
+        sgraphs.clear();
+    }
+    ~wcs_factor_s() { drop_graphs(); }
 
     template <typename P> P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
 };
@@ -426,13 +465,13 @@ double panel_flops(const Plan &P, int32_t s, int32_t k0)
     double below = P.mfront[s] - k0 - nb;
     return nb * nb * nb / 3.0 + below * nb * nb;
 }
-double update_flops(const Plan &P, const int4 &t, int32_t ka, int32_t kw)
+double update_flops(const Plan &P, const int4 &t, int32_t ka, int32_t kw, int32_t tw)
 {
     int32_t m = P.mfront[t.x], p = P.pfront[t.x];
     double K = std::min(kw, p - ka);
     double cnt = 0;
-    for (int32_t col = t.z; col < std::min(t.z + UT, t.w); col++)
-        cnt += std::max(0, std::min(t.y + UT, m) - std::max(t.y, col));
+    for (int32_t col = t.z; col < std::min(t.z + tw, t.w); col++)
+        cnt += std::max(0, std::min(t.y + tw, m) - std::max(t.y, col));
     return 2.0 * K * cnt;
 }
 
@@ -444,7 +483,6 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     const Symbolic &S = *f->S;
     const size_t esz = sizeof(T);
     T *fronts = f->at<T>(Lo.fronts);
-    int64_t nel = S.front_off.back();
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, f->at<int32_t>(Lo.bad), (int64_t)1, INT32_MAX);
     PROF_BEGIN(KC_FILL);
     hipLaunchKernelGGL(k_zero_lower<T>, dim3((unsigned)std::min<int64_t>(P.zero_tasks.size(), 1 << 30)), dim3(256), 0,
@@ -499,13 +537,19 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
         }
         for (const Op &op : L.ops) {
             if (op.kind == OP_UPDATE) {
+                bool small = L.upd_tile == 64;
+                int64_t off = small ? op.off64 : op.off, cnt = small ? op.cnt64 : op.cnt;
                 PROF_BEGIN(KC_UPDATE);
-                hipLaunchKernelGGL(k_update<T>, dim3((unsigned)op.cnt), dim3(THREADS), 0, st, upd + op.off, op.ka,
-                                   op.kw, fo, mf, pf, fronts);
+                if (small)
+                    hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, st, upd + off, op.ka,
+                                       op.kw, fo, mf, pf, fronts);
+                else
+                    hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, st, upd + off,
+                                       op.ka, op.kw, fo, mf, pf, fronts);
                 PROF_END(KC_UPDATE);
                 if (prof)
-                    for (int64_t q = op.off; q < op.off + op.cnt; q++)
-                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], op.ka, op.kw);
+                    for (int64_t q = off; q < off + cnt; q++)
+                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], op.ka, op.kw, L.upd_tile);
             } else {
                 int c = op.kind == OP_PANEL ? KC_PANEL : KC_PANEL_FP64DIAG;
                 PROF_BEGIN(c);
@@ -605,6 +649,48 @@ int launch_solve_internal(wcs_factor f, int part, int k, hipStream_t st)
     return launch_sweeps<T, 64>(f, part, k, st);
 }
 
+// Records the launches made by fn on st into an executable graph.  The
+// sequences recorded here are kernel launches only (no memset or copy nodes).
+template <typename Fn>
+int record(hipStream_t st, hipGraphExec_t *out, Fn &&fn)
+{
+    HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = fn();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc == WCS_OK && e != hipSuccess) {
+        set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        rc = WCS_EHIP;
+    }
+    if (rc == WCS_OK) {
+        e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            rc = WCS_EHIP;
+        }
+    }
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+}
+
+// The sweeps of one solve, replayed from a recorded graph when graphs are on
+// (a stream other than the legacy default stream is needed for recording).
+template <typename T>
+int run_sweeps(wcs_factor f, int part, int k, hipStream_t st)
+{
+    if (!f->graphs || st == nullptr) return launch_solve_internal<T>(f, part, k, st);
+    hipGraphExec_t ex = nullptr;
+    for (auto &g : f->sgraphs)
+        if (g.part == part && g.k == k) ex = g.exec;
+    if (!ex) {
+        int rc = record(st, &ex, [&] { return launch_solve_internal<T>(f, part, k, st); });
+        if (rc) return rc;
+        f->sgraphs.push_back({part, k, ex});
+    }
+    HIP_TRY(hipGraphLaunch(ex, st));
+    return WCS_OK;
+}
+
 template <typename T>
 int launch_solve(wcs_factor f, int part, int k, double *B, int64_t ld, hipStream_t st)
 {
@@ -618,7 +704,7 @@ int launch_solve(wcs_factor f, int part, int k, double *B, int64_t ld, hipStream
     else
         hipLaunchKernelGGL(k_perm_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Y,
                            (const double *)nullptr);
-    int rc = launch_solve_internal<T>(f, part, k, st);
+    int rc = run_sweeps<T>(f, part, k, st);
     if (rc) return rc;
     if (part == WCS_SOLVE_L)
         hipLaunchKernelGGL(k_rows_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, n, k, B, ld);
@@ -661,17 +747,24 @@ int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R
     return WCS_OK;
 }
 
-// out[c] = column reduction (op 0: sum of squares, op 1: max |a|) of row-major A
-void launch_colred(wcs_factor f, const double *A, int n, int k, int op, double *out, hipStream_t st)
+// out[c] (whole column) or out[sg * k + c] (per segment) = column reduction
+// (op 0: sum of squares, op 1: max |a|) of row-major n x k A
+void launch_colred(wcs_factor f, const double *A, int n, int k, int op, bool segmented, double *out, hipStream_t st)
 {
     double *part = f->at<double>(f->lay.part);
-    hipLaunchKernelGGL(k_colred_part, dim3(kPartBlocks), dim3(THREADS), 0, st, A, n, k, op, part);
-    hipLaunchKernelGGL(k_colred_final, dim3(1), dim3(256), 0, st, part, kPartBlocks, k, op, out);
+    int nseg = segmented ? (int)nseg_of(*f->S) : 1;
+    const int32_t *sp = segmented && nseg > 1 ? f->at<int32_t>(f->lay.segp) : nullptr;
+    int bps = std::max(1, kPartBlocks / nseg);
+    hipLaunchKernelGGL(k_colred_part, dim3((unsigned)(bps * nseg)), dim3(THREADS), 0, st, A, n, k, op, sp, nseg,
+                       part);
+    hipLaunchKernelGGL(k_colred_final, dim3((unsigned)nseg), dim3(256), 0, st, part, bps, k, op, out);
 }
 
 // Refinement in pivot order: Bp = P B, Xp = solve(Bp), then while any
 // column has ||Bp - C Xp|| > tol ||Bp||: Xp += solve(R s) / s with the
 // per-column scale s = 1 / max|R| (keeps R inside the FP32 range); X = P^T Xp.
+// For a batch the test is per instance and column (each block of the
+// block-diagonal matrix is its own system).
 template <typename T>
 int solve_refined(wcs_factor f, const double *values, int k, const double *B, double *X, int64_t ld, double tol,
                   int max_iter, wcs_ir_report *rep, hipStream_t st)
@@ -683,18 +776,22 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     double *Bp = f->at<double>(Lo.Br);      // row-major n x k, pivot order
     double *Xp = f->at<double>(Lo.Xr);
     double *Rp = f->at<double>(Lo.Rr);
-    double *vec = f->at<double>(Lo.vec);    // [0,k): |B|^2, [k,2k): |R|^2, [2k,3k): amax, [3k,4k): scale
+    const int nseg = (int)nseg_of(*f->S), nsk = nseg * k;
+    // vec: [0,nsk) |B|^2 and [nsk,2nsk) |R|^2 per (segment, column); then amax[k], scale[k]
+    double *vec = f->at<double>(Lo.vec);
+    double *amax = vec + 2 * nsk, *scale = amax + k;
     T *Y = f->at<T>(Lo.Y);
     const int32_t *perm = f->at<int32_t>(Lo.perm);
     int64_t nk = (int64_t)n * k;
     hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Bp);
-    launch_colred(f, Bp, n, k, 0, vec, st);
+    launch_colred(f, Bp, n, k, 0, true, vec, st);
     hipLaunchKernelGGL(k_cast_scaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Bp, nk, k, (const double *)nullptr, Y);
-    rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
+    rc = run_sweeps<T>(f, WCS_SOLVE_FULL, k, st);
     if (rc) return rc;
     hipLaunchKernelGGL(k_add_unscaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, nk, k, (const double *)nullptr, 0,
                        Xp);
-    std::vector<double> h((size_t)2 * k);
+    std::vector<double> h((size_t)2 * nsk);
+    f->last_rel.assign((size_t)nsk, -1.0);
     rep->iterations = 0;
     rep->raw_residual = -1;
     rep->final_residual = -1;
@@ -702,27 +799,28 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     for (int it = 0;; it++) {
         rc = launch_spmv(f, k, Xp, Bp, Rp, k, 1, st);
         if (rc) return rc;
-        launch_colred(f, Rp, n, k, 0, vec + k, st);
-        HIP_TRY(hipMemcpyAsync(h.data(), vec, sizeof(double) * 2 * k, hipMemcpyDeviceToHost, st));
+        launch_colred(f, Rp, n, k, 0, true, vec + nsk, st);
+        HIP_TRY(hipMemcpyAsync(h.data(), vec, sizeof(double) * 2 * nsk, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         double worst = 0;
-        for (int c = 0; c < k; c++) {
-            double bn = std::sqrt(h[c]), rn = std::sqrt(h[k + c]);
+        for (int c = 0; c < nsk; c++) {
+            double bn = std::sqrt(h[c]), rn = std::sqrt(h[nsk + c]);
             double rel = bn > 0 ? rn / bn : rn;
+            f->last_rel[c] = rel;
             if (!(rel <= worst)) worst = rel;   // NaN propagates as worst
         }
         if (it == 0) rep->raw_residual = worst;
         rep->final_residual = worst;
         if (worst <= tol) { status = WCS_OK; break; }
         if (it >= max_iter) break;
-        launch_colred(f, Rp, n, k, 1, vec + 2 * k, st);
-        hipLaunchKernelGGL(k_inv_scale, dim3(1), dim3(64 * ((k + 63) / 64)), 0, st, vec + 2 * k, k, vec + 3 * k);
+        launch_colred(f, Rp, n, k, 1, false, amax, st);
+        hipLaunchKernelGGL(k_inv_scale, dim3(1), dim3(64 * ((k + 63) / 64)), 0, st, amax, k, scale);
         hipLaunchKernelGGL(k_cast_scaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Rp, nk, k,
-                           (const double *)(vec + 3 * k), Y);
-        rc = launch_solve_internal<T>(f, WCS_SOLVE_FULL, k, st);
+                           (const double *)scale, Y);
+        rc = run_sweeps<T>(f, WCS_SOLVE_FULL, k, st);
         if (rc) return rc;
         hipLaunchKernelGGL(k_add_unscaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, nk, k,
-                           (const double *)(vec + 3 * k), 1, Xp);
+                           (const double *)scale, 1, Xp);
         rep->iterations = it + 1;
     }
     hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, Xp, perm, n, k, X, ld);
@@ -834,6 +932,8 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.sbwd, P.sbwd_tasks, st);
     rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
     rc = rc ? rc : upload(f, L.ztasks, P.zero_tasks, st);
+    std::vector<int32_t> segp = S.seg_ptr.size() >= 2 ? S.seg_ptr : std::vector<int32_t>{0, S.n};
+    rc = rc ? rc : upload(f, L.segp, segp, st);
     if (rc == WCS_OK) {
         hipError_t e = hipStreamSynchronize(st);   // host vectors are pageable: finish the copies
         if (e != hipSuccess) {
@@ -850,8 +950,26 @@ int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream
 {
     if (!f || !values_dev) { set_error("invalid argument to wcs_factor_numeric"); return WCS_EINVAL; }
     hipStream_t st = (hipStream_t)stream;
-    int rc = f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st, nullptr)
-                                 : launch_factor<float>(f, values_dev, st, nullptr);
+    int rc;
+    auto eager = [&] {
+        return f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st, nullptr)
+                                   : launch_factor<float>(f, values_dev, st, nullptr);
+    };
+    if (f->graphs && st != nullptr) {
+        if (f->fgraph && f->fgraph_values != values_dev) {
+            (void)hipGraphExecDestroy(f->fgraph);
+            f->fgraph = nullptr;
+        }
+        if (!f->fgraph) {
+            rc = record(st, &f->fgraph, eager);
+            if (rc) { f->fgraph = nullptr; return rc; }
+            f->fgraph_values = values_dev;
+        }
+        HIP_TRY(hipGraphLaunch(f->fgraph, st));
+        rc = WCS_OK;
+    } else {
+        rc = eager();
+    }
     if (rc) return rc;
     f->have_values = true;
     f->csr_values_from = nullptr;
@@ -906,6 +1024,95 @@ int wcs_factor_profile_levels(wcs_factor f, const double *values_dev, wcs_stream
 }
 
 void wcs_factor_free(wcs_factor f) { delete f; }
+
+int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *tiles, double *ms)
+{
+    if (!f || !values_dev) { set_error("invalid argument to wcs_factor_autotune"); return WCS_EINVAL; }
+    hipStream_t st = (hipStream_t)stream;
+    Plan &P = f->plan;
+    size_t H = P.levels.size();
+    auto timed = [&](std::vector<double> &lev_ms) -> int {
+        std::vector<wcs_kernel_stat> out(H);
+        Prof prof;
+        prof.st = st;
+        prof.levels = true;
+        int rc = f->prec == WCS_FP64 ? launch_factor<double>(f, values_dev, st, &prof)
+                                     : launch_factor<float>(f, values_dev, st, &prof);
+        if (rc) return rc;
+        rc = prof.collect_levels(out.data());
+        if (rc) return rc;
+        lev_ms.resize(H);
+        for (size_t h = 0; h < H; h++) lev_ms[h] = out[h].ms;
+        return WCS_OK;
+    };
+    // each candidate tile on every level: a warm-up factorization, then a timed one
+    std::vector<double> t[2];
+    const int32_t cand[2] = {UT, 64};
+    for (int v = 0; v < 2; v++) {
+        for (Level &L : P.levels) L.upd_tile = cand[v];
+        std::vector<double> warm;
+        int rc = timed(warm);
+        if (!rc) rc = timed(t[v]);
+        if (rc) {
+            for (Level &L : P.levels) L.upd_tile = UT;
+            return rc;
+        }
+    }
+    double before = 0, after = 0;
+    for (size_t h = 0; h < H; h++) {
+        int best = t[1][h] < t[0][h] ? 1 : 0;
+        P.levels[h].upd_tile = cand[best];
+        before += t[0][h];
+        after += t[best][h];
+        if (tiles) tiles[h] = cand[best];
+    }
+    if (ms) {
+        ms[0] = before;
+        ms[1] = after;
+    }
+    if (f->fgraph) {   // recorded launches used the old tiles
+        (void)hipGraphExecDestroy(f->fgraph);
+        f->fgraph = nullptr;
+        f->fgraph_values = nullptr;
+    }
+    f->have_values = true;
+    f->csr_values_from = nullptr;
+    return WCS_OK;
+}
+
+int wcs_factor_set_tiles(wcs_factor f, const int32_t *tiles)
+{
+    if (!f || !tiles) { set_error("invalid argument to wcs_factor_set_tiles"); return WCS_EINVAL; }
+    for (size_t h = 0; h < f->plan.levels.size(); h++)
+        if (tiles[h] != UT && tiles[h] != 64) { set_error("update tile must be 128 or 64"); return WCS_EINVAL; }
+    for (size_t h = 0; h < f->plan.levels.size(); h++) f->plan.levels[h].upd_tile = tiles[h];
+    if (f->fgraph) {
+        (void)hipGraphExecDestroy(f->fgraph);
+        f->fgraph = nullptr;
+        f->fgraph_values = nullptr;
+    }
+    return WCS_OK;
+}
+
+int wcs_factor_use_graphs(wcs_factor f, int enable)
+{
+    if (!f) { set_error("null factor"); return WCS_EINVAL; }
+    if (!enable) f->drop_graphs();
+    f->graphs = enable != 0;
+    return WCS_OK;
+}
+
+int wcs_factor_residuals(wcs_factor f, double *rel, int64_t count)
+{
+    if (!f || !rel || count < 0) { set_error("invalid argument to wcs_factor_residuals"); return WCS_EINVAL; }
+    if (f->last_rel.empty()) { set_error("no refinement has run on this factor"); return WCS_ESTATE; }
+    if (count < (int64_t)f->last_rel.size()) {
+        set_error("residual buffer too small: need " + std::to_string(f->last_rel.size()));
+        return WCS_EINVAL;
+    }
+    std::copy(f->last_rel.begin(), f->last_rel.end(), rel);
+    return WCS_OK;
+}
 
 int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t *Li, double *Lx, wcs_stream stream)
 {

@@ -67,6 +67,27 @@ class Symbolic:
         self.handle = h
         self.n = int(n)
 
+    @classmethod
+    def batch(cls, parts) -> "Symbolic":
+        """Block-diagonal batch of independent analyses (wcs_symbolic_batch):
+        instance b owns the unknowns seg_ptr[b]:seg_ptr[b+1]; its values follow
+        those of instance b-1 in the batch's value array."""
+        parts = list(parts)
+        arr = (C.c_void_p * len(parts))(*[p.handle.value for p in parts])
+        h = C.c_void_p()
+        check(lib().wcs_symbolic_batch(len(parts), C.cast(arr, C.c_void_p), C.byref(h)), "wcs_symbolic_batch")
+        self = cls.__new__(cls)
+        self._keep = []
+        self.handle = h
+        self.n = int(sum(p.n for p in parts))
+        return self
+
+    @property
+    def seg_ptr(self) -> np.ndarray:
+        sp = np.empty(self.info["nseg"] + 1, np.int32)
+        check(lib().wcs_symbolic_segments(self.handle, sp.ctypes.data), "wcs_symbolic_segments")
+        return sp
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h is not None and h.value:
@@ -145,6 +166,33 @@ class Factor:
             check(lib().wcs_factor_numeric(self.handle, _dptr(values), _stream_ptr(stream), None),
                   "wcs_factor_numeric")
 
+    def use_graphs(self, enable: bool = True) -> None:
+        """Record the factorization and the sweeps into HIP graphs and replay them."""
+        check(lib().wcs_factor_use_graphs(self.handle, 1 if enable else 0), "wcs_factor_use_graphs")
+
+    def autotune(self, values, stream=None) -> dict:
+        """Pick the trailing-update tile per tree level by timing (leaves a valid factor)."""
+        self.values = values
+        H = self.sym.info["nlevels"]
+        tiles = np.zeros(max(H, 1), np.int32)
+        ms = np.zeros(2, np.float64)
+        check(lib().wcs_factor_autotune(self.handle, _dptr(values), _stream_ptr(stream), tiles.ctypes.data,
+                                        ms.ctypes.data), "wcs_factor_autotune")
+        return {"tiles": tiles[:H], "ms_default": float(ms[0]), "ms_tuned": float(ms[1])}
+
+    def set_tiles(self, tiles) -> None:
+        t = np.ascontiguousarray(tiles, np.int32)
+        assert t.size == self.sym.info["nlevels"]
+        check(lib().wcs_factor_set_tiles(self.handle, t.ctypes.data), "wcs_factor_set_tiles")
+
+    def residuals(self) -> np.ndarray:
+        """Relative residuals of the last refinement, shape (instances, nrhs)."""
+        nseg = self.sym.info["nseg"]
+        k = getattr(self, "_last_k", self.max_nrhs)
+        out = np.empty(nseg * k, np.float64)
+        check(lib().wcs_factor_residuals(self.handle, out.ctypes.data, out.size), "wcs_factor_residuals")
+        return out.reshape(nseg, k)
+
     def profile(self, values, stream=None) -> dict:
         """One factorization with HIP events around every launch; per kernel class
         {launches, ms, flops, bytes} (algorithmic work)."""
@@ -193,6 +241,7 @@ class Factor:
         bc = Bm.t().contiguous()
         xc = torch.empty_like(bc)
         rep = IRReport()
+        self._last_k = k
         rc = lib().wcs_solve_refined(self.handle, _dptr(vals), k, _dptr(bc), _dptr(xc), self.n, tol, max_iter,
                                      C.byref(rep), _stream_ptr(stream))
         report = {"iterations": rep.iterations, "raw_residual": rep.raw_residual,

@@ -82,3 +82,16 @@ ALL = {
     "headline": headline,
     "grf": random_field,
 }
+
+
+def block_diagonal(mats: List[Dict[str, np.ndarray]]) -> Dict[str, np.ndarray]:
+    """The matrices of a batch stacked as diag(A_0, A_1, ...): lower CSC with the
+    instances' columns, rows and values in order (rows shifted by the instances
+    before), plus seg_ptr, the first unknown of every instance."""
+    ns = [int(m["n"]) for m in mats]
+    seg = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    zs = np.concatenate([[0], np.cumsum([int(m["colptr"][-1]) for m in mats])]).astype(np.int64)
+    colptr = np.concatenate([[0]] + [m["colptr"][1:] + zs[b] for b, m in enumerate(mats)]).astype(np.int64)
+    rowind = np.concatenate([m["rowind"] + seg[b] for b, m in enumerate(mats)]).astype(np.int32)
+    values = np.concatenate([m["values"] for m in mats])
+    return {"n": int(seg[-1]), "colptr": colptr, "rowind": rowind, "values": values, "seg_ptr": seg.astype(np.int32)}
