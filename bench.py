@@ -87,12 +87,112 @@ def cpu_baseline(m, perm, target_seconds: float) -> dict:
                       f"single thread"}
 
 
+def bench_batch(args) -> int:
+    """Many uneven instances factored and solved together: grid side 2^J with J
+    uniform in {5,6,7}, 4 right-hand sides each, FP32 factor + FP64 refinement
+    per instance to the tolerance, update tiles from the autotuner, factor and
+    sweeps replayed from HIP graphs.  Also times the same instances factored
+    one after another (eager, one handle each) for comparison."""
+    import numpy as np
+    import workloads
+    t0 = time.perf_counter()
+    mats = workloads.batch_matrices(args.instances, workers=8)     # forked workers: before any GPU work
+    log(f"generated {len(mats)} instances in {time.perf_counter() - t0:.1f}s")
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2007_01541_amd import FP32, Factor, Symbolic
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(8) as ex:
+        syms = list(ex.map(lambda m: Symbolic(m["n"], m["colptr"], m["rowind"], coords=m["coords"]), mats))
+    t_an = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bs = Symbolic.batch(syms)
+    info = bs.info
+    t_comb = time.perf_counter() - t0
+    log(f"analyze {t_an:.1f}s (8 threads), combine {t_comb:.1f}s: n={info['n']} nnz(L)={info['nnz_l']} "
+        f"flops={info['flops']:.4e} fronts={info['nsuper']} levels={info['nlevels']}")
+    ws = workloads.batch(args.instances)
+    k = 4
+    B = np.vstack([workloads.normal_rhs(m["n"], k, w.seed + 1) for m, w in zip(mats, ws)])
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    vals = torch.as_tensor(np.concatenate([m["values"] for m in mats]), device=dev)
+    Bd = torch.as_tensor(B, device=dev)
+    F = float(info["flops"])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        f = Factor(bs, FP32, max_nrhs=k)
+        log(f"workspace {f.workspace.numel() / 2**30:.1f} GiB")
+        f.numeric(vals)
+        tune = f.autotune(vals)
+        log(f"autotune: tiles per level {tune['tiles'].tolist()}, level sum {tune['ms_default']:.2f} ms with "
+            f"128x128 -> {tune['ms_tuned']:.2f} ms")
+        f.use_graphs(True)
+        reps = []
+
+        def step():
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            f.numeric(vals, check_pivots=False)
+            e1.record(stream)
+            X, rep = f.solve_refined(Bd, vals, tol=args.tol, max_iter=10)
+            reps.append(rep)
+            return e0, e1
+        for _ in range(args.warmup):
+            step()
+        stream.synchronize()
+        reps.clear()
+        t0 = time.perf_counter()
+        evs = [step() for _ in range(args.steps)]
+        stream.synchronize()
+        t_step = (time.perf_counter() - t0) / args.steps
+        fact_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+        assert f.pivot_check() == -1
+        rel = f.residuals()
+        log(f"{args.steps} steps: {t_step * 1e3:.1f} ms/step, factor {fact_ms:.2f} ms ({F / fact_ms / 1e9:.1f} "
+            f"TFLOP/s), refinement {reps[-1]}, worst instance residual {rel.max():.3e}")
+        del f
+        torch.cuda.empty_cache()
+        # the same instances one after another, each with its own handle (eager launches)
+        one = []
+        for s_, m in zip(syms, mats):
+            fi = Factor(s_, FP32, max_nrhs=k)
+            one.append((fi, torch.as_tensor(m["values"], device=dev)))
+        for fi, v in one:
+            fi.numeric(v, check_pivots=False)
+        stream.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for fi, v in one:
+            fi.numeric(v, check_pivots=False)
+        e1.record(stream)
+        stream.synchronize()
+        seq_ms = e0.elapsed_time(e1)
+        log(f"one instance at a time: factor {seq_ms:.2f} ms")
+    out = {
+        "metric": "batched factor TFLOP/s, 256 uneven instances (FP32 + FP64 refinement per instance to 1e-10)",
+        "value": F / fact_ms / 1e9, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch{args.instances}_J5-7_nrhs4", "instances": args.instances, "n": info["n"],
+                   "nnz_lower": info["nnz_lower"], "nnz_l": info["nnz_l"], "flops": info["flops"],
+                   "fronts": info["nsuper"], "levels": info["nlevels"]},
+        "factor_ms": fact_ms, "sequential_factor_ms": seq_ms, "batching_speedup": seq_ms / fact_ms,
+        "autotune": {"tiles": tune["tiles"].tolist(), "ms_128": tune["ms_default"], "ms_tuned": tune["ms_tuned"]},
+        "ir": reps[-1], "worst_instance_residual": float(rel.max()),
+        "host": {"analyze_s": round(t_an, 2), "combine_s": round(t_comb, 2)},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batch"])
+    ap.add_argument("--instances", type=int, default=256, help="batch workload: number of instances")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -102,6 +202,9 @@ def main() -> int:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(the elimination-tree sharding across GPUs is described in DESIGN.md only).", file=sys.stderr)
         return 2
+
+    if args.workload == "batch":
+        return bench_batch(args)
 
     import numpy as np
     import torch

@@ -21,11 +21,13 @@
 // sort has a total order.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <numeric>
 #include <queue>
 #include <string>
+#include <thread>
 
 #include "internal.h"
 
@@ -699,72 +701,125 @@ int analyze(int32_t n, const int64_t *colptr, const int32_t *rowind, const wcs_a
 int combine(int32_t count, const Symbolic *const *parts, Symbolic &S)
 {
     if (count <= 0) { set_error("batch needs at least one part"); return WCS_EINVAL; }
-    int64_t n_tot = 0;
+    // totals first, so every array is sized once and filled in place
+    int64_t n_tot = 0, nnz_tot = 0, ns_tot = 0, rows_tot = 0, tree_tot = 0, fund_tot = 0, csr_tot = 0;
     for (int32_t b = 0; b < count; b++) {
-        if (!parts[b]) { set_error("null part in batch"); return WCS_EINVAL; }
-        n_tot += parts[b]->n;
+        const Symbolic *P = parts[b];
+        if (!P) { set_error("null part in batch"); return WCS_EINVAL; }
+        n_tot += P->n;
+        nnz_tot += P->nnz;
+        ns_tot += P->ns;
+        rows_tot += (int64_t)P->rows.size();
+        tree_tot += (int64_t)P->sep_tree.size();
+        fund_tot += (int64_t)P->fund_ptr.size() - 1;
+        csr_tot += (int64_t)P->csr_col.size();
     }
-    if (n_tot > INT32_MAX) { set_error("batch too large for 32-bit indices"); return WCS_EINVAL; }
+    if (n_tot > INT32_MAX || ns_tot > INT32_MAX) { set_error("batch too large for 32-bit indices"); return WCS_EINVAL; }
     S = Symbolic();
     S.n = (int32_t)n_tot;
-    S.colptr.push_back(0);
-    S.fund_ptr.push_back(0);
-    S.sptr.push_back(0);
-    S.rptr.push_back(0);
-    S.front_off.push_back(0);
-    S.csr_ptr.push_back(0);
-    S.seg_ptr.push_back(0);
-    int32_t noff = 0, soff = 0, toff = 0;
-    int64_t zoff = 0, roff = 0, foff = 0, coff = 0;
-    auto shift = [](std::vector<int32_t> &dst, const std::vector<int32_t> &src, int32_t d, bool keep_neg) {
-        for (int32_t v : src) dst.push_back(keep_neg && v < 0 ? v : v + d);
-    };
+    S.nnz = nnz_tot;
+    S.ns = (int32_t)ns_tot;
+    S.colptr.resize((size_t)n_tot + 1);
+    S.rowind.resize((size_t)nnz_tot);
+    S.perm.resize((size_t)n_tot);
+    S.iperm.resize((size_t)n_tot);
+    S.sep_tree.resize((size_t)tree_tot);
+    S.parent.resize((size_t)n_tot);
+    S.colcount.resize((size_t)n_tot);
+    S.fund_ptr.resize((size_t)fund_tot + 1);
+    S.sptr.resize((size_t)ns_tot + 1);
+    S.snode_of.resize((size_t)n_tot);
+    S.rptr.resize((size_t)ns_tot + 1);
+    S.rows.resize((size_t)rows_tot);
+    S.rel.resize((size_t)rows_tot);
+    S.sparent.resize((size_t)ns_tot);
+    S.height.resize((size_t)ns_tot);
+    S.front_off.resize((size_t)ns_tot + 1);
+    S.amap.resize((size_t)nnz_tot);
+    S.csr_ptr.resize((size_t)n_tot + 1);
+    S.csr_col.resize((size_t)csr_tot);
+    S.csr_src.resize((size_t)csr_tot);
+    S.seg_ptr.resize((size_t)count + 1);
+    S.colptr[0] = 0;
+    S.fund_ptr[0] = 0;
+    S.sptr[0] = 0;
+    S.rptr[0] = 0;
+    S.front_off[0] = 0;
+    S.csr_ptr[0] = 0;
+    S.seg_ptr[0] = 0;
+    // per-part offsets into every concatenated array
+    struct Off { int32_t n, s, t; int64_t z, r, f, c, tp, fp; };
+    std::vector<Off> off((size_t)count + 1);
+    off[0] = Off{0, 0, 0, 0, 0, 0, 0, 0, 0};
     for (int32_t b = 0; b < count; b++) {
         const Symbolic &P = *parts[b];
-        for (int32_t j = 0; j < P.n; j++) S.colptr.push_back(P.colptr[j + 1] + zoff);
-        shift(S.rowind, P.rowind, noff, false);
-        shift(S.perm, P.perm, noff, false);
-        shift(S.iperm, P.iperm, noff, false);
-        for (size_t q = 0; q < P.sep_tree.size(); q += 6) {
-            const int32_t *nd = &P.sep_tree[q];
-            S.sep_tree.push_back(nd[0] + noff);
-            S.sep_tree.push_back(nd[1] < 0 ? -1 : nd[1] + noff);
-            S.sep_tree.push_back(nd[2] + noff);
-            S.sep_tree.push_back(nd[3] + noff);
-            S.sep_tree.push_back(nd[4] < 0 ? -1 : nd[4] + toff);
-            S.sep_tree.push_back(nd[5] < 0 ? -1 : nd[5] + toff);
-        }
+        const Off &o = off[b];
+        off[b + 1] = Off{o.n + P.n, o.s + P.ns, o.t + (int32_t)(P.sep_tree.size() / 6), o.z + P.nnz,
+                         o.r + (int64_t)P.rows.size(), o.f + P.front_off.back(), o.c + (int64_t)P.csr_col.size(),
+                         o.tp + (int64_t)P.sep_tree.size(), o.fp + (int64_t)P.fund_ptr.size() - 1};
+        S.seg_ptr[b + 1] = off[b + 1].n;
         S.npeeled += P.npeeled;
-        shift(S.parent, P.parent, noff, true);
-        S.colcount.insert(S.colcount.end(), P.colcount.begin(), P.colcount.end());
-        for (size_t q = 1; q < P.fund_ptr.size(); q++) S.fund_ptr.push_back(P.fund_ptr[q] + noff);
         S.nnz_l += P.nnz_l;
         S.flops += P.flops;
         S.flops_padded += P.flops_padded;
-        for (int32_t q = 1; q <= P.ns; q++) S.sptr.push_back(P.sptr[q] + noff);
-        shift(S.snode_of, P.snode_of, soff, false);
-        for (int32_t q = 1; q <= P.ns; q++) S.rptr.push_back(P.rptr[q] + roff);
-        shift(S.rows, P.rows, noff, false);
-        S.rel.insert(S.rel.end(), P.rel.begin(), P.rel.end());
-        shift(S.sparent, P.sparent, soff, true);
-        S.height.insert(S.height.end(), P.height.begin(), P.height.end());
         S.nlevels = std::max(S.nlevels, P.nlevels);
-        for (int32_t q = 1; q <= P.ns; q++) S.front_off.push_back(P.front_off[q] + foff);
-        for (int64_t v : P.amap) S.amap.push_back(v + foff);
-        for (int32_t r = 0; r < P.n; r++) S.csr_ptr.push_back(P.csr_ptr[r + 1] + coff);
-        shift(S.csr_col, P.csr_col, noff, false);
-        for (int64_t v : P.csr_src) S.csr_src.push_back(v + zoff);
-        noff += P.n;
-        soff += P.ns;
-        toff += (int32_t)(P.sep_tree.size() / 6);
-        zoff += P.nnz;
-        roff += (int64_t)P.rows.size();
-        foff += P.front_off.back();
-        coff += P.csr_ptr.back();
-        S.seg_ptr.push_back(noff);
     }
-    S.nnz = zoff;
-    S.ns = soff;
+    // the parts write disjoint ranges: copy them on a few threads
+    auto copy_part = [&](int32_t b) {
+        const Symbolic &P = *parts[b];
+        const int32_t n = P.n, ns = P.ns;
+        const int32_t noff = off[b].n, soff = off[b].s, toff = off[b].t;
+        const int64_t zoff = off[b].z, roff = off[b].r, foff = off[b].f, coff = off[b].c, tpos = off[b].tp,
+                      fpos = off[b].fp;
+        for (int32_t j = 0; j < n; j++) {
+            S.colptr[noff + j + 1] = P.colptr[j + 1] + zoff;
+            S.perm[noff + j] = P.perm[j] + noff;
+            S.iperm[noff + j] = P.iperm[j] + noff;
+            S.parent[noff + j] = P.parent[j] < 0 ? -1 : P.parent[j] + noff;
+            S.colcount[noff + j] = P.colcount[j];
+            S.snode_of[noff + j] = P.snode_of[j] + soff;
+            S.csr_ptr[noff + j + 1] = P.csr_ptr[j + 1] + coff;
+        }
+        for (int64_t q = 0; q < P.nnz; q++) {
+            S.rowind[zoff + q] = P.rowind[q] + noff;
+            S.amap[zoff + q] = P.amap[q] + foff;
+        }
+        for (size_t q = 0; q < P.sep_tree.size(); q += 6) {
+            const int32_t *nd = &P.sep_tree[q];
+            int32_t *od = &S.sep_tree[tpos + q];
+            od[0] = nd[0] + noff;
+            od[1] = nd[1] < 0 ? -1 : nd[1] + noff;
+            od[2] = nd[2] + noff;
+            od[3] = nd[3] + noff;
+            od[4] = nd[4] < 0 ? -1 : nd[4] + toff;
+            od[5] = nd[5] < 0 ? -1 : nd[5] + toff;
+        }
+        for (size_t q = 1; q < P.fund_ptr.size(); q++) S.fund_ptr[fpos + q] = P.fund_ptr[q] + noff;
+        for (int32_t q = 0; q < ns; q++) {
+            S.sptr[soff + q + 1] = P.sptr[q + 1] + noff;
+            S.rptr[soff + q + 1] = P.rptr[q + 1] + roff;
+            S.sparent[soff + q] = P.sparent[q] < 0 ? -1 : P.sparent[q] + soff;
+            S.height[soff + q] = P.height[q];
+            S.front_off[soff + q + 1] = P.front_off[q + 1] + foff;
+        }
+        for (size_t q = 0; q < P.rows.size(); q++) {
+            S.rows[roff + q] = P.rows[q] + noff;
+            S.rel[roff + q] = P.rel[q];
+        }
+        for (size_t q = 0; q < P.csr_col.size(); q++) {
+            S.csr_col[coff + q] = P.csr_col[q] + noff;
+            S.csr_src[coff + q] = P.csr_src[q] + zoff;
+        }
+    };
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, (unsigned)count);
+    std::vector<std::thread> pool;
+    std::atomic<int32_t> next{0};
+    for (unsigned t = 0; t < nth; t++)
+        pool.emplace_back([&] {
+            for (int32_t b; (b = next.fetch_add(1)) < count;) copy_part(b);
+        });
+    for (auto &th : pool) th.join();
     return WCS_OK;
 }
 
