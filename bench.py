@@ -29,6 +29,24 @@ PEAK = {"fp32_mfma_tflops": 157.3, "fp64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
 METRIC = "factor TFLOP/s + % MFMA peak, N=2^18: FP32+IR vs FP64 at resid 1e-10"
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_fp32_headline_hbm_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_01541_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 update kernel from the committed
+    counter summary, or None when the kernel source changed since then."""
+    import hashlib
+    try:
+        fields = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines() if ": " in l)
+        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if fields.get("kernels_hip_sha256", "").strip() != src:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def log(msg: str) -> None:
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
@@ -197,6 +215,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 1 GiB FP32 tensor three times (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -226,6 +246,14 @@ def main() -> int:
     F = float(info["flops"])
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 copies of 1 GiB done")
     vals = torch.as_tensor(m["values"], device=dev)
     Bd = torch.as_tensor(B, device=dev)
     stream = torch.cuda.current_stream()
@@ -301,7 +329,8 @@ def main() -> int:
     if d["flops"] > 0:
         achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32_mfma_tflops"], "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32_mfma_tflops"], "traffic": None, "kernel": dom,
+                "frac": achieved / PEAK["fp32_mfma_tflops"],
+                "traffic": measured_traffic() if dom == "update" else None, "kernel": dom,
                 "launches": d["launches"], "avg_launch_us": d["ms"] * 1e3 / max(1, d["launches"])}
     else:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
