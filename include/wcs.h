@@ -214,18 +214,27 @@ int wcs_factor_residuals(wcs_factor f, double *rel, int64_t count);
  */
 int wcs_factor_use_graphs(wcs_factor f, int enable);
 
+/* Trailing-update kernels (per level of the assembly tree). */
+typedef enum {
+    WCS_UPD_REG128 = 0,     /* 128 x 128 tiles, operands staged through registers into LDS */
+    WCS_UPD_REG64 = 1,      /* 64 x 64 tiles (one wave per tile), same staging */
+    WCS_UPD_STREAM128 = 2   /* 128 x 128 tiles, operands streamed global -> LDS, four chunks in flight */
+} wcs_update_variant;
+
 /*
- * Autotuner for the trailing-update tile shape.  Factors values_dev (which
- * leaves a valid factor, as wcs_factor_numeric does) four times on the
- * stream: a warm-up and a timed run with 128 x 128 tiles on every level, the
- * same with 64 x 64 tiles, timing each level of the assembly tree with HIP
- * events; then keeps, per level, the faster tile.  Synchronous.  tiles
- * (nlevels entries, may be NULL) receives the choice per level, ms (2
- * entries, may be NULL) the summed level times with 128 x 128 tiles only and
- * with the chosen tiles.  Drops a recorded factorization graph.
+ * Autotuner for the trailing-update kernel.  Factors values_dev (which leaves
+ * a valid factor, as wcs_factor_numeric does) six times on the stream: a
+ * warm-up and a timed run with each wcs_update_variant on every level, timing
+ * each level of the assembly tree with HIP events; then keeps, per level, the
+ * fastest variant.  All variants compute bitwise the same factor (same
+ * products in the same order).  Synchronous.  tiles (nlevels entries, may be
+ * NULL) receives the choice per level; ms (2 entries, may be NULL) the summed
+ * level times with the default variant (WCS_UPD_STREAM128 for FP64 fronts,
+ * WCS_UPD_REG128 for FP32) and with the chosen ones.  Drops a recorded
+ * factorization graph.
  */
 int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *tiles, double *ms);
-/* Sets the update tile per level (nlevels entries, each 128 or 64), e.g. from an earlier autotune. */
+/* Sets the update kernel per level (nlevels wcs_update_variant values), e.g. from an earlier autotune. */
 int wcs_factor_set_tiles(wcs_factor f, const int32_t *tiles);
 
 /*

@@ -10,6 +10,8 @@
 // against that block, then subtract the panel's outer product from the
 // trailing lower triangle on the matrix cores (16x16x4 MFMA).
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <stdint.h>
 
 namespace wcs {
@@ -478,6 +480,189 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const int4 *__restrict_
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 int row = i0 + wr + x * 16 + Mfma<T>::row(kq, e);
+                if (row < m && row >= col) Cc[row] -= acc[x][y][e];
+            }
+        }
+}
+
+// Trailing update, streamed form.  Same task and result as k_update<T, 128>,
+// but the operand chunks go from global memory straight into LDS through the
+// load unit's LDS path (global_load_lds, 16 bytes per lane), with NS chunks in
+// flight, so no registers hold staged data and the load latency is covered by
+// NS - 1 chunks of matrix-core work.  One DMA instruction fills a contiguous
+// 1 KB run of LDS in lane order, so the LDS tile keeps the natural row order
+// (rows contiguous for each k) and the MFMA blocks of a wave take interleaved
+// rows instead: block x of a wave covers the rows wr + 4 i + x (i = 0..15), so
+// the four A operands of a lane (x = 0..3) are the four consecutive rows
+// wr + 4 ln + {0..3}, one 16-byte LDS read; the same for B and the columns.
+// Rows past the front are clamped to its last row (their products land in
+// rows that are never stored); k past K is clamped to the last valid column
+// and masked to zero in the last chunk.  The fronts buffer must be followed
+// by at least 16 bytes of other workspace memory (it is).
+template <typename T> struct DmaCfg;
+template <> struct DmaCfg<float> { static constexpr int KC = 16, NS = 4; };
+template <> struct DmaCfg<double> { static constexpr int KC = 8, NS = 4; };
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// wait until at most N vector-memory operations of this wave are outstanding
+template <int N> __device__ __forceinline__ void wait_vmcnt()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+// workgroup barrier without a memory fence: the fence of __syncthreads would
+// wait for every LDS transfer in flight; the streaming loop below waits for
+// exactly the chunk it needs instead.  The empty asm statements keep the
+// compiler from moving memory operations across the barrier.
+__device__ __forceinline__ void barrier_nofence()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// One global -> LDS transfer of 16 bytes per lane (global_load_lds_dwordx4):
+// lane l's 16 bytes from g land at LDS byte address lds + 16 l, lds being
+// wave-uniform.  Issued from inline assembly so that the compiler does not
+// treat it as an LDS write it must wait for before every LDS read; the
+// caller orders it with explicit vmcnt waits and barriers.  M0 (the LDS base
+// register of the transfer) is restored before the statement ends.
+__device__ __forceinline__ void dma_to_lds16(const void *g, uint32_t lds)
+{
+    uint32_t saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\tglobal_load_lds_dwordx4 %1, off\n\ts_mov_b32 m0, %0"
+                 : "=&s"(saved)
+                 : "v"(g), "s"(lds)
+                 : "memory");
+}
+
+// compile-time loop: fn(integral_constant<int, I>) for I = B, B + S, ... < E
+template <int B, int E, int S, typename Fn> __device__ __forceinline__ void static_for(Fn &&fn)
+{
+    if constexpr (B < E) {
+        fn(std::integral_constant<int, B>());
+        static_for<B + S, E, S>(fn);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_update_dma(const int4 *__restrict__ tasks, int ka, int kw,
+                                                    const int64_t *__restrict__ front_off,
+                                                    const int32_t *__restrict__ mfront,
+                                                    const int32_t *__restrict__ pfront, T *__restrict__ fronts)
+{
+    constexpr int KC = DmaCfg<T>::KC, NS = DmaCfg<T>::NS;
+    static_assert(NS == 4, "the stage arrays below assume four stages");
+    constexpr int VEC = 16 / (int)sizeof(T);       // elements per lane per DMA instruction
+    constexpr int LPR = 128 / VEC;                 // lanes per 128-element k row
+    constexpr int RPI = 64 / LPR;                  // k rows per DMA instruction (f32 2, f64 1)
+    constexpr int IPO = KC / RPI;                  // DMA instructions per operand per chunk
+    constexpr int IPW = 2 * IPO / 4;               // ... per wave
+    static_assert(IPW * 4 == 2 * IPO, "chunk must split evenly over the waves");
+    // one array per stage: distinct objects, so the compiler can tell a read
+    // of one stage from a transfer into another
+    __shared__ __align__(16) T S0[2][KC][128];
+    __shared__ __align__(16) T S1[2][KC][128];
+    __shared__ __align__(16) T S2[2][KC][128];
+    __shared__ __align__(16) T S3[2][KC][128];
+    auto stage = [&](auto st_) -> T(*)[KC][128] {
+        constexpr int st = decltype(st_)::value;
+        if constexpr (st == 0) return S0;
+        else if constexpr (st == 1) return S1;
+        else if constexpr (st == 2) return S2;
+        else return S3;
+    };
+    int4 t = tasks[blockIdx.x];
+    int f = t.x, i0 = t.y, j0 = t.z, jend = t.w;
+    int m = mfront[f], p = pfront[f], ld = front_ld(m);
+    int K = min(kw, p - ka);
+    T *F = fronts + front_off[f];
+    int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    int wr = (wave / 2) * 64, wc = (wave % 2) * 64;
+    int kq = lane / 16, ln = lane % 16;
+    bool active = (i0 + wr + 63 >= j0 + wc) && (j0 + wc < jend) && (i0 + wr < m);
+    typedef __attribute__((address_space(3))) T *lds_t;
+    // this lane's part of every DMA instruction of the wave: k row in the chunk and tile row
+    const int lrow = (lane % LPR) * VEC, lk = lane / LPR;
+    // tile origins need not be multiples of VEC, so a lane's VEC rows may run
+    // up to VEC - 1 elements past the end of a column (into the next column or
+    // the next buffer of the workspace: in bounds); those rows are never stored
+    const int rowA = min(i0 + lrow, m - 1), rowB = min(j0 + lrow, m - 1);
+    auto issue = [&](auto st_, int c) {
+        T(*Sx)[KC][128] = stage(st_);
+#pragma unroll
+        for (int s = 0; s < IPW; s++) {
+            int q = wave + 4 * s, op = q / IPO, qq = q % IPO;
+            int kr = qq * RPI;
+            int kg = min(c * KC + kr + lk, K - 1);
+            const T *g = F + (int64_t)(ka + kg) * ld + (op ? rowB : rowA);
+            uint32_t dst = (uint32_t)(uintptr_t)(lds_t)&Sx[op][kr][0];
+            dma_to_lds16((const void *)g, __builtin_amdgcn_readfirstlane(dst));
+        }
+    };
+    typedef typename Mfma<T>::V V;
+    typedef typename Vec4<T>::type V4;
+    V acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
+    auto compute = [&](auto st_, int kleft) {
+        T(*Sx)[KC][128] = stage(st_);
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4) {
+            V4 a4 = *reinterpret_cast<const V4 *>(&Sx[0][kk + kq][wr + 4 * ln]);
+            V4 b4 = *reinterpret_cast<const V4 *>(&Sx[1][kk + kq][wc + 4 * ln]);
+            bool kv = kk + kq < kleft;
+            T av[4] = {kv ? a4.x : (T)0, kv ? a4.y : (T)0, kv ? a4.z : (T)0, kv ? a4.w : (T)0};
+            T bv[4] = {b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++) acc[x][y] = Mfma<T>::mma(av[x], bv[y], acc[x][y]);
+        }
+    };
+    const int nchunk = (K + KC - 1) / KC;
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    // chunk c lives in stage c % 4
+    auto step = [&](auto st_, auto nx_, int c) {
+        if (c >= nchunk) return;
+        int after = min(NS - 2, nchunk - 1 - c);   // chunks this wave issued after chunk c
+        if (after >= 2) wait_vmcnt<2 * IPW>();
+        else if (after == 1) wait_vmcnt<IPW>();
+        else wait_vmcnt<0>();
+        barrier_nofence();                          // chunk c visible from every wave; chunk c-1 consumed
+        if (c + NS - 1 < nchunk) issue(nx_, c + NS - 1);   // refills the stage of chunk c-1
+        if (active) compute(st_, K - c * KC);
+    };
+    issue(I0(), 0);
+    if (nchunk > 1) issue(I1(), 1);
+    if (nchunk > 2) issue(I2(), 2);
+    for (int c = 0; c < nchunk; c += NS) {
+        step(I0(), I3(), c);
+        step(I1(), I0(), c + 1);
+        step(I2(), I1(), c + 2);
+        step(I3(), I2(), c + 3);
+    }
+    wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
+    if (!active) return;
+#pragma unroll
+    for (int x = 0; x < 4; x++)
+#pragma unroll
+        for (int y = 0; y < 4; y++) {
+            int col = j0 + wc + 4 * ln + y;
+            if (col >= jend) continue;
+            T *Cc = F + (int64_t)col * ld;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int row = i0 + wr + 4 * Mfma<T>::row(kq, e) + x;
                 if (row < m && row >= col) Cc[row] -= acc[x][y][e];
             }
         }

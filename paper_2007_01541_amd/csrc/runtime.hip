@@ -69,7 +69,7 @@ struct SolveLevel {
 };
 struct Level {
     SolveLevel sv;
-    int32_t upd_tile = UT;                         // update tile of this level (128 or 64; autotuned)
+    int32_t upd_var = 0;                           // update kernel of this level (WCS_UPD_*; autotuned)
     std::vector<Op> ops;
     std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds (offset, count)
     int64_t fl_off = 0, fl_cnt = 0;                // fronts of this level in flist
@@ -282,7 +282,7 @@ struct Layout {
         size_t o = 0;
         auto seg = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
         size_t n = (size_t)S.n, ns = (size_t)S.ns;
-        fronts = seg((size_t)S.front_off.back() * esz);
+        fronts = seg((size_t)S.front_off.back() * esz + 64);   // + slack read past the last column by k_update_dma
         W = seg((size_t)P.wrows * k * esz);
         Y = seg(n * k * esz);
         Xr = seg(n * k * 8);
@@ -331,6 +331,10 @@ struct Layout {
 };
 
 size_t elem_size(wcs_precision p) { return p == WCS_FP64 ? 8 : 4; }
+
+// Update kernel used before any autotuning: on large fronts the streamed form
+// is the faster one in FP64 and the register-staged one in FP32.
+int32_t default_update_variant(wcs_precision p) { return p == WCS_FP64 ? WCS_UPD_STREAM128 : WCS_UPD_REG128; }
 
 int grid_for(int64_t work, int threads = 256)
 {
@@ -537,11 +541,14 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
         }
         for (const Op &op : L.ops) {
             if (op.kind == OP_UPDATE) {
-                bool small = L.upd_tile == 64;
+                bool small = L.upd_var == WCS_UPD_REG64;
                 int64_t off = small ? op.off64 : op.off, cnt = small ? op.cnt64 : op.cnt;
                 PROF_BEGIN(KC_UPDATE);
                 if (small)
                     hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, st, upd + off, op.ka,
+                                       op.kw, fo, mf, pf, fronts);
+                else if (L.upd_var == WCS_UPD_STREAM128)
+                    hipLaunchKernelGGL(k_update_dma<T>, dim3((unsigned)cnt), dim3(256), 0, st, upd + off, op.ka,
                                        op.kw, fo, mf, pf, fronts);
                 else
                     hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, st, upd + off,
@@ -549,7 +556,7 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                 PROF_END(KC_UPDATE);
                 if (prof)
                     for (int64_t q = off; q < off + cnt; q++)
-                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], op.ka, op.kw, L.upd_tile);
+                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], op.ka, op.kw, small ? 64 : UT);
             } else {
                 int c = op.kind == OP_PANEL ? KC_PANEL : KC_PANEL_FP64DIAG;
                 PROF_BEGIN(c);
@@ -883,6 +890,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
         f->prec = prec;
         f->max_nrhs = max_nrhs;
         f->plan.build(*f->S);
+        for (Level &L : f->plan.levels) L.upd_var = default_update_variant(prec);
         f->lay.compute(*f->S, f->plan, elem_size(prec), max_nrhs);
     } catch (const std::bad_alloc &) {
         delete f;
@@ -1045,26 +1053,29 @@ int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream strea
         for (size_t h = 0; h < H; h++) lev_ms[h] = out[h].ms;
         return WCS_OK;
     };
-    // each candidate tile on every level: a warm-up factorization, then a timed one
-    std::vector<double> t[2];
-    const int32_t cand[2] = {UT, 64};
-    for (int v = 0; v < 2; v++) {
-        for (Level &L : P.levels) L.upd_tile = cand[v];
+    // each candidate kernel on every level: a warm-up factorization, then a timed one
+    constexpr int NV = 3;
+    std::vector<double> t[NV];
+    const int32_t dflt = default_update_variant(f->prec);
+    for (int v = 0; v < NV; v++) {
+        for (Level &L : P.levels) L.upd_var = v;
         std::vector<double> warm;
         int rc = timed(warm);
         if (!rc) rc = timed(t[v]);
         if (rc) {
-            for (Level &L : P.levels) L.upd_tile = UT;
+            for (Level &L : P.levels) L.upd_var = dflt;
             return rc;
         }
     }
     double before = 0, after = 0;
     for (size_t h = 0; h < H; h++) {
-        int best = t[1][h] < t[0][h] ? 1 : 0;
-        P.levels[h].upd_tile = cand[best];
-        before += t[0][h];
+        int best = dflt;
+        for (int v = 0; v < NV; v++)
+            if (t[v][h] < t[best][h]) best = v;
+        P.levels[h].upd_var = best;
+        before += t[dflt][h];
         after += t[best][h];
-        if (tiles) tiles[h] = cand[best];
+        if (tiles) tiles[h] = best;
     }
     if (ms) {
         ms[0] = before;
@@ -1084,8 +1095,11 @@ int wcs_factor_set_tiles(wcs_factor f, const int32_t *tiles)
 {
     if (!f || !tiles) { set_error("invalid argument to wcs_factor_set_tiles"); return WCS_EINVAL; }
     for (size_t h = 0; h < f->plan.levels.size(); h++)
-        if (tiles[h] != UT && tiles[h] != 64) { set_error("update tile must be 128 or 64"); return WCS_EINVAL; }
-    for (size_t h = 0; h < f->plan.levels.size(); h++) f->plan.levels[h].upd_tile = tiles[h];
+        if (tiles[h] < WCS_UPD_REG128 || tiles[h] > WCS_UPD_STREAM128) {
+            set_error("update kernel variant must be WCS_UPD_REG128, WCS_UPD_REG64 or WCS_UPD_STREAM128");
+            return WCS_EINVAL;
+        }
+    for (size_t h = 0; h < f->plan.levels.size(); h++) f->plan.levels[h].upd_var = tiles[h];
     if (f->fgraph) {
         (void)hipGraphExecDestroy(f->fgraph);
         f->fgraph = nullptr;

@@ -171,7 +171,8 @@ class Factor:
         check(lib().wcs_factor_use_graphs(self.handle, 1 if enable else 0), "wcs_factor_use_graphs")
 
     def autotune(self, values, stream=None) -> dict:
-        """Pick the trailing-update tile per tree level by timing (leaves a valid factor)."""
+        """Pick the trailing-update kernel per tree level by timing (leaves a valid factor):
+        0 = 128x128 register-staged, 1 = 64x64, 2 = 128x128 streamed into LDS."""
         self.values = values
         H = self.sym.info["nlevels"]
         tiles = np.zeros(max(H, 1), np.int32)

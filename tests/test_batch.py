@@ -175,20 +175,23 @@ def test_graph_replay_matches_eager():
 
 
 @pytest.mark.gpu
-def test_autotune_keeps_factor_exact():
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_autotune_keeps_factor_exact(prec):
+    """Every update kernel variant sums the same products in the same order,
+    so the factor is bitwise the same whichever the autotuner picks."""
     mats = small_instances()
     bs = Symbolic.batch(analyses(mats))
     big = block_diagonal(mats)
     vals = dev(big["values"])
-    f = Factor(bs, FP64)
+    f = Factor(bs, prec)
     f.numeric(vals)
     L0 = f.export_L()[2]
     res = f.autotune(vals)
     print(f"autotune {res}", flush=True)
-    assert set(res["tiles"].tolist()) <= {64, 128}
+    assert set(res["tiles"].tolist()) <= {0, 1, 2}
     assert res["ms_tuned"] <= res["ms_default"] + 1e-9
-    # the tuned factor: 64 x 64 tiles sum the same products in the same order
     assert np.array_equal(f.export_L()[2], L0)
-    f.set_tiles(np.full(bs.info["nlevels"], 64, np.int32))
-    f.numeric(vals)
-    assert np.array_equal(f.export_L()[2], L0)
+    for v in (0, 1, 2):
+        f.set_tiles(np.full(bs.info["nlevels"], v, np.int32))
+        f.numeric(vals)
+        assert np.array_equal(f.export_L()[2], L0), v
