@@ -814,6 +814,74 @@ __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ r
     }
 }
 
+// Vector form for row-major X with k = 4 LPE columns (LPE = 1, 2, 4, 8, 16):
+// one wave per row; a group of LPE lanes takes one matrix entry and four
+// columns per lane (two 16-byte loads of the X row), so one wave instruction
+// gathers the X rows of 64 / LPE entries at once.  Partial sums of the
+// groups are added with shuffles (fixed order).  Rows go to blocks in plain
+// order: consecutive rows of the dissection order share their X rows in L2.
+template <int LPE>
+__global__ __launch_bounds__(256) void k_spmv_vec(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ v, int n, const double *__restrict__ X,
+                                                  const double *__restrict__ B, double *__restrict__ R)
+{
+    constexpr int K = 4 * LPE, EPI = 64 / LPE, U = EPI >= 8 ? 1 : 8 / EPI;
+    int row = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (row >= n) return;
+    int q = lane / LPE, ql = lane % LPE;
+    int64_t a = rp[row], b = rp[row + 1];
+    const double2 *xc = reinterpret_cast<const double2 *>(X) + 2 * ql;
+    double s[4] = {0, 0, 0, 0};
+    for (int64_t q0 = a; q0 < b; q0 += 64) {
+        int cnt = (int)min((int64_t)64, b - q0);
+        int myc = lane < cnt ? __builtin_nontemporal_load(ci + q0 + lane) : 0;
+        double myv = lane < cnt ? __builtin_nontemporal_load(v + q0 + lane) : 0.0;
+        int t = 0;
+        for (; t + U * EPI <= cnt; t += U * EPI) {
+            double2 x0[U], x1[U];
+            double w[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                int e = t + EPI * u + q;
+                const double2 *pr = xc + (int64_t)__shfl(myc, e) * (K / 2);
+                x0[u] = pr[0];
+                x1[u] = pr[1];
+                w[u] = __shfl(myv, e);
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                s[0] += w[u] * x0[u].x;
+                s[1] += w[u] * x0[u].y;
+                s[2] += w[u] * x1[u].x;
+                s[3] += w[u] * x1[u].y;
+            }
+        }
+        for (; t < cnt; t += EPI) {
+            int e = t + q;
+            bool ok = e < cnt;
+            int cc = __shfl(myc, ok ? e : t);
+            double ww = __shfl(myv, ok ? e : t);
+            if (ok) {
+                const double2 *pr = xc + (int64_t)cc * (K / 2);
+                double2 a0 = pr[0], a1 = pr[1];
+                s[0] += ww * a0.x;
+                s[1] += ww * a0.y;
+                s[2] += ww * a1.x;
+                s[3] += ww * a1.y;
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= LPE; off >>= 1)
+#pragma unroll
+        for (int j = 0; j < 4; j++) s[j] += __shfl_down(s[j], off, 64);
+    if (q == 0) {
+        int64_t o = (int64_t)row * K + 4 * ql;
+#pragma unroll
+        for (int j = 0; j < 4; j++) R[o + j] = B ? B[o + j] - s[j] : s[j];
+    }
+}
+
 // Xp[i * k + c] = X[perm[i] + c * ld]  (caller column-major -> row-major pivot order)
 __global__ void k_gather_rows(const double *__restrict__ X, int64_t ld, const int32_t *__restrict__ perm, int n, int k,
                               double *__restrict__ Xp)
@@ -864,9 +932,6 @@ __global__ void k_add_unscaled(const T *__restrict__ Y, int64_t total, int k, co
     }
 }
 
-// Column reductions of a row-major n x k block in two passes with a fixed
-// order (deterministic): part[b * k + c] over the rows of block b, then
-// out[c] over the blocks.  op 0: sum of squares, op 1: max |a|.
 // Column reductions of a row-major n x k array, per segment of rows: op 0 sum
 // of squares, op 1 max |a|.  seg_ptr (nseg + 1 row offsets) splits the rows
 // into independent blocks; null means one segment [0, n).  Each segment gets

@@ -59,13 +59,19 @@ struct Op {
     int64_t off, cnt;    // tasks (update: 128 x 128 tiles)
     int64_t off64 = 0, cnt64 = 0;   // update: the same work as 64 x 64 tiles
 };
+struct SuperStep {
+    int32_t s0;                  // first pivot of the super-block
+    int64_t d_off, d_cnt;        // (front, 64-block of the super-block) tasks in sblk_tasks: X_S products
+    int64_t t_off, t_cnt;        // wide part: forward (front, 64-row tile) / backward (front, column block)
+};
 struct SolveLevel {
     int64_t fused_off = 0, fused_cnt = 0;          // fronts solved by one workgroup each (in slist)
-    int64_t step_off = 0, step_cnt = 0;            // fronts solved block by block (in slist)
-    std::pair<int64_t, int64_t> assemble{0, 0};                         // forward assembly tasks
-    std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> fwd;   // (kb, tasks)
-    std::pair<int64_t, int64_t> below{0, 0};                            // backward update-row tasks
-    std::vector<std::pair<int32_t, std::pair<int64_t, int64_t>>> bwd;   // (block b, tasks), b descending
+    int64_t step_off = 0, step_cnt = 0;            // fronts solved super-block by super-block (in slist)
+    std::pair<int64_t, int64_t> assemble{0, 0};    // forward assembly tasks
+    std::vector<SuperStep> fwd;                    // s0 ascending
+    std::pair<int64_t, int64_t> below{0, 0};       // backward update-row partial tasks (sbelow_tasks)
+    std::pair<int64_t, int64_t> below_sum{0, 0};   // ... and their sums (sbsum_tasks)
+    std::vector<SuperStep> bwd;                    // s0 descending
 };
 struct Level {
     SolveLevel sv;
@@ -92,7 +98,11 @@ struct Plan {
     std::vector<int32_t> child_ptr, child_list;
     std::vector<int32_t> colof;                   // column of each stored entry
     std::vector<int32_t> slist;                   // fronts per level for the solves (fused first, then stepped)
-    std::vector<int2> sfwd_tasks, sbelow_tasks, sbwd_tasks, sasm_tasks;
+    std::vector<int2> sfwd_tasks, sbwd_tasks, sasm_tasks, sblk_tasks;
+    std::vector<int4> sbelow_tasks, sbsum_tasks, xinv_tasks;
+    int64_t part_blocks = 0;                      // SB x k partial blocks of the split update-row sums
+    std::vector<int64_t> xoff;                    // per front: offset of its super-block inverses (-1: none)
+    int64_t xelems = 0;
 
     void build(const Symbolic &S)
     {
@@ -210,6 +220,12 @@ struct Plan {
         // solve schedule
         slist.clear();
         sfwd_tasks.clear();
+        sblk_tasks.clear();
+        sbsum_tasks.clear();
+        xinv_tasks.clear();
+        part_blocks = 0;
+        xoff.assign(ns, -1);
+        xelems = 0;
         sbelow_tasks.clear();
         sbwd_tasks.clear();
         sasm_tasks.clear();
@@ -232,29 +248,56 @@ struct Plan {
             for (int32_t s : big)
                 for (int32_t t = 0; t < (mfront[s] + SROWS - 1) / SROWS; t++) sasm_tasks.push_back(make_int2(s, t));
             V.assemble.second = (int64_t)sasm_tasks.size() - V.assemble.first;
-            for (int32_t kb = 0; kb < maxp; kb += SB) {
+            for (int32_t s : big) {
+                int32_t nsup = (pfront[s] + SS - 1) / SS;
+                xoff[s] = xelems;
+                xelems += (int64_t)nsup * SS * SS;
+                for (int32_t si = 0; si < nsup; si++) {
+                    int32_t nb = (std::min(pfront[s], (si + 1) * SS) - si * SS + SB - 1) / SB;
+                    for (int32_t jb = 0; jb < nb; jb++) xinv_tasks.push_back(make_int4(s, si, jb, 0));
+                }
+            }
+            auto blk_tasks = [&](int32_t s0) {
+                int64_t off = (int64_t)sblk_tasks.size();
+                for (int32_t s : big) {
+                    if (pfront[s] <= s0) continue;
+                    int32_t nb = (std::min(pfront[s], s0 + SS) - s0 + SB - 1) / SB;
+                    for (int32_t b = 0; b < nb; b++) sblk_tasks.push_back(make_int2(s, b));
+                }
+                return std::make_pair(off, (int64_t)sblk_tasks.size() - off);
+            };
+            for (int32_t s0 = 0; s0 < maxp; s0 += SS) {
+                auto d = blk_tasks(s0);
                 int64_t off = (int64_t)sfwd_tasks.size();
                 for (int32_t s : big) {
-                    if (pfront[s] <= kb) continue;
-                    int32_t nbk = std::min(SB, pfront[s] - kb);
-                    int32_t rows = mfront[s] - kb - nbk;
-                    int32_t nt = std::max(1, (rows + SROWS - 1) / SROWS);
+                    if (pfront[s] <= s0) continue;
+                    int32_t s1 = std::min(pfront[s], s0 + SS);
+                    int32_t nt = (mfront[s] - s1 + SB - 1) / SB;
                     for (int32_t t = 0; t < nt; t++) sfwd_tasks.push_back(make_int2(s, t));
                 }
-                V.fwd.push_back({kb, {off, (int64_t)sfwd_tasks.size() - off}});
+                V.fwd.push_back({s0, d.first, d.second, off, (int64_t)sfwd_tasks.size() - off});
             }
             V.below.first = (int64_t)sbelow_tasks.size();
+            V.below_sum.first = (int64_t)sbsum_tasks.size();
             for (int32_t s : big)
-                for (int32_t a = 0; a < (pfront[s] + SB - 1) / SB; a++) sbelow_tasks.push_back(make_int2(s, a));
+                for (int32_t a = 0; a < (pfront[s] + SB - 1) / SB; a++) {
+                    int64_t slot0 = part_blocks;
+                    for (int32_t r0 = pfront[s]; r0 < mfront[s]; r0 += BELOW_ROWS)
+                        sbelow_tasks.push_back(make_int4(s, a, r0, (int32_t)part_blocks++));
+                    sbsum_tasks.push_back(make_int4(s, a, (int32_t)slot0, (int32_t)(part_blocks - slot0)));
+                }
             V.below.second = (int64_t)sbelow_tasks.size() - V.below.first;
-            int32_t maxb = (maxp + SB - 1) / SB;
-            for (int32_t b = maxb - 1; b >= 0; b--) {
+            V.below_sum.second = (int64_t)sbsum_tasks.size() - V.below_sum.first;
+            int32_t nsup = (maxp + SS - 1) / SS;
+            for (int32_t si = nsup - 1; si >= 0; si--) {
+                int32_t s0 = si * SS;
+                auto d = blk_tasks(s0);
                 int64_t off = (int64_t)sbwd_tasks.size();
                 for (int32_t s : big) {
-                    if ((pfront[s] + SB - 1) / SB <= b) continue;
-                    for (int32_t a = 0; a <= b; a++) sbwd_tasks.push_back(make_int2(s, a));
+                    if (pfront[s] <= s0) continue;
+                    for (int32_t a = 0; a < s0 / SB; a++) sbwd_tasks.push_back(make_int2(s, a));
                 }
-                V.bwd.push_back({b, {off, (int64_t)sbwd_tasks.size() - off}});
+                V.bwd.push_back({s0, d.first, d.second, off, (int64_t)sbwd_tasks.size() - off});
             }
         }
         zero_tasks.clear();
@@ -275,6 +318,7 @@ struct Layout {
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
+    size_t sblk, sbsum, xinvt, xoff, xinv, part2;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -318,8 +362,14 @@ struct Layout {
         dinv = seg((size_t)P.dscr_elems * esz);
         slist = seg(std::max<size_t>(1, P.slist.size()) * 4);
         sfwd = seg(std::max<size_t>(1, P.sfwd_tasks.size()) * sizeof(int2));
-        sbelow = seg(std::max<size_t>(1, P.sbelow_tasks.size()) * sizeof(int2));
+        sbelow = seg(std::max<size_t>(1, P.sbelow_tasks.size()) * sizeof(int4));
         sbwd = seg(std::max<size_t>(1, P.sbwd_tasks.size()) * sizeof(int2));
+        sblk = seg(std::max<size_t>(1, P.sblk_tasks.size()) * sizeof(int2));
+        sbsum = seg(std::max<size_t>(1, P.sbsum_tasks.size()) * sizeof(int4));
+        xinvt = seg(std::max<size_t>(1, P.xinv_tasks.size()) * sizeof(int4));
+        xoff = seg(ns * 8);
+        xinv = seg((size_t)std::max<int64_t>(1, P.xelems) * esz);
+        part2 = seg((size_t)std::max<int64_t>(1, P.part_blocks) * SB * k * esz);
         sasm = seg(std::max<size_t>(1, P.sasm_tasks.size()) * sizeof(int2));
         part = seg(std::max<size_t>(kPartBlocks, nseg) * k * 8 * 2);
         segp = seg((nseg + 1) * 4);
@@ -582,6 +632,13 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                        pf, dso, dscr, fronts);
     PROF_END(KC_FILL);
     if (prof) prof->bytes[KC_FILL] += (double)P.dscr_elems * esz * 2;
+    if (!P.xinv_tasks.empty()) {
+        PROF_BEGIN(KC_FILL);
+        hipLaunchKernelGGL(k_build_xinv<T>, dim3((unsigned)P.xinv_tasks.size()), dim3(THREADS), 0, st,
+                           f->at<int4>(Lo.xinvt), fo, mf, pf, dso, f->at<int64_t>(Lo.xoff), fronts, dinv,
+                           f->at<T>(Lo.xinv));
+        PROF_END(KC_FILL);
+    }
     HIP_TRY(hipGetLastError());
     return WCS_OK;
 }
@@ -606,14 +663,19 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
     a.dscr_off = f->at<int64_t>(Lo.dscr_off);
     a.fronts = f->at<T>(Lo.fronts);
     a.dinv = f->at<T>(Lo.dinv);
+    a.xoff = f->at<int64_t>(Lo.xoff);
+    a.xinv = f->at<T>(Lo.xinv);
+    a.part = f->at<T>(Lo.part2);
     a.W = f->at<T>(Lo.W);
     a.Y = f->at<T>(Lo.Y);
     a.k = k;
     const int32_t *sl = f->at<int32_t>(Lo.slist);
     const int2 *tf = f->at<int2>(Lo.sfwd);
-    const int2 *tb = f->at<int2>(Lo.sbelow);
+    const int4 *tb = f->at<int4>(Lo.sbelow);
+    const int4 *tbs = f->at<int4>(Lo.sbsum);
     const int2 *ts = f->at<int2>(Lo.sbwd);
     const int2 *tas = f->at<int2>(Lo.sasm);
+    const int2 *sbk = f->at<int2>(Lo.sblk);
     if (part == WCS_SOLVE_FULL || part == WCS_SOLVE_L) {
         for (const Level &L : P.levels) {
             const SolveLevel &V = L.sv;
@@ -623,9 +685,13 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
             if (V.step_cnt) {
                 hipLaunchKernelGGL(k_fwd_assemble<T>, dim3((unsigned)V.assemble.second), dim3(THREADS), 0, st,
                                    tas + V.assemble.first, a);
-                for (auto &s : V.fwd)
-                    hipLaunchKernelGGL((k_fwd_step<T, KT>), dim3((unsigned)s.second.second), dim3(THREADS), 0, st,
-                                       tf + s.second.first, s.first, a);
+                for (const SuperStep &s : V.fwd) {
+                    hipLaunchKernelGGL((k_fwd_sz<T, KT>), dim3((unsigned)s.d_cnt), dim3(THREADS), 0, st,
+                                       sbk + s.d_off, s.s0, a);
+                    if (s.t_cnt)
+                        hipLaunchKernelGGL((k_fwd_srows<T, KT>), dim3((unsigned)s.t_cnt), dim3(THREADS), 0, st,
+                                           tf + s.t_off, s.s0, a);
+                }
             }
         }
     }
@@ -636,11 +702,18 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
                 hipLaunchKernelGGL((k_bwd_fused<T, KT>), dim3((unsigned)V.fused_cnt), dim3(THREADS), 0, st,
                                    sl + V.fused_off, a);
             if (V.step_cnt) {
-                hipLaunchKernelGGL((k_bwd_below<T, KT>), dim3((unsigned)V.below.second), dim3(THREADS), 0, st,
-                                   tb + V.below.first, a);
-                for (auto &s : V.bwd)
-                    hipLaunchKernelGGL((k_bwd_step<T, KT>), dim3((unsigned)s.second.second), dim3(THREADS), 0, st,
-                                       ts + s.second.first, s.first, a);
+                if (V.below.second)
+                    hipLaunchKernelGGL((k_bwd_below_part<T, KT>), dim3((unsigned)V.below.second), dim3(THREADS), 0,
+                                       st, tb + V.below.first, a);
+                hipLaunchKernelGGL(k_bwd_below_sum<T>, dim3((unsigned)V.below_sum.second), dim3(THREADS), 0, st,
+                                   tbs + V.below_sum.first, a);
+                for (const SuperStep &s : V.bwd) {
+                    hipLaunchKernelGGL((k_bwd_sx<T, KT>), dim3((unsigned)s.d_cnt), dim3(THREADS), 0, st,
+                                       sbk + s.d_off, s.s0, a);
+                    if (s.t_cnt)
+                        hipLaunchKernelGGL((k_bwd_scols<T, KT>), dim3((unsigned)s.t_cnt), dim3(THREADS), 0, st,
+                                           ts + s.t_off, s.s0, a);
+                }
             }
         }
     }
@@ -743,8 +816,17 @@ int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R
     const int64_t *rp = f->at<int64_t>(f->lay.csr_ptr);
     const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
     const double *v = f->at<double>(f->lay.csr_val);
-    if (k >= 8 && sx == k && sc == 1) {
-        int nrb = (n + 3) / 4, per = (nrb + 7) / 8;
+    unsigned nrb = (unsigned)((n + 3) / 4);
+    if (sx == k && sc == 1 && (k == 4 || k == 8 || k == 16 || k == 32 || k == 64)) {
+        switch (k) {
+        case 4: hipLaunchKernelGGL(k_spmv_vec<1>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
+        case 8: hipLaunchKernelGGL(k_spmv_vec<2>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
+        case 16: hipLaunchKernelGGL(k_spmv_vec<4>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
+        case 32: hipLaunchKernelGGL(k_spmv_vec<8>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
+        default: hipLaunchKernelGGL(k_spmv_vec<16>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
+        }
+    } else if (k >= 8 && sx == k && sc == 1) {
+        int per = ((int)nrb + 7) / 8;
         hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)(8 * per)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R);
     } else {
         hipLaunchKernelGGL(k_spmv_narrow, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R,
@@ -938,6 +1020,10 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.sfwd, P.sfwd_tasks, st);
     rc = rc ? rc : upload(f, L.sbelow, P.sbelow_tasks, st);
     rc = rc ? rc : upload(f, L.sbwd, P.sbwd_tasks, st);
+    rc = rc ? rc : upload(f, L.sblk, P.sblk_tasks, st);
+    rc = rc ? rc : upload(f, L.sbsum, P.sbsum_tasks, st);
+    rc = rc ? rc : upload(f, L.xinvt, P.xinv_tasks, st);
+    rc = rc ? rc : upload(f, L.xoff, P.xoff, st);
     rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
     rc = rc ? rc : upload(f, L.ztasks, P.zero_tasks, st);
     std::vector<int32_t> segp = S.seg_ptr.size() >= 2 ? S.seg_ptr : std::vector<int32_t>{0, S.n};

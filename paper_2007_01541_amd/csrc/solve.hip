@@ -9,10 +9,13 @@
 //   backward (x = L^-T y):   v = y_pivots - L_update,:^T x_update, then from the last
 //                            block down: x_b = L_bb^-T v_b,  v_a -= L_b,a^T x_b (a < b).
 // Fronts with few rows run one workgroup per front for the whole sweep
-// ("fused"); larger fronts run one launch per 64-column block with the rows
-// (forward) or column blocks (backward) spread over workgroups.  With 64
-// right-hand sides at a time the block products run on the matrix cores.
-// Summation order is fixed everywhere, so results are deterministic.
+// ("fused").  Larger fronts go super-block by super-block (SS = 256 pivots):
+// one workgroup per front solves the (at most four) 64-blocks of the
+// super-block in sequence, then one wide launch applies the whole super-block
+// to every row below it (forward) or to every earlier column block (backward)
+// with K = 256.  With 64 right-hand sides at a time the block products run on
+// the matrix cores.  Summation order is fixed everywhere, so results are
+// deterministic.
 
 namespace wcs {
 namespace dev {
@@ -26,12 +29,16 @@ template <typename T> struct SolveArgs {
     const int32_t *rel, *rows;
     const int64_t *dscr_off;
     const T *fronts, *dinv;
+    const int64_t *xoff;        // per front: element offset of its super-block inverses (-1: none)
+    const T *xinv;
     T *W, *Y;
+    T *part;                    // partial products of the split backward update-row sums
     int k;
 };
 
 constexpr int SB = 64;          // block size of the solves (= panel width of the factorization)
-constexpr int SROWS = THREADS;  // rows per workgroup in a forward block step
+constexpr int SS = 4 * SB;      // super-block of the large-front sweeps
+constexpr int SROWS = THREADS;  // rows per workgroup in a forward row launch
 
 // ---- shared pieces (all threads of the workgroup call them)
 
@@ -370,33 +377,6 @@ __global__ __launch_bounds__(THREADS) void k_fwd_assemble(const int2 *__restrict
     }
 }
 
-// task = (front, row slab) for block kb; slab 0 also stores z_b into Y.  The
-// block rows w_b are only read in this launch (z goes to Y), so the
-// workgroups of one launch never race.
-template <typename T, int KT>
-__global__ __launch_bounds__(THREADS) void k_fwd_step(const int2 *__restrict__ tasks, int kb, SolveArgs<T> a)
-{
-    __shared__ SolveLds<T, KT> sh;
-    int2 t = tasks[blockIdx.x];
-    int f = t.x;
-    int m = a.mfront[f], p = a.pfront[f], k = a.k, f0 = a.first[f];
-    int nbk = min(SB, p - kb);
-    const T *L = a.fronts + a.front_off[f];
-    T *w = a.W + a.woff[f] * k;
-    int r0 = kb + nbk + t.y * SROWS, r1 = min(m, r0 + SROWS);
-    for (int c0 = 0; c0 < k; c0 += KT) {
-        __syncthreads();
-        block_apply<T, KT>(a.dinv + a.dscr_off[f] + (int64_t)(kb / SB) * SB * SB, w + (int64_t)kb * k, k, c0, nbk,
-                           false, sh.Ds, sh.Ss, sh.Zs);
-        if (t.y == 0)
-            for (int i = threadIdx.x; i < nbk * KT; i += blockDim.x) {
-                int r = i / KT, c = i % KT;
-                if (c0 + c < k) a.Y[(int64_t)(f0 + kb + r) * k + c0 + c] = sh.Zs[r][c];
-            }
-        if (r0 < r1) fwd_rows_any<T, KT>(L, front_ld(m), kb, nbk, w, k, c0, r0, r1, sh.Zs);
-    }
-}
-
 // ---- backward
 
 template <typename T, int KT> struct BwdLds {
@@ -455,42 +435,341 @@ __global__ __launch_bounds__(THREADS) void k_bwd_fused(const int32_t *__restrict
     }
 }
 
-// task = (front, column block a): v_a = y_a - L(update rows, a)^T x(update rows)
+
+// ---- super-block sweeps of large fronts
+//
+// X_S = L_SS^-1 of every diagonal super-block S = [s0, s1) of a large front is
+// built once per factorization (k_build_xinv): column-major SS x SS at
+// xinv + xoff[f] + (s0 / SS) SS^2, element (r, c) at c SS + r, lower block
+// triangle filled (64-blocks X_ij, i >= j).  A super-step is then two wide
+// launches: forward z_S = X_S w_S, then w_r -= L(r, S) z_S for every row
+// below; backward x_S = X_S^T v_S, then v_a -= L(S, a)^T x_S for every
+// column block before S.
+
+// acc (+)= op(D) S over a 64-deep product staged in LDS: D[j][i] is the
+// factor applied to S row j for output row i.  Matrix cores for 64
+// right-hand sides (wave w owns output rows [16w, 16w+16)); otherwise each
+// thread owns outputs t, t + 256, ... of the 64 x KT block.
+template <typename T, int KT> struct BlkAcc {
+    static constexpr int NQ = KT == 64 ? 4 : (SB * KT + THREADS - 1) / THREADS;
+    typename Mfma<T>::V v[4];
+    T f[NQ];
+    __device__ void zero()
+    {
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) v[q][e] = 0;
+#pragma unroll
+        for (int q = 0; q < NQ; q++) f[q] = 0;
+    }
+    __device__ void add(T (*D)[SB + 1], T (*S)[KT])
+    {
+        if constexpr (KT == 64) {
+            int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+#pragma unroll
+            for (int kk = 0; kk < SB; kk += 4) {
+                T av = D[kk + kq][wave * 16 + ln];
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++) v[cb] = Mfma<T>::mma(av, S[kk + kq][cb * 16 + ln], v[cb]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                int idx = threadIdx.x + q * THREADS;
+                if (idx < SB * KT) {
+                    int r = idx / KT, c = idx % KT;
+                    T s = 0;
+#pragma unroll 8
+                    for (int j = 0; j < SB; j++) s += D[j][r] * S[j][c];
+                    f[q] += s;
+                }
+            }
+        }
+    }
+    // out(r, c) for r < nr, c0 + c < k: fn(r, c, value)
+    template <typename Fn> __device__ void store(int nr, int k, int c0, Fn fn)
+    {
+        if constexpr (KT == 64) {
+            int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int r = wave * 16 + Mfma<T>::row(kq, e), c = cb * 16 + ln;
+                    if (r < nr && c0 + c < k) fn(r, c, v[cb][e]);
+                }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NQ; q++) {
+                int idx = threadIdx.x + q * THREADS;
+                if (idx < SB * KT) {
+                    int r = idx / KT, c = idx % KT;
+                    if (r < nr && c0 + c < k) fn(r, c, f[q]);
+                }
+            }
+        }
+    }
+};
+
+template <typename T, int KT> struct SxLds {
+    T D[SB][SB + 1];
+    T S[SB][KT];
+};
+
+// forward, task = (front, block i of the super-block at s0): z_i = sum_{j <= i} X_ij w_j -> Y
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS) void k_bwd_below(const int2 *__restrict__ tasks, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS) void k_fwd_sz(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
-    __shared__ BwdLds<T, KT> sh;
+    __shared__ SxLds<T, KT> sh;
     int2 t = tasks[blockIdx.x];
-    bwd_below<T, KT>(a, t.x, t.y * SB, sh.Ls, sh.Ss);
+    int f = t.x, ib = t.y;
+    int p = a.pfront[f], k = a.k, f0 = a.first[f];
+    int s1 = min(p, s0 + SS);
+    int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
+    const T *X = a.xinv + a.xoff[f] + (int64_t)(s0 / SS) * SS * SS;
+    const T *w = a.W + a.woff[f] * k;
+    BlkAcc<T, KT> acc;
+    for (int c0 = 0; c0 < k; c0 += KT) {
+        acc.zero();
+        for (int jb = 0; jb <= ib; jb++) {
+            int j0 = s0 + jb * SB, nj = min(SB, s1 - j0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < SB * SB; e += THREADS) {
+                int j = e / SB, i = e % SB;    // X column j, row i: X(i0 + i, j0 + j)
+                sh.D[j][i] = (i < ni && j < nj) ? X[(int64_t)(j0 - s0 + j) * SS + (i0 - s0 + i)] : (T)0;
+            }
+            for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
+                int j = e / KT, c = e % KT;
+                sh.S[j][c] = (j < nj && c0 + c < k) ? w[(int64_t)(j0 + j) * k + c0 + c] : (T)0;
+            }
+            __syncthreads();
+            acc.add(sh.D, sh.S);
+        }
+        acc.store(ni, k, c0, [&](int r, int c, T val) { a.Y[(int64_t)(f0 + i0 + r) * k + c0 + c] = val; });
+    }
 }
 
-// task = (front, column block a) for block b: x_b = L_bb^-T v_b (every
-// workgroup); a == b stores x_b into Y, a < b updates v_a.  v_b is only read.
+// forward, task = (front, 64-row tile below s1): w_r -= sum over the blocks b of
+// the super-block of L(r, b) z_b (z from Y); wave w takes rows [16w, 16w+16)
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS) void k_bwd_step(const int2 *__restrict__ tasks, int b, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS) void k_fwd_srows(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+{
+    __shared__ T Zs[SB][KT];
+    int2 t = tasks[blockIdx.x];
+    int f = t.x;
+    int m = a.mfront[f], p = a.pfront[f], k = a.k, f0 = a.first[f], ld = front_ld(m);
+    int s1 = min(p, s0 + SS);
+    int r0 = s1 + t.y * SB, r1 = min(m, r0 + SB);
+    const T *L = a.fronts + a.front_off[f];
+    T *w = a.W + a.woff[f] * k;
+    for (int c0 = 0; c0 < k; c0 += KT) {
+        if constexpr (KT == 64) {
+            typedef typename Mfma<T>::V V;
+            int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+            V acc[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) acc[cb][e] = 0;
+            int r = r0 + wave * 16 + ln;
+            for (int kb = s0; kb < s1; kb += SB) {
+                int nbk = min(SB, s1 - kb);
+                __syncthreads();
+                for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
+                    int j = e / KT, c = e % KT;
+                    Zs[j][c] = (j < nbk && c0 + c < k) ? a.Y[(int64_t)(f0 + kb + j) * k + c0 + c] : (T)0;
+                }
+                T av[SB / 4];
+#pragma unroll
+                for (int ks = 0; ks < SB / 4; ks++) {
+                    int j = ks * 4 + kq;
+                    av[ks] = (r < r1 && j < nbk) ? L[(int64_t)(kb + j) * ld + r] : (T)0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int ks = 0; ks < SB / 4; ks++)
+#pragma unroll
+                    for (int cb = 0; cb < 4; cb++) acc[cb] = Mfma<T>::mma(av[ks], Zs[ks * 4 + kq][cb * 16 + ln], acc[cb]);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int rr = r0 + wave * 16 + Mfma<T>::row(kq, e);
+                if (rr >= r1) continue;
+                T *wr = w + (int64_t)rr * k + c0;
+#pragma unroll
+                for (int cb = 0; cb < 4; cb++)
+                    if (c0 + cb * 16 + ln < k) wr[cb * 16 + ln] -= acc[cb][e];
+            }
+        } else {
+            for (int kb = s0; kb < s1; kb += SB) {
+                int nbk = min(SB, s1 - kb);
+                __syncthreads();
+                for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
+                    int j = e / KT, c = e % KT;
+                    Zs[j][c] = (j < nbk && c0 + c < k) ? a.Y[(int64_t)(f0 + kb + j) * k + c0 + c] : (T)0;
+                }
+                __syncthreads();
+                fwd_rows<T, KT>(L, ld, kb, nbk, w, k, c0, r0, r1, Zs);
+            }
+        }
+    }
+}
+
+// backward, task = (front, block j of the super-block at s0): x_j = sum_{i >= j} X_ij^T v_i -> Y
+template <typename T, int KT>
+__global__ __launch_bounds__(THREADS) void k_bwd_sx(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+{
+    __shared__ SxLds<T, KT> sh;
+    int2 t = tasks[blockIdx.x];
+    int f = t.x, jb = t.y;
+    int p = a.pfront[f], k = a.k, f0 = a.first[f];
+    int s1 = min(p, s0 + SS);
+    int nblk = (s1 - s0 + SB - 1) / SB;
+    int j0 = s0 + jb * SB, nj = min(SB, s1 - j0);
+    const T *X = a.xinv + a.xoff[f] + (int64_t)(s0 / SS) * SS * SS;
+    const T *w = a.W + a.woff[f] * k;
+    BlkAcc<T, KT> acc;
+    for (int c0 = 0; c0 < k; c0 += KT) {
+        acc.zero();
+        for (int ib = jb; ib < nblk; ib++) {
+            int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < SB * SB; e += THREADS) {
+                int jj = e / SB, i = e % SB;   // X(i0 + i, j0 + jj), applied to v row i for output jj
+                sh.D[i][jj] = (i < ni && jj < nj) ? X[(int64_t)(j0 - s0 + jj) * SS + (i0 - s0 + i)] : (T)0;
+            }
+            for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
+                int i = e / KT, c = e % KT;
+                sh.S[i][c] = (i < ni && c0 + c < k) ? w[(int64_t)(i0 + i) * k + c0 + c] : (T)0;
+            }
+            __syncthreads();
+            acc.add(sh.D, sh.S);
+        }
+        acc.store(nj, k, c0, [&](int r, int c, T val) { a.Y[(int64_t)(f0 + j0 + r) * k + c0 + c] = val; });
+    }
+}
+
+// backward, task = (front, column block a) with 64 a < s0: v_a -= L([s0, s1), a)^T x_[s0, s1)
+// (x read from Y); each workgroup owns its block a
+template <typename T, int KT>
+__global__ __launch_bounds__(THREADS) void k_bwd_scols(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     __shared__ BwdLds<T, KT> sh;
     int2 t = tasks[blockIdx.x];
     int f = t.x;
-    int p = a.pfront[f], k = a.k, f0 = a.first[f];
-    int kb = b * SB, nbk = min(SB, p - kb);
+    int m = a.mfront[f], p = a.pfront[f], k = a.k, f0 = a.first[f];
+    int s1 = min(p, s0 + SS);
+    int ab = t.y * SB;
     const T *L = a.fronts + a.front_off[f];
     T *w = a.W + a.woff[f] * k;
-    for (int c0 = 0; c0 < k; c0 += KT) {
-        __syncthreads();
-        block_apply<T, KT>(a.dinv + a.dscr_off[f] + (int64_t)b * SB * SB, w + (int64_t)kb * k, k, c0, nbk, true,
-                           sh.Ds, sh.Ss, sh.Zs);
-        if (t.y == b) {
-            for (int i = threadIdx.x; i < nbk * KT; i += blockDim.x) {
-                int r = i / KT, c = i % KT;
-                if (c0 + c < k) a.Y[(int64_t)(f0 + kb + r) * k + c0 + c] = sh.Zs[r][c];
+    const T *Y = a.Y;
+    auto xrow = [&](int r) { return Y + (int64_t)(f0 + r) * k; };
+    for (int c0 = 0; c0 < k; c0 += KT)
+        bwd_cols_any<T, KT>(L, front_ld(m), ab, SB, s0, s1, xrow, k, c0, w + (int64_t)ab * k, sh.Ls, sh.Ss);
+}
+
+// backward update rows, split: task = (front, column block a, first row, slot):
+// part[slot] = -L(rows [r0, r0 + BELOW_ROWS) of the update part, a)^T x(rows)
+constexpr int BELOW_ROWS = 512;
+template <typename T, int KT>
+__global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restrict__ tasks, SolveArgs<T> a)
+{
+    __shared__ BwdLds<T, KT> sh;
+    int4 t = tasks[blockIdx.x];
+    int f = t.x, ab = t.y * SB, r0 = t.z;
+    int m = a.mfront[f], p = a.pfront[f], k = a.k;
+    int na = min(SB, p - ab), r1 = min(m, r0 + BELOW_ROWS);
+    const T *L = a.fronts + a.front_off[f];
+    T *out = a.part + (int64_t)t.w * SB * k;
+    for (int64_t i = threadIdx.x; i < (int64_t)SB * k; i += blockDim.x) out[i] = (T)0;
+    const int32_t *rw = a.rows + a.rptr[f];
+    const T *Y = a.Y;
+    auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
+    for (int c0 = 0; c0 < k; c0 += KT)
+        bwd_cols_any<T, KT>(L, front_ld(m), ab, na, r0, r1, xrow, k, c0, out, sh.Ls, sh.Ss);
+}
+
+// task = (front, column block a, first slot, slots): v_a = y_a + sum of the partial blocks (in slot order)
+template <typename T>
+__global__ __launch_bounds__(THREADS) void k_bwd_below_sum(const int4 *__restrict__ tasks, SolveArgs<T> a)
+{
+    int4 t = tasks[blockIdx.x];
+    int f = t.x, ab = t.y * SB;
+    int p = a.pfront[f], k = a.k, f0 = a.first[f];
+    int na = min(SB, p - ab);
+    T *w = a.W + a.woff[f] * k + (int64_t)ab * k;
+    const T *y = a.Y + (int64_t)(f0 + ab) * k;
+    for (int64_t i = threadIdx.x; i < (int64_t)na * k; i += blockDim.x) {
+        T s = y[i];
+        for (int q = 0; q < t.w; q++) s += a.part[(int64_t)(t.z + q) * SB * k + i];
+        w[i] = s;
+    }
+}
+
+// ---- super-block inverses (after the factorization)
+// task = (front, super-block index si, column block jb): X_jj = L_jj^-1 (the
+// stored 64-block inverse), then for i > j: X_ij = -L_ii^-1 sum_{j <= q < i} L_iq X_qj.
+// Rows and columns past the end of the super-block are zero.
+template <typename T>
+__global__ __launch_bounds__(THREADS) void k_build_xinv(const int4 *__restrict__ tasks, const int64_t *__restrict__ front_off,
+                                                        const int32_t *__restrict__ mfront,
+                                                        const int32_t *__restrict__ pfront,
+                                                        const int64_t *__restrict__ dscr_off,
+                                                        const int64_t *__restrict__ xoff, const T *__restrict__ fronts,
+                                                        const T *__restrict__ dinv, T *__restrict__ xinv)
+{
+    __shared__ T D[SB][SB + 1];
+    __shared__ T S[SB][64];
+    int4 t = tasks[blockIdx.x];
+    int f = t.x, s0 = t.y * SS, jb = t.z;
+    int m = mfront[f], p = pfront[f], ld = front_ld(m);
+    int s1 = min(p, s0 + SS);
+    int nblk = (s1 - s0 + SB - 1) / SB;
+    int j0 = s0 + jb * SB, nj = min(SB, s1 - j0);
+    const T *L = fronts + front_off[f];
+    T *X = xinv + xoff[f] + (int64_t)t.y * SS * SS;
+    auto Xat = [&](int ib, int r, int c) -> T & { return X[(int64_t)(jb * SB + c) * SS + ib * SB + r]; };
+    // X_jj: the stored inverse of block j (column-major 64 x 64, identity-padded)
+    const T *Dj = dinv + dscr_off[f] + (int64_t)(j0 / SB) * SB * SB;
+    for (int e = threadIdx.x; e < SB * SB; e += THREADS) {
+        int c = e / SB, r = e % SB;
+        Xat(jb, r, c) = (r < nj && c < nj) ? Dj[e] : (T)0;
+    }
+    for (int ib = jb + 1; ib < nblk; ib++) {
+        int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
+        BlkAcc<T, 64> acc;
+        acc.zero();
+        // T_i = sum_q L_iq X_qj
+        for (int qb = jb; qb < ib; qb++) {
+            int q0 = s0 + qb * SB, nq = min(SB, s1 - q0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < SB * SB; e += THREADS) {
+                int q = e / SB, i = e % SB;            // L(i0 + i, q0 + q) applied to X row q for output row i
+                D[q][i] = (i < ni && q < nq) ? L[(int64_t)(q0 + q) * ld + i0 + i] : (T)0;
             }
-        } else {
-            T(*Zs)[KT] = sh.Zs;
-            auto xrow = [&](int r) { return &Zs[r - kb][0] - c0; };
-            bwd_cols_any<T, KT>(L, front_ld(a.mfront[f]), t.y * SB, SB, kb, kb + nbk, xrow, k, c0, w + (int64_t)t.y * SB * k,
-                                sh.Ls, sh.Ss);
+            for (int e = threadIdx.x; e < SB * 64; e += THREADS) {
+                int q = e / 64, c = e % 64;
+                S[q][c] = Xat(qb, q, c);
+            }
+            __syncthreads();
+            acc.add(D, S);
         }
+        __syncthreads();
+        acc.store(SB, 64, 0, [&](int r, int c, T val) { S[r][c] = val; });
+        // X_ij = -L_ii^-1 T_i
+        const T *Di = dinv + dscr_off[f] + (int64_t)(i0 / SB) * SB * SB;
+        for (int e = threadIdx.x; e < SB * SB; e += THREADS) {
+            int c = e / SB, r = e % SB;                 // Linv(r, c) applied to T row c for output row r
+            D[c][r] = Di[e];
+        }
+        __syncthreads();
+        BlkAcc<T, 64> res;
+        res.zero();
+        res.add(D, S);
+        __syncthreads();
+        res.store(SB, 64, 0, [&](int r, int c, T val) { Xat(ib, r, c) = (r < ni && c < nj) ? -val : (T)0; });
+        __syncthreads();
     }
 }
 

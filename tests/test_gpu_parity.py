@@ -134,12 +134,13 @@ def test_refinement_not_converged_reports():
     assert e.value.code == -5 and e.value.report["iterations"] == 0
 
 
-def test_spmv_matches_oracle():
+@pytest.mark.parametrize("k", [1, 3, 4, 8, 9, 16, 32, 64, 70])
+def test_spmv_matches_oracle(k):
     m, sym, _ = prepared("small")
-    X = normal_rhs(m["n"], 3, 4)
-    f = Factor(sym, FP64, max_nrhs=3)
-    Y = f.spmv(dev(X), dev(m["values"])).cpu().numpy()
-    Yo = oracle.symv(m["n"], m["colptr"], m["rowind"], m["values"], X)
+    X = normal_rhs(m["n"], k, 4)
+    f = Factor(sym, FP64, max_nrhs=k)
+    Y = f.spmv(dev(X), dev(m["values"])).cpu().numpy().reshape(m["n"], k)
+    Yo = oracle.symv(m["n"], m["colptr"], m["rowind"], m["values"], X).reshape(m["n"], k)
     assert np.abs(Y - Yo).max() <= 1e-13 * np.abs(Yo).max()
 
 
@@ -193,3 +194,22 @@ def test_refactor_and_determinism():
     assert np.array_equal(a, c)                      # bitwise reproducible
     # L(2A) = sqrt(2) L(A): exact up to rounding, measured against max |L|
     assert np.abs(b - a * np.sqrt(2.0)).max() <= 1e-13 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("kind,leaf,coords", CASES)
+@pytest.mark.parametrize("k", [1, 9, 64, 70])
+def test_solve_all_fronts_by_super_blocks(kind, leaf, coords, k, monkeypatch):
+    """Every front through the super-block path (the plan reads the routing
+    threshold when the factor is created): same solution as the oracle."""
+    monkeypatch.setenv("WCS_SOLVE_STEP_ROWS", "16")
+    m, sym, orc = prepared(kind, leaf, coords)
+    n = m["n"]
+    B = normal_rhs(n, k, 78)
+    for prec, eps in ((FP64, EPS64), (FP32, EPS32)):
+        f = Factor(sym, prec, max_nrhs=k)
+        f.numeric(dev(m["values"]))
+        X = f.solve(dev(B)).cpu().numpy()
+        Xo = orc.solve(B)
+        tol = factor_tol(m, int(orc.colcount.max()), eps)
+        print(f"case {kind} k={k} prec={prec}", flush=True)
+        assert np.abs(X - Xo).max() <= tol * np.abs(Xo).max()
