@@ -58,6 +58,10 @@ struct Op {
     int32_t ka, kw;      // panel: ka = k0; update: columns [ka, ka + min(kw, p - ka)) form K
     int64_t off, cnt;    // tasks (update: 128 x 128 tiles)
     int64_t off64 = 0, cnt64 = 0;   // update: the same work as 64 x 64 tiles
+    // look-ahead: the part of an outer block's trailing update beyond the next
+    // outer block's pivot columns runs on the side stream (side); the update of
+    // those next pivot columns by the following block first waits for it (join)
+    bool side = false, join = false;
 };
 struct SuperStep {
     int32_t s0;                  // first pivot of the super-block
@@ -201,20 +205,29 @@ struct Plan {
                     }
                     if (up.cnt) L.ops.push_back(up);
                 }
-                Op up{OP_UPDATE, K0, NBO, 0, 0};
-                for (int v = 0; v < 2; v++) {
-                    tw = v == 0 ? UT : 64;
-                    int64_t o = (int64_t)upd_tasks.size();
-                    for (int32_t s : fr) {
-                        int32_t p = pfront[s], m = mfront[s];
-                        if (p <= K0) continue;
-                        int32_t kend = K0 + std::min(NBO, p - K0);
-                        if (kend < m) tiles(s, kend, m);
+                // trailing update with the outer block (K = NBO): first the next outer
+                // block's pivot columns (main stream), then everything to their right
+                // (side stream, overlapping the next block's panels)
+                for (int part = 0; part < 2; part++) {
+                    Op up{OP_UPDATE, K0, NBO, 0, 0};
+                    up.side = part == 1;
+                    up.join = part == 0 && K0 > 0;
+                    for (int v = 0; v < 2; v++) {
+                        tw = v == 0 ? UT : 64;
+                        int64_t o = (int64_t)upd_tasks.size();
+                        for (int32_t s : fr) {
+                            int32_t p = pfront[s], m = mfront[s];
+                            if (p <= K0) continue;
+                            int32_t kend = K0 + std::min(NBO, p - K0);
+                            int32_t nend = kend < p ? std::min(p, kend + NBO) : kend;
+                            if (part == 0 && kend < nend) tiles(s, kend, nend);
+                            if (part == 1 && nend < m) tiles(s, nend, m);
+                        }
+                        (v == 0 ? up.off : up.off64) = o;
+                        (v == 0 ? up.cnt : up.cnt64) = (int64_t)upd_tasks.size() - o;
                     }
-                    (v == 0 ? up.off : up.off64) = o;
-                    (v == 0 ? up.cnt : up.cnt64) = (int64_t)upd_tasks.size() - o;
+                    if (up.cnt || up.join) L.ops.push_back(up);
                 }
-                if (up.cnt) L.ops.push_back(up);
             }
         }
         // solve schedule
@@ -417,6 +430,10 @@ struct wcs_factor_s {
     };
     std::vector<SweepGraph> sgraphs;           // triangular sweeps per (part, nrhs)
 
+    // look-ahead: side stream (default priority) and the two events that order it
+    hipStream_t side = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+
     void drop_graphs()
     {
         if (fgraph) (void)hipGraphExecDestroy(fgraph);
@@ -425,7 +442,13 @@ struct wcs_factor_s {
         for (auto &g : sgraphs) (void)hipGraphExecDestroy(g.exec);
         sgraphs.clear();
     }
-    ~wcs_factor_s() { drop_graphs(); }
+    ~wcs_factor_s()
+    {
+        drop_graphs();
+        if (ev_main) (void)hipEventDestroy(ev_main);
+        if (ev_side) (void)hipEventDestroy(ev_side);
+        if (side) (void)hipStreamDestroy(side);
+    }
 
     template <typename P> P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
 };
@@ -564,6 +587,11 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     const int64_t *dso = f->at<int64_t>(Lo.dscr_off);
     T *dscr = f->at<T>(Lo.dscr);
     T *dinv = f->at<T>(Lo.dinv);
+    // trailing updates marked `side` go to the side stream (not while timing
+    // kernel classes, whose events time one stream; level timing is fine, as
+    // every level joins the side stream before its closing event)
+    hipStream_t side = ((prof && !prof->levels) || !f->side) ? st : f->side;
+    bool pending = false;   // side-stream work not yet joined into st
     for (size_t h = 0; h < P.levels.size(); h++) {
         const Level &L = P.levels[h];
         if (prof && prof->levels) {
@@ -593,17 +621,32 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
             if (op.kind == OP_UPDATE) {
                 bool small = L.upd_var == WCS_UPD_REG64;
                 int64_t off = small ? op.off64 : op.off, cnt = small ? op.cnt64 : op.cnt;
+                if (op.join && pending) {
+                    HIP_TRY(hipStreamWaitEvent(st, f->ev_side, 0));
+                    pending = false;
+                }
+                if (cnt == 0) continue;
+                hipStream_t us = st;
+                if (op.side && side != st) {
+                    HIP_TRY(hipEventRecord(f->ev_main, st));
+                    HIP_TRY(hipStreamWaitEvent(side, f->ev_main, 0));
+                    us = side;
+                }
                 PROF_BEGIN(KC_UPDATE);
                 if (small)
-                    hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, st, upd + off, op.ka,
+                    hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, us, upd + off, op.ka,
                                        op.kw, fo, mf, pf, fronts);
                 else if (L.upd_var == WCS_UPD_STREAM128)
-                    hipLaunchKernelGGL(k_update_dma<T>, dim3((unsigned)cnt), dim3(256), 0, st, upd + off, op.ka,
+                    hipLaunchKernelGGL(k_update_dma<T>, dim3((unsigned)cnt), dim3(256), 0, us, upd + off, op.ka,
                                        op.kw, fo, mf, pf, fronts);
                 else
-                    hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, st, upd + off,
+                    hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, us, upd + off,
                                        op.ka, op.kw, fo, mf, pf, fronts);
                 PROF_END(KC_UPDATE);
+                if (us != st) {
+                    HIP_TRY(hipEventRecord(f->ev_side, side));
+                    pending = true;
+                }
                 if (prof)
                     for (int64_t q = off; q < off + cnt; q++)
                         prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], op.ka, op.kw, small ? 64 : UT);
@@ -621,6 +664,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                     for (int64_t q = op.off; q < op.off + op.cnt; q++)
                         if (P.pan_tasks[q].y == 0) prof->flops[c] += panel_flops(P, P.pan_tasks[q].x, op.ka);
             }
+        }
+        if (pending) {   // the next level's extend-add reads this level's update matrices
+            HIP_TRY(hipStreamWaitEvent(st, f->ev_side, 0));
+            pending = false;
         }
         if (prof && prof->levels) {
             int r_ = prof->mark(prof->lev);
@@ -986,6 +1033,13 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     }
     f->ws = (char *)workspace;
     f->bytes = bytes;
+    if (hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&f->ev_main, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&f->ev_side, hipEventDisableTiming) != hipSuccess) {
+        set_error("could not create the look-ahead stream or its events");
+        delete f;
+        return WCS_EHIP;
+    }
     hipStream_t st = (hipStream_t)stream;
     const Symbolic &S = *f->S;
     const Plan &P = f->plan;
