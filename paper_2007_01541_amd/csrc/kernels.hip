@@ -104,11 +104,26 @@ __global__ void k_extend_add(const int2 *__restrict__ tasks, const int64_t *__re
     T *Fp = fronts + front_off[par];
     const int32_t *rl = rel + rptr[c] + pc;
     int c1 = min(t.y + EA_COLS, nu);
+    constexpr int B = 4;   // rows per thread per round: all loads of a round before its stores
     for (int col = t.y; col < c1; col++) {
         int pcol = rl[col];
         const T *u = U + (int64_t)col * ldc;
         T *dst = Fp + (int64_t)pcol * ldp;
-        for (int r = col + threadIdx.x; r < nu; r += blockDim.x) dst[rl[r]] += u[r];
+        for (int r0 = col + threadIdx.x; r0 < nu; r0 += B * blockDim.x) {
+            int pr[B];
+            T uv[B], dv[B];
+#pragma unroll
+            for (int b = 0; b < B; b++) {
+                int r = r0 + b * blockDim.x;
+                pr[b] = r < nu ? rl[r] : -1;
+                uv[b] = r < nu ? u[r] : (T)0;
+            }
+#pragma unroll
+            for (int b = 0; b < B; b++) dv[b] = dst[pr[b] >= 0 ? pr[b] : 0];
+#pragma unroll
+            for (int b = 0; b < B; b++)
+                if (pr[b] >= 0) dst[pr[b]] = dv[b] + uv[b];
+        }
     }
 }
 
@@ -123,6 +138,23 @@ __device__ __forceinline__ double readlane(double v, int l)
     int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
     int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
     return __hiloint2double(hi, lo);
+}
+
+// 1 / sqrt(d) to working precision: the hardware estimate refined by Newton
+// steps r <- r (3 - d r^2) / 2 (two for FP64, one for FP32), so that a pivot
+// costs one square-root estimate and multiplications instead of a correctly
+// rounded square root and divisions.
+__device__ __forceinline__ double rsqrt_refined(double d)
+{
+    double r = __builtin_amdgcn_rsq(d);
+    r = r * (1.5 - 0.5 * d * r * r);
+    r = r * (1.5 - 0.5 * d * r * r);
+    return r;
+}
+__device__ __forceinline__ float rsqrt_refined(float d)
+{
+    float r = __builtin_amdgcn_rsqf(d);
+    return r * (1.5f - 0.5f * d * r * r);
 }
 
 // 16 x 16 x 16 product on one wave: acc += X * Y with X(r, k) = fx(r, k),
@@ -169,6 +201,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
     typedef typename Mfma<TD>::V VD;
     __shared__ TD A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L
     __shared__ TD Iv[NB][NB + 1];    // column-major: Iv[c][r] = L^-1(r, c)
+    __shared__ TD Rd[NB];            // 1 / L(r, r)
     __shared__ T Li[NB][NB + 1];     // row-major copy of L^-1 in the panel precision
     int2 t = tasks[blockIdx.x];
     int f = t.x;
@@ -209,9 +242,11 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
                         if (lane == 0 && t.y == 0 && kb + u < nb) atomicMin(bad, first[f] + k0 + kb + u);
                         d = (TD)1;
                     }
-                    TD piv = sqrt(d);
-                    TD l = (lane == u) ? piv : a[u] / piv;
+                    TD rp = rsqrt_refined(d);
+                    TD piv = d * rp;
+                    TD l = (lane == u) ? piv : a[u] * rp;
                     a[u] = l;
+                    if (lane == u) Rd[kb + u] = rp;
 #pragma unroll
                     for (int v = u + 1; v < 16; v++) a[v] -= l * readlane(l, v);
                 }
@@ -228,7 +263,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
                     TD s2 = (rr == c) ? (TD)1 : (TD)0;
 #pragma unroll
                     for (int q = 0; q < rr; q++) s2 -= A[kb + q][kb + rr] * y[q];
-                    y[rr] = s2 / A[kb + rr][kb + rr];
+                    y[rr] = s2 * Rd[kb + rr];
                 }
 #pragma unroll
                 for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
@@ -366,6 +401,42 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
 }
 
 // ---------------------------------------------------------------- trailing update
+// C(row, col) -= acc[x][y][e] on the lower part (row >= col, row < m,
+// col < jend) for the 64 elements of a lane, rows from rowf(x, e) and columns
+// from colf(y).  All loads of a half (x in {0,1}, then {2,3}) are issued
+// before any store, a masked-off element loading a harmless in-bounds word
+// (F[0]) that is never stored, so the round trips to memory overlap instead
+// of being serialised element by element.
+template <typename T, typename V, typename RowFn, typename ColFn>
+__device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int jend, const V (&acc)[4][4], RowFn rowf,
+                                         ColFn colf)
+{
+#pragma unroll
+    for (int h = 0; h < 4; h += 2) {
+        T cv[2][4][4];
+#pragma unroll
+        for (int x = 0; x < 2; x++)
+#pragma unroll
+            for (int y = 0; y < 4; y++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int row = rowf(h + x, e), col = colf(y);
+                    bool ok = col < jend && row < m && row >= col;
+                    cv[x][y][e] = F[ok ? (int64_t)col * ld + row : 0];
+                }
+#pragma unroll
+        for (int x = 0; x < 2; x++)
+#pragma unroll
+            for (int y = 0; y < 4; y++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int row = rowf(h + x, e), col = colf(y);
+                    if (col < jend && row < m && row >= col) F[(int64_t)col * ld + row] = cv[x][y][e] - acc[h + x][y][e];
+                }
+    }
+}
+
+
 // task = (front, i0, j0, jend): C = F[i0:i0+UT, j0:min(j0+UT, jend)] -= A B^T
 // on the lower part (row >= column), with A = F[i0:, ka:ka+K], B = F[j0:, ka:ka+K]
 // and K = min(kw, p - ka) for the front's p.  Tiles are TW x TW (128 or 64):
@@ -470,19 +541,8 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const int4 *__restrict_
         __syncthreads();
     }
     if (!active) return;
-#pragma unroll
-    for (int x = 0; x < 4; x++)
-#pragma unroll
-        for (int y = 0; y < 4; y++) {
-            int col = j0 + wc + y * 16 + ln;
-            if (col >= jend) continue;
-            T *Cc = F + (int64_t)col * ld;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                int row = i0 + wr + x * 16 + Mfma<T>::row(kq, e);
-                if (row < m && row >= col) Cc[row] -= acc[x][y][e];
-            }
-        }
+    tile_sub<T>(F, ld, m, jend, acc, [&](int x, int e) { return i0 + wr + x * 16 + Mfma<T>::row(kq, e); },
+                [&](int y) { return j0 + wc + y * 16 + ln; });
 }
 
 // Trailing update, streamed form.  Same task and result as k_update<T, 128>,
@@ -653,19 +713,8 @@ __global__ __launch_bounds__(256) void k_update_dma(const int4 *__restrict__ tas
     }
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;
-#pragma unroll
-    for (int x = 0; x < 4; x++)
-#pragma unroll
-        for (int y = 0; y < 4; y++) {
-            int col = j0 + wc + 4 * ln + y;
-            if (col >= jend) continue;
-            T *Cc = F + (int64_t)col * ld;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                int row = i0 + wr + 4 * Mfma<T>::row(kq, e) + x;
-                if (row < m && row >= col) Cc[row] -= acc[x][y][e];
-            }
-        }
+    tile_sub<T>(F, ld, m, jend, acc, [&](int x, int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e) + x; },
+                [&](int y) { return j0 + wc + 4 * ln + y; });
 }
 
 // ---------------------------------------------------------------- solves

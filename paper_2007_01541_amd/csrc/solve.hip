@@ -36,6 +36,25 @@ template <typename T> struct SolveArgs {
     int k;
 };
 
+// dst[i] -= val[i] for the N elements with ok[i]; every load is issued before
+// any store (a masked-off element reads dst[0] of the caller's block, which
+// is in bounds, and is not written), so the round trips to memory overlap
+// instead of being serialised element by element.
+template <int N, typename T, typename OffFn, typename ValFn>
+__device__ __forceinline__ void sub_batch(T *__restrict__ base, OffFn off, ValFn val)
+{
+    T cur[N];
+    int64_t o[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        o[i] = off(i);
+        cur[i] = base[o[i] >= 0 ? o[i] : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < N; i++)
+        if (o[i] >= 0) base[o[i]] = cur[i] - val(i);
+}
+
 constexpr int SB = 64;          // block size of the solves (= panel width of the factorization)
 constexpr int SS = 4 * SB;      // super-block of the large-front sweeps
 constexpr int SROWS = THREADS;  // rows per workgroup in a forward row launch
@@ -129,17 +148,14 @@ __device__ void fwd_rows_mfma(const T *__restrict__ L, int ld, int kb, int nbk, 
         }
 #pragma unroll
         for (int rb = 0; rb < 4; rb++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                int r = s0 + rb * 16 + Mfma<T>::row(kq, e);
-                if (r >= r1) continue;
-                T *wr = w + (int64_t)r * k + c0;
-#pragma unroll
-                for (int cb = 0; cb < 4; cb++) {
-                    int n = cb * 16 + ln;
-                    if (c0 + n < k) wr[n] -= acc[rb][cb][e];
-                }
-            }
+            sub_batch<16>(
+                w,
+                [&](int i) -> int64_t {
+                    int e = i / 4, cb = i % 4;
+                    int r = s0 + rb * 16 + Mfma<T>::row(kq, e), n = cb * 16 + ln;
+                    return (r < r1 && c0 + n < k) ? (int64_t)r * k + c0 + n : -1;
+                },
+                [&](int i) { return acc[rb][i % 4][i / 4]; });
     }
 }
 
@@ -179,16 +195,14 @@ __device__ void bwd_cols_mfma(const T *__restrict__ L, int ld, int a, int na, in
             for (int cb = 0; cb < 4; cb++) acc[cb] = Mfma<T>::mma(av, Xs[kk + kq][cb * 16 + ln], acc[cb]);
         }
     }
-#pragma unroll
-    for (int e = 0; e < 4; e++) {
-        int c = wave * 16 + Mfma<T>::row(kq, e);
-        if (c >= na) continue;
-#pragma unroll
-        for (int cb = 0; cb < 4; cb++) {
-            int n = cb * 16 + ln;
-            if (c0 + n < k) v[(int64_t)c * k + c0 + n] -= acc[cb][e];
-        }
-    }
+    sub_batch<16>(
+        v,
+        [&](int i) -> int64_t {
+            int e = i / 4, cb = i % 4;
+            int c = wave * 16 + Mfma<T>::row(kq, e), n = cb * 16 + ln;
+            return (c < na && c0 + n < k) ? (int64_t)c * k + c0 + n : -1;
+        },
+        [&](int i) { return acc[i % 4][i / 4]; });
     __syncthreads();
 }
 
@@ -237,10 +251,9 @@ __device__ void fwd_rows(const T *__restrict__ L, int ld, int kb, int nbk, T *__
 #pragma unroll
             for (int c = 0; c < KT; c++) acc[c] += l * Zs[j][c];
         }
-        T *wr = w + (int64_t)r * k + c0;
-#pragma unroll
-        for (int c = 0; c < KT; c++)
-            if (c0 + c < k) wr[c] -= acc[c];
+        sub_batch<KT>(
+            w, [&](int c) -> int64_t { return c0 + c < k ? (int64_t)r * k + c0 + c : -1; },
+            [&](int c) { return acc[c]; });
     }
 }
 
@@ -283,13 +296,13 @@ __device__ void bwd_cols(const T *__restrict__ L, int ld, int a, int na, int r0,
             }
         }
     }
-    if (c < na) {
-#pragma unroll
-        for (int q = 0; q < PG; q++) {
+    sub_batch<PG>(
+        v,
+        [&](int q) -> int64_t {
             int cc = g + 4 * q;
-            if (cc < KT && c0 + cc < k) v[(int64_t)c * k + c0 + cc] -= acc[q];
-        }
-    }
+            return (c < na && cc < KT && c0 + cc < k) ? (int64_t)c * k + c0 + cc : -1;
+        },
+        [&](int q) { return acc[q]; });
     __syncthreads();
 }
 
@@ -369,9 +382,23 @@ __global__ __launch_bounds__(THREADS) void k_fwd_assemble(const int2 *__restrict
         while (lo < hi) { int md = (lo + hi) / 2; if (rl[md] < r1) lo = md + 1; else hi = md; }
         int t1 = lo;
         const T *wc = a.W + a.woff[c] * k + (int64_t)pc * k;
-        for (int64_t i = (int64_t)t0 * k + threadIdx.x; i < (int64_t)t1 * k; i += blockDim.x) {
-            int r = (int)(i / k), cc = (int)(i % k);
-            w[(int64_t)rl[r] * k + cc] += wc[i];
+        constexpr int B = 4;   // elements per thread per round: loads first, then stores
+        for (int64_t i0 = (int64_t)t0 * k + threadIdx.x; i0 < (int64_t)t1 * k; i0 += B * blockDim.x) {
+            int64_t di[B];
+            T uv[B], dv[B];
+#pragma unroll
+            for (int b = 0; b < B; b++) {
+                int64_t i = i0 + (int64_t)b * blockDim.x;
+                bool ok = i < (int64_t)t1 * k;
+                int r = ok ? (int)(i / k) : t0, cc = ok ? (int)(i % k) : 0;
+                di[b] = ok ? (int64_t)rl[r] * k + cc : -1;
+                uv[b] = ok ? wc[i] : (T)0;
+            }
+#pragma unroll
+            for (int b = 0; b < B; b++) dv[b] = w[di[b] >= 0 ? di[b] : (int64_t)r0 * k];
+#pragma unroll
+            for (int b = 0; b < B; b++)
+                if (di[b] >= 0) w[di[b]] = dv[b] + uv[b];
         }
         __syncthreads();
     }
@@ -592,15 +619,14 @@ __global__ __launch_bounds__(THREADS) void k_fwd_srows(const int2 *__restrict__ 
 #pragma unroll
                     for (int cb = 0; cb < 4; cb++) acc[cb] = Mfma<T>::mma(av[ks], Zs[ks * 4 + kq][cb * 16 + ln], acc[cb]);
             }
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                int rr = r0 + wave * 16 + Mfma<T>::row(kq, e);
-                if (rr >= r1) continue;
-                T *wr = w + (int64_t)rr * k + c0;
-#pragma unroll
-                for (int cb = 0; cb < 4; cb++)
-                    if (c0 + cb * 16 + ln < k) wr[cb * 16 + ln] -= acc[cb][e];
-            }
+            sub_batch<16>(
+                w,
+                [&](int i) -> int64_t {
+                    int e = i / 4, cb = i % 4;
+                    int rr = r0 + wave * 16 + Mfma<T>::row(kq, e), n = cb * 16 + ln;
+                    return (rr < r1 && c0 + n < k) ? (int64_t)rr * k + c0 + n : -1;
+                },
+                [&](int i) { return acc[i % 4][i / 4]; });
         } else {
             for (int kb = s0; kb < s1; kb += SB) {
                 int nbk = min(SB, s1 - kb);
