@@ -463,6 +463,78 @@ __global__ __launch_bounds__(THREADS) void k_bwd_fused(const int32_t *__restrict
 }
 
 
+// ---- 64 x 64 tiles for 64 right-hand sides: each wave takes a slice of the
+// contraction and multiplies straight from global memory (no LDS staging, no
+// workgroup barrier inside the loop); the four partial tiles are added
+// through LDS at the end.  Within a group of 16 k values, lane kq of a
+// 16x16x4 product supplies k = kg + 4 kq + j in product j (j = 0..3), so a
+// lane's four k values are consecutive in memory; the order of summation is
+// fixed, so results are deterministic.
+
+// acc[x][y] += sum over k in [kb, ke) of fa(16 x + ln, k) fb(k, 16 y + ln)
+// (fa / fb return 0 outside their ranges)
+template <typename T, typename FA, typename FB>
+__device__ __forceinline__ void wave_mm(typename Mfma<T>::V (&acc)[4][4], int kb, int ke, FA fa, FB fb)
+{
+    const int lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+    for (int kg = kb; kg < ke; kg += 16) {
+        T av[4][4], bv[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            int k = kg + 4 * kq + j;
+            bool ok = k < ke;
+#pragma unroll
+            for (int x = 0; x < 4; x++) av[j][x] = ok ? fa(16 * x + ln, k) : (T)0;
+#pragma unroll
+            for (int y = 0; y < 4; y++) bv[j][y] = ok ? fb(k, 16 * y + ln) : (T)0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++) acc[x][y] = Mfma<T>::mma(av[j][x], bv[j][y], acc[x][y]);
+    }
+}
+
+// Sums the four waves' tiles: out(r, c, v) for every (r, c) of the 64 x 64
+// tile, called by 16 elements per thread in two halves of 32 columns; red is
+// LDS of 4 * 64 * 32 elements.  All threads of the workgroup call it.
+template <typename T, typename Out>
+__device__ __forceinline__ void reduce4(typename Mfma<T>::V (&acc)[4][4], T *red, Out out)
+{
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        __syncthreads();
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+#pragma unroll
+            for (int y = 0; y < 2; y++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int r = 16 * x + Mfma<T>::row(kq, e), c = 16 * y + ln;
+                    red[(wave * 64 + r) * 32 + c] = acc[x][2 * h + y][e];
+                }
+        __syncthreads();
+        T v[8];
+        int rr[8], cc[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            int idx = tid + 256 * q;            // 0 .. 2047 over 64 rows x 32 columns
+            rr[q] = idx / 32;
+            cc[q] = idx % 32;
+            v[q] = red[(0 * 64 + rr[q]) * 32 + cc[q]] + red[(1 * 64 + rr[q]) * 32 + cc[q]] +
+                   red[(2 * 64 + rr[q]) * 32 + cc[q]] + red[(3 * 64 + rr[q]) * 32 + cc[q]];
+        }
+        out(rr, cc, v, 32 * h);
+    }
+}
+
+template <typename T> struct MmLds {
+    T red[4 * 64 * 32];
+};
+
 // ---- super-block sweeps of large fronts
 //
 // X_S = L_SS^-1 of every diagonal super-block S = [s0, s1) of a large front is
@@ -548,7 +620,6 @@ template <typename T, int KT> struct SxLds {
 template <typename T, int KT>
 __global__ __launch_bounds__(THREADS) void k_fwd_sz(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
-    __shared__ SxLds<T, KT> sh;
     int2 t = tasks[blockIdx.x];
     int f = t.x, ib = t.y;
     int p = a.pfront[f], k = a.k, f0 = a.first[f];
@@ -556,6 +627,36 @@ __global__ __launch_bounds__(THREADS) void k_fwd_sz(const int2 *__restrict__ tas
     int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
     const T *X = a.xinv + a.xoff[f] + (int64_t)(s0 / SS) * SS * SS;
     const T *w = a.W + a.woff[f] * k;
+    if constexpr (KT == 64) {
+        // wave jb adds X_ij w_j for its block j <= i
+        __shared__ MmLds<T> mm;
+        int wave = threadIdx.x / 64;
+        for (int c0 = 0; c0 < k; c0 += 64) {
+            typename Mfma<T>::V acc[4][4];
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+            if (wave <= ib) {
+                int j0 = s0 + wave * SB, nj = min(SB, s1 - j0);
+                wave_mm<T>(
+                    acc, 0, nj,
+                    [&](int r, int kk) { return r < ni ? X[(int64_t)(j0 - s0 + kk) * SS + (i0 - s0 + r)] : (T)0; },
+                    [&](int kk, int c) { return c0 + c < k ? w[(int64_t)(j0 + kk) * k + c0 + c] : (T)0; });
+            }
+            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *v, int cb) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    int r = rr[q], c = cb + cc[q];
+                    if (r < ni && c0 + c < k) a.Y[(int64_t)(f0 + i0 + r) * k + c0 + c] = v[q];
+                }
+            });
+        }
+        return;
+    }
+    __shared__ SxLds<T, KT> sh;
     BlkAcc<T, KT> acc;
     for (int c0 = 0; c0 < k; c0 += KT) {
         acc.zero();
@@ -582,7 +683,6 @@ __global__ __launch_bounds__(THREADS) void k_fwd_sz(const int2 *__restrict__ tas
 template <typename T, int KT>
 __global__ __launch_bounds__(THREADS) void k_fwd_srows(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
-    __shared__ T Zs[SB][KT];
     int2 t = tasks[blockIdx.x];
     int f = t.x;
     int m = a.mfront[f], p = a.pfront[f], k = a.k, f0 = a.first[f], ld = front_ld(m);
@@ -592,42 +692,33 @@ __global__ __launch_bounds__(THREADS) void k_fwd_srows(const int2 *__restrict__ 
     T *w = a.W + a.woff[f] * k;
     for (int c0 = 0; c0 < k; c0 += KT) {
         if constexpr (KT == 64) {
-            typedef typename Mfma<T>::V V;
-            int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
-            V acc[4];
+            // wave q takes the pivot columns [s0 + 64 q, s0 + 64 q + 64) of the super-block
+            __shared__ MmLds<T> mm;
+            int wave = threadIdx.x / 64;
+            typename Mfma<T>::V acc[4][4];
 #pragma unroll
-            for (int cb = 0; cb < 4; cb++)
+            for (int x = 0; x < 4; x++)
 #pragma unroll
-                for (int e = 0; e < 4; e++) acc[cb][e] = 0;
-            int r = r0 + wave * 16 + ln;
-            for (int kb = s0; kb < s1; kb += SB) {
-                int nbk = min(SB, s1 - kb);
-                __syncthreads();
-                for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
-                    int j = e / KT, c = e % KT;
-                    Zs[j][c] = (j < nbk && c0 + c < k) ? a.Y[(int64_t)(f0 + kb + j) * k + c0 + c] : (T)0;
-                }
-                T av[SB / 4];
+                for (int y = 0; y < 4; y++)
 #pragma unroll
-                for (int ks = 0; ks < SB / 4; ks++) {
-                    int j = ks * 4 + kq;
-                    av[ks] = (r < r1 && j < nbk) ? L[(int64_t)(kb + j) * ld + r] : (T)0;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int ks = 0; ks < SB / 4; ks++)
-#pragma unroll
-                    for (int cb = 0; cb < 4; cb++) acc[cb] = Mfma<T>::mma(av[ks], Zs[ks * 4 + kq][cb * 16 + ln], acc[cb]);
-            }
-            sub_batch<16>(
-                w,
-                [&](int i) -> int64_t {
-                    int e = i / 4, cb = i % 4;
-                    int rr = r0 + wave * 16 + Mfma<T>::row(kq, e), n = cb * 16 + ln;
-                    return (rr < r1 && c0 + n < k) ? (int64_t)rr * k + c0 + n : -1;
-                },
-                [&](int i) { return acc[i % 4][i / 4]; });
+                    for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+            int kb = s0 + wave * SB;
+            if (kb < s1)
+                wave_mm<T>(
+                    acc, kb, min(s1, kb + SB),
+                    [&](int r, int kk) { return r0 + r < r1 ? L[(int64_t)kk * ld + r0 + r] : (T)0; },
+                    [&](int kk, int c) { return c0 + c < k ? a.Y[(int64_t)(f0 + kk) * k + c0 + c] : (T)0; });
+            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *v, int cb) {
+                sub_batch<8>(
+                    w,
+                    [&](int q) -> int64_t {
+                        int r = r0 + rr[q], c = cb + cc[q];
+                        return (r < r1 && c0 + c < k) ? (int64_t)r * k + c0 + c : -1;
+                    },
+                    [&](int q) { return v[q]; });
+            });
         } else {
+            __shared__ T Zs[SB][KT];
             for (int kb = s0; kb < s1; kb += SB) {
                 int nbk = min(SB, s1 - kb);
                 __syncthreads();
@@ -646,7 +737,6 @@ __global__ __launch_bounds__(THREADS) void k_fwd_srows(const int2 *__restrict__ 
 template <typename T, int KT>
 __global__ __launch_bounds__(THREADS) void k_bwd_sx(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
-    __shared__ SxLds<T, KT> sh;
     int2 t = tasks[blockIdx.x];
     int f = t.x, jb = t.y;
     int p = a.pfront[f], k = a.k, f0 = a.first[f];
@@ -655,6 +745,37 @@ __global__ __launch_bounds__(THREADS) void k_bwd_sx(const int2 *__restrict__ tas
     int j0 = s0 + jb * SB, nj = min(SB, s1 - j0);
     const T *X = a.xinv + a.xoff[f] + (int64_t)(s0 / SS) * SS * SS;
     const T *w = a.W + a.woff[f] * k;
+    if constexpr (KT == 64) {
+        // wave q adds X_ij^T v_i for block i = j + q
+        __shared__ MmLds<T> mm;
+        int wave = threadIdx.x / 64;
+        for (int c0 = 0; c0 < k; c0 += 64) {
+            typename Mfma<T>::V acc[4][4];
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+            int ib = jb + wave;
+            if (ib < nblk) {
+                int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
+                wave_mm<T>(
+                    acc, 0, ni,
+                    [&](int r, int kk) { return r < nj ? X[(int64_t)(j0 - s0 + r) * SS + (i0 - s0 + kk)] : (T)0; },
+                    [&](int kk, int c) { return c0 + c < k ? w[(int64_t)(i0 + kk) * k + c0 + c] : (T)0; });
+            }
+            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *v, int cb) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    int r = rr[q], c = cb + cc[q];
+                    if (r < nj && c0 + c < k) a.Y[(int64_t)(f0 + j0 + r) * k + c0 + c] = v[q];
+                }
+            });
+        }
+        return;
+    }
+    __shared__ SxLds<T, KT> sh;
     BlkAcc<T, KT> acc;
     for (int c0 = 0; c0 < k; c0 += KT) {
         acc.zero();
@@ -681,7 +802,6 @@ __global__ __launch_bounds__(THREADS) void k_bwd_sx(const int2 *__restrict__ tas
 template <typename T, int KT>
 __global__ __launch_bounds__(THREADS) void k_bwd_scols(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
-    __shared__ BwdLds<T, KT> sh;
     int2 t = tasks[blockIdx.x];
     int f = t.x;
     int m = a.mfront[f], p = a.pfront[f], k = a.k, f0 = a.first[f];
@@ -690,6 +810,38 @@ __global__ __launch_bounds__(THREADS) void k_bwd_scols(const int2 *__restrict__ 
     const T *L = a.fronts + a.front_off[f];
     T *w = a.W + a.woff[f] * k;
     const T *Y = a.Y;
+    if constexpr (KT == 64) {
+        // out^T(n, c) = sum_r x_r[n] L(r, ab + c); wave q takes the rows [s0 + 64 q, s0 + 64 q + 64)
+        __shared__ MmLds<T> mm;
+        int wave = threadIdx.x / 64, ld = front_ld(m);
+        for (int c0 = 0; c0 < k; c0 += 64) {
+            typename Mfma<T>::V acc[4][4];
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+            int rb = s0 + wave * SB;
+            if (rb < s1)
+                wave_mm<T>(
+                    acc, rb, min(s1, rb + SB),
+                    [&](int n, int r) { return c0 + n < k ? Y[(int64_t)(f0 + r) * k + c0 + n] : (T)0; },
+                    [&](int r, int c) { return L[(int64_t)(ab + c) * ld + r]; });
+            T *v = w + (int64_t)ab * k;
+            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+                sub_batch<8>(
+                    v,
+                    [&](int q) -> int64_t {
+                        int n = rr[q], c = cb + cc[q];
+                        return c0 + n < k ? (int64_t)c * k + c0 + n : -1;
+                    },
+                    [&](int q) { return val[q]; });
+            });
+        }
+        return;
+    }
+    __shared__ BwdLds<T, KT> sh;
     auto xrow = [&](int r) { return Y + (int64_t)(f0 + r) * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
         bwd_cols_any<T, KT>(L, front_ld(m), ab, SB, s0, s1, xrow, k, c0, w + (int64_t)ab * k, sh.Ls, sh.Ss);
@@ -697,20 +849,49 @@ __global__ __launch_bounds__(THREADS) void k_bwd_scols(const int2 *__restrict__ 
 
 // backward update rows, split: task = (front, column block a, first row, slot):
 // part[slot] = -L(rows [r0, r0 + BELOW_ROWS) of the update part, a)^T x(rows)
-constexpr int BELOW_ROWS = 512;
+constexpr int BELOW_ROWS = 256;
 template <typename T, int KT>
 __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restrict__ tasks, SolveArgs<T> a)
 {
-    __shared__ BwdLds<T, KT> sh;
     int4 t = tasks[blockIdx.x];
     int f = t.x, ab = t.y * SB, r0 = t.z;
     int m = a.mfront[f], p = a.pfront[f], k = a.k;
     int na = min(SB, p - ab), r1 = min(m, r0 + BELOW_ROWS);
     const T *L = a.fronts + a.front_off[f];
     T *out = a.part + (int64_t)t.w * SB * k;
-    for (int64_t i = threadIdx.x; i < (int64_t)SB * k; i += blockDim.x) out[i] = (T)0;
     const int32_t *rw = a.rows + a.rptr[f];
     const T *Y = a.Y;
+    if constexpr (KT == 64) {
+        // part^T(n, c) = -sum_r x(rows[r])[n] L(r, ab + c); wave q takes a quarter of the rows
+        __shared__ MmLds<T> mm;
+        constexpr int RW = BELOW_ROWS / 4;
+        int wave = threadIdx.x / 64, ld = front_ld(m);
+        for (int c0 = 0; c0 < k; c0 += 64) {
+            typename Mfma<T>::V acc[4][4];
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+            int rb = r0 + wave * RW;
+            if (rb < r1)
+                wave_mm<T>(
+                    acc, rb, min(r1, rb + RW),
+                    [&](int n, int r) { return c0 + n < k ? Y[(int64_t)rw[r] * k + c0 + n] : (T)0; },
+                    [&](int r, int c) { return c < na ? L[(int64_t)(ab + c) * ld + r] : (T)0; });
+            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    int n = rr[q], c = cb + cc[q];
+                    if (c0 + n < k) out[(int64_t)c * k + c0 + n] = -val[q];
+                }
+            });
+        }
+        return;
+    }
+    __shared__ BwdLds<T, KT> sh;
+    for (int64_t i = threadIdx.x; i < (int64_t)SB * k; i += blockDim.x) out[i] = (T)0;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
         bwd_cols_any<T, KT>(L, front_ld(m), ab, na, r0, r1, xrow, k, c0, out, sh.Ls, sh.Ss);
