@@ -68,8 +68,16 @@ __global__ void k_zero_lower(const int2 *__restrict__ tasks, const int64_t *__re
     int m = mfront[t.x], ld = front_ld(m);
     T *F = fronts + front_off[t.x];
     int c1 = min(t.y + ZCOLS, m);
-    for (int c = t.y; c < c1; c++)
-        for (int r = c + threadIdx.x; r < m; r += blockDim.x) F[(int64_t)c * ld + r] = (T)0;
+    // 16-byte stores over the aligned groups of VEC rows that hold rows >= c (the
+    // column starts are 32-byte aligned; a group may reach into the upper
+    // triangle or the padding rows, which are zeroed as well: harmless)
+    constexpr int VEC = 16 / (int)sizeof(T);
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
+    for (int c = t.y; c < c1; c++) {
+        V *col = reinterpret_cast<V *>(F + (int64_t)c * ld);
+        int g1 = (m + VEC - 1) / VEC;
+        for (int g = c / VEC + threadIdx.x; g < g1; g += blockDim.x) col[g] = V{};
+    }
 }
 
 // fronts[amap[e]] = values[e]: the stored entries of A into their fronts
@@ -77,9 +85,21 @@ template <typename T>
 __global__ void k_scatter(const double *__restrict__ values, const int64_t *__restrict__ amap, int64_t nnz,
                           T *__restrict__ fronts)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (; i < nnz; i += stride) fronts[amap[i]] = (T)values[i];
+    constexpr int B = 4;   // loads of B entries before their stores
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nnz; i0 += B * stride) {
+        int64_t dst[B];
+        T v[B];
+#pragma unroll
+        for (int b = 0; b < B; b++) {
+            int64_t i = i0 + b * stride;
+            dst[b] = i < nnz ? amap[i] : -1;
+            v[b] = i < nnz ? (T)values[i] : (T)0;
+        }
+#pragma unroll
+        for (int b = 0; b < B; b++)
+            if (dst[b] >= 0) fronts[dst[b]] = v[b];
+    }
 }
 
 // ---------------------------------------------------------------- extend-add
@@ -874,7 +894,7 @@ __global__ __launch_bounds__(256) void k_spmv_vec(const int64_t *__restrict__ rp
                                                   const double *__restrict__ v, int n, const double *__restrict__ X,
                                                   const double *__restrict__ B, double *__restrict__ R)
 {
-    constexpr int K = 4 * LPE, EPI = 64 / LPE, U = EPI >= 8 ? 1 : 8 / EPI;
+    constexpr int K = 4 * LPE, EPI = 64 / LPE, U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
     int row = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
     if (row >= n) return;
     int q = lane / LPE, ql = lane % LPE;
