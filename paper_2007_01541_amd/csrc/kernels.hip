@@ -234,21 +234,34 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
     int row0 = k0 + nb + t.y * TRW + (wave - 1) * 64;
     T bv[NB / 4][4];                 // waves 1..3: the slab in MFMA A-operand order
     if (wave == 0) {
-        {
-            const int r = lane;
-            TD col[NB];
+        // every load unconditional (clamped into the block) so all 64 are in
+        // flight at once; the select afterwards pads with the identity
+        const int r = lane;
+        const int rc = min(r, nb - 1);
+        T raw[NB];
 #pragma unroll
-            for (int c = 0; c < NB; c++)
-                col[c] = (r < nb && c < nb && c <= r) ? (TD)F[(int64_t)(k0 + c) * ld + k0 + r]
-                                                      : (c == r ? (TD)1 : (TD)0);
+        for (int c = 0; c < NB; c++) raw[c] = F[(int64_t)(k0 + min(c, nb - 1)) * ld + k0 + rc];
 #pragma unroll
-            for (int c = 0; c < NB; c++) {
-                A[c][r] = col[c];
-                Iv[c][r] = 0;
+        for (int c = 0; c < NB; c++) {
+            A[c][r] = (r < nb && c < nb && c <= r) ? (TD)raw[c] : (c == r ? (TD)1 : (TD)0);
+            Iv[c][r] = 0;
+        }
+    } else if (row0 < m) {
+#pragma unroll
+        for (int ks = 0; ks < NB / 4; ks++) {
+            int k = ks * 4 + kq;
+#pragma unroll
+            for (int rb = 0; rb < 4; rb++) {
+                int row = row0 + rb * 16 + ln;
+                bv[ks][rb] = (row < m && k < nb) ? F[(int64_t)(k0 + k) * ld + row] : (T)0;
             }
         }
-        for (int kb = 0; kb < NB; kb += 16) {
-            __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // the diagonal block, 16 columns at a time; the sub-block products of a
+    // step are spread over the four waves
+    for (int kb = 0; kb < NB; kb += 16) {
+        if (wave == 0) {
             // (1) diagonal 16 x 16 sub-block, lanes 0..15 own its rows
             if (lane < 16) {
                 const int r = kb + lane;
@@ -288,20 +301,27 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
 #pragma unroll
                 for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
             }
-            __builtin_amdgcn_wave_barrier();
-            // (3) sub-panel below: X(i, n) = sum_k A(i, kb+k) L_kk^-1(n, k)
-            for (int ib = kb + 16; ib < NB; ib += 16) {
+        }
+        __syncthreads();
+        // (3) sub-panel below, one 16-row block per wave: X(i, n) = sum_k A(i, kb+k) L_kk^-1(n, k)
+        {
+            int ib = kb + 16 * (wave + 1);
+            if (ib < NB) {
                 VD acc = {0, 0, 0, 0};
                 acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
                                [&](int k, int n) { return Iv[kb + k][kb + n]; });
                 __builtin_amdgcn_wave_barrier();
 #pragma unroll
                 for (int e = 0; e < 4; e++) A[kb + ln][ib + Mfma<TD>::row(kq, e)] = acc[e];
-                __builtin_amdgcn_wave_barrier();
             }
-            // (4) trailing update: A(i, j) -= X_i X_j^T for kb < j <= i
+        }
+        __syncthreads();
+        // (4) trailing update A(i, j) -= X_i X_j^T for kb < j <= i, block pairs dealt round-robin to the waves
+        {
+            int q = 0;
             for (int ib = kb + 16; ib < NB; ib += 16)
-                for (int jb = kb + 16; jb <= ib; jb += 16) {
+                for (int jb = kb + 16; jb <= ib; jb += 16, q++) {
+                    if (q % 4 != wave) continue;
                     VD acc = {0, 0, 0, 0};
                     acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
                                    [&](int k, int n) { return A[kb + k][jb + n]; });
@@ -309,56 +329,55 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
                     for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<TD>::row(kq, e)] -= acc[e];
                 }
         }
-        __builtin_amdgcn_wave_barrier();
-        // block inverse: (L^-1)_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij (L^-1)_jk
-        for (int ib = 16; ib < NB; ib += 16)
-            for (int kb = 0; kb < ib; kb += 16) {
-                VD acc = {0, 0, 0, 0};
-                for (int jb = kb; jb < ib; jb += 16)
-                    acc = mm16<TD>(acc, [&](int r, int k) { return A[jb + k][ib + r]; },
-                                   [&](int k, int n) { return Iv[kb + n][jb + k]; });
-                __builtin_amdgcn_wave_barrier();
-                // stage T = acc in the upper (unused) part of A: A[ib + col][kb + row] for the product
-                // with L_ii^-1 (rows ib.., cols kb..): T(row, col) stored at A[kb + col][... ] is busy,
-                // so use the 16 x 16 block of Iv above the diagonal, Iv[ib + col][kb + row] (row < 16).
+        __syncthreads();
+    }
+    // block inverse, column block kb = 16 wave per wave (independent columns):
+    // (L^-1)_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij (L^-1)_jk
+    {
+        const int kb = 16 * wave;
+        for (int ib = kb + 16; ib < NB; ib += 16) {
+            VD acc = {0, 0, 0, 0};
+            for (int jb = kb; jb < ib; jb += 16)
+                acc = mm16<TD>(acc, [&](int r, int k) { return A[jb + k][ib + r]; },
+                               [&](int k, int n) { return Iv[kb + n][jb + k]; });
+            __builtin_amdgcn_wave_barrier();
+            // stage T = acc in the unused upper block of Iv at (rows kb.., cols ib..)
 #pragma unroll
-                for (int e = 0; e < 4; e++) Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = acc[e];
-                __builtin_amdgcn_wave_barrier();
-                VD res = {0, 0, 0, 0};
-                res = mm16<TD>(res, [&](int r, int k) { return Iv[ib + k][ib + r]; },
-                               [&](int k, int n) { return Iv[ib + n][kb + k]; });
-                __builtin_amdgcn_wave_barrier();
+            for (int e = 0; e < 4; e++) Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = acc[e];
+            __builtin_amdgcn_wave_barrier();
+            VD res = {0, 0, 0, 0};
+            res = mm16<TD>(res, [&](int r, int k) { return Iv[ib + k][ib + r]; },
+                           [&](int k, int n) { return Iv[ib + n][kb + k]; });
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    Iv[kb + ln][ib + Mfma<TD>::row(kq, e)] = -res[e];
-                    Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = 0;
-                }
-                __builtin_amdgcn_wave_barrier();
+            for (int e = 0; e < 4; e++) {
+                Iv[kb + ln][ib + Mfma<TD>::row(kq, e)] = -res[e];
+                Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = 0;
             }
-        __builtin_amdgcn_wave_barrier();
-        {
-            const int r = lane;
-            if (t.y == 0) {
-                int64_t o = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
-                T *D = dscr + o;
-                T *DI = dinv + o;
-#pragma unroll
-                for (int c = 0; c < NB; c++) {
-                    if (c <= r) D[c * NB + r] = (T)A[c][r];
-                    DI[c * NB + r] = (T)Iv[c][r];     // column-major L^-1 of the padded block
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < NB; c++) Li[r][c] = (T)Iv[c][r];
+            __builtin_amdgcn_wave_barrier();
         }
-    } else if (row0 < m) {
+    }
+    __syncthreads();
+    // outputs: wave w handles the columns [16 w, 16 w + 16) of L^-1 (and of the factored block)
+    {
+        const int r = lane, cb = 16 * wave;
+        T iv[16];
 #pragma unroll
-        for (int ks = 0; ks < NB / 4; ks++) {
-            int k = ks * 4 + kq;
+        for (int c = 0; c < 16; c++) iv[c] = (T)Iv[cb + c][r];
 #pragma unroll
-            for (int rb = 0; rb < 4; rb++) {
-                int row = row0 + rb * 16 + ln;
-                bv[ks][rb] = (row < m && k < nb) ? F[(int64_t)(k0 + k) * ld + row] : (T)0;
+        for (int c = 0; c < 16; c++) Li[r][cb + c] = iv[c];
+        if (t.y == 0) {
+            int64_t o = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
+            T *D = dscr + o;
+            T *DI = dinv + o;
+            T lv[16];
+#pragma unroll
+            for (int c = 0; c < 16; c++) lv[c] = (T)A[cb + c][r];
+            // the full block goes to the scratch (the fix-up copies only its lower part)
+#pragma unroll
+            for (int c = 0; c < 16; c++) {
+                D[(cb + c) * NB + r] = lv[c];
+                DI[(cb + c) * NB + r] = iv[c];     // column-major L^-1 of the padded block
             }
         }
     }
