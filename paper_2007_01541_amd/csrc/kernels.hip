@@ -58,25 +58,28 @@ __global__ void k_fill(T *__restrict__ p, int64_t n, T v)
     for (; i < n; i += stride) p[i] = v;
 }
 
-// zero the lower triangle of columns [c0, c0 + ZCOLS) of a front (task = (front, c0))
+// zero the lower triangle of the pivot columns [c0, c0 + ZCOLS) of a front
+// (task = (front, c0)), one wave per column.  The update-matrix columns are
+// not zeroed: the front's first trailing update assigns them.
 constexpr int ZCOLS = 16;
 template <typename T>
 __global__ void k_zero_lower(const int2 *__restrict__ tasks, const int64_t *__restrict__ front_off,
-                             const int32_t *__restrict__ mfront, T *__restrict__ fronts)
+                             const int32_t *__restrict__ mfront, const int32_t *__restrict__ pfront,
+                             T *__restrict__ fronts)
 {
     int2 t = tasks[blockIdx.x];
     int m = mfront[t.x], ld = front_ld(m);
     T *F = fronts + front_off[t.x];
-    int c1 = min(t.y + ZCOLS, m);
+    int c1 = min(t.y + ZCOLS, pfront[t.x]);
     // 16-byte stores over the aligned groups of VEC rows that hold rows >= c (the
     // column starts are 32-byte aligned; a group may reach into the upper
     // triangle or the padding rows, which are zeroed as well: harmless)
     constexpr int VEC = 16 / (int)sizeof(T);
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type V;
-    for (int c = t.y; c < c1; c++) {
+    int g1 = (m + VEC - 1) / VEC;
+    for (int c = t.y + (int)threadIdx.x / 64; c < c1; c += (int)blockDim.x / 64) {
         V *col = reinterpret_cast<V *>(F + (int64_t)c * ld);
-        int g1 = (m + VEC - 1) / VEC;
-        for (int g = c / VEC + threadIdx.x; g < g1; g += blockDim.x) col[g] = V{};
+        for (int g = c / VEC + (int)threadIdx.x % 64; g < g1; g += 64) col[g] = V{};
     }
 }
 
@@ -107,23 +110,29 @@ __global__ void k_scatter(const double *__restrict__ values, const int64_t *__re
 // U = F_c[p_c:m_c, p_c:m_c] (lower) is added into its parent front through
 // rel (positions of the child's update rows in the parent's row list).  All
 // tasks of one launch have distinct parents, so the adds do not race.
+// The update columns split in two: the first split[c] land in the parent's
+// pivot columns and are added before the parent is factored (split given:
+// columns below split[c] only); the rest land in the parent's own update
+// matrix and are added after the parent's trailing updates (split null).
 template <typename T>
 __global__ void k_extend_add(const int2 *__restrict__ tasks, const int64_t *__restrict__ front_off,
                              const int32_t *__restrict__ mfront, const int32_t *__restrict__ pfront,
                              const int32_t *__restrict__ sparent, const int64_t *__restrict__ rptr,
-                             const int32_t *__restrict__ rel, T *__restrict__ fronts)
+                             const int32_t *__restrict__ rel, const int32_t *__restrict__ split,
+                             T *__restrict__ fronts)
 {
     int2 t = tasks[blockIdx.x];
     int c = t.x;
     int mc = mfront[c], pc = pfront[c];
     int nu = mc - pc;
+    int cend = split ? split[c] : nu;
     int par = sparent[c];
     int mp = mfront[par];
     int ldc = front_ld(mc), ldp = front_ld(mp);
     const T *U = fronts + front_off[c] + (int64_t)pc * ldc + pc;
     T *Fp = fronts + front_off[par];
     const int32_t *rl = rel + rptr[c] + pc;
-    int c1 = min(t.y + EA_COLS, nu);
+    int c1 = min(t.y + EA_COLS, cend);
     constexpr int B = 4;   // rows per thread per round: all loads of a round before its stores
     for (int col = t.y; col < c1; col++) {
         int pcol = rl[col];
@@ -447,9 +456,11 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
 // (F[0]) that is never stored, so the round trips to memory overlap instead
 // of being serialised element by element.
 template <typename T, typename V, typename RowFn, typename ColFn>
-__device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int jend, const V (&acc)[4][4], RowFn rowf,
-                                         ColFn colf)
+__device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int jend, int pa, const V (&acc)[4][4],
+                                         RowFn rowf, ColFn colf)
 {
+    // columns >= pa hold no earlier value (update matrix before its first
+    // update): they are assigned -acc instead of updated, and not read
 #pragma unroll
     for (int h = 0; h < 4; h += 2) {
         T cv[2][4][4];
@@ -460,7 +471,7 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     int row = rowf(h + x, e), col = colf(y);
-                    bool ok = col < jend && row < m && row >= col;
+                    bool ok = col < jend && row < m && row >= col && col < pa;
                     cv[x][y][e] = F[ok ? (int64_t)col * ld + row : 0];
                 }
 #pragma unroll
@@ -470,7 +481,8 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     int row = rowf(h + x, e), col = colf(y);
-                    if (col < jend && row < m && row >= col) F[(int64_t)col * ld + row] = cv[x][y][e] - acc[h + x][y][e];
+                    if (col < jend && row < m && row >= col)
+                        F[(int64_t)col * ld + row] = col < pa ? cv[x][y][e] - acc[h + x][y][e] : -acc[h + x][y][e];
                 }
     }
 }
@@ -478,7 +490,9 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 
 // task = (front, i0, j0, jend): C = F[i0:i0+UT, j0:min(j0+UT, jend)] -= A B^T
 // on the lower part (row >= column), with A = F[i0:, ka:ka+K], B = F[j0:, ka:ka+K]
-// and K = min(kw, p - ka) for the front's p.  Tiles are TW x TW (128 or 64):
+// and K = min(kw, p - ka) for the front's p.  The first outer block's update
+// (ka = 0) assigns C = -A B^T in the update-matrix columns (>= p), which are
+// not zeroed beforehand.  Tiles are TW x TW (128 or 64):
 // one wave per 64 x 64 quarter (4 x 4 MFMA 16x16 blocks each); K advances in
 // chunks of KC staged through double-buffered LDS.  The 64 x 64 variant gives
 // four times as many workgroups for the same front, which pays on mid-size
@@ -580,7 +594,8 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const int4 *__restrict_
         __syncthreads();
     }
     if (!active) return;
-    tile_sub<T>(F, ld, m, jend, acc, [&](int x, int e) { return i0 + wr + x * 16 + Mfma<T>::row(kq, e); },
+    tile_sub<T>(F, ld, m, jend, ka == 0 ? p : m, acc,
+                [&](int x, int e) { return i0 + wr + x * 16 + Mfma<T>::row(kq, e); },
                 [&](int y) { return j0 + wc + y * 16 + ln; });
 }
 
@@ -752,7 +767,8 @@ __global__ __launch_bounds__(256) void k_update_dma(const int4 *__restrict__ tas
     }
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;
-    tile_sub<T>(F, ld, m, jend, acc, [&](int x, int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e) + x; },
+    tile_sub<T>(F, ld, m, jend, ka == 0 ? p : m, acc,
+                [&](int x, int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e) + x; },
                 [&](int y) { return j0 + wc + 4 * ln + y; });
 }
 

@@ -81,7 +81,8 @@ struct Level {
     SolveLevel sv;
     int32_t upd_var = 0;                           // update kernel of this level (WCS_UPD_*; autotuned)
     std::vector<Op> ops;
-    std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds (offset, count)
+    std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds into the pivot columns (offset, count)
+    std::vector<std::pair<int64_t, int64_t>> ea_post;   // ... into the update matrices, after the trailing updates
     int64_t fl_off = 0, fl_cnt = 0;                // fronts of this level in flist
 };
 
@@ -100,6 +101,7 @@ struct Plan {
     std::vector<int2> zero_tasks;                 // (front, first column) chunks of ZCOLS columns
     int64_t lower_elems = 0;
     std::vector<int32_t> child_ptr, child_list;
+    std::vector<int32_t> ea_split;                // per front: update columns that land in the parent's pivot columns
     std::vector<int32_t> colof;                   // column of each stored entry
     std::vector<int32_t> slist;                   // fronts per level for the solves (fused first, then stepped)
     std::vector<int2> sfwd_tasks, sbwd_tasks, sasm_tasks, sblk_tasks;
@@ -139,6 +141,15 @@ struct Plan {
             for (int32_t s = 0; s < ns; s++)
                 if (S.sparent[s] >= 0) child_list[fill[S.sparent[s]]++] = s;   // ascending
         }
+        ea_split.assign((size_t)ns, 0);
+        for (int32_t c = 0; c < ns; c++) {
+            int32_t par = S.sparent[c];
+            if (par < 0) continue;
+            const int32_t *rl = S.rel.data() + S.rptr[c] + pfront[c];
+            int32_t nu = mfront[c] - pfront[c], js = 0;
+            while (js < nu && rl[js] < pfront[par]) js++;   // rel ascends
+            ea_split[c] = js;
+        }
         int32_t H = S.nlevels;
         std::vector<std::vector<int32_t>> bylev(H);
         for (int32_t s = 0; s < ns; s++) bylev[S.height[s]].push_back(s);
@@ -153,20 +164,26 @@ struct Plan {
             L.fl_off = (int64_t)flist.size();
             flist.insert(flist.end(), fr.begin(), fr.end());
             L.fl_cnt = (int64_t)fr.size();
-            // extend-add rounds: round r adds the r-th child of every parent
+            // extend-add rounds: round r adds the r-th child of every parent;
+            // first the children's columns that land in the pivot columns, and
+            // after the level's trailing updates the rest
             int32_t maxk = 0;
             for (int32_t s : fr) maxk = std::max(maxk, child_ptr[s + 1] - child_ptr[s]);
-            for (int32_t r = 0; r < maxk; r++) {
-                int64_t off = (int64_t)ea_tasks.size();
-                for (int32_t s : fr) {
-                    if (child_ptr[s] + r >= child_ptr[s + 1]) continue;
-                    int32_t c = child_list[child_ptr[s] + r];
-                    int32_t nu = mfront[c] - pfront[c];
-                    for (int32_t c0 = 0; c0 < nu; c0 += EA_COLS) ea_tasks.push_back(make_int2(c, c0));
+            for (int post = 0; post < 2; post++)
+                for (int32_t r = 0; r < maxk; r++) {
+                    int64_t off = (int64_t)ea_tasks.size();
+                    for (int32_t s : fr) {
+                        if (child_ptr[s] + r >= child_ptr[s + 1]) continue;
+                        int32_t c = child_list[child_ptr[s] + r];
+                        int32_t nu = mfront[c] - pfront[c], js = ea_split[c];
+                        if (post)
+                            for (int32_t c0 = js; c0 < nu; c0 += EA_COLS) ea_tasks.push_back(make_int2(c, c0));
+                        else
+                            for (int32_t c0 = 0; c0 < js; c0 += EA_COLS) ea_tasks.push_back(make_int2(c, c0));
+                    }
+                    int64_t cnt = (int64_t)ea_tasks.size() - off;
+                    if (cnt) (post ? L.ea_post : L.ea).push_back({off, cnt});
                 }
-                int64_t cnt = (int64_t)ea_tasks.size() - off;
-                if (cnt) L.ea.push_back({off, cnt});
-            }
             int32_t maxp = 0;
             for (int32_t s : fr) maxp = std::max(maxp, pfront[s]);
             int32_t tw = UT;
@@ -316,8 +333,8 @@ struct Plan {
         zero_tasks.clear();
         lower_elems = 0;
         for (int32_t s = 0; s < ns; s++) {
-            for (int32_t c0 = 0; c0 < mfront[s]; c0 += ZCOLS) zero_tasks.push_back(make_int2(s, c0));
-            lower_elems += (int64_t)mfront[s] * (mfront[s] + 1) / 2;
+            for (int32_t c0 = 0; c0 < pfront[s]; c0 += ZCOLS) zero_tasks.push_back(make_int2(s, c0));
+            lower_elems += (int64_t)pfront[s] * mfront[s] - (int64_t)pfront[s] * (pfront[s] - 1) / 2;
         }
         colof.resize((size_t)S.nnz);
         for (int32_t j = 0; j < S.n; j++)
@@ -328,7 +345,7 @@ struct Plan {
 // Workspace layout (byte offsets), all segments 256-byte aligned.
 struct Layout {
     size_t fronts, W, Y, Xr, Rr, Br, vec, bad;
-    size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list;
+    size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list, easplit;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2;
@@ -360,6 +377,7 @@ struct Layout {
         woff = seg(ns * 8);
         child_ptr = seg((ns + 1) * 4);
         child_list = seg(std::max<size_t>(1, P.child_list.size()) * 4);
+        easplit = seg(ns * 4);
         perm = seg(n * 4);
         csr_ptr = seg((n + 1) * 8);
         csr_col = seg(S.csr_col.size() * 4);
@@ -563,7 +581,8 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, f->at<int32_t>(Lo.bad), (int64_t)1, INT32_MAX);
     PROF_BEGIN(KC_FILL);
     hipLaunchKernelGGL(k_zero_lower<T>, dim3((unsigned)std::min<int64_t>(P.zero_tasks.size(), 1 << 30)), dim3(256), 0,
-                       st, f->at<int2>(Lo.ztasks), f->at<int64_t>(Lo.front_off), f->at<int32_t>(Lo.mfront), fronts);
+                       st, f->at<int2>(Lo.ztasks), f->at<int64_t>(Lo.front_off), f->at<int32_t>(Lo.mfront),
+                       f->at<int32_t>(Lo.pfront), fronts);
     PROF_END(KC_FILL);
     PROF_BEGIN(KC_SCATTER);
     hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(S.nnz)), dim3(256), 0, st, values, f->at<int64_t>(Lo.amap),
@@ -592,6 +611,23 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     // every level joins the side stream before its closing event)
     hipStream_t side = ((prof && !prof->levels) || !f->side) ? st : f->side;
     bool pending = false;   // side-stream work not yet joined into st
+    const int32_t *esp = f->at<int32_t>(Lo.easplit);
+    auto extend_add = [&](const std::vector<std::pair<int64_t, int64_t>> &rounds, bool pre) -> int {
+        for (auto &r : rounds) {
+            PROF_BEGIN(KC_EXTEND_ADD);
+            hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)r.second), dim3(256), 0, st, ea + r.first, fo, mf,
+                               pf, sp, rp, rl, pre ? esp : nullptr, fronts);
+            PROF_END(KC_EXTEND_ADD);
+            if (prof)
+                for (int64_t t = r.first; t < r.first + r.second; t++) {
+                    int2 task = P.ea_tasks[t];
+                    double nu = P.mfront[task.x] - P.pfront[task.x];
+                    double c1 = std::min<double>(task.y + EA_COLS, pre ? P.ea_split[task.x] : nu);
+                    for (double col = task.y; col < c1; col++) prof->bytes[KC_EXTEND_ADD] += (nu - col) * (3 * esz + 4);
+                }
+        }
+        return WCS_OK;
+    };
     for (size_t h = 0; h < P.levels.size(); h++) {
         const Level &L = P.levels[h];
         if (prof && prof->levels) {
@@ -604,19 +640,8 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
             }
             prof->lev_flops.push_back(fl);
         }
-        for (auto &r : L.ea) {
-            PROF_BEGIN(KC_EXTEND_ADD);
-            hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)r.second), dim3(256), 0, st, ea + r.first, fo, mf,
-                               pf, sp, rp, rl, fronts);
-            PROF_END(KC_EXTEND_ADD);
-            if (prof)
-                for (int64_t t = r.first; t < r.first + r.second; t++) {
-                    int2 task = P.ea_tasks[t];
-                    double nu = P.mfront[task.x] - P.pfront[task.x];
-                    double c1 = std::min<double>(task.y + EA_COLS, nu);
-                    for (double col = task.y; col < c1; col++) prof->bytes[KC_EXTEND_ADD] += (nu - col) * (3 * esz + 4);
-                }
-        }
+        int r_ea = extend_add(L.ea, true);
+        if (r_ea) return r_ea;
         for (const Op &op : L.ops) {
             if (op.kind == OP_UPDATE) {
                 bool small = L.upd_var == WCS_UPD_REG64;
@@ -669,6 +694,8 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
             HIP_TRY(hipStreamWaitEvent(st, f->ev_side, 0));
             pending = false;
         }
+        r_ea = extend_add(L.ea_post, false);
+        if (r_ea) return r_ea;
         if (prof && prof->levels) {
             int r_ = prof->mark(prof->lev);
             if (r_) return r_;
@@ -1058,6 +1085,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.woff, P.woff, st);
     rc = rc ? rc : upload(f, L.child_ptr, P.child_ptr, st);
     rc = rc ? rc : upload(f, L.child_list, P.child_list, st);
+    rc = rc ? rc : upload(f, L.easplit, P.ea_split, st);
     rc = rc ? rc : upload(f, L.perm, S.perm, st);
     rc = rc ? rc : upload(f, L.csr_ptr, S.csr_ptr, st);
     rc = rc ? rc : upload(f, L.csr_col, S.csr_col, st);
