@@ -213,6 +213,8 @@ def main() -> int:
     ap.add_argument("--instances", type=int, default=256, help="batch workload: number of instances")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default update kernel on every level instead of timing the variants first")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -258,10 +260,19 @@ def main() -> int:
     Bd = torch.as_tensor(B, device=dev)
     stream = torch.cuda.current_stream()
 
+    tuned = {}
+
     def run_path(prec, refine):
         f = Factor(sym, prec, max_nrhs=nrhs, device=dev)
         log(f"{'FP32' if prec == FP32 else 'FP64'} workspace {f.workspace.numel() / 2**30:.1f} GiB")
         reports = []
+        if not args.no_autotune:
+            # setup, like the analysis: time the update kernel variants per tree level
+            tune = f.autotune(vals)
+            torch.cuda.synchronize()
+            tuned[prec] = tune["tiles"].tolist()
+            log(f"  autotune: variants per level {tuned[prec]}, levels {tune['ms_default']:.2f} ms with the "
+                f"default, {tune['ms_tuned']:.2f} ms tuned")
 
         def step():
             e0 = torch.cuda.Event(enable_timing=True)
@@ -367,6 +378,7 @@ def main() -> int:
         "fp64": fp64,
         "speedup_e2e_vs_fp64": (fp64["ms_per_step"] / (step32 * 1e3)) if fp64 else None,
         "kernels": prof,
+        "update_variants": {("fp32" if k == FP32 else "fp64"): v for k, v in tuned.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
