@@ -115,11 +115,11 @@ __global__ void k_scatter(const double *__restrict__ values, const int64_t *__re
 // columns below split[c] only); the rest land in the parent's own update
 // matrix and are added after the parent's trailing updates (split null).
 template <typename T>
-__global__ void k_extend_add(const int2 *__restrict__ tasks, const int64_t *__restrict__ front_off,
-                             const int32_t *__restrict__ mfront, const int32_t *__restrict__ pfront,
-                             const int32_t *__restrict__ sparent, const int64_t *__restrict__ rptr,
-                             const int32_t *__restrict__ rel, const int32_t *__restrict__ split,
-                             T *__restrict__ fronts)
+__global__ __launch_bounds__(256) void k_extend_add(const int2 *__restrict__ tasks, const int64_t *__restrict__ front_off,
+                                                    const int32_t *__restrict__ mfront, const int32_t *__restrict__ pfront,
+                                                    const int32_t *__restrict__ sparent, const int64_t *__restrict__ rptr,
+                                                    const int32_t *__restrict__ rel, const int32_t *__restrict__ split,
+                                                    T *__restrict__ fronts)
 {
     int2 t = tasks[blockIdx.x];
     int c = t.x;
@@ -132,27 +132,42 @@ __global__ void k_extend_add(const int2 *__restrict__ tasks, const int64_t *__re
     const T *U = fronts + front_off[c] + (int64_t)pc * ldc + pc;
     T *Fp = fronts + front_off[par];
     const int32_t *rl = rel + rptr[c] + pc;
-    int c1 = min(t.y + EA_COLS, cend);
-    constexpr int B = 4;   // rows per thread per round: all loads of a round before its stores
-    for (int col = t.y; col < c1; col++) {
-        int pcol = rl[col];
-        const T *u = U + (int64_t)col * ldc;
-        T *dst = Fp + (int64_t)pcol * ldp;
-        for (int r0 = col + threadIdx.x; r0 < nu; r0 += B * blockDim.x) {
-            int pr[B];
-            T uv[B], dv[B];
+    const int c0 = t.y, nc = min(EA_COLS, cend - c0);
+    // each thread keeps its rows for all EA_COLS columns of the task: the row
+    // positions are read once, and the loads of every column are in flight
+    // together before the adds (one wait for the child, one for the parent)
+    int64_t pcol[EA_COLS];
 #pragma unroll
-            for (int b = 0; b < B; b++) {
-                int r = r0 + b * blockDim.x;
-                pr[b] = r < nu ? rl[r] : -1;
-                uv[b] = r < nu ? u[r] : (T)0;
+    for (int j = 0; j < EA_COLS; j++) pcol[j] = (int64_t)rl[c0 + min(j, nc - 1)] * ldp;
+    constexpr int RB = 2;   // rows per thread per round
+    for (int r0 = c0 + (int)threadIdx.x; r0 < nu; r0 += RB * (int)blockDim.x) {
+        int pr[RB];
+        T uv[RB][EA_COLS], dv[RB][EA_COLS];
+#pragma unroll
+        for (int i = 0; i < RB; i++) {
+            int r = r0 + i * (int)blockDim.x;
+            pr[i] = r < nu ? rl[r] : 0;
+#pragma unroll
+            for (int j = 0; j < EA_COLS; j++) {
+                bool ok = r < nu && j < nc && r >= c0 + j;
+                uv[i][j] = ok ? U[(int64_t)(c0 + j) * ldc + r] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; i++)
+#pragma unroll
+            for (int j = 0; j < EA_COLS; j++) {
+                int r = r0 + i * (int)blockDim.x;
+                bool ok = r < nu && j < nc && r >= c0 + j;
+                dv[i][j] = Fp[ok ? pcol[j] + pr[i] : 0];
             }
 #pragma unroll
-            for (int b = 0; b < B; b++) dv[b] = dst[pr[b] >= 0 ? pr[b] : 0];
+        for (int i = 0; i < RB; i++)
 #pragma unroll
-            for (int b = 0; b < B; b++)
-                if (pr[b] >= 0) dst[pr[b]] = dv[b] + uv[b];
-        }
+            for (int j = 0; j < EA_COLS; j++) {
+                int r = r0 + i * (int)blockDim.x;
+                if (r < nu && j < nc && r >= c0 + j) Fp[pcol[j] + pr[i]] = dv[i][j] + uv[i][j];
+            }
     }
 }
 
