@@ -47,6 +47,15 @@ template <> struct Mfma<double> {
 
 // ---------------------------------------------------------------- utilities
 
+// compile-time loop: fn(integral_constant<int, I>) for I = B, B + S, ... < E
+template <int B, int E, int S, typename Fn> __device__ __forceinline__ void static_for(Fn &&fn)
+{
+    if constexpr (B < E) {
+        fn(std::integral_constant<int, B>());
+        static_for<B + S, E, S>(fn);
+    }
+}
+
 // leading dimension of an m x m front (m rounded up to 8 elements)
 __device__ __forceinline__ int front_ld(int m) { return (m + 7) & ~7; }
 
@@ -172,16 +181,45 @@ __global__ __launch_bounds__(256) void k_extend_add(const int2 *__restrict__ tas
 }
 
 // ---------------------------------------------------------------- panel
-// Broadcast of lane `l` (a compile-time constant after unrolling) to the wave.
-__device__ __forceinline__ float readlane(float v, int l)
+// Broadcast of lane v (a compile-time constant after unrolling) of each row of
+// 16 lanes to its row: a DPP row_newbcast move, which stays in the vector
+// unit (no round trip through a scalar register, as v_readlane takes).
+template <int V>
+__device__ __forceinline__ int row_bcast_i(int x)
 {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+    return __builtin_amdgcn_update_dpp(0, x, 0x150 + V, 0xF, 0xF, false);
 }
-__device__ __forceinline__ double readlane(double v, int l)
+template <int V>
+__device__ __forceinline__ float row_bcast_t(float x)
 {
-    int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-    int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-    return __hiloint2double(hi, lo);
+    return __int_as_float(row_bcast_i<V>(__float_as_int(x)));
+}
+template <int V>
+__device__ __forceinline__ double row_bcast_t(double x)
+{
+    return __hiloint2double(row_bcast_i<V>(__double2hiint(x)), row_bcast_i<V>(__double2loint(x)));
+}
+template <typename T>
+__device__ __forceinline__ T row_bcast(T x, int v)
+{
+    switch (v) {
+    case 0: return row_bcast_t<0>(x);
+    case 1: return row_bcast_t<1>(x);
+    case 2: return row_bcast_t<2>(x);
+    case 3: return row_bcast_t<3>(x);
+    case 4: return row_bcast_t<4>(x);
+    case 5: return row_bcast_t<5>(x);
+    case 6: return row_bcast_t<6>(x);
+    case 7: return row_bcast_t<7>(x);
+    case 8: return row_bcast_t<8>(x);
+    case 9: return row_bcast_t<9>(x);
+    case 10: return row_bcast_t<10>(x);
+    case 11: return row_bcast_t<11>(x);
+    case 12: return row_bcast_t<12>(x);
+    case 13: return row_bcast_t<13>(x);
+    case 14: return row_bcast_t<14>(x);
+    default: return row_bcast_t<15>(x);
+    }
 }
 
 // 1 / sqrt(d) to working precision: the hardware estimate refined by Newton
@@ -221,9 +259,14 @@ __device__ __forceinline__ typename Mfma<TD>::V mm16(typename Mfma<TD>::V acc, F
 // inverse by forward substitution, the sub-panel below it as X = A L_kk^-T
 // and the trailing update A -= X X^T as 16x16x16 matrix-core products.  The
 // inverse of the whole block is then assembled blockwise:
-// (L^-1)_ik = -L_ii^-1 sum_{k<=j<i} L_ij (L^-1)_jk.  Meanwhile waves 1..3 load
-// their 64-row slabs of the panel below the block; afterwards they solve them
-// as X = B L^-T on the matrix cores (rows [k0+nb+t*TRW, +TRW)).
+// (L^-1)_ik = -L_ii^-1 sum_{k<=j<i} L_ij (L^-1)_jk.  Waves 1..3 own 64-row
+// slabs of the panel below the block (rows [k0+nb+t*TRW, +TRW)) and solve
+// X L^T = B by 16-column blocks, X_c = (B_c - sum_{j<c} X_j L_cj^T) L_cc^-T,
+// as matrix-core products, each block as soon as its diagonal sub-block is
+// inverted, while wave 0 factors the next one.  They work on transposed
+// blocks (X_c^T = L_cc^-1 (B_c^T - L_cj X_j^T)), so a product's accumulator
+// is the next product's B operand: the contraction index of step s in lane
+// group q is Mfma<T>::row(q, s), the row an accumulator element holds.
 // Tile 0 writes the factored block to `dscr` (the front must keep the
 // unfactored block readable for the other workgroups of this launch, and a
 // later launch copies it into place) and the block's inverse to `dinv`, which
@@ -246,7 +289,6 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
     __shared__ TD A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L
     __shared__ TD Iv[NB][NB + 1];    // column-major: Iv[c][r] = L^-1(r, c)
     __shared__ TD Rd[NB];            // 1 / L(r, r)
-    __shared__ T Li[NB][NB + 1];     // row-major copy of L^-1 in the panel precision
     int2 t = tasks[blockIdx.x];
     int f = t.x;
     int m = mfront[f], p = pfront[f], ld = front_ld(m);
@@ -256,7 +298,12 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
     int wave = tid / 64, lane = tid % 64;
     int kq = lane / 16, ln = lane % 16;
     int row0 = k0 + nb + t.y * TRW + (wave - 1) * 64;
-    T bv[NB / 4][4];                 // waves 1..3: the slab in MFMA A-operand order
+    typedef typename Mfma<T>::V V;
+    // waves 1..3: xs[c][rb] holds the transposed 16 x 16 block (rows
+    // row0 + 16 rb.., panel columns 16 c..) of B, later of X: element e of
+    // lane (kq, ln) is column 16 c + Mfma<T>::row(kq, e) of row row0 + 16 rb + ln
+    V xs[NB / 16][4];
+    const bool slab = wave > 0 && row0 < m;
     if (wave == 0) {
         // every load unconditional (clamped into the block) so all 64 are in
         // flight at once; the select afterwards pads with the identity
@@ -272,19 +319,46 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
         }
     } else if (row0 < m) {
 #pragma unroll
-        for (int ks = 0; ks < NB / 4; ks++) {
-            int k = ks * 4 + kq;
+        for (int c = 0; c < NB / 16; c++)
 #pragma unroll
-            for (int rb = 0; rb < 4; rb++) {
-                int row = row0 + rb * 16 + ln;
-                bv[ks][rb] = (row < m && k < nb) ? F[(int64_t)(k0 + k) * ld + row] : (T)0;
-            }
-        }
+            for (int rb = 0; rb < 4; rb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int row = row0 + rb * 16 + ln, k = c * 16 + Mfma<T>::row(kq, e);
+                    xs[c][rb][e] = (row < m && k < nb) ? F[(int64_t)(k0 + k) * ld + row] : (T)0;
+                }
     }
+    // slab block c: X_c^T = L_cc^-1 (B_c^T - sum_{j<c} L_cj X_j^T), then stored
+    auto slab_block = [&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        const int kb = 16 * c;
+#pragma unroll
+        for (int rb = 0; rb < 4; rb++) {
+            V acc = xs[c][rb];
+#pragma unroll
+            for (int j = 0; j < c; j++)
+#pragma unroll
+                for (int st = 0; st < 4; st++)
+                    acc = Mfma<T>::mma(-(T)A[16 * j + Mfma<T>::row(kq, st)][kb + ln], xs[j][rb][st], acc);
+            V x = {0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < 4; st++)
+                x = Mfma<T>::mma((T)Iv[kb + Mfma<T>::row(kq, st)][kb + ln], acc[st], x);
+            xs[c][rb] = x;
+            int row = row0 + rb * 16 + ln;
+            if (row < m)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int n = kb + Mfma<T>::row(kq, e);
+                    if (n < nb) F[(int64_t)(k0 + n) * ld + row] = x[e];
+                }
+        }
+    };
     __syncthreads();
     // the diagonal block, 16 columns at a time; the sub-block products of a
     // step are spread over the four waves
-    for (int kb = 0; kb < NB; kb += 16) {
+    static_for<0, NB / 16, 1>([&](auto cc) {
+        constexpr int kb = 16 * decltype(cc)::value;
         if (wave == 0) {
             // (1) diagonal 16 x 16 sub-block, lanes 0..15 own its rows
             if (lane < 16) {
@@ -294,7 +368,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
                 for (int u = 0; u < 16; u++) a[u] = A[kb + u][r];
 #pragma unroll
                 for (int u = 0; u < 16; u++) {
-                    TD d = readlane(a[u], u);
+                    TD d = row_bcast(a[u], u);
                     if (!(d > (TD)0)) {
                         if (lane == 0 && t.y == 0 && kb + u < nb) atomicMin(bad, first[f] + k0 + kb + u);
                         d = (TD)1;
@@ -305,26 +379,33 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
                     a[u] = l;
                     if (lane == u) Rd[kb + u] = rp;
 #pragma unroll
-                    for (int v = u + 1; v < 16; v++) a[v] -= l * readlane(l, v);
+                    for (int v = u + 1; v < 16; v++) a[v] -= l * row_bcast(l, v);
                 }
 #pragma unroll
                 for (int u = 0; u < 16; u++) A[kb + u][r] = (u <= lane) ? a[u] : (TD)0;
             }
             __builtin_amdgcn_wave_barrier();
-            // (2) its inverse: lane c < 16 solves L_kk y = e_c
+            // (2) its inverse: lane c < 16 solves L_kk y = e_c, column by column
+            // (each y entry, once known, is taken out of all later right-hand
+            // sides: 15 independent updates per step instead of one chain)
             if (lane < 16) {
                 const int c = lane;
-                TD y[16];
+                TD y[16], s2[16];
+#pragma unroll
+                for (int rr = 0; rr < 16; rr++) s2[rr] = (rr == c) ? (TD)1 : (TD)0;
 #pragma unroll
                 for (int rr = 0; rr < 16; rr++) {
-                    TD s2 = (rr == c) ? (TD)1 : (TD)0;
+                    y[rr] = s2[rr] * Rd[kb + rr];
 #pragma unroll
-                    for (int q = 0; q < rr; q++) s2 -= A[kb + q][kb + rr] * y[q];
-                    y[rr] = s2 * Rd[kb + rr];
+                    for (int q = rr + 1; q < 16; q++) s2[q] -= A[kb + rr][kb + q] * y[rr];
                 }
 #pragma unroll
                 for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
             }
+        } else {
+            // meanwhile waves 1..3: the slab block of the previous sub-block
+            if constexpr (kb > 0)
+                if (slab) slab_block(std::integral_constant<int, kb / 16 - 1>());
         }
         __syncthreads();
         // (3) sub-panel below, one 16-row block per wave: X(i, n) = sum_k A(i, kb+k) L_kk^-1(n, k)
@@ -354,7 +435,10 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
                 }
         }
         __syncthreads();
-    }
+    });
+    // the last slab block (it reads only A and the diagonal blocks of Iv, which
+    // the block inverse below leaves alone)
+    if (slab) slab_block(std::integral_constant<int, NB / 16 - 1>());
     // block inverse, column block kb = 16 wave per wave (independent columns):
     // (L^-1)_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij (L^-1)_jk
     {
@@ -383,14 +467,12 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
     }
     __syncthreads();
     // outputs: wave w handles the columns [16 w, 16 w + 16) of L^-1 (and of the factored block)
-    {
+    if (t.y == 0) {
         const int r = lane, cb = 16 * wave;
-        T iv[16];
+        {
+            T iv[16];
 #pragma unroll
-        for (int c = 0; c < 16; c++) iv[c] = (T)Iv[cb + c][r];
-#pragma unroll
-        for (int c = 0; c < 16; c++) Li[r][cb + c] = iv[c];
-        if (t.y == 0) {
+            for (int c = 0; c < 16; c++) iv[c] = (T)Iv[cb + c][r];
             int64_t o = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
             T *D = dscr + o;
             T *DI = dinv + o;
@@ -405,40 +487,6 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
             }
         }
     }
-    __syncthreads();
-    if (wave == 0 || row0 >= m) return;
-    typedef typename Mfma<T>::V V;
-    V acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++)
-#pragma unroll
-            for (int e = 0; e < 4; e++) acc[i][j][e] = 0;
-    // X(i, n) = sum_k B(i, k) L^-1(n, k): A operand from the panel, B operand L^-T
-#pragma unroll
-    for (int ks = 0; ks < NB / 4; ks++) {
-        int k = ks * 4 + kq;
-        T lv[4];
-#pragma unroll
-        for (int cb = 0; cb < 4; cb++) lv[cb] = Li[cb * 16 + ln][k];
-#pragma unroll
-        for (int rb = 0; rb < 4; rb++)
-#pragma unroll
-            for (int cb = 0; cb < 4; cb++) acc[rb][cb] = Mfma<T>::mma(bv[ks][rb], lv[cb], acc[rb][cb]);
-    }
-#pragma unroll
-    for (int rb = 0; rb < 4; rb++)
-#pragma unroll
-        for (int cb = 0; cb < 4; cb++) {
-            int n = cb * 16 + ln;
-            if (n >= nb) continue;
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                int row = row0 + rb * 16 + Mfma<T>::row(kq, e);
-                if (row < m) F[(int64_t)(k0 + n) * ld + row] = acc[rb][cb][e];
-            }
-        }
 }
 
 // Copies the factored diagonal blocks of every listed front from the scratch
@@ -665,15 +713,6 @@ __device__ __forceinline__ void dma_to_lds16(const void *g, uint32_t lds)
                  : "=&s"(saved)
                  : "v"(g), "s"(lds)
                  : "memory");
-}
-
-// compile-time loop: fn(integral_constant<int, I>) for I = B, B + S, ... < E
-template <int B, int E, int S, typename Fn> __device__ __forceinline__ void static_for(Fn &&fn)
-{
-    if constexpr (B < E) {
-        fn(std::integral_constant<int, B>());
-        static_for<B + S, E, S>(fn);
-    }
 }
 
 template <typename T>
