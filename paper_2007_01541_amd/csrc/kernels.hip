@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void k_extend_add(const int2 *__restrict__ tas
 template <int V>
 __device__ __forceinline__ int row_bcast_i(int x)
 {
-    return __builtin_amdgcn_update_dpp(0, x, 0x150 + V, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, 0x150 + V, 0xF, 0xF, true);
 }
 template <int V>
 __device__ __forceinline__ float row_bcast_t(float x)
