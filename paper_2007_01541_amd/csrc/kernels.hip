@@ -257,9 +257,9 @@ __device__ __forceinline__ typename Mfma<TD>::V mm16(typename Mfma<TD>::V acc, F
 // sub-block with one lane per row in registers (l_jj = sqrt(a_jj),
 // l_rj = a_rj / l_jj, a_rc -= l_rj l_cj, l_cj broadcast from lane c), its
 // inverse by forward substitution, the sub-panel below it as X = A L_kk^-T
-// and the trailing update A -= X X^T as 16x16x16 matrix-core products.  The
-// inverse of the whole block is then assembled blockwise:
-// (L^-1)_ik = -L_ii^-1 sum_{k<=j<i} L_ij (L^-1)_jk.  Waves 1..3 own 64-row
+// and the trailing update A -= X X^T as 16x16x16 matrix-core products; wave 0
+// updates only the next diagonal sub-block and goes on factoring it while the
+// other waves take the other block pairs.  Waves 1..3 own 64-row
 // slabs of the panel below the block (rows [k0+nb+t*TRW, +TRW)) and solve
 // X L^T = B by 16-column blocks, X_c = (B_c - sum_{j<c} X_j L_cj^T) L_cc^-T,
 // as matrix-core products, each block as soon as its diagonal sub-block is
@@ -269,8 +269,7 @@ __device__ __forceinline__ typename Mfma<TD>::V mm16(typename Mfma<TD>::V acc, F
 // group q is Mfma<T>::row(q, s), the row an accumulator element holds.
 // Tile 0 writes the factored block to `dscr` (the front must keep the
 // unfactored block readable for the other workgroups of this launch, and a
-// later launch copies it into place) and the block's inverse to `dinv`, which
-// the triangular solves use.
+// later launch copies it into place; another one inverts it for the solves).
 // A non-positive (or NaN) pivot is reported through atomicMin on *bad (global
 // pivot numbering) and replaced by 1 so the rest stays finite.
 constexpr int TRW = THREADS - 64;   // panel rows per workgroup (waves 1..3)
@@ -282,8 +281,7 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
                                                    const int32_t *__restrict__ pfront,
                                                    const int32_t *__restrict__ first,
                                                    const int64_t *__restrict__ dscr_off, T *__restrict__ fronts,
-                                                   T *__restrict__ dscr, T *__restrict__ dinv,
-                                                   int32_t *__restrict__ bad)
+                                                   T *__restrict__ dscr, int32_t *__restrict__ bad)
 {
     typedef typename Mfma<TD>::V VD;
     __shared__ TD A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L
@@ -357,58 +355,65 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
     __syncthreads();
     // the diagonal block, 16 columns at a time; the sub-block products of a
     // step are spread over the four waves
-    static_for<0, NB / 16, 1>([&](auto cc) {
-        constexpr int kb = 16 * decltype(cc)::value;
-        if (wave == 0) {
-            // (1) diagonal 16 x 16 sub-block, lanes 0..15 own its rows
-            if (lane < 16) {
-                const int r = kb + lane;
-                TD a[16];
+    // wave 0: the diagonal 16 x 16 sub-block kb, lanes 0..15 owning its rows,
+    // then its inverse
+    auto diag_step = [&](auto kbc) {
+        constexpr int kb = decltype(kbc)::value;
+        if (lane < 16) {
+            const int r = kb + lane;
+            TD a[16];
 #pragma unroll
-                for (int u = 0; u < 16; u++) a[u] = A[kb + u][r];
+            for (int u = 0; u < 16; u++) a[u] = A[kb + u][r];
 #pragma unroll
-                for (int u = 0; u < 16; u++) {
-                    TD d = row_bcast(a[u], u);
-                    if (!(d > (TD)0)) {
-                        if (lane == 0 && t.y == 0 && kb + u < nb) atomicMin(bad, first[f] + k0 + kb + u);
-                        d = (TD)1;
-                    }
-                    TD rp = rsqrt_refined(d);
-                    TD piv = d * rp;
-                    TD l = (lane == u) ? piv : a[u] * rp;
-                    a[u] = l;
-                    if (lane == u) Rd[kb + u] = rp;
-#pragma unroll
-                    for (int v = u + 1; v < 16; v++) a[v] -= l * row_bcast(l, v);
+            for (int u = 0; u < 16; u++) {
+                TD d = row_bcast(a[u], u);
+                if (!(d > (TD)0)) {
+                    if (lane == 0 && t.y == 0 && kb + u < nb) atomicMin(bad, first[f] + k0 + kb + u);
+                    d = (TD)1;
                 }
+                TD rp = rsqrt_refined(d);
+                TD piv = d * rp;
+                TD l = (lane == u) ? piv : a[u] * rp;
+                a[u] = l;
+                if (lane == u) Rd[kb + u] = rp;
 #pragma unroll
-                for (int u = 0; u < 16; u++) A[kb + u][r] = (u <= lane) ? a[u] : (TD)0;
+                for (int v = u + 1; v < 16; v++) a[v] -= l * row_bcast(l, v);
             }
-            __builtin_amdgcn_wave_barrier();
-            // (2) its inverse: lane c < 16 solves L_kk y = e_c, column by column
-            // (each y entry, once known, is taken out of all later right-hand
-            // sides: 15 independent updates per step instead of one chain)
-            if (lane < 16) {
-                const int c = lane;
-                TD y[16], s2[16];
 #pragma unroll
-                for (int rr = 0; rr < 16; rr++) s2[rr] = (rr == c) ? (TD)1 : (TD)0;
-#pragma unroll
-                for (int rr = 0; rr < 16; rr++) {
-                    y[rr] = s2[rr] * Rd[kb + rr];
-#pragma unroll
-                    for (int q = rr + 1; q < 16; q++) s2[q] -= A[kb + rr][kb + q] * y[rr];
-                }
-#pragma unroll
-                for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
-            }
-        } else {
-            // meanwhile waves 1..3: the slab block of the previous sub-block
-            if constexpr (kb > 0)
-                if (slab) slab_block(std::integral_constant<int, kb / 16 - 1>());
+            for (int u = 0; u < 16; u++) A[kb + u][r] = (u <= lane) ? a[u] : (TD)0;
         }
-        __syncthreads();
-        // (3) sub-panel below, one 16-row block per wave: X(i, n) = sum_k A(i, kb+k) L_kk^-1(n, k)
+        __builtin_amdgcn_wave_barrier();
+        // its inverse: lane c < 16 solves L_kk y = e_c, column by column (each y
+        // entry, once known, is taken out of all later right-hand sides: 15
+        // independent updates per step instead of one chain)
+        if (lane < 16) {
+            const int c = lane;
+            TD y[16], s2[16];
+#pragma unroll
+            for (int rr = 0; rr < 16; rr++) s2[rr] = (rr == c) ? (TD)1 : (TD)0;
+#pragma unroll
+            for (int rr = 0; rr < 16; rr++) {
+                y[rr] = s2[rr] * Rd[kb + rr];
+#pragma unroll
+                for (int q = rr + 1; q < 16; q++) s2[q] -= A[kb + rr][kb + q] * y[rr];
+            }
+#pragma unroll
+            for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
+        }
+    };
+    // A(ib.., jb..) -= X_i X_j^T with the sub-panel blocks X of column block kb
+    auto syrk_pair = [&](int kb, int ib, int jb) {
+        VD acc = {0, 0, 0, 0};
+        acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
+                       [&](int k, int n) { return A[kb + k][jb + n]; });
+#pragma unroll
+        for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<TD>::row(kq, e)] -= acc[e];
+    };
+    if (wave == 0) diag_step(std::integral_constant<int, 0>());
+    __syncthreads();
+    static_for<0, NB / 16 - 1, 1>([&](auto cc) {
+        constexpr int c = decltype(cc)::value, kb = 16 * c;
+        // sub-panel below, one 16-row block per wave: X(i, n) = sum_k A(i, kb+k) L_kk^-1(n, k)
         {
             int ib = kb + 16 * (wave + 1);
             if (ib < NB) {
@@ -421,72 +426,69 @@ __global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ task
             }
         }
         __syncthreads();
-        // (4) trailing update A(i, j) -= X_i X_j^T for kb < j <= i, block pairs dealt round-robin to the waves
-        {
+        // trailing update of the block by X X^T: wave 0 takes the next diagonal
+        // sub-block and goes on to factor it; waves 1..3 share the other block
+        // pairs and then solve their slab block c (disjoint parts of A and Iv)
+        if (wave == 0) {
+            syrk_pair(kb, kb + 16, kb + 16);
+            __builtin_amdgcn_wave_barrier();
+            diag_step(std::integral_constant<int, kb + 16>());
+        } else {
             int q = 0;
             for (int ib = kb + 16; ib < NB; ib += 16)
-                for (int jb = kb + 16; jb <= ib; jb += 16, q++) {
-                    if (q % 4 != wave) continue;
-                    VD acc = {0, 0, 0, 0};
-                    acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
-                                   [&](int k, int n) { return A[kb + k][jb + n]; });
-#pragma unroll
-                    for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<TD>::row(kq, e)] -= acc[e];
+                for (int jb = kb + 16; jb <= ib; jb += 16) {
+                    if (ib == kb + 16) continue;   // the diagonal sub-block (wave 0)
+                    if (q++ % 3 == wave - 1) syrk_pair(kb, ib, jb);
                 }
+            if (slab) slab_block(cc);
         }
         __syncthreads();
     });
-    // the last slab block (it reads only A and the diagonal blocks of Iv, which
-    // the block inverse below leaves alone)
     if (slab) slab_block(std::integral_constant<int, NB / 16 - 1>());
-    // block inverse, column block kb = 16 wave per wave (independent columns):
-    // (L^-1)_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij (L^-1)_jk
-    {
-        const int kb = 16 * wave;
-        for (int ib = kb + 16; ib < NB; ib += 16) {
-            VD acc = {0, 0, 0, 0};
-            for (int jb = kb; jb < ib; jb += 16)
-                acc = mm16<TD>(acc, [&](int r, int k) { return A[jb + k][ib + r]; },
-                               [&](int k, int n) { return Iv[kb + n][jb + k]; });
-            __builtin_amdgcn_wave_barrier();
-            // stage T = acc in the unused upper block of Iv at (rows kb.., cols ib..)
-#pragma unroll
-            for (int e = 0; e < 4; e++) Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = acc[e];
-            __builtin_amdgcn_wave_barrier();
-            VD res = {0, 0, 0, 0};
-            res = mm16<TD>(res, [&](int r, int k) { return Iv[ib + k][ib + r]; },
-                           [&](int k, int n) { return Iv[ib + n][kb + k]; });
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int e = 0; e < 4; e++) {
-                Iv[kb + ln][ib + Mfma<TD>::row(kq, e)] = -res[e];
-                Iv[ib + ln][kb + Mfma<TD>::row(kq, e)] = 0;
-            }
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
-    __syncthreads();
-    // outputs: wave w handles the columns [16 w, 16 w + 16) of L^-1 (and of the factored block)
+    // tile 0: the factored block (full, padding and upper part included) to the scratch
     if (t.y == 0) {
         const int r = lane, cb = 16 * wave;
-        {
-            T iv[16];
+        T *D = dscr + dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
+        T lv[16];
 #pragma unroll
-            for (int c = 0; c < 16; c++) iv[c] = (T)Iv[cb + c][r];
-            int64_t o = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
-            T *D = dscr + o;
-            T *DI = dinv + o;
-            T lv[16];
+        for (int c = 0; c < 16; c++) lv[c] = (T)A[cb + c][r];
 #pragma unroll
-            for (int c = 0; c < 16; c++) lv[c] = (T)A[cb + c][r];
-            // the full block goes to the scratch (the fix-up copies only its lower part)
-#pragma unroll
-            for (int c = 0; c < 16; c++) {
-                D[(cb + c) * NB + r] = lv[c];
-                DI[(cb + c) * NB + r] = iv[c];     // column-major L^-1 of the padded block
-            }
-        }
+        for (int c = 0; c < 16; c++) D[(cb + c) * NB + r] = lv[c];
     }
+}
+
+// Inverse of every factored NB x NB diagonal block (task = (front, block)),
+// from its copy in dscr, formed in FP64 and rounded to T into dinv (column
+// major, same offsets): one wave per block, lane c forms column c of L^-1 by
+// forward substitution, right-looking (15 and more independent updates per
+// step).  The triangular solves use these inverses; nothing in the
+// factorization does, so this runs once at its end, off the panel chain.
+template <typename T>
+__global__ __launch_bounds__(64) void k_diag_inv(const int2 *__restrict__ tasks,
+                                                 const int64_t *__restrict__ dscr_off, const T *__restrict__ dscr,
+                                                 T *__restrict__ dinv)
+{
+    __shared__ double L[NB][NB + 1];   // column-major: L[c][r] = L(r, c)
+    int2 t = tasks[blockIdx.x];
+    int64_t o = dscr_off[t.x] + (int64_t)t.y * NB * NB;
+    const T *D = dscr + o;
+    const int c = threadIdx.x;
+    for (int i = c; i < NB * NB; i += 64) L[i / NB][i % NB] = (double)D[i];
+    __syncthreads();
+    double y[NB];
+#pragma unroll
+    for (int r = 0; r < NB; r++) y[r] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int r = 0; r < NB; r++) {
+        y[r] = y[r] / L[r][r];
+#pragma unroll
+        for (int q = r + 1; q < NB; q++) y[q] -= L[r][q] * y[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NB; r++) L[c][r] = y[r];
+    __syncthreads();
+    for (int i = c; i < NB * NB; i += 64) dinv[o + i] = (T)L[i / NB][i % NB];
 }
 
 // Copies the factored diagonal blocks of every listed front from the scratch

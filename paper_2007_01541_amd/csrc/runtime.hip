@@ -83,6 +83,7 @@ struct Level {
     std::vector<Op> ops;
     std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds into the pivot columns (offset, count)
     std::vector<std::pair<int64_t, int64_t>> ea_post;   // ... into the update matrices, after the trailing updates
+    int64_t dinv_off = 0, dinv_cnt = 0;            // diagonal blocks of this level's fronts (dinv_tasks)
     int64_t fl_off = 0, fl_cnt = 0;                // fronts of this level in flist
 };
 
@@ -96,6 +97,7 @@ struct Plan {
     std::vector<int64_t> woff;                    // per front: row offset of its solve buffer
     int64_t wrows = 0;
     std::vector<int64_t> dscr_off;                // per front: element offset of its diagonal-block scratch
+    std::vector<int2> dinv_tasks;                 // (front, diagonal block) of every NB x NB block
     int64_t dscr_elems = 0;
     std::vector<int32_t> all_fronts;
     std::vector<int2> zero_tasks;                 // (front, first column) chunks of ZCOLS columns
@@ -121,6 +123,7 @@ struct Plan {
         all_fronts.resize(ns);
         wrows = 0;
         dscr_elems = 0;
+        dinv_tasks.clear();
         for (int32_t s = 0; s < ns; s++) {
             mfront[s] = S.m_of(s);
             pfront[s] = S.p_of(s);
@@ -164,6 +167,10 @@ struct Plan {
             L.fl_off = (int64_t)flist.size();
             flist.insert(flist.end(), fr.begin(), fr.end());
             L.fl_cnt = (int64_t)fr.size();
+            L.dinv_off = (int64_t)dinv_tasks.size();
+            for (int32_t s : fr)
+                for (int32_t b = 0; b < (pfront[s] + NB - 1) / NB; b++) dinv_tasks.push_back(make_int2(s, b));
+            L.dinv_cnt = (int64_t)dinv_tasks.size() - L.dinv_off;
             // extend-add rounds: round r adds the r-th child of every parent;
             // first the children's columns that land in the pivot columns, and
             // after the level's trailing updates the rest
@@ -348,7 +355,7 @@ struct Layout {
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list, easplit;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
-    size_t sblk, sbsum, xinvt, xoff, xinv, part2;
+    size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -398,6 +405,7 @@ struct Layout {
         sblk = seg(std::max<size_t>(1, P.sblk_tasks.size()) * sizeof(int2));
         sbsum = seg(std::max<size_t>(1, P.sbsum_tasks.size()) * sizeof(int4));
         xinvt = seg(std::max<size_t>(1, P.xinv_tasks.size()) * sizeof(int4));
+        dinvt = seg(std::max<size_t>(1, P.dinv_tasks.size()) * sizeof(int2));
         xoff = seg(ns * 8);
         xinv = seg((size_t)std::max<int64_t>(1, P.xelems) * esz);
         part2 = seg((size_t)std::max<int64_t>(1, P.part_blocks) * SB * k * esz);
@@ -448,9 +456,11 @@ struct wcs_factor_s {
     };
     std::vector<SweepGraph> sgraphs;           // triangular sweeps per (part, nrhs)
 
-    // look-ahead: side stream (default priority) and the two events that order it
-    hipStream_t side = nullptr;
-    hipEvent_t ev_main = nullptr, ev_side = nullptr;
+    // look-ahead: side stream (default priority) and the two events that order
+    // it; a third stream inverts each level's diagonal blocks beside the
+    // following levels
+    hipStream_t side = nullptr, aux = nullptr;
+    hipEvent_t ev_main = nullptr, ev_side = nullptr, ev_aux = nullptr;
 
     void drop_graphs()
     {
@@ -465,7 +475,9 @@ struct wcs_factor_s {
         drop_graphs();
         if (ev_main) (void)hipEventDestroy(ev_main);
         if (ev_side) (void)hipEventDestroy(ev_side);
+        if (ev_aux) (void)hipEventDestroy(ev_aux);
         if (side) (void)hipStreamDestroy(side);
+        if (aux) (void)hipStreamDestroy(aux);
     }
 
     template <typename P> P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
@@ -610,6 +622,7 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     // kernel classes, whose events time one stream; level timing is fine, as
     // every level joins the side stream before its closing event)
     hipStream_t side = ((prof && !prof->levels) || !f->side) ? st : f->side;
+    hipStream_t aux = ((prof && !prof->levels) || !f->aux) ? st : f->aux;
     bool pending = false;   // side-stream work not yet joined into st
     const int32_t *esp = f->at<int32_t>(Lo.easplit);
     auto extend_add = [&](const std::vector<std::pair<int64_t, int64_t>> &rounds, bool pre) -> int {
@@ -680,10 +693,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                 PROF_BEGIN(c);
                 if (op.kind == OP_PANEL)
                     hipLaunchKernelGGL((k_panel<T, T>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
-                                       pan + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr, dinv, bad);
+                                       pan + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr, bad);
                 else
                     hipLaunchKernelGGL((k_panel<T, double>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
-                                       pan + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr, dinv, bad);
+                                       pan + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr, bad);
                 PROF_END(c);
                 if (prof)
                     for (int64_t q = op.off; q < op.off + op.cnt; q++)
@@ -693,6 +706,17 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
         if (pending) {   // the next level's extend-add reads this level's update matrices
             HIP_TRY(hipStreamWaitEvent(st, f->ev_side, 0));
             pending = false;
+        }
+        if (L.dinv_cnt) {   // this level's diagonal blocks are final: invert them beside the next levels
+            if (aux != st) {
+                HIP_TRY(hipEventRecord(f->ev_main, st));
+                HIP_TRY(hipStreamWaitEvent(aux, f->ev_main, 0));
+            }
+            PROF_BEGIN(KC_FILL);
+            hipLaunchKernelGGL(k_diag_inv<T>, dim3((unsigned)L.dinv_cnt), dim3(64), 0, aux,
+                               f->at<int2>(Lo.dinvt) + L.dinv_off, dso, dscr, dinv);
+            PROF_END(KC_FILL);
+            if (prof) prof->bytes[KC_FILL] += (double)L.dinv_cnt * NB * NB * esz * 2;
         }
         r_ea = extend_add(L.ea_post, false);
         if (r_ea) return r_ea;
@@ -706,6 +730,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                        pf, dso, dscr, fronts);
     PROF_END(KC_FILL);
     if (prof) prof->bytes[KC_FILL] += (double)P.dscr_elems * esz * 2;
+    if (aux != st) {   // the block inverses, then the super-block inverses built from them
+        HIP_TRY(hipEventRecord(f->ev_aux, aux));
+        HIP_TRY(hipStreamWaitEvent(st, f->ev_aux, 0));
+    }
     if (!P.xinv_tasks.empty()) {
         PROF_BEGIN(KC_FILL);
         hipLaunchKernelGGL(k_build_xinv<T>, dim3((unsigned)P.xinv_tasks.size()), dim3(THREADS), 0, st,
@@ -1061,8 +1089,10 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     f->ws = (char *)workspace;
     f->bytes = bytes;
     if (hipStreamCreateWithFlags(&f->side, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&f->aux, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&f->ev_main, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&f->ev_side, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&f->ev_side, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&f->ev_aux, hipEventDisableTiming) != hipSuccess) {
         set_error("could not create the look-ahead stream or its events");
         delete f;
         return WCS_EHIP;
@@ -1105,6 +1135,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.sblk, P.sblk_tasks, st);
     rc = rc ? rc : upload(f, L.sbsum, P.sbsum_tasks, st);
     rc = rc ? rc : upload(f, L.xinvt, P.xinv_tasks, st);
+    rc = rc ? rc : upload(f, L.dinvt, P.dinv_tasks, st);
     rc = rc ? rc : upload(f, L.xoff, P.xoff, st);
     rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
     rc = rc ? rc : upload(f, L.ztasks, P.zero_tasks, st);
