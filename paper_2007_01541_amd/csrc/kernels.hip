@@ -564,6 +564,13 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 // fronts; the autotuner picks the tile per level.
 constexpr int UT = 128;
 
+// A trailing-update task with its front's descriptors, so that one 32-byte
+// (scalar) load gives the workgroup everything it needs:
+// a = (front offset low, high 32 bits, m, p), b = (i0, j0, jend, unused).
+struct UpdTask {
+    int4 a, b;
+};
+
 template <typename T> struct UpdCfg;
 template <> struct UpdCfg<float> { static constexpr int KC = 32; };
 template <> struct UpdCfg<double> { static constexpr int KC = 16; };
@@ -579,10 +586,8 @@ template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
 
 template <typename T, int TW>
-__global__ __launch_bounds__(TW * TW / 64) void k_update(const int4 *__restrict__ tasks, int ka, int kw,
-                                                    const int64_t *__restrict__ front_off,
-                                                    const int32_t *__restrict__ mfront,
-                                                    const int32_t *__restrict__ pfront, T *__restrict__ fronts)
+__global__ __launch_bounds__(TW * TW / 64) void k_update(const UpdTask *__restrict__ tasks, int ka, int kw,
+                                                    T *__restrict__ fronts)
 {
     constexpr int KC = UpdCfg<T>::KC;
     constexpr int NTH = TW * TW / 64;          // one wave per 64 x 64 quarter
@@ -591,12 +596,13 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const int4 *__restrict_
     __shared__ __align__(16) T Bs[2][KC][LD];
     constexpr int KSTEP = NTH / TW;            // k rows covered by one pass of the block
     constexpr int PER = KC / KSTEP;            // elements of each operand per thread per chunk
-    int4 t = tasks[blockIdx.x];
-    int f = t.x, i0 = t.y, j0 = t.z, jend = t.w;
-    int m = mfront[f], p = pfront[f], ld = front_ld(m);
+    const UpdTask t = tasks[blockIdx.x];
+    int i0 = t.b.x, j0 = t.b.y, jend = t.b.z;
+    int m = t.a.z, p = t.a.w, ld = front_ld(m);
     int K = min(kw, p - ka);
-    const T *F0 = fronts + front_off[f];
-    T *F = fronts + front_off[f];
+    const int64_t foff = (int64_t)(((uint64_t)(uint32_t)t.a.y << 32) | (uint32_t)t.a.x);
+    const T *F0 = fronts + foff;
+    T *F = fronts + foff;
     int tid = threadIdx.x;
     int wave = tid / 64, lane = tid % 64;
     int wr = (wave / (TW / 64)) * 64, wc = (wave % (TW / 64)) * 64;
@@ -718,10 +724,8 @@ __device__ __forceinline__ void dma_to_lds16(const void *g, uint32_t lds)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_update_dma(const int4 *__restrict__ tasks, int ka, int kw,
-                                                    const int64_t *__restrict__ front_off,
-                                                    const int32_t *__restrict__ mfront,
-                                                    const int32_t *__restrict__ pfront, T *__restrict__ fronts)
+__global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ tasks, int ka, int kw,
+                                                    T *__restrict__ fronts)
 {
     constexpr int KC = DmaCfg<T>::KC, NS = DmaCfg<T>::NS;
     static_assert(NS == 4, "the stage arrays below assume four stages");
@@ -744,11 +748,11 @@ __global__ __launch_bounds__(256) void k_update_dma(const int4 *__restrict__ tas
         else if constexpr (st == 2) return S2;
         else return S3;
     };
-    int4 t = tasks[blockIdx.x];
-    int f = t.x, i0 = t.y, j0 = t.z, jend = t.w;
-    int m = mfront[f], p = pfront[f], ld = front_ld(m);
+    const UpdTask t = tasks[blockIdx.x];
+    int i0 = t.b.x, j0 = t.b.y, jend = t.b.z;
+    int m = t.a.z, p = t.a.w, ld = front_ld(m);
     int K = min(kw, p - ka);
-    T *F = fronts + front_off[f];
+    T *F = fronts + (int64_t)(((uint64_t)(uint32_t)t.a.y << 32) | (uint32_t)t.a.x);
     int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     int wr = (wave / 2) * 64, wc = (wave % 2) * 64;
     int kq = lane / 16, ln = lane % 16;

@@ -393,7 +393,7 @@ struct Layout {
         rowind = seg((size_t)S.nnz * 4);
         colof = seg((size_t)S.nnz * 4);
         pan = seg(std::max<size_t>(1, P.pan_tasks.size()) * sizeof(int2));
-        upd = seg(std::max<size_t>(1, P.upd_tasks.size()) * sizeof(int4));
+        upd = seg(std::max<size_t>(1, P.upd_tasks.size()) * sizeof(UpdTask));
         ea = seg(std::max<size_t>(1, P.ea_tasks.size()) * sizeof(int2));
         flist = seg(std::max<size_t>(1, P.flist.size()) * 4);
         dscr = seg((size_t)P.dscr_elems * esz);
@@ -612,7 +612,7 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     const int64_t *rp = f->at<int64_t>(Lo.rptr);
     const int32_t *rl = f->at<int32_t>(Lo.rel);
     const int2 *pan = f->at<int2>(Lo.pan);
-    const int4 *upd = f->at<int4>(Lo.upd);
+    const UpdTask *upd = f->at<UpdTask>(Lo.upd);
     const int2 *ea = f->at<int2>(Lo.ea);
     int32_t *bad = f->at<int32_t>(Lo.bad);
     const int64_t *dso = f->at<int64_t>(Lo.dscr_off);
@@ -673,13 +673,13 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                 PROF_BEGIN(KC_UPDATE);
                 if (small)
                     hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, us, upd + off, op.ka,
-                                       op.kw, fo, mf, pf, fronts);
+                                       op.kw, fronts);
                 else if (L.upd_var == WCS_UPD_STREAM128)
                     hipLaunchKernelGGL(k_update_dma<T>, dim3((unsigned)cnt), dim3(256), 0, us, upd + off, op.ka,
-                                       op.kw, fo, mf, pf, fronts);
+                                       op.kw, fronts);
                 else
                     hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, us, upd + off,
-                                       op.ka, op.kw, fo, mf, pf, fronts);
+                                       op.ka, op.kw, fronts);
                 PROF_END(KC_UPDATE);
                 if (us != st) {
                     HIP_TRY(hipEventRecord(f->ev_side, side));
@@ -1123,7 +1123,17 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.rowind, S.rowind, st);
     rc = rc ? rc : upload(f, L.colof, P.colof, st);
     rc = rc ? rc : upload(f, L.pan, P.pan_tasks, st);
-    rc = rc ? rc : upload(f, L.upd, P.upd_tasks, st);
+    {
+        std::vector<UpdTask> ud(P.upd_tasks.size());
+        for (size_t q = 0; q < ud.size(); q++) {
+            int4 t = P.upd_tasks[q];
+            int64_t o = S.front_off[t.x];
+            ud[q].a = make_int4((int32_t)(uint32_t)(uint64_t)o, (int32_t)((uint64_t)o >> 32), P.mfront[t.x],
+                                P.pfront[t.x]);
+            ud[q].b = make_int4(t.y, t.z, t.w, 0);
+        }
+        rc = rc ? rc : upload(f, L.upd, ud, st);
+    }
     rc = rc ? rc : upload(f, L.ea, P.ea_tasks, st);
     rc = rc ? rc : upload(f, L.flist, P.flist, st);
     rc = rc ? rc : upload(f, L.dscr_off, P.dscr_off, st);
