@@ -520,6 +520,10 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
 // before any store, a masked-off element loading a harmless in-bounds word
 // (F[0]) that is never stored, so the round trips to memory overlap instead
 // of being serialised element by element.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
 template <typename T, typename V, typename RowFn, typename ColFn>
 __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int jend, int pa, const V (&acc)[4][4],
                                          RowFn rowf, ColFn colf)
@@ -552,6 +556,66 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
     }
 }
 
+// The same update for a tile whose accumulators come in quads of consecutive
+// rows: acc[x][y][e] belongs to row rowq(e) + x (x = 0..3) and column
+// colf(y).  With the quad's first row a multiple of 4 (aligned) and all four
+// rows inside the stored lower part, the quad is read and written as one
+// 16-byte (FP32) or 32-byte (FP64) access; other quads element by element.
+template <typename T, typename V, typename RowFn, typename ColFn>
+__device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m, int jend, int pa, bool aligned,
+                                               const V (&acc)[4][4], RowFn rowq, ColFn colf)
+{
+    typedef typename Vec4<T>::type V4;
+#pragma unroll
+    for (int h = 0; h < 4; h += 2) {
+        T cv[2][4][4];
+#pragma unroll
+        for (int e2 = 0; e2 < 2; e2++)
+#pragma unroll
+            for (int y = 0; y < 4; y++) {
+                int r0 = rowq(h + e2), c = colf(y);
+                if (aligned && c < jend && r0 >= c && r0 + 3 < m) {
+                    V4 v = *reinterpret_cast<const V4 *>(F + (c < pa ? (int64_t)c * ld + r0 : 0));
+                    cv[e2][y][0] = v.x;
+                    cv[e2][y][1] = v.y;
+                    cv[e2][y][2] = v.z;
+                    cv[e2][y][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int x = 0; x < 4; x++) {
+                        int r = r0 + x;
+                        bool ok = c < jend && r < m && r >= c && c < pa;
+                        cv[e2][y][x] = F[ok ? (int64_t)c * ld + r : 0];
+                    }
+                }
+            }
+#pragma unroll
+        for (int e2 = 0; e2 < 2; e2++)
+#pragma unroll
+            for (int y = 0; y < 4; y++) {
+                int r0 = rowq(h + e2), c = colf(y);
+                T o[4];
+#pragma unroll
+                for (int x = 0; x < 4; x++) o[x] = c < pa ? cv[e2][y][x] - acc[x][y][h + e2] : -acc[x][y][h + e2];
+                if (aligned && c < jend && r0 >= c && r0 + 3 < m) {
+                    V4 v;
+                    v.x = o[0];
+                    v.y = o[1];
+                    v.z = o[2];
+                    v.w = o[3];
+                    *reinterpret_cast<V4 *>(F + (int64_t)c * ld + r0) = v;
+                } else {
+#pragma unroll
+                    for (int x = 0; x < 4; x++) {
+                        int r = r0 + x;
+                        if (c < jend && r < m && r >= c) F[(int64_t)c * ld + r] = o[x];
+                    }
+                }
+            }
+    }
+}
+
+
 
 // task = (front, i0, j0, jend): C = F[i0:i0+UT, j0:min(j0+UT, jend)] -= A B^T
 // on the lower part (row >= column), with A = F[i0:, ka:ka+K], B = F[j0:, ka:ka+K]
@@ -580,10 +644,6 @@ template <> struct UpdCfg<double> { static constexpr int KC = 16; };
 // lane needs for its four 16-row MFMA blocks are adjacent (one 16-byte read
 // for FP32, two for FP64).
 __device__ __forceinline__ int frag_pos(int r) { return (r & ~63) + (r & 15) * 4 + ((r >> 4) & 3); }
-
-template <typename T> struct Vec4;
-template <> struct Vec4<float> { typedef float4 type; };
-template <> struct Vec4<double> { typedef double4 type; };
 
 template <typename T, int TW>
 __global__ __launch_bounds__(TW * TW / 64) void k_update(const UpdTask *__restrict__ tasks, int ka, int kw,
@@ -827,9 +887,9 @@ __global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ 
     }
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;
-    tile_sub<T>(F, ld, m, jend, ka == 0 ? p : m, acc,
-                [&](int x, int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e) + x; },
-                [&](int y) { return j0 + wc + 4 * ln + y; });
+    tile_sub_quads<T>(F, ld, m, jend, ka == 0 ? p : m, (i0 & 3) == 0, acc,
+                      [&](int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e); },
+                      [&](int y) { return j0 + wc + 4 * ln + y; });
 }
 
 // ---------------------------------------------------------------- solves
