@@ -557,13 +557,13 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 }
 
 // The same update for a tile whose accumulators come in quads of consecutive
-// rows: acc[x][y][e] belongs to row rowq(e) + x (x = 0..3) and column
-// colf(y).  With the quad's first row a multiple of 4 (aligned) and all four
-// rows inside the stored lower part, the quad is read and written as one
+// rows: av(q, y, t) belongs to row rowq(q) + t (t = 0..3) and column colf(y),
+// q, y = 0..3.  With the quad's first row a multiple of 4 (aligned) and all
+// four rows inside the stored lower part, the quad is read and written as one
 // 16-byte (FP32) or 32-byte (FP64) access; other quads element by element.
-template <typename T, typename V, typename RowFn, typename ColFn>
+template <typename T, typename AccFn, typename RowFn, typename ColFn>
 __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m, int jend, int pa, bool aligned,
-                                               const V (&acc)[4][4], RowFn rowq, ColFn colf)
+                                               AccFn av, RowFn rowq, ColFn colf)
 {
     typedef typename Vec4<T>::type V4;
 #pragma unroll
@@ -596,7 +596,7 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
                 int r0 = rowq(h + e2), c = colf(y);
                 T o[4];
 #pragma unroll
-                for (int x = 0; x < 4; x++) o[x] = c < pa ? cv[e2][y][x] - acc[x][y][h + e2] : -acc[x][y][h + e2];
+                for (int x = 0; x < 4; x++) o[x] = c < pa ? cv[e2][y][x] - av(h + e2, y, x) : -av(h + e2, y, x);
                 if (aligned && c < jend && r0 >= c && r0 + 3 < m) {
                     V4 v;
                     v.x = o[0];
@@ -725,9 +725,15 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const UpdTask *__restri
         __syncthreads();
     }
     if (!active) return;
-    tile_sub<T>(F, ld, m, jend, ka == 0 ? p : m, acc,
-                [&](int x, int e) { return i0 + wr + x * 16 + Mfma<T>::row(kq, e); },
-                [&](int y) { return j0 + wc + y * 16 + ln; });
+    if constexpr (sizeof(T) == 4)   // FP32 accumulator element e is row 4 kq + e: quads over e
+        tile_sub_quads<T>(F, ld, m, jend, ka == 0 ? p : m, (i0 & 3) == 0,
+                          [&](int q, int y, int t) { return acc[q][y][t]; },
+                          [&](int x) { return i0 + wr + x * 16 + 4 * kq; },
+                          [&](int y) { return j0 + wc + y * 16 + ln; });
+    else
+        tile_sub<T>(F, ld, m, jend, ka == 0 ? p : m, acc,
+                    [&](int x, int e) { return i0 + wr + x * 16 + Mfma<T>::row(kq, e); },
+                    [&](int y) { return j0 + wc + y * 16 + ln; });
 }
 
 // Trailing update, streamed form.  Same task and result as k_update<T, 128>,
@@ -887,7 +893,8 @@ __global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ 
     }
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;
-    tile_sub_quads<T>(F, ld, m, jend, ka == 0 ? p : m, (i0 & 3) == 0, acc,
+    tile_sub_quads<T>(F, ld, m, jend, ka == 0 ? p : m, (i0 & 3) == 0,
+                      [&](int q, int y, int t) { return acc[t][y][q]; },
                       [&](int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e); },
                       [&](int y) { return j0 + wc + 4 * ln + y; });
 }
