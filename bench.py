@@ -34,7 +34,7 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2007_01541_amd", "csrc", "kernels.hip")
 
 
 def measured_traffic():
-    """HBM bytes per launch of the FP32 update kernel from the committed
+    """HBM bytes per launch of the FP32 update kernel class from the committed
     counter summary, or None when the kernel source changed since then."""
     import hashlib
     try:
