@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     pattern,
     factor,
     solve,
+    apply,
     symv,
     residual,
     grad,

@@ -18,7 +18,10 @@
  *     up to i).
  *   - Section 1 / Section 5: the factor is used as an exact inverse:
  *     x = P^T L^-T L^-1 P b, and the half solves L^-1 P b and P^T L^-T z
- *     (the latter draws a Gaussian field with covariance A^-1, cf. Section 5.3).
+ *     (the latter draws a Gaussian field with covariance A^-1, cf. Section 5.3),
+ *     and the products with the factor itself, P^T L b and L^T P b: the
+ *     sampling of Section 5.3 multiplies white noise by the Cholesky factor
+ *     of the covariance matrix, so that x = P^T L z has covariance A.
  *   - Section 4 nested dissection: V = V1 u V2 u S with no edge between V1
  *     and V2, ordered V1, V2, S, recursively; orc_check_nd verifies that
  *     block structure for a given ordering and separator tree.
@@ -352,6 +355,46 @@ int orc_solve(int32_t n, const int32_t *perm, const int64_t *Lp, const int32_t *
         }
     }
     free(y);
+    return ORC_OK;
+}
+
+/*
+ * Products with the factor itself (the operators of P A P^T = L L^T, reused
+ * like the solves; x = P^T L z with white noise z has covariance A):
+ *   part 1: X = P^T L B     (input in pivot order)
+ *   part 2: X = L^T P B     (result in pivot order)
+ * so part 1 applied to the result of part 2 gives P^T L L^T P B = A B.
+ * B and X are column-major n x nrhs with leading dimension ld; they may alias.
+ */
+int orc_apply(int32_t n, const int32_t *perm, const int64_t *Lp, const int32_t *Li, const double *Lx,
+              int32_t part, int32_t nrhs, const double *B, double *X, int64_t ld)
+{
+    if (part < 1 || part > 2 || ld < n) return ORC_EINVAL;
+    double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *z = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!y || !z) { free(y); free(z); return ORC_ENOMEM; }
+    for (int32_t c = 0; c < nrhs; c++) {
+        const double *b = B + (size_t)c * (size_t)ld;
+        double *x = X + (size_t)c * (size_t)ld;
+        if (part == 1) {
+            /* z = L y, column by column: column j of L scaled by y_j */
+            for (int32_t k = 0; k < n; k++) { y[k] = b[k]; z[k] = 0.0; }
+            for (int32_t j = 0; j < n; j++)
+                for (int64_t p = Lp[j]; p < Lp[j + 1]; p++) z[Li[p]] += Lx[p] * y[j];
+            for (int32_t k = 0; k < n; k++) x[perm[k]] = z[k];
+        } else {
+            /* z = L^T y: entry j is column j of L dotted with y */
+            for (int32_t k = 0; k < n; k++) y[k] = b[perm[k]];
+            for (int32_t j = 0; j < n; j++) {
+                double s = 0.0;
+                for (int64_t p = Lp[j]; p < Lp[j + 1]; p++) s += Lx[p] * y[Li[p]];
+                z[j] = s;
+            }
+            for (int32_t k = 0; k < n; k++) x[k] = z[k];
+        }
+    }
+    free(y);
+    free(z);
     return ORC_OK;
 }
 

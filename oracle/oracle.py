@@ -57,11 +57,13 @@ def load() -> C.CDLL:
     lib.orc_pattern.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P]
     lib.orc_factor.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P, i32, _P]
     lib.orc_solve.argtypes = [i32, _P, _P, _P, _P, i32, i32, _P, _P, i64]
+    lib.orc_apply.argtypes = [i32, _P, _P, _P, _P, i32, i32, _P, _P, i64]
     lib.orc_symv.argtypes = [i32, _P, _P, _P, i32, _P, _P, i64]
     lib.orc_grad.argtypes = [i32, _P, _P, _P, _P, _P]
     lib.orc_check_nd.argtypes = [i32, _P, _P, _P, i32, _P]
     lib.orc_check_nd.restype = i64
-    for f in ("orc_check_perm", "orc_symbolic", "orc_pattern", "orc_factor", "orc_solve", "orc_symv", "orc_grad"):
+    for f in ("orc_check_perm", "orc_symbolic", "orc_pattern", "orc_factor", "orc_solve", "orc_apply", "orc_symv",
+              "orc_grad"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -133,6 +135,18 @@ def solve(perm, Lp, Li, Lx, B: np.ndarray, part: int = 0) -> np.ndarray:
     return X.reshape(B.shape)
 
 
+def apply(perm, Lp, Li, Lx, B: np.ndarray, part: int) -> np.ndarray:
+    """part 1: P^T L B (B in pivot order); 2: L^T P B (result in pivot order).  B is n or n x k."""
+    n = Lp.size - 1
+    B2 = np.asfortranarray(B.reshape(n, -1), np.float64)
+    X = np.empty_like(B2, order="F")
+    p = np.ascontiguousarray(perm, np.int32)
+    rc = load().orc_apply(n, _ptr(p), _ptr(Lp), _ptr(Li), _ptr(Lx), part, B2.shape[1], _ptr(B2), _ptr(X), n)
+    if rc:
+        raise OracleError(rc, "apply")
+    return X.reshape(B.shape)
+
+
 def symv(n: int, colptr, rowind, values, X: np.ndarray) -> np.ndarray:
     """A X with the full symmetric A stored by its lower CSC."""
     cp, ri, v = _csc(colptr, rowind, values)
@@ -187,6 +201,9 @@ class Factor:
 
     def solve(self, B: np.ndarray, part: int = 0) -> np.ndarray:
         return solve(self.perm, self.Lp, self.Li, self.Lx, B, part)
+
+    def apply(self, B: np.ndarray, part: int) -> np.ndarray:
+        return apply(self.perm, self.Lp, self.Li, self.Lx, B, part)
 
     def dense_L(self) -> np.ndarray:
         L = np.zeros((self.n, self.n))

@@ -339,3 +339,37 @@ def test_permutation_preserves_nnz(small_matrix):
     r, c = iperm[m["rowind"]], iperm[cols]
     assert np.unique(np.stack([np.maximum(r, c), np.minimum(r, c)]), axis=1).shape[1] == m["rowind"].size
     assert full_nnz(m) == 1254448
+
+
+def test_factor_products_compose_to_A():
+    """P^T L (L^T P b) = A b: the two factor products of the oracle against its
+    symmetric product with the stored matrix (a different code path), and
+    P^T L (L^-1 P b) = b against its forward solve."""
+    w = tiny(4, 1.5)
+    m = w.matrix()
+    n = m["n"]
+    perm = perms(n, 2)
+    f = oracle.factorize(m, perm)
+    B = np.random.default_rng(7).standard_normal((n, 3))
+    AB = oracle.symv(n, m["colptr"], m["rowind"], m["values"], B)
+    X = f.apply(f.apply(B, 2), 1)
+    assert np.abs(X - AB).max() <= 1e-12 * np.abs(AB).max()
+    Y = f.apply(f.solve(B, 1), 1)
+    assert np.abs(Y - B).max() <= 1e-12 * np.abs(B).max()
+
+
+@pytest.mark.parametrize("part", [1, 2])
+def test_factor_products_against_dense(part):
+    m = sparse_haar(G=3, a=1.5)
+    n = m["n"]
+    perm = perms(n, 2)
+    f = oracle.factorize(m, perm)
+    L = f.dense_L()
+    B = np.random.default_rng(4).standard_normal((n, 2))
+    X = f.apply(B, part)
+    if part == 1:
+        ref = np.empty_like(B)
+        ref[perm] = L @ B
+    else:
+        ref = L.T @ B[perm]
+    assert np.abs(X - ref).max() <= 1e-13 * np.abs(ref).max()
