@@ -70,6 +70,12 @@ typedef enum {
     WCS_SOLVE_LT = 2    /* X = P^T L^-T B       (input in pivot order)  */
 } wcs_part;
 
+/* Products with the factor itself, P A P^T = L L^T (see wcs_apply). */
+typedef enum {
+    WCS_APPLY_L = 1,    /* X = P^T L B          (input in pivot order)  */
+    WCS_APPLY_LT = 2    /* X = L^T P B          (result in pivot order) */
+} wcs_apply_part;
+
 typedef struct {
     int32_t leaf_size;          /* nested dissection stops at <= leaf_size vertices (default 64) */
     double dense_degree_frac;   /* peel vertices whose degree >= dense_degree_frac * n ... */
@@ -284,6 +290,21 @@ int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t
  * of B to FP32 and of the result back to FP64).
  */
 int wcs_solve(wcs_factor f, wcs_part part, int32_t nrhs, double *B_dev, int64_t ld, wcs_stream stream);
+
+/*
+ * Products with the factor (Section 5.3: the Gaussian field is drawn by
+ * multiplying white noise with the Cholesky factor of the covariance matrix;
+ * here x = P^T L z has covariance P^T L L^T P = A).  WCS_APPLY_L: X = P^T L B
+ * with B in pivot order; WCS_APPLY_LT: X = L^T P B with the result in pivot
+ * order; so APPLY_L(APPLY_LT(B)) = A B and APPLY_L(SOLVE_L(B)) = B up to
+ * rounding.  B_dev: device FP64, n x nrhs column-major, ld >= n, overwritten
+ * in place; 1 <= nrhs <= max_nrhs.  FP32 factors compute in FP32 (one rounding
+ * of B to FP32 and of the result back).  Asynchronous on the stream; uses the
+ * factor's right-hand-side buffers, so calls on one factor are ordered by the
+ * stream like its solves.  Errors: WCS_EINVAL for bad arguments,
+ * WCS_ESTATE before a numeric factorization.
+ */
+int wcs_apply(wcs_factor f, wcs_apply_part part, int32_t nrhs, double *B_dev, int64_t ld, wcs_stream stream);
 
 /*
  * X = A^-1 B by iterative refinement against the FP64 input matrix:

@@ -79,6 +79,7 @@ SIGNATURES = [
     ("wcs_factor_profile_levels", C.c_int, [c_p, c_p, c_p, c_p]),
     ("wcs_factor_export", C.c_int, [c_p, c_i32, c_i32, c_p, c_p, c_p, c_p]),
     ("wcs_solve", C.c_int, [c_p, C.c_int, c_i32, c_p, c_i64, c_p]),
+    ("wcs_apply", C.c_int, [c_p, C.c_int, c_i32, c_p, c_i64, c_p]),
     ("wcs_solve_refined", C.c_int, [c_p, c_p, c_i32, c_p, c_p, c_i64, C.c_double, c_i32,
                                     C.POINTER(IRReport), c_p]),
     ("wcs_spmv", C.c_int, [c_p, c_p, c_i32, c_p, c_p, c_i64, c_p]),

@@ -110,6 +110,8 @@ struct Plan {
     std::vector<int4> sbelow_tasks, sbsum_tasks, xinv_tasks;
     int64_t part_blocks = 0;                      // SB x k partial blocks of the split update-row sums
     std::vector<int64_t> xoff;                    // per front: offset of its super-block inverses (-1: none)
+    std::vector<int2> alt_tasks, al_tasks;        // products with the factor: (front, column block) / (front, row tile)
+    std::vector<int64_t> gptr, glist;             // rows of the L product: W rows holding each row, fronts ascending
     int64_t xelems = 0;
 
     void build(const Symbolic &S)
@@ -337,6 +339,24 @@ struct Plan {
                 V.bwd.push_back({s0, d.first, d.second, off, (int64_t)sbwd_tasks.size() - off});
             }
         }
+        // products with the factor
+        alt_tasks.clear();
+        al_tasks.clear();
+        for (int32_t s = 0; s < ns; s++) {
+            for (int32_t b = 0; b < (pfront[s] + SB - 1) / SB; b++) alt_tasks.push_back(make_int2(s, b));
+            for (int32_t t = 0; t < (mfront[s] + SB - 1) / SB; t++) al_tasks.push_back(make_int2(s, t));
+        }
+        gptr.assign((size_t)S.n + 1, 0);
+        for (int32_t s = 0; s < ns; s++)
+            for (int64_t q = S.rptr[s]; q < S.rptr[s + 1]; q++) gptr[S.rows[q] + 1]++;
+        for (int32_t i = 0; i < S.n; i++) gptr[i + 1] += gptr[i];
+        glist.resize((size_t)gptr[S.n]);
+        {
+            std::vector<int64_t> fill(gptr.begin(), gptr.end() - 1);
+            for (int32_t s = 0; s < ns; s++)
+                for (int64_t q = S.rptr[s]; q < S.rptr[s + 1]; q++)
+                    glist[fill[S.rows[q]]++] = woff[s] + (q - S.rptr[s]);
+        }
         zero_tasks.clear();
         lower_elems = 0;
         for (int32_t s = 0; s < ns; s++) {
@@ -355,7 +375,7 @@ struct Layout {
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list, easplit;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
-    size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt;
+    size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -406,6 +426,10 @@ struct Layout {
         sbsum = seg(std::max<size_t>(1, P.sbsum_tasks.size()) * sizeof(int4));
         xinvt = seg(std::max<size_t>(1, P.xinv_tasks.size()) * sizeof(int4));
         dinvt = seg(std::max<size_t>(1, P.dinv_tasks.size()) * sizeof(int2));
+        altt = seg(std::max<size_t>(1, P.alt_tasks.size()) * sizeof(int2));
+        alt2 = seg(std::max<size_t>(1, P.al_tasks.size()) * sizeof(int2));
+        gptr = seg(P.gptr.size() * 8);
+        glist = seg(std::max<size_t>(1, P.glist.size()) * 8);
         xoff = seg(ns * 8);
         xinv = seg((size_t)std::max<int64_t>(1, P.xelems) * esz);
         part2 = seg((size_t)std::max<int64_t>(1, P.part_blocks) * SB * k * esz);
@@ -745,13 +769,12 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     return WCS_OK;
 }
 
-// Y (row-major, pivot order, n x k) := L^-1 Y and/or L^-T Y
-template <typename T, int KT>
-int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
+// device pointers of the factor for the solve and product kernels
+template <typename T>
+SolveArgs<T> solve_args(wcs_factor f, int k)
 {
-    const Layout &Lo = f->lay;
-    const Plan &P = f->plan;
     SolveArgs<T> a;
+    const Layout &Lo = f->lay;
     a.front_off = f->at<int64_t>(Lo.front_off);
     a.mfront = f->at<int32_t>(Lo.mfront);
     a.pfront = f->at<int32_t>(Lo.pfront);
@@ -771,6 +794,16 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
     a.W = f->at<T>(Lo.W);
     a.Y = f->at<T>(Lo.Y);
     a.k = k;
+    return a;
+}
+
+// Y (row-major, pivot order, n x k) := L^-1 Y and/or L^-T Y
+template <typename T, int KT>
+int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    const Plan &P = f->plan;
+    SolveArgs<T> a = solve_args<T>(f, k);
     const int32_t *sl = f->at<int32_t>(Lo.slist);
     const int2 *tf = f->at<int2>(Lo.sfwd);
     const int4 *tb = f->at<int4>(Lo.sbelow);
@@ -893,6 +926,39 @@ int launch_solve(wcs_factor f, int part, int k, double *B, int64_t ld, hipStream
     else
         hipLaunchKernelGGL(k_perm_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, Y, perm, n, k, B, ld,
                            (const double *)nullptr, 0);
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+// B := P^T L B (WCS_APPLY_L, B in pivot order) or L^T P B (WCS_APPLY_LT, result
+// in pivot order); B column-major FP64, computed in the factor's precision
+template <typename T>
+int launch_apply(wcs_factor f, int part, int k, double *B, int64_t ld, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    const Plan &P = f->plan;
+    int n = f->S->n;
+    T *Y = f->at<T>(Lo.Y), *W = f->at<T>(Lo.W);
+    const int32_t *perm = f->at<int32_t>(Lo.perm);
+    int64_t nk = (int64_t)n * k;
+    SolveArgs<T> a = solve_args<T>(f, k);
+    if (part == WCS_APPLY_LT) {
+        hipLaunchKernelGGL(k_perm_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Y,
+                           (const double *)nullptr);
+        if (!P.alt_tasks.empty())
+            hipLaunchKernelGGL(k_apply_lt<T>, dim3((unsigned)P.alt_tasks.size()), dim3(THREADS), 0, st,
+                               f->at<int2>(Lo.altt), a, (const T *)Y, W);
+        hipLaunchKernelGGL(k_rows_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, (const T *)W, n, k, B, ld);
+    } else {
+        hipLaunchKernelGGL(k_rows_in<T>, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, n, k, Y);
+        if (!P.al_tasks.empty())
+            hipLaunchKernelGGL(k_apply_l<T>, dim3((unsigned)P.al_tasks.size()), dim3(THREADS), 0, st,
+                               f->at<int2>(Lo.alt2), a, (const T *)Y, W);
+        hipLaunchKernelGGL(k_apply_gather<T>, dim3(grid_for(nk)), dim3(256), 0, st, f->at<int64_t>(Lo.gptr),
+                           f->at<int64_t>(Lo.glist), n, k, (const T *)W, Y);
+        hipLaunchKernelGGL(k_perm_out<T>, dim3(grid_for(nk)), dim3(256), 0, st, (const T *)Y, perm, n, k, B, ld,
+                           (const double *)nullptr, 0);
+    }
     HIP_TRY(hipGetLastError());
     return WCS_OK;
 }
@@ -1146,6 +1212,10 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.sbsum, P.sbsum_tasks, st);
     rc = rc ? rc : upload(f, L.xinvt, P.xinv_tasks, st);
     rc = rc ? rc : upload(f, L.dinvt, P.dinv_tasks, st);
+    rc = rc ? rc : upload(f, L.altt, P.alt_tasks, st);
+    rc = rc ? rc : upload(f, L.alt2, P.al_tasks, st);
+    rc = rc ? rc : upload(f, L.gptr, P.gptr, st);
+    rc = rc ? rc : upload(f, L.glist, P.glist, st);
     rc = rc ? rc : upload(f, L.xoff, P.xoff, st);
     rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
     rc = rc ? rc : upload(f, L.ztasks, P.zero_tasks, st);
@@ -1381,6 +1451,19 @@ int wcs_solve(wcs_factor f, wcs_part part, int32_t nrhs, double *B_dev, int64_t 
     hipStream_t st = (hipStream_t)stream;
     return f->prec == WCS_FP64 ? launch_solve<double>(f, part, nrhs, B_dev, ld, st)
                                : launch_solve<float>(f, part, nrhs, B_dev, ld, st);
+}
+
+int wcs_apply(wcs_factor f, wcs_apply_part part, int32_t nrhs, double *B_dev, int64_t ld, wcs_stream stream)
+{
+    if (!f || !B_dev || nrhs < 1 || nrhs > f->max_nrhs || ld < f->S->n ||
+        (part != WCS_APPLY_L && part != WCS_APPLY_LT)) {
+        set_error("invalid argument to wcs_apply");
+        return WCS_EINVAL;
+    }
+    if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
+    hipStream_t st = (hipStream_t)stream;
+    return f->prec == WCS_FP64 ? launch_apply<double>(f, part, nrhs, B_dev, ld, st)
+                               : launch_apply<float>(f, part, nrhs, B_dev, ld, st);
 }
 
 int wcs_solve_refined(wcs_factor f, const double *values_dev, int32_t nrhs, const double *B_dev, double *X_dev,

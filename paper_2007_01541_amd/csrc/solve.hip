@@ -915,6 +915,107 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_sum(const int4 *__restric
 }
 
 // ---- super-block inverses (after the factorization)
+// ---- products with the factor itself (Y row-major n x k in pivot order)
+//
+// L^T Y: task = (front, column block a).  Output row first + ab + c is
+// sum over the front's rows r >= ab + c of L(r, ab + c) Yin(rows[r]); every
+// pivot row belongs to exactly one front, so no two tasks write a row.  The
+// front's rows [ab, m) are split over the four waves in multiples of 16.
+template <typename T>
+__global__ __launch_bounds__(THREADS) void k_apply_lt(const int2 *__restrict__ tasks, SolveArgs<T> a,
+                                                      const T *__restrict__ Yin, T *__restrict__ Yout)
+{
+    __shared__ MmLds<T> mm;
+    int2 t = tasks[blockIdx.x];
+    int f = t.x, ab = t.y * SB;
+    int m = a.mfront[f], p = a.pfront[f], k = a.k, ld = front_ld(m);
+    int na = min(SB, p - ab), first = a.first[f];
+    const T *L = a.fronts + a.front_off[f];
+    const int32_t *rw = a.rows + a.rptr[f];
+    int wave = threadIdx.x / 64;
+    int per = ((m - ab + 63) / 64) * 16;
+    int rb = ab + wave * per, re = min(m, rb + per);
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        typename Mfma<T>::V acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+#pragma unroll
+            for (int y = 0; y < 4; y++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+        if (rb < re)
+            wave_mm<T>(
+                acc, rb, re,
+                [&](int c, int r) { return (c < na && r >= ab + c) ? L[(int64_t)(ab + c) * ld + r] : (T)0; },
+                [&](int r, int col) { return c0 + col < k ? Yin[(int64_t)rw[r] * k + c0 + col] : (T)0; });
+        reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                int c = rr[q], col = cb + cc[q];
+                if (c < na && c0 + col < k) Yout[(int64_t)(first + ab + c) * k + c0 + col] = val[q];
+            }
+        });
+    }
+}
+
+// L Y, first pass: task = (front, 64-row tile).  W row woff[f] + r of the
+// front's own row block gets sum over its pivot columns c <= r of
+// L(r, c) Yin(first + c); k_apply_gather then adds up, for every row of Y,
+// the W rows of all fronts that hold it.
+template <typename T>
+__global__ __launch_bounds__(THREADS) void k_apply_l(const int2 *__restrict__ tasks, SolveArgs<T> a,
+                                                     const T *__restrict__ Yin, T *__restrict__ W)
+{
+    __shared__ MmLds<T> mm;
+    int2 t = tasks[blockIdx.x];
+    int f = t.x, r0 = t.y * SB;
+    int m = a.mfront[f], p = a.pfront[f], k = a.k, ld = front_ld(m);
+    int nr = min(SB, m - r0), first = a.first[f];
+    int kend = min(p, r0 + SB);   // columns c <= r < r0 + SB
+    const T *L = a.fronts + a.front_off[f];
+    T *out = W + a.woff[f] * k;
+    int wave = threadIdx.x / 64;
+    int per = ((kend + 63) / 64) * 16;
+    int cb0 = wave * per, ce = min(kend, cb0 + per);
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        typename Mfma<T>::V acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+#pragma unroll
+            for (int y = 0; y < 4; y++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+        if (cb0 < ce)
+            wave_mm<T>(
+                acc, cb0, ce,
+                [&](int rr, int c) { return (rr < nr && c <= r0 + rr) ? L[(int64_t)c * ld + r0 + rr] : (T)0; },
+                [&](int c, int col) { return c0 + col < k ? Yin[(int64_t)(first + c) * k + c0 + col] : (T)0; });
+        reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                int r = rr[q], col = cb + cc[q];
+                if (r < nr && c0 + col < k) out[(int64_t)(r0 + r) * k + c0 + col] = val[q];
+            }
+        });
+    }
+}
+
+// L Y, second pass: Y(i) = sum of the W rows glist[gptr[i] .. gptr[i+1]) (in
+// that fixed order: fronts ascending), i.e. every front's contribution to row i
+template <typename T>
+__global__ void k_apply_gather(const int64_t *__restrict__ gptr, const int64_t *__restrict__ glist, int n, int k,
+                               const T *__restrict__ W, T *__restrict__ Y)
+{
+    int64_t total = (int64_t)n * k;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        int i = (int)(idx / k), c = (int)(idx % k);
+        T s = 0;
+        for (int64_t q = gptr[i]; q < gptr[i + 1]; q++) s += W[glist[q] * k + c];
+        Y[idx] = s;
+    }
+}
+
 // task = (front, super-block index si, column block jb): X_jj = L_jj^-1 (the
 // stored 64-block inverse), then for i > j: X_ij = -L_ii^-1 sum_{j <= q < i} L_iq X_qj.
 // Rows and columns past the end of the super-block are zero.

@@ -21,6 +21,8 @@ FP32 = 1
 SOLVE_FULL = 0
 SOLVE_L = 1
 SOLVE_LT = 2
+APPLY_L = 1
+APPLY_LT = 2
 
 
 def _torch():
@@ -232,6 +234,16 @@ class Factor:
 
     def solve(self, B, part: int = SOLVE_FULL, stream=None):
         return self.solve_(B.clone(), part, stream)
+
+    def apply(self, B, part: int, stream=None):
+        """Product with the factor: APPLY_L gives P^T L B (B in pivot order), APPLY_LT gives
+        L^T P B (result in pivot order).  B: device FP64 tensor (n,) or (n, k); returns a new tensor."""
+        Bm = B.clone() if B.dim() == 2 else B.clone().view(-1, 1)
+        k = Bm.shape[1]
+        cm = Bm.t().contiguous()
+        check(lib().wcs_apply(self.handle, part, k, _dptr(cm), self.n, _stream_ptr(stream)), "wcs_apply")
+        Bm.copy_(cm.t())
+        return Bm if B.dim() == 2 else Bm.view(-1)
 
     def solve_refined(self, B, values=None, tol: float = 1e-10, max_iter: int = 10, stream=None):
         """X = A^-1 B by iterative refinement; returns (X, report dict)."""

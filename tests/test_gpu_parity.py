@@ -12,7 +12,8 @@ from tests.helpers import EPS32, EPS64, compare_columns, factor_tol, gershgorin_
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-from paper_2007_01541_amd import FP32, FP64, SOLVE_FULL, SOLVE_L, SOLVE_LT, Factor, Symbolic, cholesky_solve  # noqa: E402
+from paper_2007_01541_amd import (APPLY_L, APPLY_LT, FP32, FP64, SOLVE_FULL, SOLVE_L, SOLVE_LT, Factor,  # noqa: E402
+                                  Symbolic, cholesky_solve)
 from paper_2007_01541_amd.capi import WcsError  # noqa: E402
 
 
@@ -142,6 +143,49 @@ def test_spmv_matches_oracle(k):
     Y = f.spmv(dev(X), dev(m["values"])).cpu().numpy().reshape(m["n"], k)
     Yo = oracle.symv(m["n"], m["colptr"], m["rowind"], m["values"], X).reshape(m["n"], k)
     assert np.abs(Y - Yo).max() <= 1e-13 * np.abs(Yo).max()
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("k", [1, 3, 64, 70])
+def test_factor_products_match_oracle(prec, k):
+    """P^T L B and L^T P B against the oracle's products with the same (exported)
+    L, entrywise within the rounding bound of a sum of at most n terms, and
+    their composition against the oracle's A B."""
+    m, sym, _ = prepared("small")
+    n = m["n"]
+    print(f"factor products prec={prec} k={k} n={n}", flush=True)
+    f = Factor(sym, prec, max_nrhs=k)
+    f.numeric(dev(m["values"]))
+    Lp, Li, Lx = f.export_L()
+    perm = sym.export()["perm"]
+    eps = EPS64 if prec == FP64 else EPS32
+    B = normal_rhs(n, k, 21)
+    for part in (APPLY_L, APPLY_LT):
+        X = f.apply(dev(B), part).cpu().numpy()
+        ref = oracle.apply(perm, Lp, Li, Lx, B, part)
+        bound = (n + 2) * eps * oracle.apply(perm, Lp, Li, np.abs(Lx), np.abs(B), part)
+        assert np.all(np.abs(X - ref) <= bound), part
+    X = f.apply(f.apply(dev(B), APPLY_LT), APPLY_L).cpu().numpy()
+    AB = oracle.symv(n, m["colptr"], m["rowind"], m["values"], B)
+    tol = 1e-12 if prec == FP64 else 1e-4
+    assert np.abs(X - AB).max() <= tol * np.abs(AB).max()
+    if prec == FP64:
+        # the forward solve undone by the product: P^T L (L^-1 P B) = B
+        Y = f.apply(f.solve(dev(B), SOLVE_L), APPLY_L).cpu().numpy()
+        assert np.abs(Y - B).max() <= 1e-11 * np.abs(B).max()
+
+
+def test_factor_products_reject_bad_arguments():
+    m, sym, _ = prepared("small")
+    f = Factor(sym, FP64, max_nrhs=2)
+    B = dev(normal_rhs(m["n"], 2, 1))
+    with pytest.raises(Exception):
+        f.apply(B, APPLY_L)          # no numeric factorization yet
+    f.numeric(dev(m["values"]))
+    with pytest.raises(Exception):
+        f.apply(B, 0)                # not a product part
+    with pytest.raises(Exception):
+        f.apply(dev(normal_rhs(m["n"], 3, 1)), APPLY_L)   # more columns than max_nrhs
 
 
 @pytest.mark.parametrize("kind", ["small", "g5a13"])
