@@ -313,6 +313,22 @@ def main() -> int:
     for nm, st in prof.items():
         log(f"  kernel class {nm}: {st['launches']} launches, {st['ms']:.2f} ms, "
             f"{st['flops'] / 1e9:.1f} GFLOP, {st['bytes'] / 1e9:.2f} GB")
+    # products with the factor (P^T L B and L^T P B, 64 RHS): 2 nnz(L) k flops each
+    from paper_2007_01541_amd import APPLY_L, APPLY_LT
+    products = {}
+    for nm_, part in (("L", APPLY_L), ("LT", APPLY_LT)):
+        f32.apply(Bd, part)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            f32.apply(Bd, part)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        products[nm_] = {"ms": ms, "tflops": 2 * info["nnz_l"] * nrhs / ms / 1e9}
+    log(f"  products with the factor ({nrhs} RHS, FP32): " +
+        ", ".join(f"{k_} {v['ms']:.2f} ms ({v['tflops']:.1f} TFLOP/s)" for k_, v in products.items()))
     levels = f32.profile_levels(vals)
     torch.cuda.synchronize()
     top = levels[-3:]
@@ -373,6 +389,7 @@ def main() -> int:
                    "max_front": int(info["max_front"]), "analyze_s": round(t_analyze, 2)},
         "pct_fp32_mfma_peak": 100 * value / PEAK["fp32_mfma_tflops"],
         "root_fronts": root,
+        "factor_products": products,
         "factor_ms": fact32,
         "ir": rep32,
         "fp64": fp64,
