@@ -525,7 +525,8 @@ template <> struct Vec4<float> { typedef float4 type; };
 template <> struct Vec4<double> { typedef double4 type; };
 
 template <typename T, typename V, typename RowFn, typename ColFn>
-__device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int jend, int pa, const V (&acc)[4][4],
+__device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int jbeg, int jend, int pa,
+                                         const V (&acc)[4][4],
                                          RowFn rowf, ColFn colf)
 {
     // columns >= pa hold no earlier value (update matrix before its first
@@ -540,7 +541,7 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     int row = rowf(h + x, e), col = colf(y);
-                    bool ok = col < jend && row < m && row >= col && col < pa;
+                    bool ok = col >= jbeg && col < jend && row < m && row >= col && col < pa;
                     cv[x][y][e] = F[ok ? (int64_t)col * ld + row : 0];
                 }
 #pragma unroll
@@ -550,7 +551,7 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
                     int row = rowf(h + x, e), col = colf(y);
-                    if (col < jend && row < m && row >= col)
+                    if (col >= jbeg && col < jend && row < m && row >= col)
                         F[(int64_t)col * ld + row] = col < pa ? cv[x][y][e] - acc[h + x][y][e] : -acc[h + x][y][e];
                 }
     }
@@ -562,7 +563,8 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 // four rows inside the stored lower part, the quad is read and written as one
 // 16-byte (FP32) or 32-byte (FP64) access; other quads element by element.
 template <typename T, typename AccFn, typename RowFn, typename ColFn>
-__device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m, int jend, int pa, bool aligned,
+__device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m, int jbeg, int jend, int pa,
+                                               bool aligned,
                                                AccFn av, RowFn rowq, ColFn colf)
 {
     typedef typename Vec4<T>::type V4;
@@ -574,7 +576,7 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
 #pragma unroll
             for (int y = 0; y < 4; y++) {
                 int r0 = rowq(h + e2), c = colf(y);
-                if (aligned && c < jend && r0 >= c && r0 + 3 < m) {
+                if (aligned && c >= jbeg && c < jend && r0 >= c && r0 + 3 < m) {
                     V4 v = *reinterpret_cast<const V4 *>(F + (c < pa ? (int64_t)c * ld + r0 : 0));
                     cv[e2][y][0] = v.x;
                     cv[e2][y][1] = v.y;
@@ -584,7 +586,7 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
 #pragma unroll
                     for (int x = 0; x < 4; x++) {
                         int r = r0 + x;
-                        bool ok = c < jend && r < m && r >= c && c < pa;
+                        bool ok = c >= jbeg && c < jend && r < m && r >= c && c < pa;
                         cv[e2][y][x] = F[ok ? (int64_t)c * ld + r : 0];
                     }
                 }
@@ -597,7 +599,7 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
                 T o[4];
 #pragma unroll
                 for (int x = 0; x < 4; x++) o[x] = c < pa ? cv[e2][y][x] - av(h + e2, y, x) : -av(h + e2, y, x);
-                if (aligned && c < jend && r0 >= c && r0 + 3 < m) {
+                if (aligned && c >= jbeg && c < jend && r0 >= c && r0 + 3 < m) {
                     V4 v;
                     v.x = o[0];
                     v.y = o[1];
@@ -608,7 +610,7 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
 #pragma unroll
                     for (int x = 0; x < 4; x++) {
                         int r = r0 + x;
-                        if (c < jend && r < m && r >= c) F[(int64_t)c * ld + r] = o[x];
+                        if (c >= jbeg && c < jend && r < m && r >= c) F[(int64_t)c * ld + r] = o[x];
                     }
                 }
             }
@@ -630,7 +632,9 @@ constexpr int UT = 128;
 
 // A trailing-update task with its front's descriptors, so that one 32-byte
 // (scalar) load gives the workgroup everything it needs:
-// a = (front offset low, high 32 bits, m, p), b = (i0, j0, jend, unused).
+// a = (front offset low, high 32 bits, m, p), b = (i0, j0, jend, jbeg): the
+// tile's columns are [max(j0, jbeg), min(j0 + TW, jend)); j0 is rounded down
+// to a multiple of 4 so that the rows of the tile come in aligned quads.
 struct UpdTask {
     int4 a, b;
 };
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const UpdTask *__restri
     constexpr int KSTEP = NTH / TW;            // k rows covered by one pass of the block
     constexpr int PER = KC / KSTEP;            // elements of each operand per thread per chunk
     const UpdTask t = tasks[blockIdx.x];
-    int i0 = t.b.x, j0 = t.b.y, jend = t.b.z;
+    int i0 = t.b.x, j0 = t.b.y, jend = t.b.z, jbeg = t.b.w;
     int m = t.a.z, p = t.a.w, ld = front_ld(m);
     int K = min(kw, p - ka);
     const int64_t foff = (int64_t)(((uint64_t)(uint32_t)t.a.y << 32) | (uint32_t)t.a.x);
@@ -726,12 +730,12 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const UpdTask *__restri
     }
     if (!active) return;
     if constexpr (sizeof(T) == 4)   // FP32 accumulator element e is row 4 kq + e: quads over e
-        tile_sub_quads<T>(F, ld, m, jend, ka == 0 ? p : m, (i0 & 3) == 0,
+        tile_sub_quads<T>(F, ld, m, jbeg, jend, ka == 0 ? p : m, (i0 & 3) == 0,
                           [&](int q, int y, int t) { return acc[q][y][t]; },
                           [&](int x) { return i0 + wr + x * 16 + 4 * kq; },
                           [&](int y) { return j0 + wc + y * 16 + ln; });
     else
-        tile_sub<T>(F, ld, m, jend, ka == 0 ? p : m, acc,
+        tile_sub<T>(F, ld, m, jbeg, jend, ka == 0 ? p : m, acc,
                     [&](int x, int e) { return i0 + wr + x * 16 + Mfma<T>::row(kq, e); },
                     [&](int y) { return j0 + wc + y * 16 + ln; });
 }
@@ -815,7 +819,7 @@ __global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ 
         else return S3;
     };
     const UpdTask t = tasks[blockIdx.x];
-    int i0 = t.b.x, j0 = t.b.y, jend = t.b.z;
+    int i0 = t.b.x, j0 = t.b.y, jend = t.b.z, jbeg = t.b.w;
     int m = t.a.z, p = t.a.w, ld = front_ld(m);
     int K = min(kw, p - ka);
     T *F = fronts + (int64_t)(((uint64_t)(uint32_t)t.a.y << 32) | (uint32_t)t.a.x);
@@ -893,7 +897,7 @@ __global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ 
     }
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;
-    tile_sub_quads<T>(F, ld, m, jend, ka == 0 ? p : m, (i0 & 3) == 0,
+    tile_sub_quads<T>(F, ld, m, jbeg, jend, ka == 0 ? p : m, (i0 & 3) == 0,
                       [&](int q, int y, int t) { return acc[t][y][q]; },
                       [&](int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e); },
                       [&](int y) { return j0 + wc + 4 * ln + y; });

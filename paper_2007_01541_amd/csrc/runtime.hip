@@ -91,6 +91,7 @@ struct Plan {
     std::vector<Level> levels;
     std::vector<int2> pan_tasks;
     std::vector<int4> upd_tasks;
+    std::vector<int32_t> upd_jbeg;                // per update task: first column it writes
     std::vector<int2> ea_tasks;
     std::vector<int32_t> flist;
     std::vector<int32_t> mfront, pfront, first;
@@ -162,6 +163,7 @@ struct Plan {
         flist.clear();
         pan_tasks.clear();
         upd_tasks.clear();
+        upd_jbeg.clear();
         ea_tasks.clear();
         for (int32_t h = 0; h < H; h++) {
             Level &L = levels[h];
@@ -196,10 +198,15 @@ struct Plan {
             int32_t maxp = 0;
             for (int32_t s : fr) maxp = std::max(maxp, pfront[s]);
             int32_t tw = UT;
+            // tiles start at a multiple of 4 (the columns before clo masked):
+            // every tile then holds whole aligned quads of rows
             auto tiles = [&](int32_t s, int32_t clo, int32_t jend) {
                 int32_t m = mfront[s];
-                for (int32_t j0 = clo; j0 < jend; j0 += tw)
-                    for (int32_t i0 = j0; i0 < m; i0 += tw) upd_tasks.push_back(make_int4(s, i0, j0, jend));
+                for (int32_t j0 = clo & ~3; j0 < jend; j0 += tw)
+                    for (int32_t i0 = j0; i0 < m; i0 += tw) {
+                        upd_tasks.push_back(make_int4(s, i0, j0, jend));
+                        upd_jbeg.push_back(clo);
+                    }
             };
             for (int32_t K0 = 0; K0 < maxp; K0 += NBO) {
                 for (int32_t k0 = K0; k0 < std::min(K0 + NBO, maxp); k0 += NB) {
@@ -596,12 +603,12 @@ double panel_flops(const Plan &P, int32_t s, int32_t k0)
     double below = P.mfront[s] - k0 - nb;
     return nb * nb * nb / 3.0 + below * nb * nb;
 }
-double update_flops(const Plan &P, const int4 &t, int32_t ka, int32_t kw, int32_t tw)
+double update_flops(const Plan &P, const int4 &t, int32_t jbeg, int32_t ka, int32_t kw, int32_t tw)
 {
     int32_t m = P.mfront[t.x], p = P.pfront[t.x];
     double K = std::min(kw, p - ka);
     double cnt = 0;
-    for (int32_t col = t.z; col < std::min(t.z + tw, t.w); col++)
+    for (int32_t col = std::max(t.z, jbeg); col < std::min(t.z + tw, t.w); col++)
         cnt += std::max(0, std::min(t.y + tw, m) - std::max(t.y, col));
     return 2.0 * K * cnt;
 }
@@ -711,7 +718,8 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                 }
                 if (prof)
                     for (int64_t q = off; q < off + cnt; q++)
-                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], op.ka, op.kw, small ? 64 : UT);
+                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], P.upd_jbeg[q], op.ka, op.kw,
+                                                                small ? 64 : UT);
             } else {
                 int c = op.kind == OP_PANEL ? KC_PANEL : KC_PANEL_FP64DIAG;
                 PROF_BEGIN(c);
@@ -1196,7 +1204,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
             int64_t o = S.front_off[t.x];
             ud[q].a = make_int4((int32_t)(uint32_t)(uint64_t)o, (int32_t)((uint64_t)o >> 32), P.mfront[t.x],
                                 P.pfront[t.x]);
-            ud[q].b = make_int4(t.y, t.z, t.w, 0);
+            ud[q].b = make_int4(t.y, t.z, t.w, P.upd_jbeg[q]);
         }
         rc = rc ? rc : upload(f, L.upd, ud, st);
     }
