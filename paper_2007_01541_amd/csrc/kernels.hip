@@ -275,7 +275,7 @@ __device__ __forceinline__ typename Mfma<TD>::V mm16(typename Mfma<TD>::V acc, F
 constexpr int TRW = THREADS - 64;   // panel rows per workgroup (waves 1..3)
 
 template <typename T, typename TD>
-__global__ __launch_bounds__(THREADS) void k_panel(const int2 *__restrict__ tasks, int k0,
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_panel(const int2 *__restrict__ tasks, int k0,
                                                    const int64_t *__restrict__ front_off,
                                                    const int32_t *__restrict__ mfront,
                                                    const int32_t *__restrict__ pfront,
@@ -650,7 +650,7 @@ template <> struct UpdCfg<double> { static constexpr int KC = 16; };
 __device__ __forceinline__ int frag_pos(int r) { return (r & ~63) + (r & 15) * 4 + ((r >> 4) & 3); }
 
 template <typename T, int TW>
-__global__ __launch_bounds__(TW * TW / 64) void k_update(const UpdTask *__restrict__ tasks, int ka, int kw,
+__global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__restrict__ tasks, int ka, int kw,
                                                     T *__restrict__ fronts)
 {
     constexpr int KC = UpdCfg<T>::KC;
@@ -755,8 +755,8 @@ __global__ __launch_bounds__(TW * TW / 64) void k_update(const UpdTask *__restri
 // and masked to zero in the last chunk.  The fronts buffer must be followed
 // by at least 16 bytes of other workspace memory (it is).
 template <typename T> struct DmaCfg;
-template <> struct DmaCfg<float> { static constexpr int KC = 16, NS = 4; };
-template <> struct DmaCfg<double> { static constexpr int KC = 8, NS = 4; };
+template <> struct DmaCfg<float> { static constexpr int KC = 16; };
+template <> struct DmaCfg<double> { static constexpr int KC = 8; };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -793,12 +793,17 @@ __device__ __forceinline__ void dma_to_lds16(const void *g, uint32_t lds)
                  : "memory");
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ tasks, int ka, int kw,
-                                                    T *__restrict__ fronts)
+// NS = 4 stages (64 KB of LDS, two workgroups per compute unit) or 3 (48 KB,
+// three in FP32; FP64 stays at two, its registers would spill at three): the
+// deeper pipeline pays on long contractions, the third workgroup on short
+// ones; the autotuner picks per level.  The launch bound keeps the
+// accumulators within the register budget of that many waves.
+template <typename T, int NS>
+__global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_update_dma(const UpdTask *__restrict__ tasks, int ka, int kw,
+                                                                   T *__restrict__ fronts)
 {
-    constexpr int KC = DmaCfg<T>::KC, NS = DmaCfg<T>::NS;
-    static_assert(NS == 4, "the stage arrays below assume four stages");
+    constexpr int KC = DmaCfg<T>::KC;
+    static_assert(NS == 3 || NS == 4, "the stage arrays below hold three or four stages");
     constexpr int VEC = 16 / (int)sizeof(T);       // elements per lane per DMA instruction
     constexpr int LPR = 128 / VEC;                 // lanes per 128-element k row
     constexpr int RPI = 64 / LPR;                  // k rows per DMA instruction (f32 2, f64 1)
@@ -810,13 +815,13 @@ __global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ 
     __shared__ __align__(16) T S0[2][KC][128];
     __shared__ __align__(16) T S1[2][KC][128];
     __shared__ __align__(16) T S2[2][KC][128];
-    __shared__ __align__(16) T S3[2][KC][128];
+    __shared__ __align__(16) T S3[2][NS == 4 ? KC : 1][128];   // unused with three stages
     auto stage = [&](auto st_) -> T(*)[KC][128] {
         constexpr int st = decltype(st_)::value;
         if constexpr (st == 0) return S0;
         else if constexpr (st == 1) return S1;
         else if constexpr (st == 2) return S2;
-        else return S3;
+        else return reinterpret_cast<T(*)[KC][128]>(&S3[0][0][0]);   // (four stages only)
     };
     const UpdTask t = tasks[blockIdx.x];
     int i0 = t.b.x, j0 = t.b.y, jend = t.b.z, jbeg = t.b.w;
@@ -875,7 +880,7 @@ __global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ 
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
-    // chunk c lives in stage c % 4
+    // chunk c lives in stage c % NS
     auto step = [&](auto st_, auto nx_, int c) {
         if (c >= nchunk) return;
         int after = min(NS - 2, nchunk - 1 - c);   // chunks this wave issued after chunk c
@@ -888,12 +893,19 @@ __global__ __launch_bounds__(256) void k_update_dma(const UpdTask *__restrict__ 
     };
     issue(I0(), 0);
     if (nchunk > 1) issue(I1(), 1);
-    if (nchunk > 2) issue(I2(), 2);
+    if constexpr (NS == 4)
+        if (nchunk > 2) issue(I2(), 2);
     for (int c = 0; c < nchunk; c += NS) {
-        step(I0(), I3(), c);
-        step(I1(), I0(), c + 1);
-        step(I2(), I1(), c + 2);
-        step(I3(), I2(), c + 3);
+        if constexpr (NS == 4) {
+            step(I0(), I3(), c);
+            step(I1(), I0(), c + 1);
+            step(I2(), I1(), c + 2);
+            step(I3(), I2(), c + 3);
+        } else {
+            step(I0(), I2(), c);
+            step(I1(), I0(), c + 1);
+            step(I2(), I1(), c + 2);
+        }
     }
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;

@@ -706,7 +706,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                     hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, us, upd + off, op.ka,
                                        op.kw, fronts);
                 else if (L.upd_var == WCS_UPD_STREAM128)
-                    hipLaunchKernelGGL(k_update_dma<T>, dim3((unsigned)cnt), dim3(256), 0, us, upd + off, op.ka,
+                    hipLaunchKernelGGL((k_update_dma<T, 4>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off, op.ka,
+                                       op.kw, fronts);
+                else if (L.upd_var == WCS_UPD_STREAM128_3)
+                    hipLaunchKernelGGL((k_update_dma<T, 3>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off, op.ka,
                                        op.kw, fronts);
                 else
                     hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, us, upd + off,
@@ -1341,7 +1344,7 @@ int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream strea
         return WCS_OK;
     };
     // each candidate kernel on every level: a warm-up factorization, then a timed one
-    constexpr int NV = 3;
+    constexpr int NV = 4;
     std::vector<double> t[NV];
     const int32_t dflt = default_update_variant(f->prec);
     for (int v = 0; v < NV; v++) {
@@ -1382,8 +1385,9 @@ int wcs_factor_set_tiles(wcs_factor f, const int32_t *tiles)
 {
     if (!f || !tiles) { set_error("invalid argument to wcs_factor_set_tiles"); return WCS_EINVAL; }
     for (size_t h = 0; h < f->plan.levels.size(); h++)
-        if (tiles[h] < WCS_UPD_REG128 || tiles[h] > WCS_UPD_STREAM128) {
-            set_error("update kernel variant must be WCS_UPD_REG128, WCS_UPD_REG64 or WCS_UPD_STREAM128");
+        if (tiles[h] < WCS_UPD_REG128 || tiles[h] > WCS_UPD_STREAM128_3) {
+            set_error("update kernel variant must be WCS_UPD_REG128, WCS_UPD_REG64, WCS_UPD_STREAM128 or "
+                      "WCS_UPD_STREAM128_3");
             return WCS_EINVAL;
         }
     for (size_t h = 0; h < f->plan.levels.size(); h++) f->plan.levels[h].upd_var = tiles[h];

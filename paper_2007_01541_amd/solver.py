@@ -174,7 +174,8 @@ class Factor:
 
     def autotune(self, values, stream=None) -> dict:
         """Pick the trailing-update kernel per tree level by timing (leaves a valid factor):
-        0 = 128x128 register-staged, 1 = 64x64, 2 = 128x128 streamed into LDS."""
+        0 = 128x128 register-staged, 1 = 64x64, 2 = 128x128 streamed into LDS (four stages), 3 = the same
+        with three stages."""
         self.values = values
         H = self.sym.info["nlevels"]
         tiles = np.zeros(max(H, 1), np.int32)
