@@ -618,7 +618,7 @@ template <typename T, int KT> struct SxLds {
 
 // forward, task = (front, block i of the super-block at s0): z_i = sum_{j <= i} X_ij w_j -> Y
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS) void k_fwd_sz(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_sz(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x, ib = t.y;
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(THREADS) void k_fwd_sz(const int2 *__restrict__ tas
 // forward, task = (front, 64-row tile below s1): w_r -= sum over the blocks b of
 // the super-block of L(r, b) z_b (z from Y); wave w takes rows [16w, 16w+16)
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS) void k_fwd_srows(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_srows(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x;
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(THREADS) void k_fwd_srows(const int2 *__restrict__ 
 
 // backward, task = (front, block j of the super-block at s0): x_j = sum_{i >= j} X_ij^T v_i -> Y
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS) void k_bwd_sx(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_sx(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x, jb = t.y;
@@ -800,7 +800,7 @@ __global__ __launch_bounds__(THREADS) void k_bwd_sx(const int2 *__restrict__ tas
 // backward, task = (front, column block a) with 64 a < s0: v_a -= L([s0, s1), a)^T x_[s0, s1)
 // (x read from Y); each workgroup owns its block a
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS) void k_bwd_scols(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_scols(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x;
@@ -922,7 +922,7 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_sum(const int4 *__restric
 // pivot row belongs to exactly one front, so no two tasks write a row.  The
 // front's rows [ab, m) are split over the four waves in multiples of 16.
 template <typename T>
-__global__ __launch_bounds__(THREADS) void k_apply_lt(const int2 *__restrict__ tasks, SolveArgs<T> a,
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_apply_lt(const int2 *__restrict__ tasks, SolveArgs<T> a,
                                                       const T *__restrict__ Yin, T *__restrict__ Yout)
 {
     __shared__ MmLds<T> mm;
@@ -963,7 +963,7 @@ __global__ __launch_bounds__(THREADS) void k_apply_lt(const int2 *__restrict__ t
 // L(r, c) Yin(first + c); k_apply_gather then adds up, for every row of Y,
 // the W rows of all fronts that hold it.
 template <typename T>
-__global__ __launch_bounds__(THREADS) void k_apply_l(const int2 *__restrict__ tasks, SolveArgs<T> a,
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_apply_l(const int2 *__restrict__ tasks, SolveArgs<T> a,
                                                      const T *__restrict__ Yin, T *__restrict__ W)
 {
     __shared__ MmLds<T> mm;
