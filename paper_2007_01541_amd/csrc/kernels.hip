@@ -562,21 +562,29 @@ __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int j
 // q, y = 0..3.  With the quad's first row a multiple of 4 (aligned) and all
 // four rows inside the stored lower part, the quad is read and written as one
 // 16-byte (FP32) or 32-byte (FP64) access; other quads element by element.
-template <typename T, typename AccFn, typename RowFn, typename ColFn>
-__device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m, int jbeg, int jend, int pa,
-                                               bool aligned,
-                                               AccFn av, RowFn rowq, ColFn colf)
-{
-    typedef typename Vec4<T>::type V4;
-#pragma unroll
-    for (int h = 0; h < 4; h += 2) {
-        T cv[2][4][4];
+// In two halves (q = h, h + 1 for h = 0, 2): load(h) reads a half's earlier
+// values, store(h, av) writes the half; a kernel may issue load(0) early (the
+// object holds no reference to the accumulators, which stay in registers).
+template <typename T, typename RowFn, typename ColFn>
+struct QuadEpilogue {
+    T *F;
+    int ld, m, jbeg, jend, pa;
+    bool aligned;
+    RowFn rowq;
+    ColFn colf;
+    __device__ __forceinline__ bool full(int r0, int c) const
+    {
+        return aligned && c >= jbeg && c < jend && r0 >= c && r0 + 3 < m;
+    }
+    __device__ __forceinline__ void load(int h, T (&cv)[2][4][4]) const
+    {
+        typedef typename Vec4<T>::type V4;
 #pragma unroll
         for (int e2 = 0; e2 < 2; e2++)
 #pragma unroll
             for (int y = 0; y < 4; y++) {
                 int r0 = rowq(h + e2), c = colf(y);
-                if (aligned && c >= jbeg && c < jend && r0 >= c && r0 + 3 < m) {
+                if (full(r0, c)) {
                     V4 v = *reinterpret_cast<const V4 *>(F + (c < pa ? (int64_t)c * ld + r0 : 0));
                     cv[e2][y][0] = v.x;
                     cv[e2][y][1] = v.y;
@@ -591,6 +599,11 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
                     }
                 }
             }
+    }
+    template <typename AccFn>
+    __device__ __forceinline__ void store(int h, const T (&cv)[2][4][4], AccFn av) const
+    {
+        typedef typename Vec4<T>::type V4;
 #pragma unroll
         for (int e2 = 0; e2 < 2; e2++)
 #pragma unroll
@@ -599,7 +612,7 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
                 T o[4];
 #pragma unroll
                 for (int x = 0; x < 4; x++) o[x] = c < pa ? cv[e2][y][x] - av(h + e2, y, x) : -av(h + e2, y, x);
-                if (aligned && c >= jbeg && c < jend && r0 >= c && r0 + 3 < m) {
+                if (full(r0, c)) {
                     V4 v;
                     v.x = o[0];
                     v.y = o[1];
@@ -614,6 +627,24 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
                     }
                 }
             }
+    }
+};
+template <typename T, typename RowFn, typename ColFn>
+__device__ __forceinline__ QuadEpilogue<T, RowFn, ColFn> quad_epilogue(T *F, int ld, int m, int jbeg, int jend,
+                                                                       int pa, bool aligned, RowFn rowq, ColFn colf)
+{
+    return QuadEpilogue<T, RowFn, ColFn>{F, ld, m, jbeg, jend, pa, aligned, rowq, colf};
+}
+template <typename T, typename AccFn, typename RowFn, typename ColFn>
+__device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m, int jbeg, int jend, int pa,
+                                               bool aligned, AccFn av, RowFn rowq, ColFn colf)
+{
+    auto q = quad_epilogue<T>(F, ld, m, jbeg, jend, pa, aligned, rowq, colf);
+#pragma unroll
+    for (int h = 0; h < 4; h += 2) {
+        T cv[2][4][4];
+        q.load(h, cv);
+        q.store(h, cv, av);
     }
 }
 
@@ -798,12 +829,11 @@ __device__ __forceinline__ void dma_to_lds16(const void *g, uint32_t lds)
 // deeper pipeline pays on long contractions, the third workgroup on short
 // ones; the autotuner picks per level.  The launch bound keeps the
 // accumulators within the register budget of that many waves.
-template <typename T, int NS>
+template <typename T, int NS, int KC = DmaCfg<T>::KC>
 __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_update_dma(const UpdTask *__restrict__ tasks, int ka, int kw,
                                                                    T *__restrict__ fronts)
 {
-    constexpr int KC = DmaCfg<T>::KC;
-    static_assert(NS == 3 || NS == 4, "the stage arrays below hold three or four stages");
+    static_assert(NS >= 2 && NS <= 4, "the stage arrays below hold two to four stages");
     constexpr int VEC = 16 / (int)sizeof(T);       // elements per lane per DMA instruction
     constexpr int LPR = 128 / VEC;                 // lanes per 128-element k row
     constexpr int RPI = 64 / LPR;                  // k rows per DMA instruction (f32 2, f64 1)
@@ -814,13 +844,13 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
     // of one stage from a transfer into another
     __shared__ __align__(16) T S0[2][KC][128];
     __shared__ __align__(16) T S1[2][KC][128];
-    __shared__ __align__(16) T S2[2][KC][128];
-    __shared__ __align__(16) T S3[2][NS == 4 ? KC : 1][128];   // unused with three stages
+    __shared__ __align__(16) T S2[2][NS >= 3 ? KC : 1][128];   // unused with two stages
+    __shared__ __align__(16) T S3[2][NS == 4 ? KC : 1][128];   // unused with fewer than four
     auto stage = [&](auto st_) -> T(*)[KC][128] {
         constexpr int st = decltype(st_)::value;
         if constexpr (st == 0) return S0;
         else if constexpr (st == 1) return S1;
-        else if constexpr (st == 2) return S2;
+        else if constexpr (st == 2) return reinterpret_cast<T(*)[KC][128]>(&S2[0][0][0]);   // (three or more)
         else return reinterpret_cast<T(*)[KC][128]>(&S3[0][0][0]);   // (four stages only)
     };
     const UpdTask t = tasks[blockIdx.x];
@@ -876,6 +906,15 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
         }
     };
     const int nchunk = (K + KC - 1) / KC;
+    // epilogue; in FP32 the first half of the tile's earlier values is read
+    // while the last chunk's products run (workgroups of one launch tend to
+    // reach their epilogues together, and their C traffic would otherwise
+    // leave the matrix cores idle)
+    auto epi = quad_epilogue<T>(F, ld, m, jbeg, jend, ka == 0 ? p : m, (i0 & 3) == 0,
+                                [=](int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e); },
+                                [=](int y) { return j0 + wc + 4 * ln + y; });
+    constexpr bool early = sizeof(T) == 4;
+    T c0v[2][4][4];
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
@@ -892,11 +931,15 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
         if (active) compute(st_, K - c * KC);
     };
     issue(I0(), 0);
-    if (nchunk > 1) issue(I1(), 1);
+    if constexpr (NS >= 3)
+        if (nchunk > 1) issue(I1(), 1);
     if constexpr (NS == 4)
         if (nchunk > 2) issue(I2(), 2);
-    for (int c = 0; c < nchunk; c += NS) {
-        if constexpr (NS == 4) {
+    auto group = [&](int c) __attribute__((always_inline)) {
+        if constexpr (NS == 2) {
+            step(I0(), I1(), c);
+            step(I1(), I0(), c + 1);
+        } else if constexpr (NS == 4) {
             step(I0(), I3(), c);
             step(I1(), I0(), c + 1);
             step(I2(), I1(), c + 2);
@@ -906,13 +949,23 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
             step(I1(), I0(), c + 1);
             step(I2(), I1(), c + 2);
         }
-    }
+    };
+    int c = 0;
+    for (; c + NS < nchunk; c += NS) group(c);
+    // before the last group: the early epilogue reads (younger than every
+    // transfer issued so far, so the group's waits now also cover the chunks
+    // still in flight: stricter, never looser)
+    if constexpr (early)
+        if (active) epi.load(0, c0v);
+    group(c);
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;
-    tile_sub_quads<T>(F, ld, m, jbeg, jend, ka == 0 ? p : m, (i0 & 3) == 0,
-                      [&](int q, int y, int t) { return acc[t][y][q]; },
-                      [&](int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e); },
-                      [&](int y) { return j0 + wc + 4 * ln + y; });
+    auto av = [&](int q, int y, int t) { return acc[t][y][q]; };
+    if constexpr (!early) epi.load(0, c0v);
+    epi.store(0, c0v, av);
+    T c1v[2][4][4];
+    epi.load(2, c1v);
+    epi.store(2, c1v, av);
 }
 
 // ---------------------------------------------------------------- solves
