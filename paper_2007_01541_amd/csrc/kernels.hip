@@ -914,7 +914,8 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
                                 [=](int e) { return i0 + wr + 4 * Mfma<T>::row(kq, e); },
                                 [=](int y) { return j0 + wc + 4 * ln + y; });
     constexpr bool early = sizeof(T) == 4;
-    T c0v[2][4][4];
+    constexpr bool early2 = early && NS != 3;   // both halves where the registers allow (two waves per SIMD)
+    T c0v[2][4][4], c1v[2][4][4];
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
@@ -956,15 +957,17 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
     // transfer issued so far, so the group's waits now also cover the chunks
     // still in flight: stricter, never looser)
     if constexpr (early)
-        if (active) epi.load(0, c0v);
+        if (active) {
+            epi.load(0, c0v);
+            if constexpr (early2) epi.load(2, c1v);
+        }
     group(c);
     wait_vmcnt<0>();   // no transfer may land in LDS after the workgroup ends
     if (!active) return;
     auto av = [&](int q, int y, int t) { return acc[t][y][q]; };
     if constexpr (!early) epi.load(0, c0v);
     epi.store(0, c0v, av);
-    T c1v[2][4][4];
-    epi.load(2, c1v);
+    if constexpr (!early2) epi.load(2, c1v);
     epi.store(2, c1v, av);
 }
 
