@@ -740,7 +740,7 @@ __global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__res
     gload(0);
     sstore(0);
     __syncthreads();
-    for (int c = 0; c < nchunk; c++) {
+    auto body = [&](int c) __attribute__((always_inline)) {
         int buf = c & 1;
         if (c + 1 < nchunk) gload((c + 1) * KC);
         if (active) {
@@ -758,9 +758,27 @@ __global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__res
         }
         if (c + 1 < nchunk) sstore(buf ^ 1);
         __syncthreads();
-    }
+    };
+    // FP32 128-tiles: the tile's earlier values are read while the last
+    // chunk's products run (quads over e: accumulator element e is row 4 kq + e)
+    constexpr bool quads = sizeof(T) == 4 && TW == 128;
+    auto epi = quad_epilogue<T>(F, ld, m, jbeg, jend, ka == 0 ? p : m, (i0 & 3) == 0,
+                                [=](int x) { return i0 + wr + x * 16 + 4 * kq; },
+                                [=](int y) { return j0 + wc + y * 16 + ln; });
+    T c0v[2][4][4], c1v[2][4][4];
+    for (int c = 0; c + 1 < nchunk; c++) body(c);
+    if constexpr (quads)
+        if (active) {
+            epi.load(0, c0v);
+            epi.load(2, c1v);
+        }
+    body(nchunk - 1);
     if (!active) return;
-    if constexpr (sizeof(T) == 4)   // FP32 accumulator element e is row 4 kq + e: quads over e
+    if constexpr (quads) {
+        auto av = [&](int q, int y, int t) { return acc[q][y][t]; };
+        epi.store(0, c0v, av);
+        epi.store(2, c1v, av);
+    } else if constexpr (sizeof(T) == 4)
         tile_sub_quads<T>(F, ld, m, jbeg, jend, ka == 0 ? p : m, (i0 & 3) == 0,
                           [&](int q, int y, int t) { return acc[q][y][t]; },
                           [&](int x) { return i0 + wr + x * 16 + 4 * kq; },
