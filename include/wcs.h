@@ -311,9 +311,16 @@ int wcs_apply(wcs_factor f, wcs_apply_part part, int32_t nrhs, double *B_dev, in
  * X = A^-1 B by iterative refinement against the FP64 input matrix:
  * X0 = solve(B); repeat R = B - A X (FP64), stop when every column has
  * ||R||_2 / ||B||_2 <= tol, else X += solve(R) — at most max_iter corrections.
- * values_dev are the FP64 values used by the factorization (same pattern).
- * Reads the residual norms back to the host once per step (synchronous).
- * Returns WCS_ENOTCONV (with *rep filled) if tol is not reached.
+ * Each correction solves with R scaled per column by a power of two (R stays
+ * inside the FP32 range, unscaling is exact).  FP32 factors with nrhs = 8,
+ * 16, 32 or 64 form R from the FP32 solve outputs instead of X: R = B - A X0,
+ * then R -= A D after each correction D (FP64 products and sums); this equals
+ * B - A X up to the FP64 rounding of the sums X + D (about eps |A| |X|), so
+ * tol should stay well above eps times the condition number.  values_dev are
+ * the FP64 values used by the factorization (same pattern).  Reads the
+ * residual norms back to the host once per step (synchronous).  Returns
+ * WCS_ENOTCONV (with *rep filled, and X_dev holding the last iterate) if tol
+ * is not reached.
  */
 int wcs_solve_refined(wcs_factor f, const double *values_dev, int32_t nrhs, const double *B_dev,
                       double *X_dev, int64_t ld, double tol, int32_t max_iter, wcs_ir_report *rep,

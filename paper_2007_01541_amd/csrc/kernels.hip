@@ -1135,47 +1135,70 @@ __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ r
     }
 }
 
-// Vector form for row-major X with k = 4 LPE columns (LPE = 1, 2, 4, 8, 16):
-// one wave per row; a group of LPE lanes takes one matrix entry and four
-// columns per lane (two 16-byte loads of the X row), so one wave instruction
-// gathers the X rows of 64 / LPE entries at once.  Partial sums of the
-// groups are added with shuffles (fixed order).  Rows go to blocks in plain
-// order: consecutive rows of the dissection order share their X rows in L2.
-template <int LPE>
+// Vector form for row-major X with k = EL * LPE columns, EL = 4 for FP64 X
+// and 8 for FP32 X (LPE = 1, 2, 4, 8, 16): one wave per row; a group of LPE
+// lanes takes one matrix entry and EL columns per lane (two 16-byte loads of
+// the X row), so one wave instruction gathers the X rows of 64 / LPE entries
+// at once.  Products and sums are FP64 whatever the type of X.  Partial sums
+// of the groups are added with shuffles (fixed order).  Rows go to blocks in
+// plain order: consecutive rows of the dissection order share their X rows in
+// L2.  Output R = B - mul[c] (A X), or R = A X when B is null (null mul means
+// 1); B may be R itself (each element is read and written by one lane).
+template <typename TX> struct SpmvVec;
+template <> struct SpmvVec<double> {
+    using V = double2;
+    static constexpr int EL = 4;
+    __device__ static double at(const V &x, int j) { return j == 0 ? x.x : x.y; }
+};
+template <> struct SpmvVec<float> {
+    using V = float4;
+    static constexpr int EL = 8;
+    __device__ static double at(const V &x, int j)
+    {
+        return (double)(j == 0 ? x.x : j == 1 ? x.y : j == 2 ? x.z : x.w);
+    }
+};
+
+template <int LPE, typename TX>
 __global__ __launch_bounds__(256) void k_spmv_vec(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ v, int n, const double *__restrict__ X,
-                                                  const double *__restrict__ B, double *__restrict__ R)
+                                                  const double *__restrict__ v, int n, const TX *__restrict__ X,
+                                                  const double *B, const double *__restrict__ mul, double *R)
 {
-    constexpr int K = 4 * LPE, EPI = 64 / LPE, U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
+    using SV = SpmvVec<TX>;
+    using V = typename SV::V;
+    constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
+    constexpr int U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
     int row = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
     if (row >= n) return;
     int q = lane / LPE, ql = lane % LPE;
     int64_t a = rp[row], b = rp[row + 1];
-    const double2 *xc = reinterpret_cast<const double2 *>(X) + 2 * ql;
-    double s[4] = {0, 0, 0, 0};
+    const V *xc = reinterpret_cast<const V *>(X) + 2 * ql;   // a row is 2 LPE vectors of 16 bytes
+    double s[EL];
+#pragma unroll
+    for (int j = 0; j < EL; j++) s[j] = 0;
     for (int64_t q0 = a; q0 < b; q0 += 64) {
         int cnt = (int)min((int64_t)64, b - q0);
         int myc = lane < cnt ? __builtin_nontemporal_load(ci + q0 + lane) : 0;
         double myv = lane < cnt ? __builtin_nontemporal_load(v + q0 + lane) : 0.0;
         int t = 0;
         for (; t + U * EPI <= cnt; t += U * EPI) {
-            double2 x0[U], x1[U];
+            V x0[U], x1[U];
             double w[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 int e = t + EPI * u + q;
-                const double2 *pr = xc + (int64_t)__shfl(myc, e) * (K / 2);
+                const V *pr = xc + (int64_t)__shfl(myc, e) * (2 * LPE);
                 x0[u] = pr[0];
                 x1[u] = pr[1];
                 w[u] = __shfl(myv, e);
             }
 #pragma unroll
-            for (int u = 0; u < U; u++) {
-                s[0] += w[u] * x0[u].x;
-                s[1] += w[u] * x0[u].y;
-                s[2] += w[u] * x1[u].x;
-                s[3] += w[u] * x1[u].y;
-            }
+            for (int u = 0; u < U; u++)
+#pragma unroll
+                for (int j = 0; j < H; j++) {
+                    s[j] += w[u] * SV::at(x0[u], j);
+                    s[H + j] += w[u] * SV::at(x1[u], j);
+                }
         }
         for (; t < cnt; t += EPI) {
             int e = t + q;
@@ -1183,23 +1206,28 @@ __global__ __launch_bounds__(256) void k_spmv_vec(const int64_t *__restrict__ rp
             int cc = __shfl(myc, ok ? e : t);
             double ww = __shfl(myv, ok ? e : t);
             if (ok) {
-                const double2 *pr = xc + (int64_t)cc * (K / 2);
-                double2 a0 = pr[0], a1 = pr[1];
-                s[0] += ww * a0.x;
-                s[1] += ww * a0.y;
-                s[2] += ww * a1.x;
-                s[3] += ww * a1.y;
+                const V *pr = xc + (int64_t)cc * (2 * LPE);
+                V a0 = pr[0], a1 = pr[1];
+#pragma unroll
+                for (int j = 0; j < H; j++) {
+                    s[j] += ww * SV::at(a0, j);
+                    s[H + j] += ww * SV::at(a1, j);
+                }
             }
         }
     }
 #pragma unroll
     for (int off = 32; off >= LPE; off >>= 1)
 #pragma unroll
-        for (int j = 0; j < 4; j++) s[j] += __shfl_down(s[j], off, 64);
+        for (int j = 0; j < EL; j++) s[j] += __shfl_down(s[j], off, 64);
     if (q == 0) {
-        int64_t o = (int64_t)row * K + 4 * ql;
+        int64_t o = (int64_t)row * K + EL * ql;
 #pragma unroll
-        for (int j = 0; j < 4; j++) R[o + j] = B ? B[o + j] - s[j] : s[j];
+        for (int j = 0; j < EL; j++) {
+            double r = s[j];
+            if (mul) r *= mul[EL * ql + j];
+            R[o + j] = B ? B[o + j] - r : r;
+        }
     }
 }
 
@@ -1304,11 +1332,17 @@ __global__ void k_colred_final(const double *__restrict__ part, int bps, int k, 
     }
 }
 
-// scale[c] = amax[c] > 0 ? 1 / amax[c] : 1
-__global__ void k_inv_scale(const double *__restrict__ amax, int k, double *__restrict__ scale)
+// Column scale of the residual before its FP32 cast: scale[c] = 2^-e with
+// 2^e <= amax[c] < 2^(e+1) (1 for a zero or non-finite column); amax[c] is
+// overwritten with 2^e = 1 / scale[c]
+__global__ void k_inv_scale(double *__restrict__ amax, int k, double *__restrict__ scale)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < k) scale[c] = amax[c] > 0 ? 1.0 / amax[c] : 1.0;
+    if (c >= k) return;
+    double m = amax[c];
+    int e = m > 0 && m <= 1.7976931348623157e308 ? ilogb(m) : 0;
+    scale[c] = ldexp(1.0, -e);     // a power of two: m * scale in [1, 2), and unscaling is exact
+    amax[c] = ldexp(1.0, e);       // its inverse, for the residual update
 }
 
 // ---------------------------------------------------------------- gradient

@@ -985,6 +985,35 @@ int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st)
     return WCS_OK;
 }
 
+// Row-major X of k = 4 LPE (FP64) or 8 LPE (FP32) columns, LPE a power of
+// two up to 16 (FP64) or 8 (FP32): the vector SpMM form
+template <typename TX> bool spmv_vec_fits(int k)
+{
+    constexpr int EL = sizeof(TX) == 8 ? 4 : 8, maxl = sizeof(TX) == 8 ? 16 : 8;
+    return k % EL == 0 && k / EL <= maxl && ((k / EL) & (k / EL - 1)) == 0;
+}
+
+// R = B - mul[c] (C X), or R = C X when B is null; C = P A P^T in pivot order,
+// row-major X, B, R with leading dimension k (spmv_vec_fits<TX>(k))
+template <typename TX>
+void launch_spmv_vec(wcs_factor f, int k, const TX *X, const double *B, const double *mul, double *R, hipStream_t st)
+{
+    int n = f->S->n;
+    const int64_t *rp = f->at<int64_t>(f->lay.csr_ptr);
+    const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
+    const double *v = f->at<double>(f->lay.csr_val);
+    dim3 g((unsigned)((n + 3) / 4)), b(256);
+    switch (k / (sizeof(TX) == 8 ? 4 : 8)) {
+    case 1: hipLaunchKernelGGL((k_spmv_vec<1, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
+    case 2: hipLaunchKernelGGL((k_spmv_vec<2, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
+    case 4: hipLaunchKernelGGL((k_spmv_vec<4, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
+    case 8: hipLaunchKernelGGL((k_spmv_vec<8, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
+    default:
+        if constexpr (sizeof(TX) == 8) hipLaunchKernelGGL((k_spmv_vec<16, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R);
+        break;
+    }
+}
+
 // R = B - C X or Y = C X (B null) with C = P A P^T in pivot order; element
 // (i, c) at i * sx + c * sc
 int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R, int64_t sx, int64_t sc,
@@ -996,14 +1025,8 @@ int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R
     const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
     const double *v = f->at<double>(f->lay.csr_val);
     unsigned nrb = (unsigned)((n + 3) / 4);
-    if (sx == k && sc == 1 && (k == 4 || k == 8 || k == 16 || k == 32 || k == 64)) {
-        switch (k) {
-        case 4: hipLaunchKernelGGL(k_spmv_vec<1>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
-        case 8: hipLaunchKernelGGL(k_spmv_vec<2>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
-        case 16: hipLaunchKernelGGL(k_spmv_vec<4>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
-        case 32: hipLaunchKernelGGL(k_spmv_vec<8>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
-        default: hipLaunchKernelGGL(k_spmv_vec<16>, dim3(nrb), dim3(256), 0, st, rp, ci, v, n, X, B, R); break;
-        }
+    if (sx == k && sc == 1 && spmv_vec_fits<double>(k)) {
+        launch_spmv_vec<double>(f, k, X, B, nullptr, R, st);
     } else if (k >= 8 && sx == k && sc == 1) {
         int per = ((int)nrb + 7) / 8;
         hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)(8 * per)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R);
@@ -1029,10 +1052,15 @@ void launch_colred(wcs_factor f, const double *A, int n, int k, int op, bool seg
 }
 
 // Refinement in pivot order: Bp = P B, Xp = solve(Bp), then while any
-// column has ||Bp - C Xp|| > tol ||Bp||: Xp += solve(R s) / s with the
-// per-column scale s = 1 / max|R| (keeps R inside the FP32 range); X = P^T Xp.
-// For a batch the test is per instance and column (each block of the
-// block-diagonal matrix is its own system).
+// column has ||R|| > tol ||Bp|| for R = Bp - C Xp: Xp += D = solve(R s) / s
+// with the per-column power of two s ~ 1 / max|R| (keeps R inside the FP32
+// range, unscaling is exact); X = P^T Xp.  With an FP32 factor Xp0 and every
+// D are FP32 numbers times 2^e, so the residual is formed from their FP32
+// rows (half the gathered bytes): R = Bp - C Y0, then R -= (C Y) / s after
+// each correction, with FP64 products and sums.  That updated residual is
+// Bp - C Xp up to the FP64 rounding of the sums Xp + D.  For a batch the test
+// is per instance and column (each block of the block-diagonal matrix is its
+// own system).
 template <typename T>
 int solve_refined(wcs_factor f, const double *values, int k, const double *B, double *X, int64_t ld, double tol,
                   int max_iter, wcs_ir_report *rep, hipStream_t st)
@@ -1047,7 +1075,9 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     const int nseg = (int)nseg_of(*f->S), nsk = nseg * k;
     // vec: [0,nsk) |B|^2 and [nsk,2nsk) |R|^2 per (segment, column); then amax[k], scale[k]
     double *vec = f->at<double>(Lo.vec);
-    double *amax = vec + 2 * nsk, *scale = amax + k;
+    double *amax = vec + 2 * nsk, *scale = amax + k;    // amax becomes 1 / scale
+    // FP32 factor: residual from the FP32 rows of the solves (see above)
+    const bool from_y = sizeof(T) == 4 && spmv_vec_fits<float>(k);
     T *Y = f->at<T>(Lo.Y);
     const int32_t *perm = f->at<int32_t>(Lo.perm);
     int64_t nk = (int64_t)n * k;
@@ -1065,8 +1095,15 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     rep->final_residual = -1;
     int status = WCS_ENOTCONV;
     for (int it = 0;; it++) {
-        rc = launch_spmv(f, k, Xp, Bp, Rp, k, 1, st);
-        if (rc) return rc;
+        if constexpr (sizeof(T) == 4) {
+            if (from_y)
+                launch_spmv_vec<float>(f, k, Y, it == 0 ? Bp : Rp, it == 0 ? nullptr : amax, Rp, st);
+        }
+        if (!from_y) {
+            rc = launch_spmv(f, k, Xp, Bp, Rp, k, 1, st);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipGetLastError());
         launch_colred(f, Rp, n, k, 0, true, vec + nsk, st);
         HIP_TRY(hipMemcpyAsync(h.data(), vec, sizeof(double) * 2 * nsk, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));

@@ -247,7 +247,9 @@ class Factor:
         return Bm if B.dim() == 2 else Bm.view(-1)
 
     def solve_refined(self, B, values=None, tol: float = 1e-10, max_iter: int = 10, stream=None):
-        """X = A^-1 B by iterative refinement; returns (X, report dict)."""
+        """X = A^-1 B by iterative refinement; returns (X, report dict).  If tol is
+        not reached in max_iter corrections, raises WcsError (code -5) carrying
+        .report and the last iterate as .result."""
         torch = _torch()
         vals = values if values is not None else self.values
         Bm = B if B.dim() == 2 else B.view(-1, 1)
@@ -260,12 +262,14 @@ class Factor:
                                      C.byref(rep), _stream_ptr(stream))
         report = {"iterations": rep.iterations, "raw_residual": rep.raw_residual,
                   "final_residual": rep.final_residual}
+        X = xc.t().contiguous()
+        X = X if B.dim() == 2 else X.view(-1)
         if rc != 0:
             err = capi.WcsError(rc, "wcs_solve_refined", lib().wcs_last_error().decode(errors="replace"))
             err.report = report
+            err.result = X if rc == -5 else None
             raise err
-        X = xc.t().contiguous()
-        return (X if B.dim() == 2 else X.view(-1)), report
+        return X, report
 
     def spmv(self, X, values=None, stream=None):
         torch = _torch()

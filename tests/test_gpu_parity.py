@@ -95,7 +95,7 @@ def test_half_solves(part, prec):
 
 
 @pytest.mark.parametrize("kind,leaf,coords", CASES)
-@pytest.mark.parametrize("k", [1, 64])
+@pytest.mark.parametrize("k", [1, 8, 64])
 def test_fp32_refined_reaches_1e10(kind, leaf, coords, k):
     m, sym, orc = prepared(kind, leaf, coords)
     n = m["n"]
@@ -112,6 +112,34 @@ def test_fp32_refined_reaches_1e10(kind, leaf, coords, k):
     assert rep["raw_residual"] > rep["final_residual"] or rep["iterations"] == 0
     Xo = orc.solve(B)
     assert np.abs(X - Xo).max() <= 1e-10 * gershgorin_kappa(m) * np.abs(Xo).max()
+
+
+@pytest.mark.parametrize("kind", ["small", "g6alg"])
+@pytest.mark.parametrize("k", [4, 8, 32, 64])
+def test_updated_residual_tracks_true_residual(kind, k):
+    """With an FP32 factor and 8, 16, 32 or 64 right-hand sides the residual is
+    updated from the FP32 corrections (R -= A D) instead of being recomputed
+    from X; the reported per-column residuals must stay the true ones
+    ||b - A x|| / ||b|| (oracle, FP64) up to the FP64 rounding of x, through
+    several corrections (tolerance far below what one correction reaches).
+    k = 4 takes the recomputed form and must agree as well."""
+    m, sym, _ = prepared(kind)
+    n = m["n"]
+    B = normal_rhs(n, k, 31) * np.logspace(-3, 3, k)     # columns of very different scales
+    f = Factor(sym, FP32, max_nrhs=k)
+    vals = dev(m["values"])
+    f.numeric(vals)
+    with pytest.raises(WcsError) as e:      # tolerance 0: every correction is taken
+        f.solve_refined(dev(B), vals, tol=0.0, max_iter=3)
+    X, rep = e.value.result, e.value.report
+    true = oracle.residual(n, m["colptr"], m["rowind"], m["values"], X.cpu().numpy(), B)
+    upd = f.residuals()[0]
+    kap = gershgorin_kappa(m)
+    print(f"{kind} k={k}: iterations {rep['iterations']}, reported {upd.max():.3e}, true {true.max():.3e}, "
+          f"largest gap {np.abs(upd - true).max():.3e}, kappa bound {kap:.1f}")
+    assert rep["iterations"] == 3
+    assert np.all(np.abs(upd - true) <= 8 * rep["iterations"] * EPS64 * kap)
+    assert true.max() <= 1e-12
 
 
 def test_fp64_refined_no_iterations_needed():
