@@ -317,8 +317,8 @@ struct Plan {
                 int64_t off = (int64_t)sfwd_tasks.size();
                 for (int32_t s : big) {
                     if (pfront[s] <= s0) continue;
-                    int32_t s1 = std::min(pfront[s], s0 + SS);
-                    int32_t nt = (mfront[s] - s1 + SB - 1) / SB;
+                    int32_t s1 = std::min(pfront[s], s0 + SS);    // row tiles start at s1 & ~3
+                    int32_t nt = mfront[s] > s1 ? (mfront[s] - (s1 & ~3) + SB - 1) / SB : 0;
                     for (int32_t t = 0; t < nt; t++) sfwd_tasks.push_back(make_int2(s, t));
                 }
                 V.fwd.push_back({s0, d.first, d.second, off, (int64_t)sfwd_tasks.size() - off});
@@ -328,7 +328,7 @@ struct Plan {
             for (int32_t s : big)
                 for (int32_t a = 0; a < (pfront[s] + SB - 1) / SB; a++) {
                     int64_t slot0 = part_blocks;
-                    for (int32_t r0 = pfront[s]; r0 < mfront[s]; r0 += BELOW_ROWS)
+                    for (int32_t r0 = pfront[s] & ~3; mfront[s] > pfront[s] && r0 < mfront[s]; r0 += BELOW_ROWS)
                         sbelow_tasks.push_back(make_int4(s, a, r0, (int32_t)part_blocks++));
                     sbsum_tasks.push_back(make_int4(s, a, (int32_t)slot0, (int32_t)(part_blocks - slot0)));
                 }

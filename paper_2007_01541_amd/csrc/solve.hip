@@ -57,7 +57,7 @@ __device__ __forceinline__ void sub_batch(T *__restrict__ base, OffFn off, ValFn
 
 constexpr int SB = 64;          // block size of the solves (= panel width of the factorization)
 constexpr int SS = 4 * SB;      // super-block of the large-front sweeps
-constexpr int SROWS = THREADS;  // rows per workgroup in a forward row launch
+constexpr int SROWS = 64;       // rows per workgroup in a forward assembly launch
 
 // ---- shared pieces (all threads of the workgroup call them)
 
@@ -358,17 +358,28 @@ __global__ __launch_bounds__(THREADS) void k_fwd_fused(const int32_t *__restrict
 // plus the update rows of every child that land in the slab.  The index map
 // of a child is increasing, so those rows are one contiguous run found by
 // binary search; children are visited in a fixed order (deterministic).
+// With k a multiple of 4 every thread moves groups of four columns of a row
+// (vector accesses); loads of a round are issued before its stores.
 template <typename T>
 __global__ __launch_bounds__(THREADS) void k_fwd_assemble(const int2 *__restrict__ tasks, SolveArgs<T> a)
 {
+    typedef typename Vec4<T>::type V4;
     int2 t = tasks[blockIdx.x];
     int f = t.x;
     int m = a.mfront[f], p = a.pfront[f], k = a.k;
     int r0 = t.y * SROWS, r1 = min(m, r0 + SROWS);
     T *w = a.W + a.woff[f] * k;
     const T *y = a.Y + (int64_t)a.first[f] * k;
-    for (int64_t i = (int64_t)r0 * k + threadIdx.x; i < (int64_t)r1 * k; i += blockDim.x)
-        w[i] = i < (int64_t)p * k ? y[i] : (T)0;
+    const bool quad = (k & 3) == 0;
+    const int g = quad ? 4 : 1, ng = k / g;     // groups of g columns per row
+    for (int i = threadIdx.x; i < (r1 - r0) * ng; i += blockDim.x) {
+        int r = r0 + i / ng, c = (i % ng) * g;
+        int64_t o = (int64_t)r * k + c;
+        if (quad)
+            *reinterpret_cast<V4 *>(w + o) = r < p ? *reinterpret_cast<const V4 *>(y + o) : V4{0, 0, 0, 0};
+        else
+            w[o] = r < p ? y[o] : (T)0;
+    }
     __syncthreads();
     for (int q = a.child_ptr[f]; q < a.child_ptr[f + 1]; q++) {
         int c = a.child_list[q];
@@ -382,23 +393,48 @@ __global__ __launch_bounds__(THREADS) void k_fwd_assemble(const int2 *__restrict
         while (lo < hi) { int md = (lo + hi) / 2; if (rl[md] < r1) lo = md + 1; else hi = md; }
         int t1 = lo;
         const T *wc = a.W + a.woff[c] * k + (int64_t)pc * k;
-        constexpr int B = 4;   // elements per thread per round: loads first, then stores
-        for (int64_t i0 = (int64_t)t0 * k + threadIdx.x; i0 < (int64_t)t1 * k; i0 += B * blockDim.x) {
-            int64_t di[B];
-            T uv[B], dv[B];
+        int tot = (t1 - t0) * ng;
+        constexpr int B = 2;   // groups per thread per round
+        for (int i0 = threadIdx.x; i0 < tot; i0 += B * blockDim.x) {
+            int64_t so[B], dof[B];
 #pragma unroll
             for (int b = 0; b < B; b++) {
-                int64_t i = i0 + (int64_t)b * blockDim.x;
-                bool ok = i < (int64_t)t1 * k;
-                int r = ok ? (int)(i / k) : t0, cc = ok ? (int)(i % k) : 0;
-                di[b] = ok ? (int64_t)rl[r] * k + cc : -1;
-                uv[b] = ok ? wc[i] : (T)0;
+                int i = i0 + b * blockDim.x;
+                bool ok = i < tot;
+                int r = t0 + (ok ? i / ng : 0), cc = ok ? (i % ng) * g : 0;
+                so[b] = (int64_t)r * k + cc;
+                dof[b] = ok ? (int64_t)rl[r] * k + cc : -1;
             }
+            if (quad) {
+                V4 uv[B], dv[B];
 #pragma unroll
-            for (int b = 0; b < B; b++) dv[b] = w[di[b] >= 0 ? di[b] : (int64_t)r0 * k];
+                for (int b = 0; b < B; b++) {
+                    bool ok = dof[b] >= 0;
+                    uv[b] = ok ? *reinterpret_cast<const V4 *>(wc + so[b]) : V4{0, 0, 0, 0};
+                    dv[b] = ok ? *reinterpret_cast<const V4 *>(w + dof[b]) : V4{0, 0, 0, 0};
+                }
 #pragma unroll
-            for (int b = 0; b < B; b++)
-                if (di[b] >= 0) w[di[b]] = dv[b] + uv[b];
+                for (int b = 0; b < B; b++)
+                    if (dof[b] >= 0) {
+                        V4 v = dv[b];
+                        v.x += uv[b].x;
+                        v.y += uv[b].y;
+                        v.z += uv[b].z;
+                        v.w += uv[b].w;
+                        *reinterpret_cast<V4 *>(w + dof[b]) = v;
+                    }
+            } else {
+                T uv[B], dv[B];
+#pragma unroll
+                for (int b = 0; b < B; b++) {
+                    bool ok = dof[b] >= 0;
+                    uv[b] = ok ? wc[so[b]] : (T)0;
+                    dv[b] = ok ? w[dof[b]] : (T)0;
+                }
+#pragma unroll
+                for (int b = 0; b < B; b++)
+                    if (dof[b] >= 0) w[dof[b]] = dv[b] + uv[b];
+            }
         }
         __syncthreads();
     }
@@ -499,22 +535,24 @@ __device__ __forceinline__ void wave_mm(typename Mfma<T>::V (&acc)[4][4], int kb
 
 // Sums the four waves' tiles: out(r, c, v) for every (r, c) of the 64 x 64
 // tile, called by 16 elements per thread in two halves of 32 columns; red is
-// LDS of 4 * 64 * 32 elements.  All threads of the workgroup call it.
-template <typename T, typename Out>
-__device__ __forceinline__ void reduce4(typename Mfma<T>::V (&acc)[4][4], T *red, Out out)
+// LDS of 4 * 64 * 32 elements.  at(x, y, e) gives the tile position (r, c)
+// of accumulator element e of acc[x][y] in this lane.  All threads of the
+// workgroup call it.
+template <typename T, typename At, typename Out>
+__device__ __forceinline__ void reduce4m(typename Mfma<T>::V (&acc)[4][4], T *red, At at, Out out)
 {
-    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+    const int tid = threadIdx.x, wave = tid / 64;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         __syncthreads();
 #pragma unroll
         for (int x = 0; x < 4; x++)
 #pragma unroll
-            for (int y = 0; y < 2; y++)
+            for (int y = 0; y < 4; y++)
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    int r = 16 * x + Mfma<T>::row(kq, e), c = 16 * y + ln;
-                    red[(wave * 64 + r) * 32 + c] = acc[x][2 * h + y][e];
+                    int2 rc = at(x, y, e);
+                    if ((rc.y >> 5) == h) red[(wave * 64 + rc.x) * 32 + (rc.y & 31)] = acc[x][y][e];
                 }
         __syncthreads();
         T v[8];
@@ -528,6 +566,91 @@ __device__ __forceinline__ void reduce4(typename Mfma<T>::V (&acc)[4][4], T *red
                    red[(2 * 64 + rr[q]) * 32 + cc[q]] + red[(3 * 64 + rr[q]) * 32 + cc[q]];
         }
         out(rr, cc, v, 32 * h);
+    }
+}
+
+// the layout of wave_mm: element e of acc[x][y] is (16 x + row(kq, e), 16 y + ln)
+template <typename T, typename Out>
+__device__ __forceinline__ void reduce4(typename Mfma<T>::V (&acc)[4][4], T *red, Out out)
+{
+    const int lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+    reduce4m<T>(acc, red, [&](int x, int y, int e) { return make_int2(16 * x + Mfma<T>::row(kq, e), 16 * y + ln); },
+                out);
+}
+
+// ---- quad forms of the 64 x 64 wave product: one vector load of four
+// consecutive elements per lane and operand feeds four 16x16x4 products.
+
+template <typename V4> __device__ __forceinline__ auto q_at(const V4 &v, int i)
+{
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// acc[x][y] += sum over k in [kb, ke) of A(4 i + x, k) B(k, 4 j + y) for the
+// product's row i and column j: qa(t, k) returns A rows 4t..4t+3 of column k,
+// qb(k, t) B columns 4t..4t+3 of row k (each a 16- or 32-byte vector).  Lane
+// kq of a product supplies k = kg + 4 u + kq in the u-th product of a group
+// (4 U values of k).  Element e of acc[x][y] is (4 row(kq, e) + x, 4 ln + y).
+template <typename T, typename QA, typename QB>
+__device__ __forceinline__ void wave_mm_q(typename Mfma<T>::V (&acc)[4][4], int kb, int ke, QA qa, QB qb)
+{
+    typedef typename Vec4<T>::type V4;
+    constexpr int U = sizeof(T) == 4 ? 4 : 2;    // products per group (FP64 quads take twice the registers)
+    const int lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+    for (int kg = kb; kg < ke; kg += 4 * U) {
+        V4 av[U], bv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            int k = kg + 4 * u + kq;
+            bool ok = k < ke;
+            av[u] = ok ? qa(ln, k) : V4{0, 0, 0, 0};
+            bv[u] = ok ? qb(k, ln) : V4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++)
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++) acc[x][y] = Mfma<T>::mma(q_at(av[u], x), q_at(bv[u], y), acc[x][y]);
+    }
+}
+
+// acc[x][y] += sum over k in [max(lo, kb), ke) of A(16 x + i, k) B(k, 4 j + y):
+// ka(i, k4) returns A(i, k4..k4+3) (four consecutive k of row i, k4 a
+// multiple of 4 relative to kb), qb(k, t) B columns 4t..4t+3 of row k.  Lane
+// kq supplies k = kg + 4 kq + s in the s-th product of a group of 16, so its
+// four k are one load of A.  Element e of acc[x][y] is (16 x + row(kq, e), 4 ln + y).
+template <typename T, typename KA, typename QB>
+__device__ __forceinline__ void wave_mm_kq(typename Mfma<T>::V (&acc)[4][4], int lo, int kb, int ke, KA ka, QB qb)
+{
+    typedef typename Vec4<T>::type V4;
+    const int lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+    for (int kg = kb; kg < ke; kg += 16) {
+        int k4 = kg + 4 * kq;
+        V4 av[4], bv[4];
+        bool any = k4 < ke;
+#pragma unroll
+        for (int x = 0; x < 4; x++) {
+            av[x] = any ? ka(16 * x + ln, k4) : V4{0, 0, 0, 0};
+            if (k4 < lo || k4 + 3 >= ke) {      // the ends of the range
+                if (k4 < lo || k4 >= ke) av[x].x = 0;
+                if (k4 + 1 < lo || k4 + 1 >= ke) av[x].y = 0;
+                if (k4 + 2 < lo || k4 + 2 >= ke) av[x].z = 0;
+                if (k4 + 3 < lo || k4 + 3 >= ke) av[x].w = 0;
+            }
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; s2++) {
+            int k = k4 + s2;
+            bv[s2] = (k >= lo && k < ke) ? qb(k, ln) : V4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < 4; s2++)
+#pragma unroll
+            for (int x = 0; x < 4; x++)
+#pragma unroll
+                for (int y = 0; y < 4; y++)
+                    acc[x][y] = Mfma<T>::mma(q_at(av[x], s2), q_at(bv[s2], y), acc[x][y]);
     }
 }
 
@@ -618,7 +741,7 @@ template <typename T, int KT> struct SxLds {
 
 // forward, task = (front, block i of the super-block at s0): z_i = sum_{j <= i} X_ij w_j -> Y
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_sz(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_fwd_sz(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x, ib = t.y;
@@ -629,8 +752,10 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_sz(cons
     const T *w = a.W + a.woff[f] * k;
     if constexpr (KT == 64) {
         // wave jb adds X_ij w_j for its block j <= i
+        typedef typename Vec4<T>::type V4;
         __shared__ MmLds<T> mm;
-        int wave = threadIdx.x / 64;
+        int wave = threadIdx.x / 64, lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+        bool quad = (k & 3) == 0;
         for (int c0 = 0; c0 < k; c0 += 64) {
             typename Mfma<T>::V acc[4][4];
 #pragma unroll
@@ -641,18 +766,36 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_sz(cons
                     for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
             if (wave <= ib) {
                 int j0 = s0 + wave * SB, nj = min(SB, s1 - j0);
-                wave_mm<T>(
-                    acc, 0, nj,
-                    [&](int r, int kk) { return r < ni ? X[(int64_t)(j0 - s0 + kk) * SS + (i0 - s0 + r)] : (T)0; },
-                    [&](int kk, int c) { return c0 + c < k ? w[(int64_t)(j0 + kk) * k + c0 + c] : (T)0; });
+                if (quad)   // rows of X_ij in quads (X is column-major, rows inside the super-block)
+                    wave_mm_q<T>(
+                        acc, 0, nj,
+                        [&](int q, int kk) {
+                            return *reinterpret_cast<const V4 *>(X + (int64_t)(j0 - s0 + kk) * SS + (i0 - s0) + 4 * q);
+                        },
+                        [&](int kk, int q) {
+                            int c = c0 + 4 * q;
+                            return c < k ? *reinterpret_cast<const V4 *>(w + (int64_t)(j0 + kk) * k + c)
+                                         : V4{0, 0, 0, 0};
+                        });
+                else
+                    wave_mm<T>(
+                        acc, 0, nj,
+                        [&](int r, int kk) { return r < ni ? X[(int64_t)(j0 - s0 + kk) * SS + (i0 - s0 + r)] : (T)0; },
+                        [&](int kk, int c) { return c0 + c < k ? w[(int64_t)(j0 + kk) * k + c0 + c] : (T)0; });
             }
-            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *v, int cb) {
+            auto put = [&](int *rr, int *cc, T *v, int cb) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
                     int r = rr[q], c = cb + cc[q];
                     if (r < ni && c0 + c < k) a.Y[(int64_t)(f0 + i0 + r) * k + c0 + c] = v[q];
                 }
-            });
+            };
+            if (quad)
+                reduce4m<T>(
+                    acc, mm.red,
+                    [&](int x, int y, int e) { return make_int2(4 * Mfma<T>::row(kq, e) + x, 4 * ln + y); }, put);
+            else
+                reduce4<T>(acc, mm.red, put);
         }
         return;
     }
@@ -678,23 +821,27 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_sz(cons
     }
 }
 
-// forward, task = (front, 64-row tile below s1): w_r -= sum over the blocks b of
-// the super-block of L(r, b) z_b (z from Y); wave w takes rows [16w, 16w+16)
+// forward, task = (front, 64-row tile of the rows below s1): w_r -= sum over
+// the blocks b of the super-block of L(r, b) z_b (z from Y).  Tiles start at
+// s1 rounded down to a multiple of 4 (aligned vector loads of L); rows before
+// s1 are not written.
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_srows(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x;
     int m = a.mfront[f], p = a.pfront[f], k = a.k, f0 = a.first[f], ld = front_ld(m);
     int s1 = min(p, s0 + SS);
-    int r0 = s1 + t.y * SB, r1 = min(m, r0 + SB);
+    int r0 = (s1 & ~3) + t.y * SB, r1 = min(m, r0 + SB);
     const T *L = a.fronts + a.front_off[f];
     T *w = a.W + a.woff[f] * k;
     for (int c0 = 0; c0 < k; c0 += KT) {
         if constexpr (KT == 64) {
             // wave q takes the pivot columns [s0 + 64 q, s0 + 64 q + 64) of the super-block
+            typedef typename Vec4<T>::type V4;
             __shared__ MmLds<T> mm;
-            int wave = threadIdx.x / 64;
+            int wave = threadIdx.x / 64, lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+            bool quad = (k & 3) == 0;   // rows of Y are then vector-aligned
             typename Mfma<T>::V acc[4][4];
 #pragma unroll
             for (int x = 0; x < 4; x++)
@@ -703,20 +850,40 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_srows(c
 #pragma unroll
                     for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
             int kb = s0 + wave * SB;
-            if (kb < s1)
-                wave_mm<T>(
-                    acc, kb, min(s1, kb + SB),
-                    [&](int r, int kk) { return r0 + r < r1 ? L[(int64_t)kk * ld + r0 + r] : (T)0; },
-                    [&](int kk, int c) { return c0 + c < k ? a.Y[(int64_t)(f0 + kk) * k + c0 + c] : (T)0; });
-            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *v, int cb) {
+            if (kb < s1) {
+                if (quad)
+                    wave_mm_q<T>(
+                        acc, kb, min(s1, kb + SB),
+                        [&](int q, int kk) {
+                            int r = r0 + 4 * q;
+                            return r < r1 ? *reinterpret_cast<const V4 *>(L + (int64_t)kk * ld + r) : V4{0, 0, 0, 0};
+                        },
+                        [&](int kk, int q) {
+                            int c = c0 + 4 * q;
+                            return c < k ? *reinterpret_cast<const V4 *>(a.Y + (int64_t)(f0 + kk) * k + c)
+                                         : V4{0, 0, 0, 0};
+                        });
+                else
+                    wave_mm<T>(
+                        acc, kb, min(s1, kb + SB),
+                        [&](int r, int kk) { return r0 + r < r1 ? L[(int64_t)kk * ld + r0 + r] : (T)0; },
+                        [&](int kk, int c) { return c0 + c < k ? a.Y[(int64_t)(f0 + kk) * k + c0 + c] : (T)0; });
+            }
+            auto out = [&](int *rr, int *cc, T *v, int cb) {
                 sub_batch<8>(
                     w,
                     [&](int q) -> int64_t {
                         int r = r0 + rr[q], c = cb + cc[q];
-                        return (r < r1 && c0 + c < k) ? (int64_t)r * k + c0 + c : -1;
+                        return (r >= s1 && r < r1 && c0 + c < k) ? (int64_t)r * k + c0 + c : -1;
                     },
                     [&](int q) { return v[q]; });
-            });
+            };
+            if (quad)
+                reduce4m<T>(
+                    acc, mm.red,
+                    [&](int x, int y, int e) { return make_int2(4 * Mfma<T>::row(kq, e) + x, 4 * ln + y); }, out);
+            else
+                reduce4<T>(acc, mm.red, out);
         } else {
             __shared__ T Zs[SB][KT];
             for (int kb = s0; kb < s1; kb += SB) {
@@ -727,7 +894,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_srows(c
                     Zs[j][c] = (j < nbk && c0 + c < k) ? a.Y[(int64_t)(f0 + kb + j) * k + c0 + c] : (T)0;
                 }
                 __syncthreads();
-                fwd_rows<T, KT>(L, ld, kb, nbk, w, k, c0, r0, r1, Zs);
+                fwd_rows<T, KT>(L, ld, kb, nbk, w, k, c0, max(r0, s1), r1, Zs);
             }
         }
     }
@@ -735,7 +902,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_fwd_srows(c
 
 // backward, task = (front, block j of the super-block at s0): x_j = sum_{i >= j} X_ij^T v_i -> Y
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_sx(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_sx(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x, jb = t.y;
@@ -747,8 +914,10 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_sx(cons
     const T *w = a.W + a.woff[f] * k;
     if constexpr (KT == 64) {
         // wave q adds X_ij^T v_i for block i = j + q
+        typedef typename Vec4<T>::type V4;
         __shared__ MmLds<T> mm;
-        int wave = threadIdx.x / 64;
+        int wave = threadIdx.x / 64, lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+        bool quad = (k & 3) == 0;
         for (int c0 = 0; c0 < k; c0 += 64) {
             typename Mfma<T>::V acc[4][4];
 #pragma unroll
@@ -760,18 +929,37 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_sx(cons
             int ib = jb + wave;
             if (ib < nblk) {
                 int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
-                wave_mm<T>(
-                    acc, 0, ni,
-                    [&](int r, int kk) { return r < nj ? X[(int64_t)(j0 - s0 + r) * SS + (i0 - s0 + kk)] : (T)0; },
-                    [&](int kk, int c) { return c0 + c < k ? w[(int64_t)(i0 + kk) * k + c0 + c] : (T)0; });
+                if (quad)   // X_ij^T: the contraction runs down a column of X (four per load)
+                    wave_mm_kq<T>(
+                        acc, 0, 0, ni,
+                        [&](int r, int k4) {
+                            return r < nj ? *reinterpret_cast<const V4 *>(X + (int64_t)(j0 - s0 + r) * SS + (i0 - s0) + k4)
+                                          : V4{0, 0, 0, 0};
+                        },
+                        [&](int kk, int q) {
+                            int c = c0 + 4 * q;
+                            return c < k ? *reinterpret_cast<const V4 *>(w + (int64_t)(i0 + kk) * k + c)
+                                         : V4{0, 0, 0, 0};
+                        });
+                else
+                    wave_mm<T>(
+                        acc, 0, ni,
+                        [&](int r, int kk) { return r < nj ? X[(int64_t)(j0 - s0 + r) * SS + (i0 - s0 + kk)] : (T)0; },
+                        [&](int kk, int c) { return c0 + c < k ? w[(int64_t)(i0 + kk) * k + c0 + c] : (T)0; });
             }
-            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *v, int cb) {
+            auto put = [&](int *rr, int *cc, T *v, int cb) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
                     int r = rr[q], c = cb + cc[q];
                     if (r < nj && c0 + c < k) a.Y[(int64_t)(f0 + j0 + r) * k + c0 + c] = v[q];
                 }
-            });
+            };
+            if (quad)
+                reduce4m<T>(
+                    acc, mm.red,
+                    [&](int x, int y, int e) { return make_int2(16 * x + Mfma<T>::row(kq, e), 4 * ln + y); }, put);
+            else
+                reduce4<T>(acc, mm.red, put);
         }
         return;
     }
@@ -800,7 +988,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_sx(cons
 // backward, task = (front, column block a) with 64 a < s0: v_a -= L([s0, s1), a)^T x_[s0, s1)
 // (x read from Y); each workgroup owns its block a
 template <typename T, int KT>
-__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_scols(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_scols(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
 {
     int2 t = tasks[blockIdx.x];
     int f = t.x;
@@ -812,8 +1000,10 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_scols(c
     const T *Y = a.Y;
     if constexpr (KT == 64) {
         // out^T(n, c) = sum_r x_r[n] L(r, ab + c); wave q takes the rows [s0 + 64 q, s0 + 64 q + 64)
+        typedef typename Vec4<T>::type V4;
         __shared__ MmLds<T> mm;
-        int wave = threadIdx.x / 64, ld = front_ld(m);
+        int wave = threadIdx.x / 64, lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16, ld = front_ld(m);
+        bool quad = (k & 3) == 0;
         for (int c0 = 0; c0 < k; c0 += 64) {
             typename Mfma<T>::V acc[4][4];
 #pragma unroll
@@ -823,13 +1013,24 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_scols(c
 #pragma unroll
                     for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
             int rb = s0 + wave * SB;
-            if (rb < s1)
-                wave_mm<T>(
-                    acc, rb, min(s1, rb + SB),
-                    [&](int n, int r) { return c0 + n < k ? Y[(int64_t)(f0 + r) * k + c0 + n] : (T)0; },
-                    [&](int r, int c) { return L[(int64_t)(ab + c) * ld + r]; });
+            if (rb < s1) {
+                if (quad)   // product rows: the block's columns c (four rows r per load of L)
+                    wave_mm_kq<T>(
+                        acc, rb, rb, min(s1, rb + SB),
+                        [&](int c, int r4) { return *reinterpret_cast<const V4 *>(L + (int64_t)(ab + c) * ld + r4); },
+                        [&](int r, int q) {
+                            int n = c0 + 4 * q;
+                            return n < k ? *reinterpret_cast<const V4 *>(Y + (int64_t)(f0 + r) * k + n)
+                                         : V4{0, 0, 0, 0};
+                        });
+                else
+                    wave_mm<T>(
+                        acc, rb, min(s1, rb + SB),
+                        [&](int n, int r) { return c0 + n < k ? Y[(int64_t)(f0 + r) * k + c0 + n] : (T)0; },
+                        [&](int r, int c) { return L[(int64_t)(ab + c) * ld + r]; });
+            }
             T *v = w + (int64_t)ab * k;
-            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+            auto put = [&](int *rr, int *cc, T *val, int cb) {
                 sub_batch<8>(
                     v,
                     [&](int q) -> int64_t {
@@ -837,7 +1038,13 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 2) void k_bwd_scols(c
                         return c0 + n < k ? (int64_t)c * k + c0 + n : -1;
                     },
                     [&](int q) { return val[q]; });
-            });
+            };
+            if (quad)
+                reduce4m<T>(
+                    acc, mm.red,
+                    [&](int x, int y, int e) { return make_int2(4 * ln + y, 16 * x + Mfma<T>::row(kq, e)); }, put);
+            else
+                reduce4<T>(acc, mm.red, put);
         }
         return;
     }
@@ -862,10 +1069,13 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restri
     const int32_t *rw = a.rows + a.rptr[f];
     const T *Y = a.Y;
     if constexpr (KT == 64) {
-        // part^T(n, c) = -sum_r x(rows[r])[n] L(r, ab + c); wave q takes a quarter of the rows
+        // part^T(n, c) = -sum_r x(rows[r])[n] L(r, ab + c) over the rows r >= p of
+        // the slab (it starts at a multiple of 4); wave q takes a quarter of them
+        typedef typename Vec4<T>::type V4;
         __shared__ MmLds<T> mm;
         constexpr int RW = BELOW_ROWS / 4;
-        int wave = threadIdx.x / 64, ld = front_ld(m);
+        int wave = threadIdx.x / 64, lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16, ld = front_ld(m);
+        bool quad = (k & 3) == 0;
         for (int c0 = 0; c0 < k; c0 += 64) {
             typename Mfma<T>::V acc[4][4];
 #pragma unroll
@@ -875,18 +1085,37 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restri
 #pragma unroll
                     for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
             int rb = r0 + wave * RW;
-            if (rb < r1)
-                wave_mm<T>(
-                    acc, rb, min(r1, rb + RW),
-                    [&](int n, int r) { return c0 + n < k ? Y[(int64_t)rw[r] * k + c0 + n] : (T)0; },
-                    [&](int r, int c) { return c < na ? L[(int64_t)(ab + c) * ld + r] : (T)0; });
-            reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+            if (rb < r1) {
+                if (quad)   // product rows: pivot columns c (four rows r per load); columns: right-hand sides
+                    wave_mm_kq<T>(
+                        acc, p, rb, min(r1, rb + RW),
+                        [&](int c, int r4) {
+                            return c < na ? *reinterpret_cast<const V4 *>(L + (int64_t)(ab + c) * ld + r4)
+                                          : V4{0, 0, 0, 0};
+                        },
+                        [&](int r, int q) {
+                            int n = c0 + 4 * q;
+                            return n < k ? *reinterpret_cast<const V4 *>(Y + (int64_t)rw[r] * k + n) : V4{0, 0, 0, 0};
+                        });
+                else
+                    wave_mm<T>(
+                        acc, max(rb, p), min(r1, rb + RW),
+                        [&](int n, int r) { return c0 + n < k ? Y[(int64_t)rw[r] * k + c0 + n] : (T)0; },
+                        [&](int r, int c) { return c < na ? L[(int64_t)(ab + c) * ld + r] : (T)0; });
+            }
+            auto put = [&](int *rr, int *cc, T *val, int cb) {
 #pragma unroll
                 for (int q = 0; q < 8; q++) {
                     int n = rr[q], c = cb + cc[q];
                     if (c0 + n < k) out[(int64_t)c * k + c0 + n] = -val[q];
                 }
-            });
+            };
+            if (quad)
+                reduce4m<T>(
+                    acc, mm.red,
+                    [&](int x, int y, int e) { return make_int2(4 * ln + y, 16 * x + Mfma<T>::row(kq, e)); }, put);
+            else
+                reduce4<T>(acc, mm.red, put);
         }
         return;
     }
@@ -894,7 +1123,7 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restri
     for (int64_t i = threadIdx.x; i < (int64_t)SB * k; i += blockDim.x) out[i] = (T)0;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
-        bwd_cols_any<T, KT>(L, front_ld(m), ab, na, r0, r1, xrow, k, c0, out, sh.Ls, sh.Ss);
+        bwd_cols_any<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
 }
 
 // task = (front, column block a, first slot, slots): v_a = y_a + sum of the partial blocks (in slot order)
