@@ -842,6 +842,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows(c
             __shared__ MmLds<T> mm;
             int wave = threadIdx.x / 64, lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
             bool quad = (k & 3) == 0;   // rows of Y are then vector-aligned
+            constexpr int kc = SB;
             typename Mfma<T>::V acc[4][4];
 #pragma unroll
             for (int x = 0; x < 4; x++)
@@ -849,11 +850,11 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows(c
                 for (int y = 0; y < 4; y++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
-            int kb = s0 + wave * SB;
+            int kb = s0 + wave * kc;
             if (kb < s1) {
                 if (quad)
                     wave_mm_q<T>(
-                        acc, kb, min(s1, kb + SB),
+                        acc, kb, min(s1, kb + kc),
                         [&](int q, int kk) {
                             int r = r0 + 4 * q;
                             return r < r1 ? *reinterpret_cast<const V4 *>(L + (int64_t)kk * ld + r) : V4{0, 0, 0, 0};
@@ -865,7 +866,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows(c
                         });
                 else
                     wave_mm<T>(
-                        acc, kb, min(s1, kb + SB),
+                        acc, kb, min(s1, kb + kc),
                         [&](int r, int kk) { return r0 + r < r1 ? L[(int64_t)kk * ld + r0 + r] : (T)0; },
                         [&](int kk, int c) { return c0 + c < k ? a.Y[(int64_t)(f0 + kk) * k + c0 + c] : (T)0; });
             }
@@ -1004,6 +1005,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_scols(c
         __shared__ MmLds<T> mm;
         int wave = threadIdx.x / 64, lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16, ld = front_ld(m);
         bool quad = (k & 3) == 0;
+        constexpr int kc = SB;
         for (int c0 = 0; c0 < k; c0 += 64) {
             typename Mfma<T>::V acc[4][4];
 #pragma unroll
@@ -1012,11 +1014,11 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_scols(c
                 for (int y = 0; y < 4; y++)
 #pragma unroll
                     for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
-            int rb = s0 + wave * SB;
+            int rb = s0 + wave * kc;
             if (rb < s1) {
                 if (quad)   // product rows: the block's columns c (four rows r per load of L)
                     wave_mm_kq<T>(
-                        acc, rb, rb, min(s1, rb + SB),
+                        acc, rb, rb, min(s1, rb + kc),
                         [&](int c, int r4) { return *reinterpret_cast<const V4 *>(L + (int64_t)(ab + c) * ld + r4); },
                         [&](int r, int q) {
                             int n = c0 + 4 * q;
@@ -1025,7 +1027,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_scols(c
                         });
                 else
                     wave_mm<T>(
-                        acc, rb, min(s1, rb + SB),
+                        acc, rb, min(s1, rb + kc),
                         [&](int n, int r) { return c0 + n < k ? Y[(int64_t)(f0 + r) * k + c0 + n] : (T)0; },
                         [&](int r, int c) { return L[(int64_t)(ab + c) * ld + r]; });
             }
@@ -1136,7 +1138,23 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_sum(const int4 *__restric
     int na = min(SB, p - ab);
     T *w = a.W + a.woff[f] * k + (int64_t)ab * k;
     const T *y = a.Y + (int64_t)(f0 + ab) * k;
-    for (int64_t i = threadIdx.x; i < (int64_t)na * k; i += blockDim.x) {
+    int64_t tot = (int64_t)na * k;
+    if ((k & 3) == 0) {     // four consecutive elements per thread (vector accesses)
+        typedef typename Vec4<T>::type V4;
+        for (int64_t i = 4 * (int64_t)threadIdx.x; i < tot; i += 4 * (int64_t)blockDim.x) {
+            V4 s = *reinterpret_cast<const V4 *>(y + i);
+            for (int q = 0; q < t.w; q++) {
+                V4 v = *reinterpret_cast<const V4 *>(a.part + (int64_t)(t.z + q) * SB * k + i);
+                s.x += v.x;
+                s.y += v.y;
+                s.z += v.z;
+                s.w += v.w;
+            }
+            *reinterpret_cast<V4 *>(w + i) = s;
+        }
+        return;
+    }
+    for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) {
         T s = y[i];
         for (int q = 0; q < t.w; q++) s += a.part[(int64_t)(t.z + q) * SB * k + i];
         w[i] = s;
