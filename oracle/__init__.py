@@ -19,4 +19,5 @@ from .oracle import (  # noqa: F401
     check_perm,
     Factor,
     factorize,
+    theta_steps,
 )

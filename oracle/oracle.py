@@ -212,6 +212,31 @@ class Factor:
         return L
 
 
+def theta_steps(m: dict, perm: np.ndarray, theta: float, dt: float, F: np.ndarray, u0: np.ndarray) -> np.ndarray:
+    """Theta scheme in time (Section 5, eq:theta) for G = I (L2-orthonormal
+    wavelets) and L = -K, K = the symmetric positive definite matrix m:
+    (I + theta dt K) u_{i+1} = (I - (1 - theta) dt K) u_i + dt ((1 - theta) f_i + theta f_{i+1}).
+    The left matrix is factored once (oracle Cholesky, ordering perm); the
+    explicit part applies K itself.  F: n x (nsteps + 1); returns U: n x (nsteps + 1)
+    with U[:, 0] = u0.  Plain NumPy around the C oracle's factor, solve and symv."""
+    n = m["n"]
+    colptr, rowind, kv = m["colptr"], m["rowind"], np.asarray(m["values"], np.float64)
+    diag = np.asarray(colptr[:-1], np.int64)
+    if not np.array_equal(np.asarray(rowind)[diag], np.arange(n)):
+        raise ValueError("theta_steps: the first stored entry of every column must be its diagonal")
+    av = theta * dt * kv
+    av[diag] += 1.0
+    fac = factorize(dict(m, values=av), perm)
+    nsteps = F.shape[1] - 1
+    U = np.empty((n, nsteps + 1))
+    U[:, 0] = u0
+    for i in range(nsteps):
+        u = U[:, i]
+        rhs = u - (1.0 - theta) * dt * symv(n, colptr, rowind, kv, u) + dt * ((1.0 - theta) * F[:, i] + theta * F[:, i + 1])
+        U[:, i + 1] = fac.solve(rhs)
+    return U
+
+
 def factorize(m: dict, perm: np.ndarray) -> Factor:
     """Symbolic + pattern + numeric factor of one instance (dict from the workload generator)."""
     n = m["n"]

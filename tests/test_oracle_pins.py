@@ -373,3 +373,78 @@ def test_factor_products_against_dense(part):
     else:
         ref = L.T @ B[perm]
     assert np.abs(X - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+# ---- theta scheme (Section 5, eq:theta with G = I, L = -K)
+
+def _theta_case(G=3, scale=None):
+    m = tiny(G, 1.5).matrix()
+    if scale is not None:        # rescale K so that its largest eigenvalue is `scale`
+        lmax = np.linalg.eigvalsh(dense_from_lower(m)).max()
+        m = dict(m, values=m["values"] * (scale / lmax))
+    return m, perms(m["n"], 2)
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.75, 1.0])
+def test_theta_eigenmode_amplification(theta):
+    """An eigenvector v of K (K v = lambda v) without forcing decays by the
+    closed-form factor rho = (1 - (1 - theta) dt lambda) / (1 + theta dt lambda)
+    per step (eigenpairs from a library dense eigensolver)."""
+    m, perm = _theta_case()
+    n = m["n"]
+    lam, V = np.linalg.eigh(dense_from_lower(m))
+    dt, nsteps = 0.02, 12
+    F = np.zeros((n, nsteps + 1))
+    for q in (0, n // 2, n - 1):
+        U = oracle.theta_steps(m, perm, theta, dt, F, V[:, q])
+        rho = (1 - (1 - theta) * dt * lam[q]) / (1 + theta * dt * lam[q])
+        ref = V[:, q][:, None] * rho ** np.arange(nsteps + 1)[None, :]
+        assert np.abs(U - ref).max() <= 1e-12, (theta, q)
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0])
+def test_theta_steady_state_is_fixed_point(theta):
+    """With constant forcing f the stationary solution u = K^-1 f (library dense
+    solve) is reproduced by every step."""
+    m, perm = _theta_case()
+    n = m["n"]
+    f = np.random.default_rng(3).standard_normal(n)
+    u = np.linalg.solve(dense_from_lower(m), f)
+    U = oracle.theta_steps(m, perm, theta, 0.05, np.repeat(f[:, None], 9, axis=1), u)
+    assert np.abs(U - u[:, None]).max() <= 1e-12 * np.abs(u).max()
+
+
+@pytest.mark.parametrize("theta", [0.5, 0.75])
+def test_theta_forcing_weights(theta):
+    """From u_0 = 0 a unit impulse of f at t_0 gives u_1 = (1 - theta) dt A^-1 g and
+    one at t_1 gives theta dt A^-1 g, A = I + theta dt K (library dense solve):
+    the trapezoid-type weights of the forcing."""
+    m, perm = _theta_case()
+    n = m["n"]
+    dt = 0.1
+    g = np.random.default_rng(5).standard_normal(n)
+    Ainv_g = np.linalg.solve(np.eye(n) + theta * dt * dense_from_lower(m), g)
+    for i, wgt in ((0, 1 - theta), (1, theta)):
+        F = np.zeros((n, 2))
+        F[:, i] = g
+        U = oracle.theta_steps(m, perm, theta, dt, F, np.zeros(n))
+        assert np.abs(U[:, 1] - wgt * dt * Ainv_g).max() <= 1e-13 * np.abs(Ainv_g).max()
+
+
+def test_crank_nicolson_is_second_order():
+    """theta = 1/2 converges at second order to the exact flow exp(-t K) u_0
+    (library matrix exponential): halving dt divides the error at T = 1 by 4
+    (K scaled so that dt lambda <= 1/4, the asymptotic regime); theta = 1 is
+    first order (ratio 2)."""
+    from scipy.linalg import expm
+    m, perm = _theta_case(scale=5.0)
+    n = m["n"]
+    u0 = np.random.default_rng(9).standard_normal(n)
+    exact = expm(-dense_from_lower(m)) @ u0
+    for theta, order in ((0.5, 4.0), (1.0, 2.0)):
+        err = []
+        for nsteps in (20, 40, 80):
+            U = oracle.theta_steps(m, perm, theta, 1.0 / nsteps, np.zeros((n, nsteps + 1)), u0)
+            err.append(np.abs(U[:, -1] - exact).max())
+        r1, r2 = err[0] / err[1], err[1] / err[2]
+        assert abs(r1 - order) <= 0.1 * order and abs(r2 - order) <= 0.1 * order, (theta, err)

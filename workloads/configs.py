@@ -13,7 +13,7 @@ from typing import Dict, List
 
 import numpy as np
 
-from .wavelet import WaveletSpec, make_matrix, normal_rhs
+from .wavelet import WaveletSpec, centers, make_matrix, normal_rhs
 
 
 @dataclasses.dataclass(frozen=True)
@@ -52,6 +52,32 @@ def headline() -> Workload:
 def random_field() -> Workload:
     """Same operator class as the headline case with its own seed, one RHS."""
     return Workload("haar512_n262144_grf", WaveletSpec(9, 2.0, 0.75, "alg", 0.3, 1.75, 5000), 1, 5000)
+
+
+def theta_scheme() -> Workload:
+    """Time-stepping case (Section 6, parabolic problem for the fractional
+    Laplacian): s = 3/8 on the 512x512 Haar grid, one trajectory.  The steps
+    use THETA, T_END and NSTEPS below and heat_spot_forcing for f."""
+    return Workload("haar512_n262144_s0375_cn", WaveletSpec(9, 2.0, 0.375, "alg", 0.3, 1.75, 6000), 1, 6000)
+
+
+THETA, T_END, NSTEPS = 0.5, 3.0, 150      # Crank-Nicolson, [0, 3], 150 equidistant steps
+
+
+def heat_spot_forcing(spec: WaveletSpec, times: np.ndarray) -> np.ndarray:
+    """n x len(times) load vectors of a Gaussian heat spot moving on a circle,
+    f(x, t) = 100 exp(-40 (x1 - r cos 2 pi t)^2 - 40 (x2 - r sin 2 pi t)^2),
+    stand-in for the paper's right-hand side: the grid [0,1]^2 is mapped to
+    [-1,1]^2 (the paper's domain is a disc), the circle has radius r = 1/2 so
+    the spot stays inside, and the coefficient of a wavelet of level j with
+    support centre c is 2^-j f(c, t)."""
+    c, level = centers(spec.grid_exp)
+    x = 2.0 * c - 1.0
+    w = 2.0 ** (-level.astype(np.float64))
+    t = np.asarray(times, np.float64)
+    px, py = 0.5 * np.cos(2 * np.pi * t), 0.5 * np.sin(2 * np.pi * t)
+    d2 = (x[:, 0:1] - px[None, :]) ** 2 + (x[:, 1:2] - py[None, :]) ** 2
+    return w[:, None] * 100.0 * np.exp(-40.0 * d2)
 
 
 def tiny(grid_exp: int, a: float = 1.5, s: float = 0.5, seed: int = 7) -> Workload:
