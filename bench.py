@@ -204,12 +204,79 @@ def bench_batch(args) -> int:
     return 0
 
 
+def bench_theta(args) -> int:
+    """Time stepping over one factor (Section 6, parabolic problem): A = I +
+    theta dt K with theta = 1/2 (Crank-Nicolson), 150 steps over [0, 3] of the
+    moving heat-spot forcing, one trajectory, N = 262144, s = 3/8.  A step of
+    this line is one whole trajectory (150 SpMVs + 150 solves) with A factored
+    beforehand (its factorization is reported beside).  The FP64 factor (as in
+    the paper) gives the value; the FP32 factor with every step refined to the
+    tolerance is reported beside it."""
+    import numpy as np
+    import torch
+    import workloads
+    from workloads import NSTEPS, T_END, THETA
+    from paper_2007_01541_amd import FP32, FP64, Factor, Symbolic
+    w = workloads.theta_scheme()
+    t0 = time.perf_counter()
+    m = w.matrix()
+    n = m["n"]
+    F = workloads.heat_spot_forcing(w.spec, np.linspace(0.0, T_END, NSTEPS + 1))
+    log(f"{w.name}: generated in {time.perf_counter() - t0:.1f}s, nnz_lower={m['colptr'][-1]}")
+    t0 = time.perf_counter()
+    sym = Symbolic(n, m["colptr"], m["rowind"], coords=m["coords"])
+    t_an = time.perf_counter() - t0
+    info = sym.info
+    dt = T_END / NSTEPS
+    kv = torch.as_tensor(m["values"], device="cuda")
+    Fd = torch.as_tensor(F, device="cuda")
+    u0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    res = {}
+    for prec, nm in ((FP64, "fp64"), (FP32, "fp32_ir")):
+        f = Factor(sym, prec)
+        A = f.theta_matrix(kv, THETA, dt)
+        f.numeric(A)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        f.numeric(A, check_pivots=False)
+        e1.record()
+        torch.cuda.synchronize()
+        fact_ms = e0.elapsed_time(e1)
+        for _ in range(args.warmup):
+            f.theta_steps(A, THETA, dt, Fd, u0, tol=args.tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            U, rep_ = f.theta_steps(A, THETA, dt, Fd, u0, tol=args.tol)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        res[nm] = {"trajectory_ms": t * 1e3, "ms_per_time_step": t * 1e3 / NSTEPS, "factor_ms": fact_ms,
+                   "report": rep_, "u_final_norm": float(torch.linalg.norm(U[:, -1]))}
+        log(f"  {nm}: factor {fact_ms:.2f} ms, {NSTEPS} steps in {t * 1e3:.1f} ms "
+            f"({t * 1e3 / NSTEPS:.3f} ms per step), report {rep_}")
+        del f, A
+        torch.cuda.empty_cache()
+    out = {
+        "metric": "theta-scheme time steps/s (150 Crank-Nicolson steps over one FP64 factor, one trajectory)",
+        "value": NSTEPS / (res["fp64"]["trajectory_ms"] / 1e3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["fp64"]["trajectory_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "nnz_lower": int(m["colptr"][-1]), "nnz_l": int(info["nnz_l"]),
+                   "theta": THETA, "t_end": T_END, "time_steps": NSTEPS, "analyze_s": round(t_an, 2)},
+        "fp64": res["fp64"], "fp32_ir": res["fp32_ir"], "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batch"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batch", "theta"])
     ap.add_argument("--instances", type=int, default=256, help="batch workload: number of instances")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -227,6 +294,8 @@ def main() -> int:
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "theta":
+        return bench_theta(args)
 
     import numpy as np
     import torch

@@ -334,6 +334,38 @@ int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double 
              int64_t ld, wcs_stream stream);
 
 /*
+ * Theta scheme in time (Section 5, eq:theta): G (u_{i+1} - u_i) / dt - L ((1 - theta) u_i
+ * + theta u_{i+1}) = (1 - theta) f_i + theta f_{i+1}, taken in an L2-orthonormal
+ * wavelet basis (mass matrix G = I) with L = -K for a symmetric positive definite
+ * operator matrix K.  The matrix of every step is A = I + theta dt K; theta = 1/2
+ * is Crank-Nicolson.
+ *
+ * wcs_theta_matrix: A_values_dev[e] = theta dt K_values_dev[e], plus 1 on the
+ * diagonal entries, for the stored lower pattern of the factor's analysis
+ * (device FP64 arrays of nnz_lower entries; A_values_dev may be K_values_dev).
+ * Factor A with wcs_factor_numeric before the steps.  Errors: WCS_EINVAL for
+ * theta outside (0, 1], dt <= 0 or null pointers.  Asynchronous on the stream.
+ *
+ * wcs_theta_steps: nsteps steps over the factor of A; A_values_dev are the values
+ * it was factored from.  F_dev: f at the nsteps + 1 times, n x (nsteps + 1)
+ * column-major with leading dimension ldf >= n.  U_dev: n x (nsteps + 1)
+ * column-major with leading dimension ldu >= n; column 0 holds u_0 on entry,
+ * columns 1..nsteps receive u_1..u_nsteps.  Each step forms the explicit part
+ * from A as (u_i - (1 - theta) A u_i) / theta (one SpMV) and solves once with
+ * the factor (FP64), or refines that solve to tol against A (FP32 factors, at most
+ * ten corrections per step; *rep gets the largest iteration count, raw and
+ * final residual over the steps; FP64 factors report 0 and -1).  Synchronous
+ * per refinement step for FP32 factors, else asynchronous.  Errors: WCS_EINVAL
+ * (bad arguments), WCS_ESTATE (no numeric factorization), WCS_ENOTCONV (a step
+ * missed tol; U holds the steps before it).
+ */
+int wcs_theta_matrix(wcs_factor f, const double *K_values_dev, double theta, double dt, double *A_values_dev,
+                     wcs_stream stream);
+int wcs_theta_steps(wcs_factor f, const double *A_values_dev, double theta, double dt, int32_t nsteps,
+                    const double *F_dev, int64_t ldf, double *U_dev, int64_t ldu, double tol, wcs_ir_report *rep,
+                    wcs_stream stream);
+
+/*
  * Gradient of a scalar loss through x = A^-1 b with respect to the stored
  * lower entries of A, given lam = A^-1 (dloss/dx): entry (i,j), i > j, gets
  * -(lam_i x_j + lam_j x_i); a diagonal entry gets -lam_i x_i.  Device arrays:

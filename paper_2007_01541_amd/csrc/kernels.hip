@@ -1345,6 +1345,32 @@ __global__ void k_inv_scale(double *__restrict__ amax, int k, double *__restrict
     amax[c] = ldexp(1.0, e);       // its inverse, for the residual update
 }
 
+// ---------------------------------------------------------------- theta scheme
+// Time stepping of G u' = L u + f with the theta scheme (Section 5, eq:theta)
+// in an L2-orthonormal wavelet basis (G = I) and L = -K, K the symmetric
+// positive definite operator matrix: A = I + theta dt K is factored once.
+
+// A = I + c K on the stored lower pattern, c = theta dt (entry e at (rowind[e], colof[e]))
+__global__ void k_theta_matrix(const int32_t *__restrict__ rowind, const int32_t *__restrict__ colof, int64_t nnz,
+                               const double *K, double c, double *A)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        A[e] = c * K[e] + (rowind[e] == colof[e] ? 1.0 : 0.0);
+}
+
+// Right-hand side of one step in pivot order from AU = A u:
+// (I - (1 - theta) dt K) u = (u - (1 - theta) A u) / theta, plus the forcing
+// dt ((1 - theta) f_i + theta f_{i+1}) read through the permutation
+__global__ void k_theta_rhs(const double *__restrict__ U, const double *__restrict__ AU,
+                            const double *__restrict__ F0, const double *__restrict__ F1,
+                            const int32_t *__restrict__ perm, int n, double theta, double dt, double *__restrict__ B)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int o = perm[i];
+        B[i] = (U[i] - (1.0 - theta) * AU[i]) / theta + dt * ((1.0 - theta) * F0[o] + theta * F1[o]);
+    }
+}
+
 // ---------------------------------------------------------------- gradient
 // gA[e] for stored entry e = (i, j): -(lam_i x_j + lam_j x_i), or -lam_i x_i on the diagonal
 __global__ void k_grad_pattern(const int32_t *__restrict__ rowind, const int32_t *__restrict__ colof, int64_t nnz,

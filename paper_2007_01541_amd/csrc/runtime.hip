@@ -1061,14 +1061,14 @@ void launch_colred(wcs_factor f, const double *A, int n, int k, int op, bool seg
 // Bp - C Xp up to the FP64 rounding of the sums Xp + D.  For a batch the test
 // is per instance and column (each block of the block-diagonal matrix is its
 // own system).
+// The loop itself: Bp (row-major n x k, pivot order) holds P B, the matrix
+// values are expanded; leaves P X in Xp and the residuals in f->last_rel.
 template <typename T>
-int solve_refined(wcs_factor f, const double *values, int k, const double *B, double *X, int64_t ld, double tol,
-                  int max_iter, wcs_ir_report *rep, hipStream_t st)
+int refine_pivot(wcs_factor f, int k, double tol, int max_iter, wcs_ir_report *rep, hipStream_t st)
 {
     const Layout &Lo = f->lay;
     int n = f->S->n;
-    int rc = ensure_csr_values(f, values, st);
-    if (rc) return rc;
+    int rc = WCS_OK;
     double *Bp = f->at<double>(Lo.Br);      // row-major n x k, pivot order
     double *Xp = f->at<double>(Lo.Xr);
     double *Rp = f->at<double>(Lo.Rr);
@@ -1079,9 +1079,7 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     // FP32 factor: residual from the FP32 rows of the solves (see above)
     const bool from_y = sizeof(T) == 4 && spmv_vec_fits<float>(k);
     T *Y = f->at<T>(Lo.Y);
-    const int32_t *perm = f->at<int32_t>(Lo.perm);
     int64_t nk = (int64_t)n * k;
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k, Bp);
     launch_colred(f, Bp, n, k, 0, true, vec, st);
     hipLaunchKernelGGL(k_cast_scaled<T>, dim3(grid_for(nk)), dim3(256), 0, st, Bp, nk, k, (const double *)nullptr, Y);
     rc = run_sweeps<T>(f, WCS_SOLVE_FULL, k, st);
@@ -1128,11 +1126,82 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
                            (const double *)scale, 1, Xp);
         rep->iterations = it + 1;
     }
-    hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, Xp, perm, n, k, X, ld);
+    HIP_TRY(hipGetLastError());
+    return status;
+}
+
+template <typename T>
+int solve_refined(wcs_factor f, const double *values, int k, const double *B, double *X, int64_t ld, double tol,
+                  int max_iter, wcs_ir_report *rep, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    int n = f->S->n;
+    int rc = ensure_csr_values(f, values, st);
+    if (rc) return rc;
+    const int32_t *perm = f->at<int32_t>(Lo.perm);
+    int64_t nk = (int64_t)n * k;
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k,
+                       f->at<double>(Lo.Br));
+    int status = refine_pivot<T>(f, k, tol, max_iter, rep, st);
+    if (status != WCS_OK && status != WCS_ENOTCONV) return status;
+    hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, f->at<double>(Lo.Xr), perm, n, k, X,
+                       ld);
     HIP_TRY(hipGetLastError());
     if (status != WCS_OK)
         set_error("iterative refinement stopped at relative residual " + std::to_string(rep->final_residual));
     return status;
+}
+
+// Theta scheme (Section 5, eq:theta with G = I, L = -K): u_{i+1} = A^-1
+// ((u_i - (1 - theta) A u_i) / theta + dt ((1 - theta) f_i + theta f_{i+1}))
+// for the factored A = I + theta dt K, in pivot order throughout; an FP64
+// factor solves each step directly, an FP32 factor refines each step to tol
+// against A.  Column 0 of U is u_0; columns 1..nsteps are written.
+template <typename T>
+int theta_steps(wcs_factor f, const double *A_values, double theta, double dt, int nsteps, const double *F,
+                int64_t ldf, double *U, int64_t ldu, double tol, wcs_ir_report *rep, hipStream_t st)
+{
+    const Layout &Lo = f->lay;
+    int n = f->S->n;
+    int rc = ensure_csr_values(f, A_values, st);
+    if (rc) return rc;
+    double *Bp = f->at<double>(Lo.Br), *Xp = f->at<double>(Lo.Xr), *AU = f->at<double>(Lo.Rr);
+    const int32_t *perm = f->at<int32_t>(Lo.perm);
+    T *Y = f->at<T>(Lo.Y);
+    unsigned g = grid_for(n);
+    hipLaunchKernelGGL(k_gather_rows, dim3(g), dim3(256), 0, st, U, ldu, perm, n, 1, Xp);
+    rep->iterations = 0;
+    rep->raw_residual = -1;
+    rep->final_residual = -1;
+    for (int i = 0; i < nsteps; i++) {
+        rc = launch_spmv(f, 1, Xp, nullptr, AU, 1, 1, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_theta_rhs, dim3(g), dim3(256), 0, st, Xp, AU, F + (int64_t)i * ldf,
+                           F + (int64_t)(i + 1) * ldf, perm, n, theta, dt, Bp);
+        if constexpr (sizeof(T) == 8) {
+            hipLaunchKernelGGL(k_cast_scaled<T>, dim3(g), dim3(256), 0, st, Bp, (int64_t)n, 1,
+                               (const double *)nullptr, Y);
+            rc = run_sweeps<T>(f, WCS_SOLVE_FULL, 1, st);
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_add_unscaled<T>, dim3(g), dim3(256), 0, st, Y, (int64_t)n, 1,
+                               (const double *)nullptr, 0, Xp);
+        } else {
+            wcs_ir_report r;
+            rc = refine_pivot<T>(f, 1, tol, 10, &r, st);
+            rep->iterations = std::max(rep->iterations, r.iterations);
+            rep->raw_residual = std::max(rep->raw_residual, r.raw_residual);
+            rep->final_residual = std::max(rep->final_residual, r.final_residual);
+            if (rc == WCS_ENOTCONV) {
+                set_error("theta scheme: refinement of step " + std::to_string(i + 1) + " stopped at relative residual " +
+                          std::to_string(r.final_residual));
+                return rc;
+            }
+            if (rc) return rc;
+        }
+        hipLaunchKernelGGL(k_scatter_rows, dim3(g), dim3(256), 0, st, Xp, perm, n, 1, U + (int64_t)(i + 1) * ldu, ldu);
+    }
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
 }
 
 template <typename V>
@@ -1551,6 +1620,37 @@ int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double 
     hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, Yp, perm, n, nrhs, Y_dev, ld);
     HIP_TRY(hipGetLastError());
     return WCS_OK;
+}
+
+int wcs_theta_matrix(wcs_factor f, const double *K_values_dev, double theta, double dt, double *A_values_dev,
+                     wcs_stream stream)
+{
+    if (!f || !K_values_dev || !A_values_dev || !(theta > 0 && theta <= 1) || !(dt > 0)) {
+        set_error("invalid argument to wcs_theta_matrix");
+        return WCS_EINVAL;
+    }
+    const Symbolic &S = *f->S;
+    hipLaunchKernelGGL(k_theta_matrix, dim3(grid_for(S.nnz)), dim3(256), 0, (hipStream_t)stream,
+                       f->at<int32_t>(f->lay.rowind), f->at<int32_t>(f->lay.colof), S.nnz, K_values_dev, theta * dt,
+                       A_values_dev);
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
+int wcs_theta_steps(wcs_factor f, const double *A_values_dev, double theta, double dt, int32_t nsteps,
+                    const double *F_dev, int64_t ldf, double *U_dev, int64_t ldu, double tol, wcs_ir_report *rep,
+                    wcs_stream stream)
+{
+    if (!f || !A_values_dev || !F_dev || !U_dev || !rep || nsteps < 1 || !(theta > 0 && theta <= 1) || !(dt > 0) ||
+        ldf < f->S->n || ldu < f->S->n || !(tol >= 0)) {
+        set_error("invalid argument to wcs_theta_steps");
+        return WCS_EINVAL;
+    }
+    if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
+    hipStream_t st = (hipStream_t)stream;
+    return f->prec == WCS_FP64
+               ? theta_steps<double>(f, A_values_dev, theta, dt, nsteps, F_dev, ldf, U_dev, ldu, tol, rep, st)
+               : theta_steps<float>(f, A_values_dev, theta, dt, nsteps, F_dev, ldf, U_dev, ldu, tol, rep, st);
 }
 
 int wcs_grad_pattern(wcs_factor f, const double *lam_dev, const double *x_dev, double *gA_dev, wcs_stream stream)

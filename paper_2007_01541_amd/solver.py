@@ -290,6 +290,34 @@ class Factor:
                                      _stream_ptr(stream)), "wcs_grad_pattern")
         return g
 
+    def theta_matrix(self, K_values, theta: float, dt: float, stream=None):
+        """Values of A = I + theta dt K on the stored lower pattern (device FP64)."""
+        torch = _torch()
+        A = torch.empty_like(K_values)
+        check(lib().wcs_theta_matrix(self.handle, _dptr(K_values), theta, dt, _dptr(A), _stream_ptr(stream)),
+              "wcs_theta_matrix")
+        return A
+
+    def theta_steps(self, A_values, theta: float, dt: float, F, u0, tol: float = 1e-10, stream=None):
+        """nsteps = F.shape[1] - 1 theta-scheme steps over this factor of A = I + theta dt K
+        (wcs_theta_steps); F: n x (nsteps + 1) device FP64, u0: n.  Returns (U, report) with
+        U: n x (nsteps + 1), column 0 = u0."""
+        torch = _torch()
+        nsteps = F.shape[1] - 1
+        fc = F.t().contiguous()                 # column-major n x (nsteps + 1)
+        uc = torch.empty((nsteps + 1, self.n), dtype=torch.float64, device=F.device)
+        uc[0] = u0
+        rep = IRReport()
+        rc = lib().wcs_theta_steps(self.handle, _dptr(A_values), theta, dt, nsteps, _dptr(fc), self.n, _dptr(uc),
+                                   self.n, tol, C.byref(rep), _stream_ptr(stream))
+        report = {"iterations": rep.iterations, "raw_residual": rep.raw_residual,
+                  "final_residual": rep.final_residual}
+        if rc != 0:
+            err = capi.WcsError(rc, "wcs_theta_steps", lib().wcs_last_error().decode(errors="replace"))
+            err.report = report
+            raise err
+        return uc.t().contiguous(), report
+
     def export_L(self, j0: int = 0, j1: Optional[int] = None):
         """Columns [j0, j1) of L in pivot order as host CSC (stored pattern, explicit zeros kept)."""
         j1 = self.n if j1 is None else j1
