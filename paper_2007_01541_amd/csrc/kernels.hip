@@ -1084,6 +1084,50 @@ __global__ void k_spmv_narrow(const int64_t *__restrict__ rp, const int32_t *__r
     }
 }
 
+// One column (k = 1), element i at i * sx: one wave per work item (as in the
+// vector form below); a lane takes the entries lane, lane + 64, ... four at a
+// time, issuing the index, value and X loads of all four before the products
+// (four partial sums, fixed order).
+__global__ __launch_bounds__(256) void k_spmv_one(const int4 *__restrict__ items, int nitems,
+                                                  const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ v, const double *__restrict__ X,
+                                                  int64_t sx, const double *__restrict__ B, double *__restrict__ R,
+                                                  double *__restrict__ P)
+{
+    int it = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (it >= nitems) return;
+    int4 w4 = items[it];
+    int row = w4.x;
+    int64_t a = rp[row] + w4.y, b = rp[row] + w4.z;
+    double s[4] = {0, 0, 0, 0};
+    for (int64_t q0 = a + lane; q0 < b; q0 += 256) {
+        int c[4];
+        double w[4], x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            int64_t q = q0 + 64 * u;
+            bool ok = q < b;
+            c[u] = ok ? __builtin_nontemporal_load(ci + q) : 0;
+            w[u] = ok ? __builtin_nontemporal_load(v + q) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) x[u] = X[(int64_t)c[u] * sx];
+#pragma unroll
+        for (int u = 0; u < 4; u++) s[u] += w[u] * x[u];
+    }
+    double t = (s[0] + s[1]) + (s[2] + s[3]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+    if (lane == 0) {
+        if (w4.w >= 0) {
+            P[w4.w] = t;
+        } else {
+            int64_t o = (int64_t)row * sx;
+            R[o] = B ? B[o] - t : t;
+        }
+    }
+}
+
 // Wide form for row-major X (k columns, leading dimension k): one wave per
 // row, lanes are the columns (64 per pass).  Each wave loads 64 (column,
 // value) pairs at once with non-temporal loads (the matrix is streamed once
@@ -1144,6 +1188,11 @@ __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ r
 // plain order: consecutive rows of the dissection order share their X rows in
 // L2.  Output R = B - mul[c] (A X), or R = A X when B is null (null mul means
 // 1); B may be R itself (each element is read and written by one lane).
+// Waves take work items (row, first, end entry within the row, slot): rows
+// longer than SPMV_CHUNK entries come in several items that leave partial sums
+// in P[slot] for k_spmv_long_sum (a single wave would otherwise walk a row of
+// all N entries alone, after everything else).
+constexpr int SPMV_CHUNK = 4096;
 template <typename TX> struct SpmvVec;
 template <> struct SpmvVec<double> {
     using V = double2;
@@ -1160,18 +1209,22 @@ template <> struct SpmvVec<float> {
 };
 
 template <int LPE, typename TX>
-__global__ __launch_bounds__(256) void k_spmv_vec(const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ v, int n, const TX *__restrict__ X,
-                                                  const double *B, const double *__restrict__ mul, double *R)
+__global__ __launch_bounds__(256) void k_spmv_vec(const int4 *__restrict__ items, int nitems,
+                                                  const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ v, const TX *__restrict__ X,
+                                                  const double *B, const double *__restrict__ mul, double *R,
+                                                  double *__restrict__ P)
 {
     using SV = SpmvVec<TX>;
     using V = typename SV::V;
     constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
     constexpr int U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
-    int row = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
-    if (row >= n) return;
+    int it = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (it >= nitems) return;
+    int4 w4 = items[it];
+    int row = w4.x;
     int q = lane / LPE, ql = lane % LPE;
-    int64_t a = rp[row], b = rp[row + 1];
+    int64_t a = rp[row] + w4.y, b = rp[row] + w4.z;
     const V *xc = reinterpret_cast<const V *>(X) + 2 * ql;   // a row is 2 LPE vectors of 16 bytes
     double s[EL];
 #pragma unroll
@@ -1221,6 +1274,11 @@ __global__ __launch_bounds__(256) void k_spmv_vec(const int64_t *__restrict__ rp
 #pragma unroll
         for (int j = 0; j < EL; j++) s[j] += __shfl_down(s[j], off, 64);
     if (q == 0) {
+        if (w4.w >= 0) {      // a chunk of a long row: its partial sums
+#pragma unroll
+            for (int j = 0; j < EL; j++) P[(int64_t)w4.w * K + EL * ql + j] = s[j];
+            return;
+        }
         int64_t o = (int64_t)row * K + EL * ql;
 #pragma unroll
         for (int j = 0; j < EL; j++) {
@@ -1228,6 +1286,22 @@ __global__ __launch_bounds__(256) void k_spmv_vec(const int64_t *__restrict__ rp
             if (mul) r *= mul[EL * ql + j];
             R[o + j] = B ? B[o + j] - r : r;
         }
+    }
+}
+
+// Long rows: R = B - mul[c] (sum of the row's chunk partials in slot order),
+// element (row, c) at row * sx + c; one workgroup per long row (row, first
+// slot, slots), threads over the k columns.
+__global__ void k_spmv_long_sum(const int4 *__restrict__ rows, int k, int64_t sx, const double *__restrict__ P,
+                                const double *B, const double *__restrict__ mul, double *R)
+{
+    int4 t = rows[blockIdx.x];
+    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+        double s = 0;
+        for (int q = 0; q < t.z; q++) s += P[(int64_t)(t.y + q) * k + c];
+        if (mul) s *= mul[c];
+        int64_t o = (int64_t)t.x * sx + c;
+        R[o] = B ? B[o] - s : s;
     }
 }
 

@@ -114,6 +114,12 @@ struct Plan {
     std::vector<int2> alt_tasks, al_tasks;        // products with the factor: (front, column block) / (front, row tile)
     std::vector<int64_t> gptr, glist;             // rows of the L product: W rows holding each row, fronts ascending
     int64_t xelems = 0;
+    // SpMV work items: (row, first entry, end entry within the row, partial
+    // slot or -1); rows longer than SPMV_CHUNK entries are split into chunks
+    // (listed first) whose partial sums spmv_long (row, first slot, slots)
+    // adds in slot order
+    std::vector<int4> spmv_chunks, spmv_long;
+    int64_t spmv_slots = 0;
 
     void build(const Symbolic &S)
     {
@@ -346,6 +352,23 @@ struct Plan {
                 V.bwd.push_back({s0, d.first, d.second, off, (int64_t)sbwd_tasks.size() - off});
             }
         }
+        // SpMV chunks of the pivot-order CSR
+        spmv_chunks.clear();
+        spmv_long.clear();
+        spmv_slots = 0;
+        for (int32_t i = 0; i < S.n; i++) {
+            int64_t len = S.csr_ptr[i + 1] - S.csr_ptr[i];
+            if (len <= SPMV_CHUNK) continue;
+            int32_t nc = (int32_t)((len + SPMV_CHUNK - 1) / SPMV_CHUNK);
+            spmv_long.push_back(make_int4(i, (int32_t)spmv_slots, nc, 0));
+            for (int32_t c = 0; c < nc; c++)
+                spmv_chunks.push_back(make_int4(i, c * SPMV_CHUNK, (int32_t)std::min<int64_t>(len, (int64_t)(c + 1) * SPMV_CHUNK),
+                                                (int32_t)spmv_slots++));
+        }
+        for (int32_t i = 0; i < S.n; i++) {
+            int64_t len = S.csr_ptr[i + 1] - S.csr_ptr[i];
+            if (len <= SPMV_CHUNK) spmv_chunks.push_back(make_int4(i, 0, (int32_t)len, -1));
+        }
         // products with the factor
         alt_tasks.clear();
         al_tasks.clear();
@@ -383,6 +406,7 @@ struct Layout {
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
+    size_t spchunk, splong, sppart;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -446,6 +470,9 @@ struct Layout {
         ztasks = seg(std::max<size_t>(1, P.zero_tasks.size()) * sizeof(int2));
         dscr_off = seg(ns * 8);
         all_fronts = seg(ns * 4);
+        spchunk = seg(std::max<size_t>(1, P.spmv_chunks.size()) * sizeof(int4));
+        splong = seg(std::max<size_t>(1, P.spmv_long.size()) * sizeof(int4));
+        sppart = seg((size_t)std::max<int64_t>(1, P.spmv_slots) * k * 8);
         total = o;
     }
 };
@@ -998,20 +1025,27 @@ template <typename TX> bool spmv_vec_fits(int k)
 template <typename TX>
 void launch_spmv_vec(wcs_factor f, int k, const TX *X, const double *B, const double *mul, double *R, hipStream_t st)
 {
-    int n = f->S->n;
+    const Plan &P = f->plan;
     const int64_t *rp = f->at<int64_t>(f->lay.csr_ptr);
     const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
     const double *v = f->at<double>(f->lay.csr_val);
-    dim3 g((unsigned)((n + 3) / 4)), b(256);
+    const int4 *items = f->at<int4>(f->lay.spchunk);
+    double *part = f->at<double>(f->lay.sppart);
+    int ni = (int)P.spmv_chunks.size();
+    dim3 g((unsigned)((ni + 3) / 4)), b(256);
     switch (k / (sizeof(TX) == 8 ? 4 : 8)) {
-    case 1: hipLaunchKernelGGL((k_spmv_vec<1, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
-    case 2: hipLaunchKernelGGL((k_spmv_vec<2, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
-    case 4: hipLaunchKernelGGL((k_spmv_vec<4, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
-    case 8: hipLaunchKernelGGL((k_spmv_vec<8, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R); break;
+    case 1: hipLaunchKernelGGL((k_spmv_vec<1, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
+    case 2: hipLaunchKernelGGL((k_spmv_vec<2, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
+    case 4: hipLaunchKernelGGL((k_spmv_vec<4, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
+    case 8: hipLaunchKernelGGL((k_spmv_vec<8, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
     default:
-        if constexpr (sizeof(TX) == 8) hipLaunchKernelGGL((k_spmv_vec<16, TX>), g, b, 0, st, rp, ci, v, n, X, B, mul, R);
+        if constexpr (sizeof(TX) == 8)
+            hipLaunchKernelGGL((k_spmv_vec<16, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part);
         break;
     }
+    if (!P.spmv_long.empty())
+        hipLaunchKernelGGL(k_spmv_long_sum, dim3((unsigned)P.spmv_long.size()), dim3(64), 0, st,
+                           f->at<int4>(f->lay.splong), k, (int64_t)k, part, B, mul, R);
 }
 
 // R = B - C X or Y = C X (B null) with C = P A P^T in pivot order; element
@@ -1027,6 +1061,15 @@ int launch_spmv(wcs_factor f, int k, const double *X, const double *B, double *R
     unsigned nrb = (unsigned)((n + 3) / 4);
     if (sx == k && sc == 1 && spmv_vec_fits<double>(k)) {
         launch_spmv_vec<double>(f, k, X, B, nullptr, R, st);
+    } else if (k == 1) {
+        const Plan &P = f->plan;
+        int ni = (int)P.spmv_chunks.size();
+        double *part = f->at<double>(f->lay.sppart);
+        hipLaunchKernelGGL(k_spmv_one, dim3((unsigned)((ni + 3) / 4)), dim3(256), 0, st, f->at<int4>(f->lay.spchunk),
+                           ni, rp, ci, v, X, sx, B, R, part);
+        if (!P.spmv_long.empty())
+            hipLaunchKernelGGL(k_spmv_long_sum, dim3((unsigned)P.spmv_long.size()), dim3(64), 0, st,
+                               f->at<int4>(f->lay.splong), 1, sx, part, B, (const double *)nullptr, R);
     } else if (k >= 8 && sx == k && sc == 1) {
         int per = ((int)nrb + 7) / 8;
         hipLaunchKernelGGL(k_spmv_wide, dim3((unsigned)(8 * per)), dim3(256), 0, st, rp, ci, v, n, k, X, B, R);
@@ -1303,6 +1346,8 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.csr_ptr, S.csr_ptr, st);
     rc = rc ? rc : upload(f, L.csr_col, S.csr_col, st);
     rc = rc ? rc : upload(f, L.csr_src, S.csr_src, st);
+    rc = rc ? rc : upload(f, L.spchunk, f->plan.spmv_chunks, st);
+    rc = rc ? rc : upload(f, L.splong, f->plan.spmv_long, st);
     rc = rc ? rc : upload(f, L.rowind, S.rowind, st);
     rc = rc ? rc : upload(f, L.colof, P.colof, st);
     rc = rc ? rc : upload(f, L.pan, P.pan_tasks, st);

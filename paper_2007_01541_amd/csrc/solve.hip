@@ -886,16 +886,38 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows(c
             else
                 reduce4<T>(acc, mm.red, out);
         } else {
-            __shared__ T Zs[SB][KT];
-            for (int kb = s0; kb < s1; kb += SB) {
-                int nbk = min(SB, s1 - kb);
-                __syncthreads();
-                for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
-                    int j = e / KT, c = e % KT;
-                    Zs[j][c] = (j < nbk && c0 + c < k) ? a.Y[(int64_t)(f0 + kb + j) * k + c0 + c] : (T)0;
+            // wave q takes the pivot block [s0 + 64 q, s0 + 64 q + 64), lane = row of the
+            // tile; z of the whole super-block is staged once, the four partial sums
+            // meet in LDS (the same array, after a barrier) and w is updated once
+            __shared__ T buf[SS * KT];          // Zs[j][c] = buf[j KT + c]; then part[q][row][c]
+            int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+            __syncthreads();
+            for (int e = threadIdx.x; e < SS * KT; e += THREADS) {
+                int j = e / KT, c = e % KT;
+                buf[e] = (s0 + j < s1 && c0 + c < k) ? a.Y[(int64_t)(f0 + s0 + j) * k + c0 + c] : (T)0;
+            }
+            __syncthreads();
+            T acc[KT];
+#pragma unroll
+            for (int c = 0; c < KT; c++) acc[c] = 0;
+            int r = r0 + lane, kb = s0 + wave * SB, ke = min(s1, kb + SB);
+            if (r >= s1 && r < r1) {
+#pragma unroll 8
+                for (int j = kb; j < ke; j++) {
+                    T l = L[(int64_t)j * ld + r];
+#pragma unroll
+                    for (int c = 0; c < KT; c++) acc[c] += l * buf[(j - s0) * KT + c];
                 }
-                __syncthreads();
-                fwd_rows<T, KT>(L, ld, kb, nbk, w, k, c0, max(r0, s1), r1, Zs);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < KT; c++) buf[(wave * SB + lane) * KT + c] = acc[c];
+            __syncthreads();
+            for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
+                int rr = e / KT, c = e % KT, rw = r0 + rr;
+                if (rw >= s1 && rw < r1 && c0 + c < k)
+                    w[(int64_t)rw * k + c0 + c] -= (buf[rr * KT + c] + buf[(SB + rr) * KT + c]) +
+                                                    (buf[(2 * SB + rr) * KT + c] + buf[(3 * SB + rr) * KT + c]);
             }
         }
     }

@@ -173,6 +173,48 @@ def test_spmv_matches_oracle(k):
     assert np.abs(Y - Yo).max() <= 1e-13 * np.abs(Yo).max()
 
 
+_MEDIUM = {}
+
+
+def medium():
+    """N = 65536: the coarsest wavelets couple to every unknown, so rows of up to
+    65536 entries are split into several SpMV work items (chunks of 4096)."""
+    if not _MEDIUM:
+        from workloads import medium_fp64
+        m = medium_fp64().matrix()
+        _MEDIUM["m"] = m
+        _MEDIUM["sym"] = Symbolic(m["n"], m["colptr"], m["rowind"], coords=m["coords"])
+    return _MEDIUM["m"], _MEDIUM["sym"]
+
+
+@pytest.mark.parametrize("k", [1, 8, 64])
+def test_spmv_long_rows_match_oracle(k):
+    m, sym = medium()
+    n = m["n"]
+    deg = np.diff(m["colptr"]) + np.bincount(m["rowind"], minlength=n) - 1
+    print(f"medium n={n}: longest row {deg.max()} entries, {(deg > 4096).sum()} rows over 4096", flush=True)
+    assert deg.max() > 4 * 4096
+    X = normal_rhs(n, k, 12)
+    f = Factor(sym, FP64, max_nrhs=k)
+    Y = f.spmv(dev(X), dev(m["values"])).cpu().numpy().reshape(n, k)
+    Yo = oracle.symv(n, m["colptr"], m["rowind"], m["values"], X).reshape(n, k)
+    assert np.abs(Y - Yo).max() <= 1e-13 * np.abs(Yo).max()
+
+
+def test_fp32_refined_long_rows():
+    """The FP32-row residual forms (first residual and updates) over split rows."""
+    m, sym = medium()
+    n, k = m["n"], 64
+    B = normal_rhs(n, k, 13)
+    f = Factor(sym, FP32, max_nrhs=k)
+    vals = dev(m["values"])
+    f.numeric(vals)
+    X, rep = f.solve_refined(dev(B), vals, tol=1e-10, max_iter=10)
+    res = oracle.residual(n, m["colptr"], m["rowind"], m["values"], X.cpu().numpy(), B)
+    print(f"medium k=64: {rep}, true residual {res.max():.3e}", flush=True)
+    assert res.max() <= 1e-10 and abs(res.max() - rep["final_residual"]) <= 1e-12
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("k", [1, 3, 64, 70])
 def test_factor_products_match_oracle(prec, k):
