@@ -40,10 +40,12 @@ size_t nseg_of(const Symbolic &S) { return S.seg_ptr.size() >= 2 ? S.seg_ptr.siz
 
 constexpr int32_t NBO = 256;   // outer block: trailing updates use K = NBO columns at once
 // fronts with more rows solve block by block over many workgroups (tuning knob WCS_SOLVE_STEP_ROWS)
+// Fronts of at most this many rows are solved one workgroup per front for the
+// whole sweep; by default none (the super-block path is faster for them too).
 int32_t solve_step_min_rows()
 {
     const char *e = std::getenv("WCS_SOLVE_STEP_ROWS");
-    return e ? std::atoi(e) : 512;
+    return e ? std::atoi(e) : 0;
 }
 constexpr int kPartBlocks = 512;             // blocks of the two-pass column reductions
 

@@ -312,10 +312,13 @@ def test_refactor_and_determinism():
 
 @pytest.mark.parametrize("kind,leaf,coords", CASES)
 @pytest.mark.parametrize("k", [1, 9, 64, 70])
-def test_solve_all_fronts_by_super_blocks(kind, leaf, coords, k, monkeypatch):
-    """Every front through the super-block path (the plan reads the routing
-    threshold when the factor is created): same solution as the oracle."""
-    monkeypatch.setenv("WCS_SOLVE_STEP_ROWS", "16")
+@pytest.mark.parametrize("rows", ["100000", "64"])
+def test_solve_fused_fronts(kind, leaf, coords, k, rows, monkeypatch):
+    """Fronts of at most `rows` rows solved one workgroup per front for the whole
+    sweep (all of them, or the small ones beside super-block fronts; the plan
+    reads the routing threshold when the factor is created; by default every
+    front takes the super-block path): same solution as the oracle."""
+    monkeypatch.setenv("WCS_SOLVE_STEP_ROWS", rows)
     m, sym, orc = prepared(kind, leaf, coords)
     n = m["n"]
     B = normal_rhs(n, k, 78)
