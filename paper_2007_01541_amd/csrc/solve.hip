@@ -1054,21 +1054,29 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_scols(c
                         [&](int r, int c) { return L[(int64_t)(ab + c) * ld + r]; });
             }
             T *v = w + (int64_t)ab * k;
-            auto put = [&](int *rr, int *cc, T *val, int cb) {
-                sub_batch<8>(
-                    v,
-                    [&](int q) -> int64_t {
-                        int n = rr[q], c = cb + cc[q];
-                        return c0 + n < k ? (int64_t)c * k + c0 + n : -1;
-                    },
-                    [&](int q) { return val[q]; });
-            };
-            if (quad)
+            if (quad)   // tile (c, n): consecutive threads update consecutive n
                 reduce4m<T>(
                     acc, mm.red,
-                    [&](int x, int y, int e) { return make_int2(4 * ln + y, 16 * x + Mfma<T>::row(kq, e)); }, put);
+                    [&](int x, int y, int e) { return make_int2(16 * x + Mfma<T>::row(kq, e), 4 * ln + y); },
+                    [&](int *rr, int *cc, T *val, int cb) {
+                        sub_batch<8>(
+                            v,
+                            [&](int q) -> int64_t {
+                                int c = rr[q], n = cb + cc[q];
+                                return c0 + n < k ? (int64_t)c * k + c0 + n : -1;
+                            },
+                            [&](int q) { return val[q]; });
+                    });
             else
-                reduce4<T>(acc, mm.red, put);
+                reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+                    sub_batch<8>(
+                        v,
+                        [&](int q) -> int64_t {
+                            int n = rr[q], c = cb + cc[q];
+                            return c0 + n < k ? (int64_t)c * k + c0 + n : -1;
+                        },
+                        [&](int q) { return val[q]; });
+                });
         }
         return;
     }
@@ -1127,19 +1135,25 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restri
                         [&](int n, int r) { return c0 + n < k ? Y[(int64_t)rw[r] * k + c0 + n] : (T)0; },
                         [&](int r, int c) { return c < na ? L[(int64_t)(ab + c) * ld + r] : (T)0; });
             }
-            auto put = [&](int *rr, int *cc, T *val, int cb) {
-#pragma unroll
-                for (int q = 0; q < 8; q++) {
-                    int n = rr[q], c = cb + cc[q];
-                    if (c0 + n < k) out[(int64_t)c * k + c0 + n] = -val[q];
-                }
-            };
-            if (quad)
+            if (quad)   // tile (c, n): consecutive threads write consecutive n
                 reduce4m<T>(
                     acc, mm.red,
-                    [&](int x, int y, int e) { return make_int2(4 * ln + y, 16 * x + Mfma<T>::row(kq, e)); }, put);
+                    [&](int x, int y, int e) { return make_int2(16 * x + Mfma<T>::row(kq, e), 4 * ln + y); },
+                    [&](int *rr, int *cc, T *val, int cb) {
+#pragma unroll
+                        for (int q = 0; q < 8; q++) {
+                            int c = rr[q], n = cb + cc[q];
+                            if (c0 + n < k) out[(int64_t)c * k + c0 + n] = -val[q];
+                        }
+                    });
             else
-                reduce4<T>(acc, mm.red, put);
+                reduce4<T>(acc, mm.red, [&](int *rr, int *cc, T *val, int cb) {
+#pragma unroll
+                    for (int q = 0; q < 8; q++) {
+                        int n = rr[q], c = cb + cc[q];
+                        if (c0 + n < k) out[(int64_t)c * k + c0 + n] = -val[q];
+                    }
+                });
         }
         return;
     }
