@@ -305,7 +305,10 @@ struct Plan {
             for (int32_t s : big) {
                 int32_t nsup = (pfront[s] + SS - 1) / SS;
                 xoff[s] = xelems;
-                xelems += (int64_t)nsup * SS * SS;
+                // SS x SS per super-block; the last one only as many 64-column blocks as it
+                // has pivots (no kernel touches the columns beyond)
+                int32_t nb_last = (pfront[s] - (nsup - 1) * SS + SB - 1) / SB;
+                xelems += (int64_t)(nsup - 1) * SS * SS + (int64_t)nb_last * SB * SS;
                 for (int32_t si = 0; si < nsup; si++) {
                     int32_t nb = (std::min(pfront[s], (si + 1) * SS) - si * SS + SB - 1) / SB;
                     for (int32_t jb = 0; jb < nb; jb++) xinv_tasks.push_back(make_int4(s, si, jb, 0));
