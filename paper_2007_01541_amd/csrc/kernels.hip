@@ -1393,16 +1393,36 @@ __global__ void k_colred_part(const double *__restrict__ A, int n, int k, int op
 }
 
 // out[sg * k + c] = reduction over the bps partials of segment sg (grid: one block per segment)
-__global__ void k_colred_final(const double *__restrict__ part, int bps, int k, int op, double *__restrict__ out)
+// Final pass (one workgroup of THREADS per segment): the partials of a column
+// are split over THREADS / k threads (strided), whose sums are then combined
+// in thread order; fixed order throughout.
+__global__ __launch_bounds__(THREADS) void k_colred_final(const double *__restrict__ part, int bps, int k, int op,
+                                                          double *__restrict__ out)
 {
+    __shared__ double red[THREADS];
     int sg = blockIdx.x;
-    for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    int kc = k < THREADS ? k : THREADS, groups = THREADS / kc;
+    for (int c0 = 0; c0 < k; c0 += kc) {
+        int c = c0 + (int)threadIdx.x % kc, g = (int)threadIdx.x / kc;
         double t = 0;
-        for (int b = 0; b < bps; b++) {
-            double x = part[((int64_t)sg * bps + b) * k + c];
-            t = op == 0 ? t + x : fmax(t, x);
+        if (g < groups && c < k) {
+#pragma unroll 8
+            for (int b = g; b < bps; b += groups) {
+                double x = part[((int64_t)sg * bps + b) * k + c];
+                t = op == 0 ? t + x : fmax(t, x);
+            }
         }
-        out[(int64_t)sg * k + c] = t;
+        red[threadIdx.x] = t;
+        __syncthreads();
+        if ((int)threadIdx.x < kc && c < k) {
+            double u = 0;
+            for (int gg = 0; gg < groups; gg++) {
+                double x = red[gg * kc + threadIdx.x];
+                u = op == 0 ? u + x : fmax(u, x);
+            }
+            out[(int64_t)sg * k + c] = u;
+        }
+        __syncthreads();
     }
 }
 

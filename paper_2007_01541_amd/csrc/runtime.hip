@@ -1096,7 +1096,7 @@ void launch_colred(wcs_factor f, const double *A, int n, int k, int op, bool seg
     int bps = std::max(1, kPartBlocks / nseg);
     hipLaunchKernelGGL(k_colred_part, dim3((unsigned)(bps * nseg)), dim3(THREADS), 0, st, A, n, k, op, sp, nseg,
                        part);
-    hipLaunchKernelGGL(k_colred_final, dim3((unsigned)nseg), dim3(256), 0, st, part, bps, k, op, out);
+    hipLaunchKernelGGL(k_colred_final, dim3((unsigned)nseg), dim3(THREADS), 0, st, part, bps, k, op, out);
 }
 
 // Refinement in pivot order: Bp = P B, Xp = solve(Bp), then while any
