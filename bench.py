@@ -283,6 +283,8 @@ def main() -> int:
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default update kernel on every level instead of timing the variants first")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--graphs", action="store_true",
+                    help="headline: replay the factorization and the sweeps from HIP graphs")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB FP32 tensor three times (a kernel of known traffic for counter scaling)")
@@ -327,6 +329,8 @@ def main() -> int:
         log("copy calibration: 3 copies of 1 GiB done")
     vals = torch.as_tensor(m["values"], device=dev)
     Bd = torch.as_tensor(B, device=dev)
+    if args.graphs:     # recording needs a created stream
+        torch.cuda.set_stream(torch.cuda.Stream())
     stream = torch.cuda.current_stream()
 
     tuned = {}
@@ -342,6 +346,8 @@ def main() -> int:
             tuned[prec] = tune["tiles"].tolist()
             log(f"  autotune: variants per level {tuned[prec]}, levels {tune['ms_default']:.2f} ms with the "
                 f"default, {tune['ms_tuned']:.2f} ms tuned")
+        if args.graphs:
+            f.use_graphs(True)
 
         def step():
             e0 = torch.cuda.Event(enable_timing=True)
