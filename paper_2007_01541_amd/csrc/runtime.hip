@@ -1110,9 +1110,12 @@ void launch_colred(wcs_factor f, const double *A, int n, int k, int op, bool seg
 // is per instance and column (each block of the block-diagonal matrix is its
 // own system).
 // The loop itself: Bp (row-major n x k, pivot order) holds P B, the matrix
-// values are expanded; leaves P X in Xp and the residuals in f->last_rel.
+// values are expanded (or will be once csr_ready, if given, has fired: the
+// first residual waits for it); leaves P X in Xp and the residuals in
+// f->last_rel.
 template <typename T>
-int refine_pivot(wcs_factor f, int k, double tol, int max_iter, wcs_ir_report *rep, hipStream_t st)
+int refine_pivot(wcs_factor f, int k, double tol, int max_iter, wcs_ir_report *rep, hipStream_t st,
+                 hipEvent_t csr_ready = nullptr)
 {
     const Layout &Lo = f->lay;
     int n = f->S->n;
@@ -1141,6 +1144,7 @@ int refine_pivot(wcs_factor f, int k, double tol, int max_iter, wcs_ir_report *r
     rep->final_residual = -1;
     int status = WCS_ENOTCONV;
     for (int it = 0;; it++) {
+        if (it == 0 && csr_ready) HIP_TRY(hipStreamWaitEvent(st, csr_ready, 0));
         if constexpr (sizeof(T) == 4) {
             if (from_y)
                 launch_spmv_vec<float>(f, k, Y, it == 0 ? Bp : Rp, it == 0 ? nullptr : amax, Rp, st);
@@ -1184,13 +1188,21 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
 {
     const Layout &Lo = f->lay;
     int n = f->S->n;
-    int rc = ensure_csr_values(f, values, st);
+    // the matrix values for the residual are expanded on the third stream
+    // while the first solve runs; the first residual waits for them
+    hipStream_t aux = f->aux ? f->aux : st;
+    if (aux != st) {
+        HIP_TRY(hipEventRecord(f->ev_main, st));
+        HIP_TRY(hipStreamWaitEvent(aux, f->ev_main, 0));
+    }
+    int rc = ensure_csr_values(f, values, aux);
     if (rc) return rc;
+    if (aux != st) HIP_TRY(hipEventRecord(f->ev_aux, aux));
     const int32_t *perm = f->at<int32_t>(Lo.perm);
     int64_t nk = (int64_t)n * k;
     hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k,
                        f->at<double>(Lo.Br));
-    int status = refine_pivot<T>(f, k, tol, max_iter, rep, st);
+    int status = refine_pivot<T>(f, k, tol, max_iter, rep, st, aux != st ? f->ev_aux : nullptr);
     if (status != WCS_OK && status != WCS_ENOTCONV) return status;
     hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, f->at<double>(Lo.Xr), perm, n, k, X,
                        ld);
