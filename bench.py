@@ -290,8 +290,8 @@ def main() -> int:
                     help="first copy a 1 GiB FP32 tensor three times (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the elimination-tree sharding across GPUs is described in DESIGN.md only).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (sharding the "
+              "elimination tree across GPUs is a design note, not code).", file=sys.stderr)
         return 2
 
     if args.workload == "batch":
