@@ -1305,6 +1305,49 @@ __global__ void k_spmv_long_sum(const int4 *__restrict__ rows, int k, int64_t sx
     }
 }
 
+// The same two permutations through LDS for k >= 4: a workgroup moves a tile
+// of 64 caller rows j (original order) by 64 columns, reading and writing
+// both layouts with consecutive threads on consecutive addresses (caller side:
+// consecutive j of a column; pivot side: consecutive columns of a row, the row
+// of j at iperm[j]).
+// Xp[iperm[j] * k + c] = X[c * ld + j]
+__global__ __launch_bounds__(256) void k_gather_rows_t(const double *__restrict__ X, int64_t ld,
+                                                       const int32_t *__restrict__ iperm, int n, int k,
+                                                       double *__restrict__ Xp)
+{
+    __shared__ double T[64][65];
+    int j0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    int nj = min(64, n - j0), nc = min(64, k - c0);
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        int c = e / 64, jj = e % 64;
+        if (jj < nj && c < nc) T[jj][c] = X[(int64_t)(c0 + c) * ld + j0 + jj];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        int jj = e / 64, c = e % 64;
+        if (jj < nj && c < nc) Xp[(int64_t)iperm[j0 + jj] * k + c0 + c] = T[jj][c];
+    }
+}
+
+// X[c * ld + j] = Xp[iperm[j] * k + c]
+__global__ __launch_bounds__(256) void k_scatter_rows_t(const double *__restrict__ Xp,
+                                                        const int32_t *__restrict__ iperm, int n, int k,
+                                                        double *__restrict__ X, int64_t ld)
+{
+    __shared__ double T[64][65];
+    int j0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    int nj = min(64, n - j0), nc = min(64, k - c0);
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        int jj = e / 64, c = e % 64;
+        if (jj < nj && c < nc) T[jj][c] = Xp[(int64_t)iperm[j0 + jj] * k + c0 + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += blockDim.x) {
+        int c = e / 64, jj = e % 64;
+        if (jj < nj && c < nc) X[(int64_t)(c0 + c) * ld + j0 + jj] = T[jj][c];
+    }
+}
+
 // Xp[i * k + c] = X[perm[i] + c * ld]  (caller column-major -> row-major pivot order)
 __global__ void k_gather_rows(const double *__restrict__ X, int64_t ld, const int32_t *__restrict__ perm, int n, int k,
                               double *__restrict__ Xp)

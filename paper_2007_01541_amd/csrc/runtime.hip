@@ -411,7 +411,7 @@ struct Layout {
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
-    size_t spchunk, splong, sppart;
+    size_t spchunk, splong, sppart, iperm;
     size_t total;
 
     void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
@@ -478,6 +478,7 @@ struct Layout {
         spchunk = seg(std::max<size_t>(1, P.spmv_chunks.size()) * sizeof(int4));
         splong = seg(std::max<size_t>(1, P.spmv_long.size()) * sizeof(int4));
         sppart = seg((size_t)std::max<int64_t>(1, P.spmv_slots) * k * 8);
+        iperm = seg(n * 4);
         total = o;
     }
 };
@@ -1017,6 +1018,28 @@ int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st)
     return WCS_OK;
 }
 
+// Caller column-major (leading dimension ld) <-> row-major n x k in pivot order
+void gather_rows(wcs_factor f, const double *X, int64_t ld, int k, double *Xp, hipStream_t st)
+{
+    int n = f->S->n;
+    if (k >= 4)
+        hipLaunchKernelGGL(k_gather_rows_t, dim3((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64)), dim3(256), 0,
+                           st, X, ld, f->at<int32_t>(f->lay.iperm), n, k, Xp);
+    else
+        hipLaunchKernelGGL(k_gather_rows, dim3(grid_for((int64_t)n * k)), dim3(256), 0, st, X, ld,
+                           f->at<int32_t>(f->lay.perm), n, k, Xp);
+}
+void scatter_rows(wcs_factor f, const double *Xp, int k, double *X, int64_t ld, hipStream_t st)
+{
+    int n = f->S->n;
+    if (k >= 4)
+        hipLaunchKernelGGL(k_scatter_rows_t, dim3((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64)), dim3(256), 0,
+                           st, Xp, f->at<int32_t>(f->lay.iperm), n, k, X, ld);
+    else
+        hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for((int64_t)n * k)), dim3(256), 0, st, Xp,
+                           f->at<int32_t>(f->lay.perm), n, k, X, ld);
+}
+
 // Row-major X of k = 4 LPE (FP64) or 8 LPE (FP32) columns, LPE a power of
 // two up to 16 (FP64) or 8 (FP32): the vector SpMM form
 template <typename TX> bool spmv_vec_fits(int k)
@@ -1187,7 +1210,6 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
                   int max_iter, wcs_ir_report *rep, hipStream_t st)
 {
     const Layout &Lo = f->lay;
-    int n = f->S->n;
     // the matrix values for the residual are expanded on the third stream
     // while the first solve runs; the first residual waits for them
     hipStream_t aux = f->aux ? f->aux : st;
@@ -1198,14 +1220,10 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
     int rc = ensure_csr_values(f, values, aux);
     if (rc) return rc;
     if (aux != st) HIP_TRY(hipEventRecord(f->ev_aux, aux));
-    const int32_t *perm = f->at<int32_t>(Lo.perm);
-    int64_t nk = (int64_t)n * k;
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, B, ld, perm, n, k,
-                       f->at<double>(Lo.Br));
+    gather_rows(f, B, ld, k, f->at<double>(Lo.Br), st);
     int status = refine_pivot<T>(f, k, tol, max_iter, rep, st, aux != st ? f->ev_aux : nullptr);
     if (status != WCS_OK && status != WCS_ENOTCONV) return status;
-    hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, f->at<double>(Lo.Xr), perm, n, k, X,
-                       ld);
+    scatter_rows(f, f->at<double>(Lo.Xr), k, X, ld, st);
     HIP_TRY(hipGetLastError());
     if (status != WCS_OK)
         set_error("iterative refinement stopped at relative residual " + std::to_string(rep->final_residual));
@@ -1365,6 +1383,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     rc = rc ? rc : upload(f, L.csr_src, S.csr_src, st);
     rc = rc ? rc : upload(f, L.spchunk, f->plan.spmv_chunks, st);
     rc = rc ? rc : upload(f, L.splong, f->plan.spmv_long, st);
+    rc = rc ? rc : upload(f, L.iperm, S.iperm, st);
     rc = rc ? rc : upload(f, L.rowind, S.rowind, st);
     rc = rc ? rc : upload(f, L.colof, P.colof, st);
     rc = rc ? rc : upload(f, L.pan, P.pan_tasks, st);
@@ -1672,14 +1691,11 @@ int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double 
     hipStream_t st = (hipStream_t)stream;
     int rc = ensure_csr_values(f, values_dev, st);
     if (rc) return rc;
-    int n = f->S->n;
-    int64_t nk = (int64_t)n * nrhs;
     double *Xp = f->at<double>(f->lay.Xr), *Yp = f->at<double>(f->lay.Rr);
-    const int32_t *perm = f->at<int32_t>(f->lay.perm);
-    hipLaunchKernelGGL(k_gather_rows, dim3(grid_for(nk)), dim3(256), 0, st, X_dev, ld, perm, n, nrhs, Xp);
+    gather_rows(f, X_dev, ld, nrhs, Xp, st);
     rc = launch_spmv(f, nrhs, Xp, nullptr, Yp, nrhs, 1, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(nk)), dim3(256), 0, st, Yp, perm, n, nrhs, Y_dev, ld);
+    scatter_rows(f, Yp, nrhs, Y_dev, ld, st);
     HIP_TRY(hipGetLastError());
     return WCS_OK;
 }
