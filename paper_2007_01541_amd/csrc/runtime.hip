@@ -69,6 +69,7 @@ struct SuperStep {
     int32_t s0;                  // first pivot of the super-block
     int64_t d_off, d_cnt;        // (front, 64-block of the super-block) tasks in sblk_tasks: X_S products
     int64_t t_off, t_cnt;        // wide part: forward (front, 64-row tile) / backward (front, column block)
+    int64_t t1_off = 0, t1_cnt = 0;   // forward: tiles of fronts whose super-block is one 64-column block
 };
 struct SolveLevel {
     int64_t fused_off = 0, fused_cnt = 0;          // fronts solved by one workgroup each (in slist)
@@ -325,14 +326,21 @@ struct Plan {
             };
             for (int32_t s0 = 0; s0 < maxp; s0 += SS) {
                 auto d = blk_tasks(s0);
-                int64_t off = (int64_t)sfwd_tasks.size();
-                for (int32_t s : big) {
-                    if (pfront[s] <= s0) continue;
-                    int32_t s1 = std::min(pfront[s], s0 + SS);    // row tiles start at s1 & ~3
-                    int32_t nt = mfront[s] > s1 ? (mfront[s] - (s1 & ~3) + SB - 1) / SB : 0;
-                    for (int32_t t = 0; t < nt; t++) sfwd_tasks.push_back(make_int2(s, t));
+                SuperStep st{s0, d.first, d.second, 0, 0};
+                for (int one = 0; one < 2; one++) {    // super-blocks of several 64-column blocks, then of one
+                    int64_t off = (int64_t)sfwd_tasks.size();
+                    for (int32_t s : big) {
+                        if (pfront[s] <= s0) continue;
+                        int32_t s1 = std::min(pfront[s], s0 + SS);    // row tiles start at s1 & ~3
+                        if ((s1 - s0 <= SB) != (one == 1)) continue;
+                        int32_t nt = mfront[s] > s1 ? (mfront[s] - (s1 & ~3) + SB - 1) / SB : 0;
+                        for (int32_t t = 0; t < nt; t++) sfwd_tasks.push_back(make_int2(s, t));
+                    }
+                    int64_t cnt = (int64_t)sfwd_tasks.size() - off;
+                    if (one) { st.t1_off = off; st.t1_cnt = cnt; }
+                    else { st.t_off = off; st.t_cnt = cnt; }
                 }
-                V.fwd.push_back({s0, d.first, d.second, off, (int64_t)sfwd_tasks.size() - off});
+                V.fwd.push_back(st);
             }
             V.below.first = (int64_t)sbelow_tasks.size();
             V.below_sum.first = (int64_t)sbsum_tasks.size();
@@ -870,6 +878,15 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
                     if (s.t_cnt)
                         hipLaunchKernelGGL((k_fwd_srows<T, KT>), dim3((unsigned)s.t_cnt), dim3(THREADS), 0, st,
                                            tf + s.t_off, s.s0, a);
+                    if (s.t1_cnt) {
+                        // one 64-column block: a wave per tile when the quad form applies
+                        if (KT == 64 && k % 4 == 0)
+                            hipLaunchKernelGGL(k_fwd_srows1<T>, dim3((unsigned)((s.t1_cnt + 3) / 4)), dim3(THREADS), 0,
+                                               st, tf + s.t1_off, (int)s.t1_cnt, s.s0, a);
+                        else
+                            hipLaunchKernelGGL((k_fwd_srows<T, KT>), dim3((unsigned)s.t1_cnt), dim3(THREADS), 0, st,
+                                               tf + s.t1_off, s.s0, a);
+                    }
                 }
             }
         }

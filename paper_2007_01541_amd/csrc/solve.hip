@@ -923,6 +923,72 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows(c
     }
 }
 
+// forward rows when the super-block is a single 64-column block (every front
+// of at most 64 pivots, as at the leaves) and k is a multiple of 4: each wave
+// takes one task (front, 64-row tile) and the whole contraction, and updates
+// its rows of w itself (no reduction between waves, no barrier)
+template <typename T>
+__global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows1(const int2 *__restrict__ tasks, int ntasks, int s0,
+                                                           SolveArgs<T> a)
+{
+    typedef typename Vec4<T>::type V4;
+    int ti = blockIdx.x * (THREADS / 64) + threadIdx.x / 64;
+    if (ti >= ntasks) return;
+    int2 t = tasks[ti];
+    int f = t.x;
+    int m = a.mfront[f], p = a.pfront[f], k = a.k, f0 = a.first[f], ld = front_ld(m);
+    int s1 = min(p, s0 + SB);
+    int r0 = (s1 & ~3) + t.y * SB, r1 = min(m, r0 + SB);
+    const T *L = a.fronts + a.front_off[f];
+    T *w = a.W + a.woff[f] * k;
+    const int lane = threadIdx.x % 64, kq = lane / 16, ln = lane % 16;
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        typename Mfma<T>::V acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; x++)
+#pragma unroll
+            for (int y = 0; y < 4; y++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+        wave_mm_q<T>(
+            acc, s0, s1,
+            [&](int q, int kk) {
+                int r = r0 + 4 * q;
+                return r < r1 ? *reinterpret_cast<const V4 *>(L + (int64_t)kk * ld + r) : V4{0, 0, 0, 0};
+            },
+            [&](int kk, int q) {
+                int c = c0 + 4 * q;
+                return c < k ? *reinterpret_cast<const V4 *>(a.Y + (int64_t)(f0 + kk) * k + c) : V4{0, 0, 0, 0};
+            });
+        // rows 4 row(kq, e) + x of the tile, columns c0 + 4 ln .. + 3: one vector each
+#pragma unroll
+        for (int xh = 0; xh < 4; xh += 2) {
+            T *dst[2][4];
+            V4 cur[2][4];
+#pragma unroll
+            for (int x = 0; x < 2; x++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    int r = r0 + 4 * Mfma<T>::row(kq, e) + xh + x, c = c0 + 4 * ln;
+                    dst[x][e] = (r >= s1 && r < r1 && c < k) ? w + (int64_t)r * k + c : nullptr;
+                    cur[x][e] = dst[x][e] ? *reinterpret_cast<const V4 *>(dst[x][e]) : V4{0, 0, 0, 0};
+                }
+#pragma unroll
+            for (int x = 0; x < 2; x++)
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    if (dst[x][e]) {
+                        V4 v = cur[x][e];
+                        v.x -= acc[xh + x][0][e];
+                        v.y -= acc[xh + x][1][e];
+                        v.z -= acc[xh + x][2][e];
+                        v.w -= acc[xh + x][3][e];
+                        *reinterpret_cast<V4 *>(dst[x][e]) = v;
+                    }
+        }
+    }
+}
+
 // backward, task = (front, block j of the super-block at s0): x_j = sum_{i >= j} X_ij^T v_i -> Y
 template <typename T, int KT>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_sx(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
