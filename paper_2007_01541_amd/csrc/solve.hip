@@ -258,10 +258,56 @@ __device__ void fwd_rows(const T *__restrict__ L, int ld, int kb, int nbk, T *__
 }
 
 // v_a[c][cc] -= sum_{r in rows} L(r, a + c) * X[r][cc] over rows [r0, r1) of the
-// front; X rows come from xrow(r) (a row pointer with stride k).  Thread
-// (c = tid % 64, g = tid / 64) owns columns cc = g, g + 4, ...
+// front; X rows come from xrow(r) (a row pointer with stride k).  The four
+// waves take a quarter of the rows each, lane = column c (each lane walks its
+// column of L, contiguous; the X row is broadcast); their partial sums meet
+// in Ls (reused, 4 x 64 x KT elements) and are added in wave order.  All
+// threads of the workgroup call it.
 template <typename T, int KT, typename XR>
 __device__ void bwd_cols(const T *__restrict__ L, int ld, int a, int na, int r0, int r1, XR xrow, int k, int c0,
+                         T *__restrict__ v, T (*Ls)[SB + 1], T (*)[KT])
+{
+    static_assert(4 * SB * KT <= SB * (SB + 1), "partial sums must fit the staging array");
+    int tid = threadIdx.x, wave = tid / SB, lane = tid % SB;
+    // v may have just been written by other waves: order those writes before
+    // the read-modify-write below even when there are no rows to sum over
+    __syncthreads();
+    if (r0 >= r1) return;
+    int chunk = (r1 - r0 + 3) / 4, rb = r0 + wave * chunk, re = min(r1, rb + chunk);
+    T acc[KT];
+#pragma unroll
+    for (int c = 0; c < KT; c++) acc[c] = 0;
+    if (lane < na) {
+        const T *lc = L + (int64_t)(a + lane) * ld;
+#pragma unroll 4
+        for (int r = rb; r < re; r++) {
+            T l = lc[r];
+            const T *xr = xrow(r) + c0;
+#pragma unroll
+            for (int c = 0; c < KT; c++)
+                if (c0 + c < k) acc[c] += l * xr[c];
+        }
+    }
+    T *part = &Ls[0][0];
+#pragma unroll
+    for (int c = 0; c < KT; c++) part[(wave * SB + lane) * KT + c] = acc[c];
+    __syncthreads();
+    for (int e = tid; e < SB * KT; e += blockDim.x) {
+        int c = e / KT, cc = e % KT;
+        if (c < na && c0 + cc < k)
+            v[(int64_t)c * k + c0 + cc] -= (part[c * KT + cc] + part[(SB + c) * KT + cc]) +
+                                          (part[(2 * SB + c) * KT + cc] + part[(3 * SB + c) * KT + cc]);
+    }
+    __syncthreads();
+}
+
+// The same, staged through LDS 64 rows at a time (all threads load): for rows
+// reached through an index (the update rows of a front), whose loads would
+// otherwise chain.  v_a[c][cc] -= sum_{r in rows} L(r, a + c) * X[r][cc] over
+// rows [r0, r1); X rows come from xrow(r) (a row pointer with stride k).  Thread
+// (c = tid % 64, g = tid / 64) owns columns cc = g, g + 4, ...
+template <typename T, int KT, typename XR>
+__device__ void bwd_cols_staged(const T *__restrict__ L, int ld, int a, int na, int r0, int r1, XR xrow, int k, int c0,
                          T *__restrict__ v, T (*Ls)[SB + 1], T (*Xs)[KT])
 {
     int tid = threadIdx.x, c = tid % SB, g = tid / SB;
@@ -463,7 +509,8 @@ __device__ void bwd_below(const SolveArgs<T> &a, int f, int ab, T (*Ls)[SB + 1],
     const T *Y = a.Y;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
-        bwd_cols_any<T, KT>(L, front_ld(m), ab, na, p, m, xrow, k, c0, w + (int64_t)ab * k, Ls, Xs);
+        if constexpr (KT == 64) bwd_cols_any<T, KT>(L, front_ld(m), ab, na, p, m, xrow, k, c0, w + (int64_t)ab * k, Ls, Xs);
+        else bwd_cols_staged<T, KT>(L, front_ld(m), ab, na, p, m, xrow, k, c0, w + (int64_t)ab * k, Ls, Xs);   // indexed rows
 }
 
 template <typename T, int KT>
@@ -799,25 +846,37 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_fwd_sz(cons
         }
         return;
     }
-    __shared__ SxLds<T, KT> sh;
-    BlkAcc<T, KT> acc;
+    // KT < 64: wave q adds X_iq w_q for its block q <= i, lane = output row
+    // (coalesced down the columns of X, w rows broadcast); the four partial
+    // sums meet in LDS and are added in wave order
+    __shared__ T part[4 * SB * KT];
+    int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     for (int c0 = 0; c0 < k; c0 += KT) {
-        acc.zero();
-        for (int jb = 0; jb <= ib; jb++) {
-            int j0 = s0 + jb * SB, nj = min(SB, s1 - j0);
-            __syncthreads();
-            for (int e = threadIdx.x; e < SB * SB; e += THREADS) {
-                int j = e / SB, i = e % SB;    // X column j, row i: X(i0 + i, j0 + j)
-                sh.D[j][i] = (i < ni && j < nj) ? X[(int64_t)(j0 - s0 + j) * SS + (i0 - s0 + i)] : (T)0;
+        T acc[KT];
+#pragma unroll
+        for (int c = 0; c < KT; c++) acc[c] = 0;
+        if (wave <= ib) {
+            int j0 = s0 + wave * SB, nj = min(SB, s1 - j0);
+            const T *xc = X + (int64_t)(j0 - s0) * SS + (i0 - s0) + lane;   // X(i0 + lane, j0 + j) at xc[j SS]
+#pragma unroll 8
+            for (int j = 0; j < nj; j++) {
+                T xv = xc[(int64_t)j * SS];
+                const T *wr = w + (int64_t)(j0 + j) * k + c0;
+#pragma unroll
+                for (int c = 0; c < KT; c++)
+                    if (c0 + c < k) acc[c] += xv * wr[c];
             }
-            for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
-                int j = e / KT, c = e % KT;
-                sh.S[j][c] = (j < nj && c0 + c < k) ? w[(int64_t)(j0 + j) * k + c0 + c] : (T)0;
-            }
-            __syncthreads();
-            acc.add(sh.D, sh.S);
         }
-        acc.store(ni, k, c0, [&](int r, int c, T val) { a.Y[(int64_t)(f0 + i0 + r) * k + c0 + c] = val; });
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < KT; c++) part[(wave * SB + lane) * KT + c] = acc[c];
+        __syncthreads();
+        for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
+            int r = e / KT, c = e % KT;
+            if (r < ni && c0 + c < k)
+                a.Y[(int64_t)(f0 + i0 + r) * k + c0 + c] =
+                    (part[r * KT + c] + part[(SB + r) * KT + c]) + (part[(2 * SB + r) * KT + c] + part[(3 * SB + r) * KT + c]);
+        }
     }
 }
 
@@ -1052,25 +1111,38 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_sx(cons
         }
         return;
     }
-    __shared__ SxLds<T, KT> sh;
-    BlkAcc<T, KT> acc;
+    // KT < 64: wave q adds X_ij^T v_i for block i = j + q, lane = output row r
+    // (each lane walks column j0 + r of X, contiguous); partial sums meet in
+    // LDS and are added in wave order
+    __shared__ T part[4 * SB * KT];
+    int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     for (int c0 = 0; c0 < k; c0 += KT) {
-        acc.zero();
-        for (int ib = jb; ib < nblk; ib++) {
+        T acc[KT];
+#pragma unroll
+        for (int c = 0; c < KT; c++) acc[c] = 0;
+        int ib = jb + wave;
+        if (ib < nblk) {
             int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
-            __syncthreads();
-            for (int e = threadIdx.x; e < SB * SB; e += THREADS) {
-                int jj = e / SB, i = e % SB;   // X(i0 + i, j0 + jj), applied to v row i for output jj
-                sh.D[i][jj] = (i < ni && jj < nj) ? X[(int64_t)(j0 - s0 + jj) * SS + (i0 - s0 + i)] : (T)0;
+            const T *xc = X + (int64_t)(j0 - s0 + lane) * SS + (i0 - s0);   // X(i0 + kk, j0 + lane) at xc[kk]
+#pragma unroll 8
+            for (int kk = 0; kk < ni; kk++) {
+                T xv = xc[kk];
+                const T *wr = w + (int64_t)(i0 + kk) * k + c0;
+#pragma unroll
+                for (int c = 0; c < KT; c++)
+                    if (c0 + c < k) acc[c] += xv * wr[c];
             }
-            for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
-                int i = e / KT, c = e % KT;
-                sh.S[i][c] = (i < ni && c0 + c < k) ? w[(int64_t)(i0 + i) * k + c0 + c] : (T)0;
-            }
-            __syncthreads();
-            acc.add(sh.D, sh.S);
         }
-        acc.store(nj, k, c0, [&](int r, int c, T val) { a.Y[(int64_t)(f0 + j0 + r) * k + c0 + c] = val; });
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < KT; c++) part[(wave * SB + lane) * KT + c] = acc[c];
+        __syncthreads();
+        for (int e = threadIdx.x; e < SB * KT; e += THREADS) {
+            int r = e / KT, c = e % KT;
+            if (r < nj && c0 + c < k)
+                a.Y[(int64_t)(f0 + j0 + r) * k + c0 + c] =
+                    (part[r * KT + c] + part[(SB + r) * KT + c]) + (part[(2 * SB + r) * KT + c] + part[(3 * SB + r) * KT + c]);
+        }
     }
 }
 
@@ -1227,7 +1299,7 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restri
     for (int64_t i = threadIdx.x; i < (int64_t)SB * k; i += blockDim.x) out[i] = (T)0;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
-        bwd_cols_any<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
+        bwd_cols_staged<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
 }
 
 // task = (front, column block a, first slot, slots): v_a = y_a + sum of the partial blocks (in slot order)
