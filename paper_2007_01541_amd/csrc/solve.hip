@@ -279,13 +279,24 @@ __device__ void bwd_cols(const T *__restrict__ L, int ld, int a, int na, int r0,
     for (int c = 0; c < KT; c++) acc[c] = 0;
     if (lane < na) {
         const T *lc = L + (int64_t)(a + lane) * ld;
-#pragma unroll 4
-        for (int r = rb; r < re; r++) {
-            T l = lc[r];
-            const T *xr = xrow(r) + c0;
+        // UR rows at a time: their row pointers (an index load for update rows),
+        // then every value, are in flight before the products
+        constexpr int UR = KT <= 4 ? 16 : 4;
+        for (int rg = rb; rg < re; rg += UR) {
+            const T *xr[UR];
+            T lv[UR], xv[UR][KT];
 #pragma unroll
-            for (int c = 0; c < KT; c++)
-                if (c0 + c < k) acc[c] += l * xr[c];
+            for (int u = 0; u < UR; u++) xr[u] = rg + u < re ? xrow(rg + u) + c0 : nullptr;
+#pragma unroll
+            for (int u = 0; u < UR; u++) {
+                lv[u] = xr[u] ? lc[rg + u] : (T)0;
+#pragma unroll
+                for (int c = 0; c < KT; c++) xv[u][c] = (xr[u] && c0 + c < k) ? xr[u][c] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < UR; u++)
+#pragma unroll
+                for (int c = 0; c < KT; c++) acc[c] += lv[u] * xv[u][c];
         }
     }
     T *part = &Ls[0][0];
@@ -858,13 +869,23 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_fwd_sz(cons
         if (wave <= ib) {
             int j0 = s0 + wave * SB, nj = min(SB, s1 - j0);
             const T *xc = X + (int64_t)(j0 - s0) * SS + (i0 - s0) + lane;   // X(i0 + lane, j0 + j) at xc[j SS]
-#pragma unroll 8
-            for (int j = 0; j < nj; j++) {
-                T xv = xc[(int64_t)j * SS];
-                const T *wr = w + (int64_t)(j0 + j) * k + c0;
+            // UJ columns at a time, every load issued before the products
+            constexpr int UJ = KT <= 4 ? 16 : 4;
+            for (int jg = 0; jg < nj; jg += UJ) {
+                T xv[UJ], wv[UJ][KT];
 #pragma unroll
-                for (int c = 0; c < KT; c++)
-                    if (c0 + c < k) acc[c] += xv * wr[c];
+                for (int u = 0; u < UJ; u++) {
+                    int j = jg + u;
+                    bool ok = j < nj;
+                    xv[u] = ok ? xc[(int64_t)j * SS] : (T)0;
+#pragma unroll
+                    for (int c = 0; c < KT; c++)
+                        wv[u][c] = (ok && c0 + c < k) ? w[(int64_t)(j0 + j) * k + c0 + c] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < UJ; u++)
+#pragma unroll
+                    for (int c = 0; c < KT; c++) acc[c] += xv[u] * wv[u][c];
             }
         }
         __syncthreads();
@@ -1299,7 +1320,10 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restri
     for (int64_t i = threadIdx.x; i < (int64_t)SB * k; i += blockDim.x) out[i] = (T)0;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
-        bwd_cols_staged<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
+        if constexpr (sizeof(T) == 4)   // measured: staged 64 rows at a time is faster in FP32, not in FP64
+            bwd_cols_staged<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
+        else
+            bwd_cols_any<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
 }
 
 // task = (front, column block a, first slot, slots): v_a = y_a + sum of the partial blocks (in slot order)
