@@ -982,11 +982,16 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 3 : 1) void k_fwd_srows(c
             for (int c = 0; c < KT; c++) acc[c] = 0;
             int r = r0 + lane, kb = s0 + wave * SB, ke = min(s1, kb + SB);
             if (r >= s1 && r < r1) {
-#pragma unroll 8
-                for (int j = kb; j < ke; j++) {
-                    T l = L[(int64_t)j * ld + r];
+                constexpr int UJ = 16;      // loads of 16 columns in flight before their products
+                for (int jg = kb; jg < ke; jg += UJ) {
+                    T lv[UJ];
 #pragma unroll
-                    for (int c = 0; c < KT; c++) acc[c] += l * buf[(j - s0) * KT + c];
+                    for (int u = 0; u < UJ; u++) lv[u] = jg + u < ke ? L[(int64_t)(jg + u) * ld + r] : (T)0;
+#pragma unroll
+                    for (int u = 0; u < UJ; u++)
+                        if (jg + u < ke)
+#pragma unroll
+                            for (int c = 0; c < KT; c++) acc[c] += lv[u] * buf[(jg + u - s0) * KT + c];
                 }
             }
             __syncthreads();
@@ -1145,13 +1150,21 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_sx(cons
         if (ib < nblk) {
             int i0 = s0 + ib * SB, ni = min(SB, s1 - i0);
             const T *xc = X + (int64_t)(j0 - s0 + lane) * SS + (i0 - s0);   // X(i0 + kk, j0 + lane) at xc[kk]
-#pragma unroll 8
-            for (int kk = 0; kk < ni; kk++) {
-                T xv = xc[kk];
-                const T *wr = w + (int64_t)(i0 + kk) * k + c0;
+            constexpr int UK = KT <= 4 ? 16 : 4;     // loads of UK rows in flight before their products
+            for (int kg = 0; kg < ni; kg += UK) {
+                T xv[UK], wv[UK][KT];
 #pragma unroll
-                for (int c = 0; c < KT; c++)
-                    if (c0 + c < k) acc[c] += xv * wr[c];
+                for (int u = 0; u < UK; u++) {
+                    bool ok = kg + u < ni;
+                    xv[u] = ok ? xc[kg + u] : (T)0;
+#pragma unroll
+                    for (int c = 0; c < KT; c++)
+                        wv[u][c] = (ok && c0 + c < k) ? w[(int64_t)(i0 + kg + u) * k + c0 + c] : (T)0;
+                }
+#pragma unroll
+                for (int u = 0; u < UK; u++)
+#pragma unroll
+                    for (int c = 0; c < KT; c++) acc[c] += xv[u] * wv[u][c];
             }
         }
         __syncthreads();
