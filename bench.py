@@ -391,6 +391,8 @@ def main() -> int:
     assert rep32["true_residual"] <= args.tol, rep32
     prof = f32.profile(vals)
     torch.cuda.synchronize()
+    for st_ in prof.values():      # algorithmic HBM bytes of the bandwidth-bound classes per second
+        st_["gbps"] = st_["bytes"] / st_["ms"] / 1e6 if st_["ms"] > 0 else 0.0
     for nm, st in prof.items():
         log(f"  kernel class {nm}: {st['launches']} launches, {st['ms']:.2f} ms, "
             f"{st['flops'] / 1e9:.1f} GFLOP, {st['bytes'] / 1e9:.2f} GB")
@@ -410,6 +412,38 @@ def main() -> int:
         products[nm_] = {"ms": ms, "tflops": 2 * info["nnz_l"] * nrhs / ms / 1e9}
     log(f"  products with the factor ({nrhs} RHS, FP32): " +
         ", ".join(f"{k_} {v['ms']:.2f} ms ({v['tflops']:.1f} TFLOP/s)" for k_, v in products.items()))
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # one FP32 solve of all right-hand sides: flops 2 (2 nnz(L) - n) k; the factor is read once per sweep
+    sol_ms = timed(lambda: f32.solve(Bd))
+    solve = {"ms": sol_ms, "tflops": 2 * (2 * info["nnz_l"] - w.n) * nrhs / sol_ms / 1e9,
+             "factor_gbps": 2 * info["nnz_l"] * 4 / sol_ms / 1e6}
+    log(f"  one FP32 solve ({nrhs} RHS): {sol_ms:.2f} ms, {solve['tflops']:.1f} TFLOP/s, "
+        f"{solve['factor_gbps']:.0f} GB/s of factor reads")
+    # Gaussian random field form on the same operator: sample x = P^T L^-T z, y = A^-1 x (refined),
+    # adjoint lambda = A^-1 (y - y*) (refined, same factor), gradient on the stored pattern
+    from paper_2007_01541_amd import SOLVE_LT
+    zs = torch.as_tensor(workloads.normal_rhs(w.n, 1, w.seed + 3)[:, 0], device=dev)
+    ystar = torch.as_tensor(workloads.normal_rhs(w.n, 1, w.seed + 2)[:, 0], device=dev)
+
+    def grf_step():
+        x = f32.solve(zs, part=SOLVE_LT)
+        y, _ = f32.solve_refined(x, vals, tol=args.tol)
+        lam, _ = f32.solve_refined(y - ystar, vals, tol=args.tol)
+        return f32.grad_pattern(lam, y)
+    grf = {"ms": timed(grf_step)}
+    log(f"  random-field sample + refined solve + refined adjoint + pattern gradient (1 RHS): {grf['ms']:.2f} ms")
     levels = f32.profile_levels(vals)
     torch.cuda.synchronize()
     top = levels[-3:]
@@ -471,6 +505,8 @@ def main() -> int:
         "pct_fp32_mfma_peak": 100 * value / PEAK["fp32_mfma_tflops"],
         "root_fronts": root,
         "factor_products": products,
+        "solve": solve,
+        "grf_gradient_step": grf,
         "factor_ms": fact32,
         "ir": rep32,
         "fp64": fp64,
