@@ -228,6 +228,8 @@ def bench_theta(args) -> int:
     t_an = time.perf_counter() - t0
     info = sym.info
     dt = T_END / NSTEPS
+    if args.graphs:     # recording needs a created stream
+        torch.cuda.set_stream(torch.cuda.Stream())
     kv = torch.as_tensor(m["values"], device="cuda")
     Fd = torch.as_tensor(F, device="cuda")
     u0 = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -236,6 +238,8 @@ def bench_theta(args) -> int:
         f = Factor(sym, prec)
         A = f.theta_matrix(kv, THETA, dt)
         f.numeric(A)
+        if args.graphs:
+            f.use_graphs(True)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -284,7 +288,7 @@ def main() -> int:
                     help="keep the default update kernel on every level instead of timing the variants first")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--graphs", action="store_true",
-                    help="headline: replay the factorization and the sweeps from HIP graphs")
+                    help="replay the factorization and the triangular sweeps from HIP graphs")
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 1 GiB FP32 tensor three times (a kernel of known traffic for counter scaling)")
