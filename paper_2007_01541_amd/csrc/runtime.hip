@@ -31,7 +31,13 @@ using namespace dev;
         }                                                                               \
     } while (0)
 
-constexpr int32_t kFp64DiagMinCols = 1024;   // FP32 fronts with >= this many pivots factor diagonal blocks in FP64
+// FP32 fronts with at least this many pivots factor their diagonal blocks in
+// FP64 (environment WCS_FP64_DIAG_COLS, default 1024; read when a factor is created)
+int32_t fp64_diag_min_cols()
+{
+    const char *e = std::getenv("WCS_FP64_DIAG_COLS");
+    return e ? std::atoi(e) : 1024;
+}
 
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
@@ -127,6 +133,7 @@ struct Plan {
     void build(const Symbolic &S)
     {
         int32_t ns = S.ns;
+        const int32_t diag64 = fp64_diag_min_cols();
         mfront.resize(ns);
         pfront.resize(ns);
         first.resize(ns);
@@ -223,7 +230,7 @@ struct Plan {
                         Op op{pass ? OP_PANEL_FP64DIAG : OP_PANEL, k0, NB, (int64_t)pan_tasks.size(), 0};
                         for (int32_t s : fr) {
                             int32_t p = pfront[s], m = mfront[s];
-                            if (p <= k0 || (p >= kFp64DiagMinCols) != (pass == 1)) continue;
+                            if (p <= k0 || (p >= diag64) != (pass == 1)) continue;
                             int32_t nb = std::min(NB, p - k0);
                             int32_t nt = std::max(1, (m - k0 - nb + TRW - 1) / TRW);
                             for (int32_t t = 0; t < nt; t++) pan_tasks.push_back(make_int2(s, t));
