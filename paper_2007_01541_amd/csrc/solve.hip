@@ -363,6 +363,66 @@ __device__ void bwd_cols_staged(const T *__restrict__ L, int ld, int a, int na, 
     __syncthreads();
 }
 
+// The same for at most four right-hand sides (KT = 4), as a transposed
+// matrix-vector product: lane = row (the four waves take 64 rows each per
+// round of 256), so each of the 64 column loads of a lane is coalesced
+// across the wave and all are in flight together; the 64 products of a lane
+// are summed over the wave by a butterfly (at step h a lane keeps the half of
+// its columns on its side of bit h and adds the partner's copy of them), which
+// leaves column c's sum in lane c; the four waves' sums meet in Ls (reused)
+// and are added in wave order.  All threads of the workgroup call it.
+template <typename T, int KT, typename XR>
+__device__ void bwd_cols_lanes(const T *__restrict__ L, int ld, int a, int na, int r0, int r1, XR xrow, int k,
+                               int c0, T *__restrict__ v, T (*Ls)[SB + 1])
+{
+    static_assert(KT <= 4 && 4 * SB * KT <= SB * (SB + 1), "few right-hand sides only");
+    int tid = threadIdx.x, wave = tid / SB, lane = tid % SB;
+    __syncthreads();            // as in bwd_cols: writes of v by other waves come first
+    if (r0 >= r1) return;
+    T tot[KT];
+#pragma unroll
+    for (int cc = 0; cc < KT; cc++) tot[cc] = 0;
+    for (int rb = r0 + wave * SB; rb < r1; rb += 4 * SB) {
+        int r = rb + lane;
+        bool ok = r < r1;
+        T xv[KT];
+        const T *xr = ok ? xrow(r) + c0 : nullptr;
+#pragma unroll
+        for (int cc = 0; cc < KT; cc++) xv[cc] = (ok && c0 + cc < k) ? xr[cc] : (T)0;
+        T lv[SB];
+#pragma unroll
+        for (int c = 0; c < SB; c++) lv[c] = (ok && c < na) ? L[(int64_t)(a + c) * ld + r] : (T)0;
+#pragma unroll
+        for (int cc = 0; cc < KT; cc++) {
+            if (c0 + cc >= k) break;
+            T pr[SB];
+#pragma unroll
+            for (int c = 0; c < SB; c++) pr[c] = lv[c] * xv[cc];
+#pragma unroll
+            for (int h = SB / 2; h >= 1; h >>= 1) {
+                bool up = (lane & h) != 0;
+#pragma unroll
+                for (int i = 0; i < h; i++) {
+                    T give = up ? pr[i] : pr[i + h], keep = up ? pr[i + h] : pr[i];
+                    pr[i] = keep + __shfl_xor(give, h, SB);
+                }
+            }
+            tot[cc] += pr[0];       // column `lane`, summed over the wave's rows
+        }
+    }
+    T *part = &Ls[0][0];
+#pragma unroll
+    for (int cc = 0; cc < KT; cc++) part[(wave * SB + lane) * KT + cc] = tot[cc];
+    __syncthreads();
+    for (int e = tid; e < SB * KT; e += blockDim.x) {
+        int c = e / KT, cc = e % KT;
+        if (c < na && c0 + cc < k)
+            v[(int64_t)c * k + c0 + cc] -= (part[c * KT + cc] + part[(SB + c) * KT + cc]) +
+                                          (part[(2 * SB + c) * KT + cc] + part[(3 * SB + c) * KT + cc]);
+    }
+    __syncthreads();
+}
+
 template <typename T, int KT>
 __device__ __forceinline__ void fwd_rows_any(const T *L, int ld, int kb, int nbk, T *w, int k, int c0, int r0, int r1,
                                              T (*Zs)[KT])
@@ -1333,7 +1393,9 @@ __global__ __launch_bounds__(THREADS) void k_bwd_below_part(const int4 *__restri
     for (int64_t i = threadIdx.x; i < (int64_t)SB * k; i += blockDim.x) out[i] = (T)0;
     auto xrow = [&](int r) { return Y + (int64_t)rw[r] * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
-        if constexpr (sizeof(T) == 4)   // measured: staged 64 rows at a time is faster in FP32, not in FP64
+        if constexpr (KT <= 4)
+            bwd_cols_lanes<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls);
+        else if constexpr (sizeof(T) == 4)   // measured: staged 64 rows at a time is faster in FP32, not in FP64
             bwd_cols_staged<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
         else
             bwd_cols_any<T, KT>(L, front_ld(m), ab, na, max(r0, p), r1, xrow, k, c0, out, sh.Ls, sh.Ss);
