@@ -1315,7 +1315,10 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_scols(c
     __shared__ BwdLds<T, KT> sh;
     auto xrow = [&](int r) { return Y + (int64_t)(f0 + r) * k; };
     for (int c0 = 0; c0 < k; c0 += KT)
-        bwd_cols_any<T, KT>(L, front_ld(m), ab, SB, s0, s1, xrow, k, c0, w + (int64_t)ab * k, sh.Ls, sh.Ss);
+        if constexpr (KT <= 4)
+            bwd_cols_lanes<T, KT>(L, front_ld(m), ab, SB, s0, s1, xrow, k, c0, w + (int64_t)ab * k, sh.Ls);
+        else
+            bwd_cols_any<T, KT>(L, front_ld(m), ab, SB, s0, s1, xrow, k, c0, w + (int64_t)ab * k, sh.Ls, sh.Ss);
 }
 
 // backward update rows, split: task = (front, column block a, first row, slot):
