@@ -852,11 +852,6 @@ template <typename T, int KT> struct BlkAcc {
     }
 };
 
-template <typename T, int KT> struct SxLds {
-    T D[SB][SB + 1];
-    T S[SB][KT];
-};
-
 // forward, task = (front, block i of the super-block at s0): z_i = sum_{j <= i} X_ij w_j -> Y
 template <typename T, int KT>
 __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_fwd_sz(const int2 *__restrict__ tasks, int s0, SolveArgs<T> a)
