@@ -370,8 +370,9 @@ __device__ void bwd_cols_staged(const T *__restrict__ L, int ld, int a, int na, 
 // are summed over the wave by a butterfly (at step h a lane keeps the half of
 // its columns on its side of bit h and adds the partner's copy of them), which
 // leaves column c's sum in lane c; the four waves' sums meet in Ls (reused)
-// and are added in wave order.  All threads of the workgroup call it.
-template <typename T, int KT, typename XR>
+// and are added in wave order (ASSIGN: v_a[c][cc] = the sum instead).  All
+// threads of the workgroup call it.
+template <typename T, int KT, typename XR, bool ASSIGN = false>
 __device__ void bwd_cols_lanes(const T *__restrict__ L, int ld, int a, int na, int r0, int r1, XR xrow, int k,
                                int c0, T *__restrict__ v, T (*Ls)[SB + 1])
 {
@@ -416,9 +417,12 @@ __device__ void bwd_cols_lanes(const T *__restrict__ L, int ld, int a, int na, i
     __syncthreads();
     for (int e = tid; e < SB * KT; e += blockDim.x) {
         int c = e / KT, cc = e % KT;
-        if (c < na && c0 + cc < k)
-            v[(int64_t)c * k + c0 + cc] -= (part[c * KT + cc] + part[(SB + c) * KT + cc]) +
-                                          (part[(2 * SB + c) * KT + cc] + part[(3 * SB + c) * KT + cc]);
+        if (c < na && c0 + cc < k) {
+            T sum = (part[c * KT + cc] + part[(SB + c) * KT + cc]) +
+                    (part[(2 * SB + c) * KT + cc] + part[(3 * SB + c) * KT + cc]);
+            if constexpr (ASSIGN) v[(int64_t)c * k + c0 + cc] = sum;
+            else v[(int64_t)c * k + c0 + cc] -= sum;
+        }
     }
     __syncthreads();
 }
@@ -1190,6 +1194,16 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_bwd_sx(cons
             else
                 reduce4<T>(acc, mm.red, put);
         }
+        return;
+    }
+    if constexpr (KT <= 4) {
+        // x_j = sum over the rows of the blocks i >= j of X(row, j0 + r) v(row):
+        // a transposed product over the super-block's rows (lane = row)
+        __shared__ T Lt[SB][SB + 1];
+        auto vrow = [&](int r) { return w + (int64_t)(s0 + r) * k; };
+        for (int c0 = 0; c0 < k; c0 += KT)
+            bwd_cols_lanes<T, KT, decltype(vrow), true>(X, SS, j0 - s0, nj, j0 - s0, s1 - s0, vrow, k, c0,
+                                                        a.Y + (int64_t)(f0 + j0) * k, Lt);
         return;
     }
     // KT < 64: wave q adds X_ij^T v_i for block i = j + q, lane = output row r
