@@ -67,3 +67,26 @@ def test_batch_instance_ranges():
         w = batch_instance(i)
         assert w.spec.grid_exp in (5, 6, 7)
         assert 0.1 <= w.spec.ell <= 0.5 and 1.2 <= w.spec.a <= 2.0 and w.spec.s in (0.25, 0.5, 0.75)
+
+
+def test_heat_spot_forcing_follows_the_circle():
+    """The time-stepping forcing: n x len(times); at each time the largest
+    coefficient among the finest wavelets sits next to the spot centre
+    r (cos 2 pi t, sin 2 pi t), r = 1/2, on [0,1]^2 mapped to [-1,1]^2; the
+    trajectory has period 1 and the coefficients carry the factor 2^-j."""
+    from workloads import WaveletSpec, centers, heat_spot_forcing
+    spec = WaveletSpec(5, 1.5, 0.375, "exp", 0.3, 1.5, 7)
+    times = np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+    F = heat_spot_forcing(spec, times)
+    c, level = centers(spec.grid_exp)
+    assert F.shape == (4 ** spec.grid_exp, times.size)
+    fine = level == spec.grid_exp - 1
+    for i, t in enumerate(times):
+        spot = np.array([0.5 * np.cos(2 * np.pi * t), 0.5 * np.sin(2 * np.pi * t)])
+        best = np.argmax(np.where(fine, F[:, i], -np.inf))
+        assert np.linalg.norm((2 * c[best] - 1) - spot) <= 2.0 ** -(spec.grid_exp - 1) * np.sqrt(2)
+    np.testing.assert_allclose(F[:, 0], F[:, -1], rtol=1e-12, atol=0)
+    # a coefficient is 2^-j times f at the support centre
+    x = 2 * c - 1
+    f0 = 100 * np.exp(-40 * (x[:, 0] - 0.5) ** 2 - 40 * x[:, 1] ** 2)
+    np.testing.assert_allclose(F[:, 0], 2.0 ** -level * f0, rtol=1e-12)
