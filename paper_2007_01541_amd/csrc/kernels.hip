@@ -1052,11 +1052,27 @@ __global__ void k_rows_out(const T *__restrict__ Y, int n, int k, double *__rest
 // ---------------------------------------------------------------- A * X (FP64)
 // Full symmetric CSR in the original order; values expanded from the stored
 // lower entries by k_expand_values.
+// Each thread takes eight grid-strided entries per pass, their source indices
+// and then their gathered values all in flight before the stores, so that a
+// small grid (one that leaves most of the chip to another stream) still keeps
+// enough loads outstanding.
 __global__ void k_expand_values(const double *__restrict__ values, const int64_t *__restrict__ src, int64_t nnz,
                                 double *__restrict__ out)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += (int64_t)gridDim.x * blockDim.x)
-        out[i] = values[src[i]];
+    constexpr int U = 8;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (U - 1) * stride < nnz; i += U * stride) {
+        int64_t s[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) s[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = values[s[u]];
+#pragma unroll
+        for (int u = 0; u < U; u++) __builtin_nontemporal_store(v[u], out + i + u * stride);
+    }
+    for (; i < nnz; i += stride) out[i] = values[src[i]];
 }
 
 // R = B - A X (or Y = A X when B is null).  Element (row i, column c) of X,

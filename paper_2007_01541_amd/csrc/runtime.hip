@@ -39,6 +39,17 @@ int32_t fp64_diag_min_cols()
     return e ? std::atoi(e) : 1024;
 }
 
+// Workgroups of the matrix-value expansion when it runs beside the first
+// solve of a refinement (environment WCS_EXPAND_BLOCKS, default 256: one per
+// CU of an MI355X; measured on the 2^18 headline system with 64 right-hand
+// sides, 128 and 256 are equally fast, 64 and 512 or more slower)
+int expand_side_blocks()
+{
+    const char *e = std::getenv("WCS_EXPAND_BLOCKS");
+    int b = e ? std::atoi(e) : 256;
+    return b > 0 ? b : 256;
+}
+
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
 // independent diagonal blocks of the matrix (1 unless it is a batch)
@@ -1031,11 +1042,16 @@ int launch_apply(wcs_factor f, int part, int k, double *B, int64_t ld, hipStream
     return WCS_OK;
 }
 
-int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st)
+// beside = true: the expansion runs on a side stream next to the first solve
+// of a refinement; its grid is then held to expand_side_blocks() workgroups,
+// so that the solve's kernels are not queued behind its 2^16 workgroups.
+int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st, bool beside = false)
 {
     const Symbolic &S = *f->S;
     int64_t nz = (int64_t)S.csr_col.size();
-    hipLaunchKernelGGL(k_expand_values, dim3(grid_for(nz)), dim3(256), 0, st, values,
+    int grid = grid_for(nz);
+    if (beside) grid = std::min(grid, expand_side_blocks());
+    hipLaunchKernelGGL(k_expand_values, dim3(grid), dim3(256), 0, st, values,
                        f->at<int64_t>(f->lay.csr_src), nz, f->at<double>(f->lay.csr_val));
     HIP_TRY(hipGetLastError());
     f->csr_values_from = values;
@@ -1241,7 +1257,7 @@ int solve_refined(wcs_factor f, const double *values, int k, const double *B, do
         HIP_TRY(hipEventRecord(f->ev_main, st));
         HIP_TRY(hipStreamWaitEvent(aux, f->ev_main, 0));
     }
-    int rc = ensure_csr_values(f, values, aux);
+    int rc = ensure_csr_values(f, values, aux, aux != st);
     if (rc) return rc;
     if (aux != st) HIP_TRY(hipEventRecord(f->ev_aux, aux));
     gather_rows(f, B, ld, k, f->at<double>(Lo.Br), st);
