@@ -533,7 +533,6 @@ struct wcs_factor_s {
     char *ws = nullptr;
     size_t bytes = 0;
     bool have_values = false;
-    const double *csr_values_from = nullptr;   // values pointer the expanded CSR values were built from
     std::vector<double> last_rel;              // last refinement residuals per (segment, column)
 
     // replay of recorded launch sequences (wcs_factor_use_graphs)
@@ -1054,7 +1053,6 @@ int ensure_csr_values(wcs_factor f, const double *values, hipStream_t st, bool b
     hipLaunchKernelGGL(k_expand_values, dim3(grid), dim3(256), 0, st, values,
                        f->at<int64_t>(f->lay.csr_src), nz, f->at<double>(f->lay.csr_val));
     HIP_TRY(hipGetLastError());
-    f->csr_values_from = values;
     return WCS_OK;
 }
 
@@ -1497,7 +1495,6 @@ int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream
     }
     if (rc) return rc;
     f->have_values = true;
-    f->csr_values_from = nullptr;
     if (bad_col) return wcs_factor_check(f, stream, bad_col);
     return WCS_OK;
 }
@@ -1512,7 +1509,6 @@ int wcs_factor_profile(wcs_factor f, const double *values_dev, wcs_stream stream
                                  : launch_factor<float>(f, values_dev, st, &prof);
     if (rc) return rc;
     f->have_values = true;
-    f->csr_values_from = nullptr;
     return prof.collect(stats);
 }
 
@@ -1544,7 +1540,6 @@ int wcs_factor_profile_levels(wcs_factor f, const double *values_dev, wcs_stream
                                  : launch_factor<float>(f, values_dev, st, &prof);
     if (rc) return rc;
     f->have_values = true;
-    f->csr_values_from = nullptr;
     return prof.collect_levels(levels);
 }
 
@@ -1604,7 +1599,6 @@ int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream strea
         f->fgraph_values = nullptr;
     }
     f->have_values = true;
-    f->csr_values_from = nullptr;
     return WCS_OK;
 }
 
