@@ -215,6 +215,35 @@ def test_fp32_refined_long_rows():
     assert res.max() <= 1e-10 and abs(res.max() - rep["final_residual"]) <= 1e-12
 
 
+@pytest.mark.parametrize("kind", ["small", "medium"])
+def test_refined_independent_of_expansion_grid(kind, monkeypatch):
+    """The matrix values for the residual are expanded on a side stream with a
+    bounded grid (environment WCS_EXPAND_BLOCKS, read at each call): one
+    workgroup (the eight-deep loop runs from 1,793 entries on), the default and
+    a grid larger than the work must give bitwise the same refined solution
+    and report, and that solution reaches 1e-10 against the oracle."""
+    if kind == "medium":
+        m, sym = medium()
+    else:
+        m, sym, _ = prepared(kind)
+    n, k = m["n"], 8
+    nnz_full = 2 * len(m["rowind"]) - n
+    B = normal_rhs(n, k, 57)
+    f = Factor(sym, FP32, max_nrhs=k)
+    vals = dev(m["values"])
+    f.numeric(vals)
+    out = []
+    for blocks in ("1", "256", "65536"):
+        monkeypatch.setenv("WCS_EXPAND_BLOCKS", blocks)
+        print(f"case {kind} n={n} nnz={nnz_full} expansion blocks {blocks}", flush=True)
+        X, rep = f.solve_refined(dev(B), vals, tol=1e-10, max_iter=10)
+        out.append((X.cpu().numpy(), rep))
+    for X, rep in out[1:]:
+        assert np.array_equal(X, out[0][0]) and rep == out[0][1]
+    res = oracle.residual(n, m["colptr"], m["rowind"], m["values"], out[0][0], B)
+    assert res.max() <= 1e-10
+
+
 @pytest.mark.parametrize("prec", [FP64, FP32])
 @pytest.mark.parametrize("k", [1, 3, 64, 70])
 def test_factor_products_match_oracle(prec, k):
