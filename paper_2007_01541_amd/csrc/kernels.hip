@@ -1223,15 +1223,20 @@ template <> struct SpmvVec<float> {
         return (double)(j == 0 ? x.x : j == 1 ? x.y : j == 2 ? x.z : x.w);
     }
 };
+// FP32 rows of exactly four columns (k = 4): two 8-byte halves per lane
+struct SpmvVecF4 {
+    using V = float2;
+    static constexpr int EL = 4;
+    __device__ static double at(const V &x, int j) { return (double)(j == 0 ? x.x : x.y); }
+};
 
-template <int LPE, typename TX>
+template <int LPE, typename TX, typename SV = SpmvVec<TX>>
 __global__ __launch_bounds__(256) void k_spmv_vec(const int4 *__restrict__ items, int nitems,
                                                   const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
                                                   const double *__restrict__ v, const TX *__restrict__ X,
                                                   const double *B, const double *__restrict__ mul, double *R,
                                                   double *__restrict__ P)
 {
-    using SV = SpmvVec<TX>;
     using V = typename SV::V;
     constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
     constexpr int U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
@@ -1241,7 +1246,7 @@ __global__ __launch_bounds__(256) void k_spmv_vec(const int4 *__restrict__ items
     int row = w4.x;
     int q = lane / LPE, ql = lane % LPE;
     int64_t a = rp[row] + w4.y, b = rp[row] + w4.z;
-    const V *xc = reinterpret_cast<const V *>(X) + 2 * ql;   // a row is 2 LPE vectors of 16 bytes
+    const V *xc = reinterpret_cast<const V *>(X) + 2 * ql;   // a row is 2 LPE vectors V
     double s[EL];
 #pragma unroll
     for (int j = 0; j < EL; j++) s[j] = 0;

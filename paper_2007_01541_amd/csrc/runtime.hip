@@ -1083,6 +1083,7 @@ void scatter_rows(wcs_factor f, const double *Xp, int k, double *X, int64_t ld, 
 template <typename TX> bool spmv_vec_fits(int k)
 {
     constexpr int EL = sizeof(TX) == 8 ? 4 : 8, maxl = sizeof(TX) == 8 ? 16 : 8;
+    if (sizeof(TX) == 4 && k == 4) return true;     // the four-column FP32 form
     return k % EL == 0 && k / EL <= maxl && ((k / EL) & (k / EL - 1)) == 0;
 }
 
@@ -1099,6 +1100,15 @@ void launch_spmv_vec(wcs_factor f, int k, const TX *X, const double *B, const do
     double *part = f->at<double>(f->lay.sppart);
     int ni = (int)P.spmv_chunks.size();
     dim3 g((unsigned)((ni + 3) / 4)), b(256);
+    if constexpr (sizeof(TX) == 4) {
+        if (k == 4) {
+            hipLaunchKernelGGL((k_spmv_vec<1, TX, SpmvVecF4>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part);
+            if (!P.spmv_long.empty())
+                hipLaunchKernelGGL(k_spmv_long_sum, dim3((unsigned)P.spmv_long.size()), dim3(64), 0, st,
+                                   f->at<int4>(f->lay.splong), k, (int64_t)k, part, B, mul, R);
+            return;
+        }
+    }
     switch (k / (sizeof(TX) == 8 ? 4 : 8)) {
     case 1: hipLaunchKernelGGL((k_spmv_vec<1, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
     case 2: hipLaunchKernelGGL((k_spmv_vec<2, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;

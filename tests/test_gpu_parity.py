@@ -117,12 +117,12 @@ def test_fp32_refined_reaches_1e10(kind, leaf, coords, k):
 @pytest.mark.parametrize("kind", ["small", "g6alg"])
 @pytest.mark.parametrize("k", [4, 8, 32, 64])
 def test_updated_residual_tracks_true_residual(kind, k):
-    """With an FP32 factor and 8, 16, 32 or 64 right-hand sides the residual is
-    updated from the FP32 corrections (R -= A D) instead of being recomputed
-    from X; the reported per-column residuals must stay the true ones
-    ||b - A x|| / ||b|| (oracle, FP64) up to the FP64 rounding of x, through
-    several corrections (tolerance far below what one correction reaches).
-    k = 4 takes the recomputed form and must agree as well."""
+    """With an FP32 factor and 4, 8, 16, 32 or 64 right-hand sides the residual
+    is updated from the FP32 corrections (R -= A D) instead of being recomputed
+    from X (k = 4 in the four-column form of the SpMV); the reported
+    per-column residuals must stay the true ones ||b - A x|| / ||b|| (oracle,
+    FP64) up to the FP64 rounding of x, through several corrections
+    (tolerance far below what one correction reaches)."""
     m, sym, _ = prepared(kind)
     n = m["n"]
     B = normal_rhs(n, k, 31) * np.logspace(-3, 3, k)     # columns of very different scales
@@ -201,17 +201,19 @@ def test_spmv_long_rows_match_oracle(k):
     assert np.abs(Y - Yo).max() <= 1e-13 * np.abs(Yo).max()
 
 
-def test_fp32_refined_long_rows():
-    """The FP32-row residual forms (first residual and updates) over split rows."""
+@pytest.mark.parametrize("k", [4, 64])
+def test_fp32_refined_long_rows(k):
+    """The FP32-row residual forms (first residual and updates; k = 4 in the
+    four-column form) over split rows."""
     m, sym = medium()
-    n, k = m["n"], 64
+    n = m["n"]
     B = normal_rhs(n, k, 13)
     f = Factor(sym, FP32, max_nrhs=k)
     vals = dev(m["values"])
     f.numeric(vals)
     X, rep = f.solve_refined(dev(B), vals, tol=1e-10, max_iter=10)
     res = oracle.residual(n, m["colptr"], m["rowind"], m["values"], X.cpu().numpy(), B)
-    print(f"medium k=64: {rep}, true residual {res.max():.3e}", flush=True)
+    print(f"medium k={k}: {rep}, true residual {res.max():.3e}", flush=True)
     assert res.max() <= 1e-10 and abs(res.max() - rep["final_residual"]) <= 1e-12
 
 
