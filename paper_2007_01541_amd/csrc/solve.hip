@@ -475,10 +475,30 @@ __global__ __launch_bounds__(THREADS) void k_fwd_fused(const int32_t *__restrict
     }
 }
 
+// First i in [lo, hi) with rl[i] >= key (hi if none), rl increasing; called
+// by every lane of a wave alike.  Each round the 64 lanes probe evenly spaced
+// entries and a ballot counts those below key, shrinking the range 64-fold:
+// a few dependent loads instead of one per halving.
+__device__ __forceinline__ int wave_lower_bound(const int32_t *__restrict__ rl, int lo, int hi, int key)
+{
+    const int lane = threadIdx.x % 64;
+    while (hi > lo) {
+        const int span = hi - lo;
+        const int step = span <= 64 ? 1 : (span + 63) / 64;
+        const int pos = lo + lane * step;
+        const int cnt = __popcll(__ballot(pos < hi && rl[pos] < key));
+        if (span <= 64 || cnt == 0) return lo + (span <= 64 ? cnt : 0);
+        const int base = lo;
+        lo = base + (cnt - 1) * step + 1;      // rl[lo - 1] < key
+        hi = min(hi, base + cnt * step);      // rl[hi] >= key, or hi unchanged
+    }
+    return lo;
+}
+
 // task = (front, row slab of SROWS rows): w rows of the slab = [Y(pivots); 0]
 // plus the update rows of every child that land in the slab.  The index map
-// of a child is increasing, so those rows are one contiguous run found by
-// binary search; children are visited in a fixed order (deterministic).
+// of a child is increasing, so those rows are one contiguous run found by a
+// wave-parallel search; children are visited in a fixed order (deterministic).
 // With k a multiple of 4 every thread moves groups of four columns of a row
 // (vector accesses); loads of a round are issued before its stores.
 template <typename T>
@@ -507,12 +527,8 @@ __global__ __launch_bounds__(THREADS) void k_fwd_assemble(const int2 *__restrict
         int mc = a.mfront[c], pc = a.pfront[c];
         const int32_t *rl = a.rel + a.rptr[c] + pc;
         int nu = mc - pc;
-        int lo = 0, hi = nu;
-        while (lo < hi) { int md = (lo + hi) / 2; if (rl[md] < r0) lo = md + 1; else hi = md; }
-        int t0 = lo;
-        hi = nu;
-        while (lo < hi) { int md = (lo + hi) / 2; if (rl[md] < r1) lo = md + 1; else hi = md; }
-        int t1 = lo;
+        const int t0 = wave_lower_bound(rl, 0, nu, r0);
+        const int t1 = wave_lower_bound(rl, t0, nu, r1);
         const T *wc = a.W + a.woff[c] * k + (int64_t)pc * k;
         int tot = (t1 - t0) * ng;
         constexpr int B = 2;   // groups per thread per round
