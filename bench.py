@@ -66,7 +66,12 @@ def sample_flops(Lp, Li, ncols: int) -> float:
     return total
 
 
-def cpu_baseline(m, perm, target_seconds: float) -> dict:
+def cpu_baseline(m, perm, target_seconds: float, analysis=None, X=None, B=None) -> dict:
+    """The oracle on the host: its symbolic analysis of the same ordering
+    (compared with the library's, `analysis` = (export dict, info dict)), the
+    true residual of the GPU solution X of A X = B formed with the oracle's
+    product on four of its columns, and the timed sample of its numeric
+    factorization."""
     import numpy as np
     import oracle
     n = m["n"]
@@ -74,6 +79,19 @@ def cpu_baseline(m, perm, target_seconds: float) -> dict:
     parent, cc, nnzL, flops = oracle.symbolic(n, m["colptr"], m["rowind"], perm)
     Lp, Li = oracle.pattern(n, m["colptr"], m["rowind"], perm, parent, cc)
     log(f"oracle symbolic+pattern {time.perf_counter() - t0:.1f}s")
+    checks = {}
+    if analysis is not None:
+        ex, inf = analysis
+        same = (np.array_equal(ex["parent"], parent) and np.array_equal(ex["colcount"], cc)
+                and inf["nnz_l"] == nnzL and inf["flops"] == flops)
+        log(f"analysis vs oracle symbolic: {'bit-exact' if same else 'MISMATCH'}")
+        assert same, "symbolic analysis differs from the oracle"
+        checks["symbolic_bit_exact"] = True
+    if X is not None:
+        cols = np.linspace(0, X.shape[1] - 1, min(4, X.shape[1])).astype(int)
+        res = oracle.residual(n, m["colptr"], m["rowind"], m["values"], X[:, cols], B[:, cols])
+        checks["oracle_true_residual"] = float(res.max())
+        log(f"oracle residual of the FP32+IR solution (columns {cols.tolist()}): {res.max():.3e}")
     # first a short calibration, then a sample sized for the target time from
     # the flops the oracle actually performs on a leading block of columns
     cum = np.cumsum(cc.astype(np.float64) ** 2)
@@ -99,10 +117,10 @@ def cpu_baseline(m, perm, target_seconds: float) -> dict:
         t = time.perf_counter() - t0
     fl = sample_flops(Lp, Li, k)
     log(f"oracle sample: {k} leading pivot columns, {fl / 1e9:.1f} GFLOP in {t:.1f}s")
-    return {"value": fl / t / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"left-looking FP64 factorization of the first {k} of {n} pivot columns "
-                      f"(nested dissection order) of the same matrix: {fl:.4g} flops in {t:.2f} s, "
-                      f"single thread"}
+    return dict({"value": fl / t / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+                 "sample": f"left-looking FP64 factorization of the first {k} of {n} pivot columns "
+                           f"(nested dissection order) of the same matrix: {fl:.4g} flops in {t:.2f} s, "
+                           f"single thread"}, **checks)
 
 
 def bench_batch(args) -> int:
@@ -393,6 +411,7 @@ def main() -> int:
     rep32 = dict(rep32, true_residual=float(res_true.max()))
     log(f"  true residual of the last FP32+IR solution: {rep32['true_residual']:.3e}")
     assert rep32["true_residual"] <= args.tol, rep32
+    X32_host = X32.cpu().numpy()
     prof = f32.profile(vals)
     torch.cuda.synchronize()
     for st_ in prof.values():      # algorithmic HBM bytes of the bandwidth-bound classes per second
@@ -486,8 +505,11 @@ def main() -> int:
 
     cpu = None
     if not args.no_cpu_baseline:
-        perm = sym.export()["perm"]
-        cpu = cpu_baseline(m, perm, args.cpu_seconds)
+        ex = sym.export()
+        cpu = cpu_baseline(m, ex["perm"], args.cpu_seconds, analysis=(ex, info), X=X32_host, B=B)
+        if "oracle_true_residual" in cpu:
+            rep32["oracle_true_residual"] = cpu["oracle_true_residual"]
+            assert cpu["oracle_true_residual"] <= args.tol
 
     value = F / fact32 / 1e9
     out = {

@@ -316,7 +316,10 @@ int wcs_apply(wcs_factor f, wcs_apply_part part, int32_t nrhs, double *B_dev, in
  * 16, 32 or 64 form R from the FP32 solve outputs instead of X: R = B - A X0,
  * then R -= A D after each correction D (FP64 products and sums); this equals
  * B - A X up to the FP64 rounding of the sums X + D (about eps |A| |X|), so
- * tol should stay well above eps times the condition number.  values_dev are
+ * tol should stay well above eps times the condition number.  When that
+ * updated residual meets tol by less than a factor 100, R is formed once more
+ * from X itself (FP64) and that residual decides; rep->final_residual and
+ * wcs_factor_residuals report the residual the decision used.  values_dev are
  * the FP64 values used by the factorization (same pattern).  Reads the
  * residual norms back to the host once per step (synchronous).  Returns
  * WCS_ENOTCONV (with *rep filled, and X_dev holding the last iterate) if tol

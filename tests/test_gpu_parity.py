@@ -110,6 +110,7 @@ def test_fp32_refined_reaches_1e10(kind, leaf, coords, k):
     assert res.max() <= 1e-10
     assert rep["final_residual"] <= 1e-10
     assert rep["raw_residual"] > rep["final_residual"] or rep["iterations"] == 0
+    assert rep["iterations"] <= 3
     Xo = orc.solve(B)
     assert np.abs(X - Xo).max() <= 1e-10 * gershgorin_kappa(m) * np.abs(Xo).max()
 

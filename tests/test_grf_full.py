@@ -3,14 +3,19 @@
 Sample x = P^T L^-T z (precision form: Cov(x) = A^-1), then y = A^-1 b with
 b = x held fixed, loss 0.5 ||y - y*||^2, and its gradient with respect to
 the stored entries of A and to b from the adjoint that reuses L.  The oracle
-cannot factor this size in seconds, so the checks are properties that hold at
-any size, the oracle's gradient formula evaluated on the same lambda and y,
-and central finite differences on the GPU FP64 path at 32 sampled entries."""
+cannot factor this size in seconds, so the checks are its factorization of
+the leading pivot columns, properties that hold at any size (residuals formed
+by the oracle's product), the oracle's gradient formula evaluated on the same
+lambda and y, and central finite differences on the GPU FP64 path at 32
+sampled entries."""
+import types
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+from tests.helpers import EPS32, EPS64, compare_columns, factor_tol, leading_columns_backward_error
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -34,10 +39,36 @@ def test_grf_sample_and_gradient_full_size():
     f32 = Factor(sym, FP32)
     f32.numeric(vals)
 
+    # leading pivot columns of both factors against the oracle's left-looking
+    # factorization of the same columns: FP64 entrywise, FP32 by the
+    # componentwise backward error of those columns (kappa-free)
+    perm = sym.export()["perm"]
+    parent, cc, _, _ = oracle.symbolic(n, m["colptr"], m["rowind"], perm)
+    Lp_o, Li_o = oracle.pattern(n, m["colptr"], m["rowind"], perm, parent, cc)
+    k = int(np.searchsorted(np.cumsum(cc.astype(np.float64) ** 2), 1e10))
+    Lx_o = oracle.factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp_o, Li_o, ncols=k)
+    orc = types.SimpleNamespace(Lp=Lp_o, Li=Li_o, Lx=Lx_o)
+    Lp, Li, Lx = f64.export_L(0, k)
+    worst, scale = compare_columns(Lp, Li, Lx, orc)
+    print(f"leading {k} columns: FP64 max |L - L_oracle| / max |L| = {worst / scale:.3e}", flush=True)
+    assert worst <= factor_tol(m, int(cc.max()), EPS64) * scale
+    Lp, Li, Lx = f32.export_L(0, k)
+    ratio = leading_columns_backward_error(m, perm, Lp, Li, Lx, EPS32)
+    print(f"leading {k} columns: FP32 backward error / gamma bound = {ratio:.3e}", flush=True)
+    assert ratio <= 1.0
+
+    def symv(v):
+        return oracle.symv(n, m["colptr"], m["rowind"], m["values"], np.asarray(v, np.float64))
+
+    def rel_residual(v, rhs):
+        v, rhs = np.asarray(v), np.asarray(rhs)
+        return float(np.linalg.norm(symv(v) - rhs) / np.linalg.norm(rhs))
+
     # sample: x^T A x = z^T z for x = P^T L^-T z (exact identity with the exact factor)
     z = workloads.normal_rhs(n, 1, w.seed + 3)[:, 0]
     x = f64.solve(dev(z), part=SOLVE_LT)
-    q = float(torch.dot(x, f64.spmv(x, vals)))
+    xh = x.cpu().numpy()
+    q = float(xh @ symv(xh))
     zz = float(z @ z)
     print(f"x^T A x = {q:.15e}, z^T z = {zz:.15e}", flush=True)
     assert abs(q - zz) <= 1e-10 * zz
@@ -56,13 +87,10 @@ def test_grf_sample_and_gradient_full_size():
     gA = v.grad.cpu().numpy()
     gb = b.grad.cpu().numpy()
     yh = y.detach().cpu().numpy()
-    # y solves A y = b to 1e-10
-    r = f64.spmv(y.detach(), vals) - b.detach()
-    assert float(torch.linalg.norm(r) / torch.linalg.norm(b.detach())) <= 1e-10
+    # y solves A y = b to 1e-10 (residual by the oracle's product)
+    assert rel_residual(yh, b.detach().cpu().numpy()) <= 1e-10
     # gb = lambda solves A lambda = y - y* to 1e-10; gA is the oracle's formula on that lambda and y
-    lam = dev(gb)
-    r = f64.spmv(lam, vals) - (y.detach() - ystar)
-    assert float(torch.linalg.norm(r) / torch.linalg.norm(y.detach() - ystar)) <= 1e-10
+    assert rel_residual(gb, yh - ystar.cpu().numpy()) <= 1e-10
     g_orc = oracle.grad(n, m["colptr"], m["rowind"], gb, yh)
     assert np.abs(gA - g_orc).max() <= 1e-14 * np.abs(g_orc).max()
 

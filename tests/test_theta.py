@@ -111,11 +111,15 @@ def test_theta_full_size_properties():
     U64, _ = fa.theta_steps(A, THETA, DT, Fd, dev(np.zeros(n)))
     U32, rep = f32.theta_steps(A, THETA, DT, Fd, dev(np.zeros(n)), tol=1e-10)
     print(f"  FP32 + refinement report {rep}", flush=True)
+    def K(v):        # the oracle's product with K
+        return oracle.symv(n, m["colptr"], m["rowind"], m["values"], v)
+
     for U in (U64, U32):
+        Uh = U.cpu().numpy()
         for i in (0, 1, 37, 74, NSTEPS - 1):
-            lhs = U[:, i + 1] + THETA * DT * fk.spmv(U[:, i + 1], kv)
-            rhs = U[:, i] - (1 - THETA) * DT * fk.spmv(U[:, i], kv) + DT * ((1 - THETA) * Fd[:, i] + THETA * Fd[:, i + 1])
-            rel = float(torch.linalg.norm(lhs - rhs) / torch.linalg.norm(rhs))
+            lhs = Uh[:, i + 1] + THETA * DT * K(Uh[:, i + 1])
+            rhs = Uh[:, i] - (1 - THETA) * DT * K(Uh[:, i]) + DT * ((1 - THETA) * F[:, i] + THETA * F[:, i + 1])
+            rel = float(np.linalg.norm(lhs - rhs) / np.linalg.norm(rhs))
             assert rel <= 1e-10, (i, rel)
     diff = float((U32 - U64).abs().max() / U64.abs().max())
     print(f"  FP32 + refinement vs FP64 trajectory: {diff:.3e}", flush=True)
