@@ -197,6 +197,29 @@ int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, s
 int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs,
                       void *workspace, size_t bytes, wcs_stream stream, wcs_factor *out);
 int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *bad_col);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc and provide
+ * no workspace): wcs_factor_create without a workspace argument.  The factor
+ * lives in a static device array of WCS_STATIC_WORKSPACE_BYTES that the
+ * library holds on every GPU it runs on until the process ends; the call
+ * allocates no device memory and creates no stream or event (every later
+ * call on this factor runs all its launches on the stream it is given, with
+ * no look-ahead or auxiliary stream).  The static array belongs to the
+ * current device and serves one factor at a time: WCS_ESTATE while another
+ * factor created by this call on the same device is alive (wcs_factor_free
+ * releases it), WCS_ENOMEM (with the needed size in wcs_last_error) when
+ * wcs_workspace_size for sym, prec and max_nrhs exceeds
+ * WCS_STATIC_WORKSPACE_BYTES.  The array keeps the last factor's contents;
+ * every numeric factorization clears what it needs.  Calls on such a factor
+ * that overlap in time on one GPU (different streams or threads) race.
+ * All other calls take the factor as they take one from wcs_factor_create and
+ * give the same results.  Synchronous (plan tables are copied on `stream`).
+ */
+#define WCS_STATIC_WORKSPACE_BYTES (64u << 20)
+int wcs_factor_create_static(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, wcs_stream stream,
+                             wcs_factor *out);
 /* Waits for the stream; *bad_col = first failing pivot or -1; returns WCS_ENOTSPD if one failed. */
 int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col);
 void wcs_factor_free(wcs_factor f);

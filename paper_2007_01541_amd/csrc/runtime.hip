@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -534,6 +535,7 @@ struct wcs_factor_s {
     size_t bytes = 0;
     bool have_values = false;
     std::vector<double> last_rel;              // last refinement residuals per (segment, column)
+    int static_device = -1;                    // device whose static workspace this factor holds, or -1
 
     // replay of recorded launch sequences (wcs_factor_use_graphs)
     bool graphs = false;
@@ -559,7 +561,8 @@ struct wcs_factor_s {
         for (auto &g : sgraphs) (void)hipGraphExecDestroy(g.exec);
         sgraphs.clear();
     }
-    ~wcs_factor_s()
+    ~wcs_factor_s();
+    void release()
     {
         drop_graphs();
         if (ev_main) (void)hipEventDestroy(ev_main);
@@ -571,6 +574,36 @@ struct wcs_factor_s {
 
     template <typename P> P *at(size_t off) const { return reinterpret_cast<P *>(ws + off); }
 };
+
+// ---------------------------------------------------------------- static workspace
+// Device memory of wcs_factor_create_static, for callers that cannot
+// allocate: a file-scope array of WCS_STATIC_WORKSPACE_BYTES that every GPU
+// the library runs on holds until the process ends.  Host code never passes
+// `scratch` itself to a kernel or a copy (on the host it names a stand-in,
+// not the device array): each device's address comes from
+// hipGetSymbolAddress, taken once per device with that device current.  At
+// most one factor per device lives in it at a time.
+__device__ __align__(256) unsigned char scratch[WCS_STATIC_WORKSPACE_BYTES];
+
+namespace wcs {
+namespace {
+struct StaticSlot {
+    char *ptr = nullptr;      // device address of `scratch` on this device
+    bool in_use = false;      // a live factor holds it
+};
+std::mutex g_static_mu;
+std::vector<StaticSlot> g_static;   // per device ordinal
+}  // namespace
+}  // namespace wcs
+
+wcs_factor_s::~wcs_factor_s()
+{
+    release();
+    if (static_device >= 0) {
+        std::lock_guard<std::mutex> lk(wcs::g_static_mu);
+        wcs::g_static[(size_t)static_device].in_use = false;
+    }
+}
 
 namespace wcs {
 namespace {
@@ -1379,18 +1412,13 @@ int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, s
     return WCS_OK;
 }
 
-int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, void *workspace, size_t bytes,
-                      wcs_stream stream, wcs_factor *out)
+}  // extern "C"
+
+namespace wcs {
+namespace {
+// Plan and layout of a new factor (host only).
+int new_factor(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, wcs_factor *fp)
 {
-    if (!sym || !out || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32) || !workspace) {
-        set_error("invalid argument to wcs_factor_create");
-        return WCS_EINVAL;
-    }
-    if (((uintptr_t)workspace) % 256) {
-        set_error("workspace must be 256-byte aligned");
-        return WCS_EINVAL;
-    }
-    *out = nullptr;
     wcs_factor f = new (std::nothrow) wcs_factor_s;
     if (!f) return WCS_ENOMEM;
     try {
@@ -1405,6 +1433,33 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
         set_error("host allocation failed");
         return WCS_ENOMEM;
     }
+    *fp = f;
+    return WCS_OK;
+}
+
+// Copies the static plan tables into the factor's workspace (stream order,
+// then waits: the host vectors are pageable).  Deletes f on failure.
+int upload_plan(wcs_factor f, hipStream_t st, wcs_factor *out);
+}  // namespace
+}  // namespace wcs
+
+extern "C" {
+
+int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, void *workspace, size_t bytes,
+                      wcs_stream stream, wcs_factor *out)
+{
+    if (!sym || !out || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32) || !workspace) {
+        set_error("invalid argument to wcs_factor_create");
+        return WCS_EINVAL;
+    }
+    if (((uintptr_t)workspace) % 256) {
+        set_error("workspace must be 256-byte aligned");
+        return WCS_EINVAL;
+    }
+    *out = nullptr;
+    wcs_factor f = nullptr;
+    int rc = new_factor(sym, prec, max_nrhs, &f);
+    if (rc) return rc;
     if (bytes < f->lay.total) {
         set_error("workspace too small: need " + std::to_string(f->lay.total) + " bytes, got " + std::to_string(bytes));
         delete f;
@@ -1421,12 +1476,66 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
         delete f;
         return WCS_EHIP;
     }
-    hipStream_t st = (hipStream_t)stream;
+    return upload_plan(f, (hipStream_t)stream, out);
+}
+
+int wcs_factor_create_static(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, wcs_stream stream,
+                             wcs_factor *out)
+{
+    if (!sym || !out || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32)) {
+        set_error("invalid argument to wcs_factor_create_static");
+        return WCS_EINVAL;
+    }
+    *out = nullptr;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    wcs_factor f = nullptr;
+    int rc = new_factor(sym, prec, max_nrhs, &f);
+    if (rc) return rc;
+    if (f->lay.total > (size_t)WCS_STATIC_WORKSPACE_BYTES) {
+        set_error("static workspace too small: this system needs " + std::to_string(f->lay.total) +
+                  " bytes, the static workspace holds " + std::to_string((size_t)WCS_STATIC_WORKSPACE_BYTES));
+        delete f;
+        return WCS_ENOMEM;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (g_static.size() <= (size_t)dev) g_static.resize((size_t)dev + 1);
+        StaticSlot &slot = g_static[(size_t)dev];
+        if (!slot.ptr) {   // first use on this device (it is current): the array's device address
+            void *p = nullptr;
+            hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+                delete f;
+                return WCS_EHIP;
+            }
+            slot.ptr = (char *)p;
+        }
+        if (slot.in_use) {
+            set_error("the static workspace of device " + std::to_string(dev) + " is held by another factor");
+            delete f;
+            return WCS_ESTATE;
+        }
+        slot.in_use = true;
+        f->ws = slot.ptr;
+        f->static_device = dev;
+    }
+    f->bytes = (size_t)WCS_STATIC_WORKSPACE_BYTES;
+    // no look-ahead or auxiliary stream: every launch goes to the caller's stream
+    return upload_plan(f, (hipStream_t)stream, out);
+}
+
+}  // extern "C"
+
+namespace wcs {
+namespace {
+int upload_plan(wcs_factor f, hipStream_t st, wcs_factor *out)
+{
     const Symbolic &S = *f->S;
     const Plan &P = f->plan;
     const Layout &L = f->lay;
     int rc = WCS_OK;
-    std::vector<int64_t> fo(S.front_off.begin(), S.front_off.end());
     rc = rc ? rc : upload(f, L.front_off, S.front_off, st);
     rc = rc ? rc : upload(f, L.mfront, P.mfront, st);
     rc = rc ? rc : upload(f, L.pfront, P.pfront, st);
@@ -1493,6 +1602,10 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
     *out = f;
     return WCS_OK;
 }
+}  // namespace
+}  // namespace wcs
+
+extern "C" {
 
 int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *bad_col)
 {

@@ -130,19 +130,28 @@ class Symbolic:
 class Factor:
     """A device factor P A P^T = L L^T living in a torch-owned workspace."""
 
-    def __init__(self, sym: Symbolic, precision: int = FP64, max_nrhs: int = 1, device=None, stream=None):
+    def __init__(self, sym: Symbolic, precision: int = FP64, max_nrhs: int = 1, device=None, stream=None,
+                 static_workspace: bool = False):
+        """static_workspace=True: no workspace tensor; the factor lives in the
+        library's static device array of the current device
+        (wcs_factor_create_static: one such factor per device at a time)."""
         torch = _torch()
         self.sym = sym
         self.n = sym.n
         self.precision = precision
         self.max_nrhs = max_nrhs
         self.device = torch.device(device if device is not None else "cuda")
-        nbytes = sym.workspace_size(precision, max_nrhs)
-        # 256-byte aligned by the caching allocator
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
-        check(lib().wcs_factor_create(sym.handle, precision, max_nrhs, _dptr(self.workspace), nbytes,
-                                      _stream_ptr(stream), C.byref(h)), "wcs_factor_create")
+        if static_workspace:
+            self.workspace = None
+            check(lib().wcs_factor_create_static(sym.handle, precision, max_nrhs, _stream_ptr(stream), C.byref(h)),
+                  "wcs_factor_create_static")
+        else:
+            nbytes = sym.workspace_size(precision, max_nrhs)
+            # 256-byte aligned by the caching allocator
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            check(lib().wcs_factor_create(sym.handle, precision, max_nrhs, _dptr(self.workspace), nbytes,
+                                          _stream_ptr(stream), C.byref(h)), "wcs_factor_create")
         self.handle = h
         self.values = None
 
