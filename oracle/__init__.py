@@ -20,4 +20,11 @@ from .oracle import (  # noqa: F401
     Factor,
     factorize,
     theta_steps,
+    lu,
+    lu_solve,
+    gemv,
+    gemv_residual,
+    LUFactor,
+    lu_factorize,
+    field_sample,
 )

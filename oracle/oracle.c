@@ -32,8 +32,16 @@
  * C = P A P^T has C[k][l] = A[perm[k]][perm[l]].  Dense right-hand sides are
  * column-major n x nrhs with leading dimension ld.
  *
+ *   - Section 5.1 (eq:PCM2) and Section 6.1: the nonsymmetric system
+ *     matrix of the polarizable continuum model is factored by LU on the
+ *     same ordering; its pattern is symmetric, so L has the Cholesky pattern
+ *     and U the transposed one.  orc_lu computes P A P^T = L U without
+ *     pivoting (L unit lower triangular, U upper triangular), orc_lu_solve
+ *     x = P^T U^-1 L^-1 P b, orc_gemv the product with the nonsymmetric A.
+ *
  * Return codes: 0 ok, -1 invalid input, -2 out of memory, -4 not positive
- * definite (first bad pivot column in *bad_col, pivot order).
+ * definite (first bad pivot column in *bad_col, pivot order), -5 a zero (or
+ * non-finite) pivot in the LU factorization (column in *bad_col).
  */
 #include <math.h>
 #include <stdint.h>
@@ -44,6 +52,7 @@
 #define ORC_EINVAL -1
 #define ORC_ENOMEM -2
 #define ORC_ENOTSPD -4
+#define ORC_ESINGULAR -5
 
 /* inverse permutation; returns -1 if perm is not a bijection of 0..n-1 */
 static int invert_perm(int32_t n, const int32_t *perm, int32_t *iperm)
@@ -496,4 +505,185 @@ int64_t orc_check_nd(int32_t n, const int64_t *colptr, const int32_t *rowind, co
     }
     free(iperm);
     return bad;
+}
+
+/* ------------------------------------------------------------------ LU */
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * Left-looking sparse LU without pivoting of C = P A P^T for a matrix A with
+ * a symmetric pattern (Section 5.1, eq:PCM2: the PCM system matrix; Section
+ * 6.1 factors it by LU on the nested dissection ordering).  A is given by its
+ * stored lower pattern (colptr, rowind) with two values per stored entry
+ * (r, c), r >= c: lval = A[r][c] and uval = A[c][r] (equal on the diagonal;
+ * uval of a diagonal entry is not read).
+ *
+ * Column j of the factors is the sparse triangular solve L(0:j,0:j) u = C(0:j, j)
+ * followed by l = (C(j+1:n, j) - L(j+1:n, 0:j) u) / u_jj: with w = C(:, j)
+ * scattered into a dense vector, for every k < j with u_kj != 0 in ascending
+ * order (each u_kj is final once the columns before k have been applied),
+ * u_kj = w[k] and w[i] -= l_ik u_kj for the rows i > k of column k of L.  The
+ * pattern of column j of U is that of row j of L (symmetric pattern), so the
+ * columns k are found with the same per-column "next row" lists as the
+ * Cholesky oracle.
+ *
+ * Output in the pattern (Lp, Li) of the Cholesky factor (orc_pattern):
+ * Lx = L with its unit diagonal stored as 1, Ux = U^T (entry q of column k,
+ * row Li[q], holds u(k, Li[q]); the diagonal slot holds u_kk).  Only the
+ * first ncols columns of both are computed (the rest untouched).
+ */
+int orc_lu(int32_t n, const int64_t *colptr, const int32_t *rowind, const double *lval, const double *uval,
+           const int32_t *perm, const int64_t *Lp, const int32_t *Li, double *Lx, double *Ux,
+           int32_t ncols, int32_t *bad_col)
+{
+    *bad_col = -1;
+    if (ncols < 0 || ncols > n) return ORC_EINVAL;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int32_t *iperm = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int64_t *cp = (int64_t *)calloc(nn + 1, sizeof(int64_t));
+    int64_t *cur = (int64_t *)malloc(sizeof(int64_t) * nn);
+    int32_t *head = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * nn);
+    int32_t *ks = (int32_t *)malloc(sizeof(int32_t) * nn);
+    double *w = (double *)calloc(nn, sizeof(double));
+    int64_t nnz = colptr[n];
+    int32_t *ci = (int32_t *)malloc(sizeof(int32_t) * (size_t)(2 * nnz > 0 ? 2 * nnz : 1));
+    double *cx = (double *)malloc(sizeof(double) * (size_t)(2 * nnz > 0 ? 2 * nnz : 1));
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (nn + 1));
+    int rc = ORC_OK;
+    if (!iperm || !cp || !cur || !head || !next || !ks || !w || !ci || !cx || !fill) {
+        rc = ORC_ENOMEM;
+        goto done;
+    }
+    if (invert_perm(n, perm, iperm)) { rc = ORC_EINVAL; goto done; }
+    /* full CSC of C (both triangles): entry (r, c) of A lands at (iperm[r], iperm[c]) */
+    for (int32_t j = 0; j < n; j++)
+        for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
+            int32_t r = rowind[p];
+            cp[iperm[j] + 1]++;                 /* C(iperm[r], iperm[j]) = A[r][j] */
+            if (r != j) cp[iperm[r] + 1]++;     /* C(iperm[j], iperm[r]) = A[j][r] */
+        }
+    for (int32_t j = 0; j < n; j++) cp[j + 1] += cp[j];
+    memcpy(fill, cp, sizeof(int64_t) * (nn + 1));
+    for (int32_t j = 0; j < n; j++)
+        for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
+            int32_t r = rowind[p];
+            int32_t a = iperm[r], b = iperm[j];
+            ci[fill[b]] = a;
+            cx[fill[b]++] = lval[p];
+            if (r != j) {
+                ci[fill[a]] = b;
+                cx[fill[a]++] = uval[p];
+            }
+        }
+    for (int32_t j = 0; j < n; j++) head[j] = -1;
+    for (int32_t j = 0; j < ncols; j++) {
+        for (int64_t p = cp[j]; p < cp[j + 1]; p++) w[ci[p]] += cx[p];
+        /* the columns k < j with l_jk != 0 (= the rows of column j of U) */
+        int32_t nk = 0;
+        for (int32_t k = head[j]; k != -1; k = next[k]) ks[nk++] = k;
+        head[j] = -1;
+        qsort(ks, (size_t)nk, sizeof(int32_t), cmp_i32);
+        for (int32_t t = 0; t < nk; t++) {
+            int32_t k = ks[t];
+            int64_t q = cur[k];                 /* Li[q] == j */
+            double ukj = w[k];
+            Ux[q] = ukj;                        /* u(k, j) in column k of U^T */
+            w[k] = 0.0;
+            for (int64_t r = Lp[k] + 1; r < Lp[k + 1]; r++) w[Li[r]] -= Lx[r] * ukj;
+            cur[k] = q + 1;
+            if (q + 1 < Lp[k + 1]) {
+                int32_t r = Li[q + 1];
+                next[k] = head[r];
+                head[r] = k;
+            }
+        }
+        double d = w[j];
+        if (d == 0.0 || !isfinite(d)) {
+            *bad_col = j;
+            rc = ORC_ESINGULAR;
+            break;
+        }
+        Ux[Lp[j]] = d;
+        Lx[Lp[j]] = 1.0;
+        w[j] = 0.0;
+        for (int64_t p = Lp[j] + 1; p < Lp[j + 1]; p++) {
+            Lx[p] = w[Li[p]] / d;
+            w[Li[p]] = 0.0;
+        }
+        cur[j] = Lp[j] + 1;
+        if (Lp[j] + 1 < Lp[j + 1]) {
+            int32_t r = Li[Lp[j] + 1];
+            next[j] = head[r];
+            head[r] = j;
+        }
+    }
+done:
+    free(iperm); free(cp); free(cur); free(head); free(next); free(ks); free(w); free(ci); free(cx); free(fill);
+    return rc;
+}
+
+/*
+ * x = P^T U^-1 L^-1 P b with the factors of orc_lu (part 0); part 1 stops
+ * after the forward substitution (L^-1 P b, pivot order), part 2 does only
+ * the backward one (P^T U^-1 b, input in pivot order).  Forward: column
+ * oriented with the unit lower L; backward: u_jj z_j = y_j - sum_{i>j}
+ * u(j, i) z_i, the sum running down column j of U^T.
+ */
+int orc_lu_solve(int32_t n, const int32_t *perm, const int64_t *Lp, const int32_t *Li, const double *Lx,
+                 const double *Ux, int32_t part, int32_t nrhs, const double *B, double *X, int64_t ld)
+{
+    if (part < 0 || part > 2 || ld < n) return ORC_EINVAL;
+    double *y = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!y) return ORC_ENOMEM;
+    for (int32_t c = 0; c < nrhs; c++) {
+        const double *b = B + (size_t)c * (size_t)ld;
+        double *x = X + (size_t)c * (size_t)ld;
+        for (int32_t k = 0; k < n; k++) y[k] = part == 2 ? b[k] : b[perm[k]];
+        if (part != 2)
+            for (int32_t j = 0; j < n; j++) {
+                double yj = y[j];
+                for (int64_t p = Lp[j] + 1; p < Lp[j + 1]; p++) y[Li[p]] -= Lx[p] * yj;
+            }
+        if (part != 1)
+            for (int32_t j = n - 1; j >= 0; j--) {
+                double s = y[j];
+                for (int64_t p = Lp[j] + 1; p < Lp[j + 1]; p++) s -= Ux[p] * y[Li[p]];
+                y[j] = s / Ux[Lp[j]];
+            }
+        for (int32_t k = 0; k < n; k++) {
+            if (part == 1) x[k] = y[k];
+            else x[perm[k]] = y[k];
+        }
+    }
+    free(y);
+    return ORC_OK;
+}
+
+/*
+ * Y = A X for the nonsymmetric A given by its stored lower pattern with the
+ * two values of orc_lu (lval below and on the diagonal, uval above), in the
+ * original order.
+ */
+int orc_gemv(int32_t n, const int64_t *colptr, const int32_t *rowind, const double *lval, const double *uval,
+             int32_t nrhs, const double *X, double *Y, int64_t ld)
+{
+    if (ld < n) return ORC_EINVAL;
+    for (int32_t c = 0; c < nrhs; c++) {
+        const double *x = X + (size_t)c * (size_t)ld;
+        double *y = Y + (size_t)c * (size_t)ld;
+        for (int32_t i = 0; i < n; i++) y[i] = 0.0;
+        for (int32_t j = 0; j < n; j++)
+            for (int64_t p = colptr[j]; p < colptr[j + 1]; p++) {
+                int32_t i = rowind[p];
+                y[i] += lval[p] * x[j];
+                if (i != j) y[j] += uval[p] * x[i];
+            }
+    }
+    return ORC_OK;
 }

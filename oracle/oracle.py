@@ -60,10 +60,13 @@ def load() -> C.CDLL:
     lib.orc_apply.argtypes = [i32, _P, _P, _P, _P, i32, i32, _P, _P, i64]
     lib.orc_symv.argtypes = [i32, _P, _P, _P, i32, _P, _P, i64]
     lib.orc_grad.argtypes = [i32, _P, _P, _P, _P, _P]
+    lib.orc_lu.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P, _P, _P, i32, _P]
+    lib.orc_lu_solve.argtypes = [i32, _P, _P, _P, _P, _P, i32, i32, _P, _P, i64]
+    lib.orc_gemv.argtypes = [i32, _P, _P, _P, _P, i32, _P, _P, i64]
     lib.orc_check_nd.argtypes = [i32, _P, _P, _P, i32, _P]
     lib.orc_check_nd.restype = i64
     for f in ("orc_check_perm", "orc_symbolic", "orc_pattern", "orc_factor", "orc_solve", "orc_apply", "orc_symv",
-              "orc_grad"):
+              "orc_grad", "orc_lu", "orc_lu_solve", "orc_gemv"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -244,3 +247,105 @@ def factorize(m: dict, perm: np.ndarray) -> Factor:
     Lp, Li = pattern(n, m["colptr"], m["rowind"], perm, parent, cc)
     Lx = factor(n, m["colptr"], m["rowind"], m["values"], perm, Lp, Li)
     return Factor(n, np.ascontiguousarray(perm, np.int32), parent, cc, nnzL, fl, Lp, Li, Lx)
+
+
+# ---------------------------------------------------------------- LU (Section 5.1, eq:PCM2)
+
+def lu(n: int, colptr, rowind, lval, uval, perm, Lp, Li, ncols: Optional[int] = None):
+    """(Lx, Ux): P A P^T = L U without pivoting for a matrix with a symmetric
+    pattern given by its stored lower entries and the values below/on
+    (lval) and above (uval) the diagonal; Lx = L (unit diagonal stored),
+    Ux = U^T, both in the Cholesky pattern (Lp, Li)."""
+    cp, ri, lv = _csc(colptr, rowind, lval)
+    uv = np.ascontiguousarray(uval, np.float64)
+    p = np.ascontiguousarray(perm, np.int32)
+    Lx = np.zeros(Li.size, np.float64)
+    Ux = np.zeros(Li.size, np.float64)
+    bad = C.c_int32(-1)
+    nc = n if ncols is None else int(ncols)
+    rc = load().orc_lu(n, _ptr(cp), _ptr(ri), _ptr(lv), _ptr(uv), _ptr(p), _ptr(Lp), _ptr(Li), _ptr(Lx), _ptr(Ux),
+                       nc, C.byref(bad))
+    if rc:
+        raise OracleError(rc, "lu", bad.value)
+    return Lx, Ux
+
+
+def lu_solve(perm, Lp, Li, Lx, Ux, B: np.ndarray, part: int = 0) -> np.ndarray:
+    """part 0: P^T U^-1 L^-1 P B; 1: L^-1 P B; 2: P^T U^-1 B.  B is n or n x k."""
+    n = Lp.size - 1
+    B2 = np.asfortranarray(B.reshape(n, -1), np.float64)
+    X = np.empty_like(B2, order="F")
+    p = np.ascontiguousarray(perm, np.int32)
+    rc = load().orc_lu_solve(n, _ptr(p), _ptr(Lp), _ptr(Li), _ptr(Lx), _ptr(np.ascontiguousarray(Ux)), part,
+                             B2.shape[1], _ptr(B2), _ptr(X), n)
+    if rc:
+        raise OracleError(rc, "lu_solve")
+    return X.reshape(B.shape)
+
+
+def gemv(n: int, colptr, rowind, lval, uval, X: np.ndarray) -> np.ndarray:
+    """A X for the nonsymmetric A of lu()."""
+    cp, ri, lv = _csc(colptr, rowind, lval)
+    uv = np.ascontiguousarray(uval, np.float64)
+    X2 = np.asfortranarray(X.reshape(n, -1), np.float64)
+    Y = np.empty_like(X2, order="F")
+    rc = load().orc_gemv(n, _ptr(cp), _ptr(ri), _ptr(lv), _ptr(uv), X2.shape[1], _ptr(X2), _ptr(Y), n)
+    if rc:
+        raise OracleError(rc, "gemv")
+    return Y.reshape(X.shape)
+
+
+def gemv_residual(n: int, colptr, rowind, lval, uval, X: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Per-column ||A x - b||_2 / ||b||_2 for the nonsymmetric A (FP64)."""
+    R = gemv(n, colptr, rowind, lval, uval, X).reshape(n, -1) - B.reshape(n, -1)
+    return np.linalg.norm(R, axis=0) / np.linalg.norm(B.reshape(n, -1), axis=0)
+
+
+@dataclasses.dataclass
+class LUFactor:
+    n: int
+    perm: np.ndarray
+    Lp: np.ndarray
+    Li: np.ndarray
+    Lx: np.ndarray
+    Ux: np.ndarray
+
+    def solve(self, B: np.ndarray, part: int = 0) -> np.ndarray:
+        return lu_solve(self.perm, self.Lp, self.Li, self.Lx, self.Ux, B, part)
+
+    def dense(self):
+        """(L, U) as dense matrices in pivot order."""
+        L = np.zeros((self.n, self.n))
+        cols = np.repeat(np.arange(self.n), np.diff(self.Lp))
+        L[self.Li, cols] = self.Lx
+        Ut = np.zeros((self.n, self.n))
+        Ut[self.Li, cols] = self.Ux
+        return L, Ut.T
+
+
+def lu_factorize(m: dict, perm: np.ndarray) -> LUFactor:
+    """Symbolic (Cholesky pattern of the symmetric pattern) + LU of one
+    nonsymmetric instance: m holds colptr, rowind and the two value arrays
+    "values" (lower and diagonal) and "upper" (above the diagonal)."""
+    n = m["n"]
+    parent, cc, _, _ = symbolic(n, m["colptr"], m["rowind"], perm)
+    Lp, Li = pattern(n, m["colptr"], m["rowind"], perm, parent, cc)
+    Lx, Ux = lu(n, m["colptr"], m["rowind"], m["values"], m["upper"], perm, Lp, Li)
+    return LUFactor(n, np.ascontiguousarray(perm, np.int32), Lp, Li, Lx, Ux)
+
+
+# ---------------------------------------------------------------- covariance-form sampling (Section 5.3)
+
+def field_sample(cov: Factor, mass: Factor, abar: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Coefficients of Gaussian random field samples in the covariance form of
+    Section 5.3 (eq:CholFastField): G^-1 (abar^G + L X), where L L^T is the
+    Cholesky decomposition of the Galerkin covariance matrix C^G (here
+    C^G = P_C^T L_C L_C^T P_C with its own ordering, so L = P_C^T L_C) and G
+    is the mass matrix, solved with its own factor (its own ordering).  X: the
+    standard normal vectors, n x k, indexed in the covariance factor's pivot
+    order; abar: n or n x k.  Returns n x k."""
+    n = cov.n
+    X2 = X.reshape(n, -1)
+    Y = cov.apply(X2, 1)                                   # P_C^T L_C X
+    Y = Y + np.asarray(abar, np.float64).reshape(n, -1)
+    return mass.solve(Y, 0)                                # G^-1 (abar + L X)

@@ -13,7 +13,7 @@ from typing import Dict, List
 
 import numpy as np
 
-from .wavelet import WaveletSpec, centers, make_matrix, normal_rhs
+from .wavelet import WaveletSpec, centers, make_matrix, make_nonsymmetric, mass_spec, normal_rhs
 
 
 @dataclasses.dataclass(frozen=True)
@@ -137,3 +137,74 @@ def batch_matrices(count: int = 256, base_seed: int = 4000, workers: int = 8) ->
         return [_instance_matrix(j) for j in jobs]
     with mp.get_context("fork").Pool(workers) as pool:
         return pool.map(_instance_matrix, jobs, chunksize=1)
+
+
+@dataclasses.dataclass(frozen=True)
+class PcmLu:
+    """Nonsymmetric system on the wavelet pattern, factored by LU (Section 5.1,
+    eq:PCM2; Section 6.1 factors A_J by LU on the nested dissection ordering
+    of the symmetric pattern)."""
+    name: str
+    spec: WaveletSpec
+    eta: float
+    nrhs: int
+    seed: int
+
+    @property
+    def n(self) -> int:
+        return self.spec.n
+
+    def matrix(self) -> Dict[str, np.ndarray]:
+        return make_nonsymmetric(self.spec, self.eta, self.seed + 7)
+
+    def rhs(self) -> np.ndarray:
+        return normal_rhs(self.n, self.nrhs, self.seed + 1)
+
+
+def pcm_lu(grid_exp: int = 8, nrhs: int = 8) -> PcmLu:
+    """256x256 grid by default (N = 65536, a = 1.5 as the FP64 case), values
+    perturbed by up to 50% independently below and above the diagonal; several
+    right-hand sides, as the PCM needs many (Section 5.1)."""
+    return PcmLu(f"pcm{1 << grid_exp}_n{4 ** grid_exp}_lu", WaveletSpec(grid_exp, 1.5, 0.5, "exp", 0.3, 1.5, 8000),
+                 0.5, nrhs, 8000)
+
+
+@dataclasses.dataclass(frozen=True)
+class CovarianceField:
+    """Gaussian random field in covariance form (Section 5.3, eq:CholFastField):
+    the Galerkin covariance matrix C^G (exponential-type decay with distance,
+    standing in for the exp(-|x - x'|) kernel of Section 6.3, whose domain has
+    side 4: correlation length 1/4 of the side) and the mass matrix G on the
+    same index set, each with its own ordering.  Samples are G^-1 (abar + L X)."""
+    name: str
+    cov: WaveletSpec
+    mass: WaveletSpec
+    nsamples: int
+    seed: int
+
+    @property
+    def n(self) -> int:
+        return self.cov.n
+
+    def cov_matrix(self) -> Dict[str, np.ndarray]:
+        return make_matrix(self.cov)
+
+    def mass_matrix(self) -> Dict[str, np.ndarray]:
+        return make_matrix(self.mass)
+
+    def noise(self, k: int = None) -> np.ndarray:
+        return normal_rhs(self.n, self.nsamples if k is None else k, self.seed + 3)
+
+    def mean(self) -> np.ndarray:
+        """abar^G: the Galerkin projection of a smooth mean field, here
+        sin(2 pi x1) cos(2 pi x2) at the support centres, weighted by 2^-j."""
+        c, level = centers(self.cov.grid_exp)
+        return np.sin(2 * np.pi * c[:, 0]) * np.cos(2 * np.pi * c[:, 1]) * 2.0 ** (-level.astype(np.float64))
+
+
+def covariance_field(grid_exp: int = 9, nsamples: int = 64) -> CovarianceField:
+    """512x512 grid by default (N = 262144): C^G with a = 2, s = 1/2,
+    exp(-|dc| / 0.25) decay; G the mass-matrix stand-in (supports that touch)."""
+    return CovarianceField(f"field{1 << grid_exp}_n{4 ** grid_exp}",
+                           WaveletSpec(grid_exp, 2.0, 0.5, "exp", 0.25, 1.5, 7000), mass_spec(grid_exp, 7001),
+                           nsamples, 7000)

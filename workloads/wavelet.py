@@ -267,3 +267,48 @@ def normal_rhs(n: int, k: int, seed: int) -> np.ndarray:
     holds the k values of unknown i."""
     g = np.random.Generator(np.random.PCG64(seed))
     return np.asfortranarray(g.standard_normal((n, k)))
+
+
+def make_nonsymmetric(spec: WaveletSpec, eta: float = 0.5, seed2: int = 1) -> Dict[str, np.ndarray]:
+    """A nonsymmetric matrix on the symmetric pattern of make_matrix(spec):
+    stand-in for the PCM system matrix ((1+eps)/2) G + (1-eps) K of Section
+    5.1, whose double-layer part K is not symmetric.  Every off-diagonal value
+    v of the symmetric instance becomes v (1 + eta xi) below the diagonal and
+    v (1 + eta xi') above it, with xi, xi' independent counter-based draws
+    (seeds spec.seed ^ seed2 and its successor); the diagonal is then
+    1.1 max(row abs sum, column abs sum) + 2^(2 j s), so A is strictly
+    diagonally dominant by rows and by columns (nonsingular; elimination
+    without pivoting is stable and partial pivoting would exchange no rows).
+
+    Returns the dict of make_matrix with "values" = the entries on and below
+    the diagonal and "upper" = the entry above the diagonal for each stored
+    lower entry (A[c][r] for the stored (r, c); the diagonal repeated)."""
+    m = make_matrix(spec)
+    n = m["n"]
+    cols = np.repeat(np.arange(n, dtype=np.int64), np.diff(m["colptr"]))
+    rows = m["rowind"].astype(np.int64)
+    off = rows != cols
+    v = m["values"]
+    lo = v.copy()
+    up = v.copy()
+    lo[off] = v[off] * (1.0 + eta * pair_uniform(spec.seed ^ seed2, rows[off], cols[off]))
+    up[off] = v[off] * (1.0 + eta * pair_uniform((spec.seed ^ seed2) + 1, rows[off], cols[off]))
+    # row i of A holds lo on (i, c < i) and up on (i, c > i); column j the opposite
+    rsum = np.bincount(rows[off], np.abs(lo[off]), n) + np.bincount(cols[off], np.abs(up[off]), n)
+    csum = np.bincount(cols[off], np.abs(lo[off]), n) + np.bincount(rows[off], np.abs(up[off]), n)
+    diag = 1.1 * np.maximum(rsum, csum) + np.exp2(2.0 * m["level"].astype(np.float64) * spec.s)
+    dpos = m["colptr"][:-1]
+    lo[dpos] = diag
+    up[dpos] = diag
+    m["values"] = lo
+    m["upper"] = up
+    return m
+
+
+def mass_spec(grid_exp: int, seed: int) -> WaveletSpec:
+    """Stand-in for the mass matrix G_J = [(psi_l', psi_l)] of a non-orthogonal
+    wavelet basis (Section 5.3): only functions whose supports overlap or touch
+    couple (cut-off a = 0, a sub-pattern of every compressed system matrix on
+    the same basis), with values decaying across levels and a unit-order
+    diagonal (s = 0: 1.1 row abs sum + 1)."""
+    return WaveletSpec(grid_exp, 0.0, 0.0, "exp", 0.3, 1.5, seed)
