@@ -55,13 +55,17 @@ typedef enum {
     WCS_EHIP = -3,      /* a HIP runtime call failed */
     WCS_ENOTSPD = -4,   /* a pivot was not positive (or NaN): matrix not SPD */
     WCS_ENOTCONV = -5,  /* iterative refinement did not reach the tolerance */
-    WCS_ESTATE = -6     /* call not valid in the handle's current state */
+    WCS_ESTATE = -6,    /* call not valid in the handle's current state */
+    WCS_ESINGULAR = -7  /* a zero (or non-finite) pivot in an LU factorization */
 } wcs_status;
 
 typedef enum {
     WCS_FP64 = 0,       /* fronts stored and factored in FP64 */
-    WCS_FP32 = 1        /* fronts stored and factored in FP32 (FP64 diagonal
+    WCS_FP32 = 1,       /* fronts stored and factored in FP32 (FP64 diagonal
                            tiles in fronts with at least fp64_diag_min_cols pivots) */
+    WCS_LU64 = 2        /* nonsymmetric matrix with the analysed (symmetric) pattern:
+                           P A P^T = L U without pivoting, L unit lower and U upper
+                           triangular, both in FP64 fronts (wcs_factor_numeric_lu) */
 } wcs_precision;
 
 typedef enum {
@@ -197,6 +201,34 @@ int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, s
 int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs,
                       void *workspace, size_t bytes, wcs_stream stream, wcs_factor *out);
 int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *bad_col);
+
+/*
+ * LU factorization (Section 5.1: the PCM system matrix of eq:PCM2 is not
+ * symmetric; Section 6.1 factors it by LU on the nested dissection ordering
+ * of its symmetric pattern) of a factor created with WCS_LU64:
+ * P A P^T = L U without pivoting, L unit lower triangular, U upper
+ * triangular; the pattern of L is that of the Cholesky factor and U's the
+ * transposed one.  lower_dev: device FP64 values of A on and below the
+ * diagonal, aligned with the analysed lower pattern (A[r][c] for the stored
+ * entry (r, c), r >= c); upper_dev: the values above the diagonal in the same
+ * positions (A[c][r] for the stored (r, c); the diagonal positions are not
+ * read).  No pivoting: the matrix must admit the factorization (for example
+ * by strict diagonal dominance by columns); a zero or non-finite pivot gives
+ * WCS_ESINGULAR with its pivot position in *bad_col (when bad_col is non-NULL,
+ * as for wcs_factor_numeric; otherwise wcs_factor_check reports it).
+ * wcs_solve on an LU factor: WCS_SOLVE_FULL gives X = A^-1 B =
+ * P^T U^-1 L^-1 P B, WCS_SOLVE_L gives L^-1 P B (pivot order), WCS_SOLVE_LT
+ * gives P^T U^-1 B (input in pivot order).  wcs_factor_export returns the
+ * columns of L (unit diagonal stored); wcs_factor_export_upper the same
+ * columns of U^T (entry (i, j) of the export is u(j, i)), in the same
+ * format.  The products, refinement, SpMV, theta-scheme, gradient, profile
+ * and autotune calls are for Cholesky factors and return WCS_EINVAL on an
+ * LU factor.  Asynchronous on the stream unless bad_col is non-NULL.
+ */
+int wcs_factor_numeric_lu(wcs_factor f, const double *lower_dev, const double *upper_dev, wcs_stream stream,
+                          int32_t *bad_col);
+int wcs_factor_export_upper(wcs_factor f, int32_t j0, int32_t j1, int64_t *Up, int32_t *Ui, double *Ux,
+                            wcs_stream stream);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph

@@ -70,6 +70,8 @@ SIGNATURES = [
     ("wcs_factor_create", C.c_int, [c_p, C.c_int, c_i32, c_p, C.c_size_t, c_p, C.POINTER(c_p)]),
     ("wcs_factor_create_static", C.c_int, [c_p, C.c_int, c_i32, c_p, C.POINTER(c_p)]),
     ("wcs_factor_numeric", C.c_int, [c_p, c_p, c_p, C.POINTER(c_i32)]),
+    ("wcs_factor_numeric_lu", C.c_int, [c_p, c_p, c_p, c_p, C.POINTER(c_i32)]),
+    ("wcs_factor_export_upper", C.c_int, [c_p, c_i32, c_i32, c_p, c_p, c_p, c_p]),
     ("wcs_factor_check", C.c_int, [c_p, c_p, C.POINTER(c_i32)]),
     ("wcs_factor_free", None, [c_p]),
     ("wcs_factor_residuals", C.c_int, [c_p, c_p, c_i64]),

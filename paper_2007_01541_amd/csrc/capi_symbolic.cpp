@@ -29,6 +29,7 @@ const char *wcs_status_string(int status)
     case WCS_ENOTSPD: return "WCS_ENOTSPD";
     case WCS_ENOTCONV: return "WCS_ENOTCONV";
     case WCS_ESTATE: return "WCS_ESTATE";
+    case WCS_ESINGULAR: return "WCS_ESINGULAR";
     default: return "WCS_UNKNOWN";
     }
 }

@@ -114,6 +114,25 @@ __global__ void k_scatter(const double *__restrict__ values, const int64_t *__re
     }
 }
 
+// LU fronts: the stored entry e = (r, c), r >= c, carries A[r][c] (lower) and
+// A[c][r] (upper); amap[e] is the position of (max, min) of their pivot
+// indices, so the L fronts (lower triangle of P A P^T) take A[r][c] when r
+// comes after c in pivot order and A[c][r] otherwise, the U^T fronts the other.
+__global__ void k_scatter_lu(const double *__restrict__ lower, const double *__restrict__ upper,
+                             const int64_t *__restrict__ amap, const int32_t *__restrict__ rowind,
+                             const int32_t *__restrict__ colof, const int32_t *__restrict__ iperm, int64_t nnz,
+                             double *__restrict__ FL, double *__restrict__ FU)
+{
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nnz; i += stride) {
+        int64_t dst = amap[i];
+        double lo = lower[i], up = upper[i];
+        bool flip = iperm[rowind[i]] < iperm[colof[i]];
+        FL[dst] = flip ? up : lo;
+        FU[dst] = flip ? lo : up;
+    }
+}
+
 // ---------------------------------------------------------------- extend-add
 // task = (child front, first update column).  The child's update matrix
 // U = F_c[p_c:m_c, p_c:m_c] (lower) is added into its parent front through
@@ -513,6 +532,136 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
     }
 }
 
+// ---------------------------------------------------------------- LU panel
+// LU without pivoting of a front with a symmetric pattern (the nonsymmetric
+// matrices of Section 5.1): two buffers with the same layout as the Cholesky
+// fronts, FL holding the lower triangle (L and the lower half of the update
+// matrix) and FU the upper triangle transposed (U^T and the transposed upper
+// half), so that every trailing update is C -= A B^T on a lower triangle:
+// FL -= L21 (U12^T)^T and FU -= U12^T L21^T.
+//
+// task = (front, tile), k0 = the panel's first column.  Every workgroup
+// assembles the panel's diagonal block A11 (lower part from FL, strict upper
+// from FU, padded to NB x NB with the identity), factors it as L11 U11
+// (Doolittle: unit lower L11, right-looking in LDS, FP64), forms L11^-1 and
+// U11^-1 by substitution (one column per thread), and then solves its TRW
+// rows below the block: L21 = A21 U11^-1 in FL and U12^T = A12^T L11^-T in
+// FU, one row per thread.  Tile 0 writes the factored block to the
+// diagonal-block scratch of both factors (L11 with its unit diagonal, U11^T),
+// which a later launch copies into place, as for the Cholesky panel.  A
+// zero or non-finite pivot is reported through atomicMin on *bad (global
+// pivot numbering) and replaced by 1.
+template <typename T>
+__global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict__ tasks, int k0,
+                                                         const int64_t *__restrict__ front_off,
+                                                         const int32_t *__restrict__ mfront,
+                                                         const int32_t *__restrict__ pfront,
+                                                         const int32_t *__restrict__ first,
+                                                         const int64_t *__restrict__ dscr_off, T *__restrict__ FL,
+                                                         T *__restrict__ FU, T *__restrict__ dscrL,
+                                                         T *__restrict__ dscrU, int32_t *__restrict__ bad)
+{
+    __shared__ double A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L11 \ U11
+    __shared__ double Li[NB][NB + 1];    // L11^-1, Li[c][r] = (r, c)
+    __shared__ double Ui[NB][NB + 1];    // U11^-1, Ui[c][r] = (r, c)
+    const int2 t = tasks[blockIdx.x];
+    const int f = t.x;
+    const int m = mfront[f], p = pfront[f], ld = front_ld(m);
+    const int nb = min(NB, p - k0);
+    T *L = FL + front_off[f];
+    T *U = FU + front_off[f];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += THREADS) {
+        int c = e / NB, r = e % NB;
+        double v = r == c ? 1.0 : 0.0;
+        if (r < nb && c < nb)
+            v = r >= c ? (double)L[(int64_t)(k0 + c) * ld + k0 + r] : (double)U[(int64_t)(k0 + r) * ld + k0 + c];
+        A[c][r] = v;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < NB; kk++) {
+        double piv = A[kk][kk];
+        const bool badp = piv == 0.0 || !(fabs(piv) <= __builtin_huge_val());
+        if (badp) piv = 1.0;
+        __syncthreads();                   // every thread has read the pivot
+        if (tid == 0 && badp) {
+            A[kk][kk] = 1.0;
+            if (t.y == 0 && kk < nb) atomicMin(bad, first[f] + k0 + kk);
+        }
+        const double rp = 1.0 / piv;
+        for (int i = kk + 1 + tid; i < NB; i += THREADS) A[kk][i] *= rp;
+        __syncthreads();
+        const int w = NB - kk - 1;
+        for (int e = tid; e < w * w; e += THREADS) {
+            int j = kk + 1 + e / w, i = kk + 1 + e % w;
+            A[j][i] -= A[kk][i] * A[j][kk];
+        }
+        __syncthreads();
+    }
+    if (tid < NB) {
+        // column c of L11^-1: y = e_c, then y_r -= l_rt y_t for r > t (unit diagonal)
+        const int c = tid;
+        double y[NB];
+#pragma unroll
+        for (int r = 0; r < NB; r++) y[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+        for (int tt = 0; tt < NB; tt++)
+#pragma unroll
+            for (int r = tt + 1; r < NB; r++) y[r] -= A[tt][r] * y[tt];
+#pragma unroll
+        for (int r = 0; r < NB; r++) Li[c][r] = y[r];
+    } else if (tid < 2 * NB) {
+        // column c of U11^-1: y = e_c, then from the last row up y_t /= u_tt and
+        // y_r -= u_rt y_t for r < t
+        const int c = tid - NB;
+        double y[NB];
+#pragma unroll
+        for (int r = 0; r < NB; r++) y[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+        for (int tt = NB - 1; tt >= 0; tt--) {
+            y[tt] /= A[tt][tt];
+#pragma unroll
+            for (int r = 0; r < tt; r++) y[r] -= A[tt][r] * y[tt];
+        }
+#pragma unroll
+        for (int r = 0; r < NB; r++) Ui[c][r] = y[r];
+    }
+    __syncthreads();
+    if (t.y == 0) {
+        T *DL = dscrL + dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
+        T *DU = dscrU + dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
+        for (int e = tid; e < NB * NB; e += THREADS) {
+            int c = e / NB, r = e % NB;
+            DL[e] = (T)(r > c ? A[c][r] : (r == c ? 1.0 : 0.0));
+            DU[e] = (T)(r >= c ? A[r][c] : 0.0);        // U11^T: (r, c) = u(c, r)
+        }
+    }
+    const int row = k0 + nb + t.y * TRW + tid;
+    if (tid < TRW && row < m) {
+        // L21 row: out_c = sum_{t <= c} a_t (U11^-1)(t, c)
+        double x[NB];
+#pragma unroll
+        for (int tt = 0; tt < NB; tt++) x[tt] = tt < nb ? (double)L[(int64_t)(k0 + tt) * ld + row] : 0.0;
+        for (int c = 0; c < nb; c++) {
+            double s = 0.0;
+#pragma unroll
+            for (int tt = 0; tt < NB; tt++)
+                if (tt <= c) s += x[tt] * Ui[c][tt];
+            L[(int64_t)(k0 + c) * ld + row] = (T)s;
+        }
+        // U12^T row: out_c = sum_{t <= c} a_t (L11^-1)(c, t)
+#pragma unroll
+        for (int tt = 0; tt < NB; tt++) x[tt] = tt < nb ? (double)U[(int64_t)(k0 + tt) * ld + row] : 0.0;
+        for (int c = 0; c < nb; c++) {
+            double s = 0.0;
+#pragma unroll
+            for (int tt = 0; tt < NB; tt++)
+                if (tt <= c) s += x[tt] * Li[tt][c];
+            U[(int64_t)(k0 + c) * ld + row] = (T)s;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- trailing update
 // C(row, col) -= acc[x][y][e] on the lower part (row >= col, row < m,
 // col < jend) for the 64 elements of a lane, rows from rowf(x, e) and columns
@@ -652,7 +801,9 @@ __device__ __forceinline__ void tile_sub_quads(T *__restrict__ F, int ld, int m,
 
 // task = (front, i0, j0, jend): C = F[i0:i0+UT, j0:min(j0+UT, jend)] -= A B^T
 // on the lower part (row >= column), with A = F[i0:, ka:ka+K], B = F[j0:, ka:ka+K]
-// and K = min(kw, p - ka) for the front's p.  The first outer block's update
+// and K = min(kw, p - ka) for the front's p.  B is read bdelta elements away
+// from F (0 for Cholesky; the LU fronts read it from the other factor's
+// buffer, whose fronts sit at the same offsets).  The first outer block's update
 // (ka = 0) assigns C = -A B^T in the update-matrix columns (>= p), which are
 // not zeroed beforehand.  Tiles are TW x TW (128 or 64):
 // one wave per 64 x 64 quarter (4 x 4 MFMA 16x16 blocks each); K advances in
@@ -682,7 +833,7 @@ __device__ __forceinline__ int frag_pos(int r) { return (r & ~63) + (r & 15) * 4
 
 template <typename T, int TW>
 __global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__restrict__ tasks, int ka, int kw,
-                                                    T *__restrict__ fronts)
+                                                    T *__restrict__ fronts, int64_t bdelta)
 {
     constexpr int KC = UpdCfg<T>::KC;
     constexpr int NTH = TW * TW / 64;          // one wave per 64 x 64 quarter
@@ -708,7 +859,7 @@ __global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__res
     const int rpos = frag_pos(r);
     const bool arow = i0 + r < m, brow = j0 + r < m;
     const T *pa = F0 + (int64_t)(ka + k_first) * ld + i0 + r;
-    const T *pb = F0 + (int64_t)(ka + k_first) * ld + j0 + r;
+    const T *pb = F0 + bdelta + (int64_t)(ka + k_first) * ld + j0 + r;
     const int64_t kstride = (int64_t)KSTEP * ld;
     T ra[PER], rb[PER];
     auto gload = [&](int kc) {
@@ -849,7 +1000,7 @@ __device__ __forceinline__ void dma_to_lds16(const void *g, uint32_t lds)
 // accumulators within the register budget of that many waves.
 template <typename T, int NS, int KC = DmaCfg<T>::KC>
 __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_update_dma(const UpdTask *__restrict__ tasks, int ka, int kw,
-                                                                   T *__restrict__ fronts)
+                                                                   T *__restrict__ fronts, int64_t bdelta)
 {
     static_assert(NS >= 2 && NS <= 4, "the stage arrays below hold two to four stages");
     constexpr int VEC = 16 / (int)sizeof(T);       // elements per lane per DMA instruction
@@ -894,7 +1045,7 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
             int q = wave + 4 * s, op = q / IPO, qq = q % IPO;
             int kr = qq * RPI;
             int kg = min(c * KC + kr + lk, K - 1);
-            const T *g = F + (int64_t)(ka + kg) * ld + (op ? rowB : rowA);
+            const T *g = F + (op ? bdelta : 0) + (int64_t)(ka + kg) * ld + (op ? rowB : rowA);
             uint32_t dst = (uint32_t)(uintptr_t)(lds_t)&Sx[op][kr][0];
             dma_to_lds16((const void *)g, __builtin_amdgcn_readfirstlane(dst));
         }

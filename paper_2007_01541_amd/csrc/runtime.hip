@@ -439,14 +439,22 @@ struct Layout {
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
     size_t spchunk, splong, sppart, iperm;
+    // LU factors only: the U^T fronts and their diagonal-block scratch, inverses and super-block inverses
+    size_t fronts_u = 0, dscr_u = 0, dinv_u = 0, xinv_u = 0;
     size_t total;
 
-    void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k)
+    void compute(const Symbolic &S, const Plan &P, size_t esz, int32_t k, bool lu = false)
     {
         size_t o = 0;
         auto seg = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
         size_t n = (size_t)S.n, ns = (size_t)S.ns;
         fronts = seg((size_t)S.front_off.back() * esz + 64);   // + slack read past the last column by k_update_dma
+        if (lu) {
+            fronts_u = seg((size_t)S.front_off.back() * esz + 64);
+            dscr_u = seg((size_t)P.dscr_elems * esz);
+            dinv_u = seg((size_t)P.dscr_elems * esz);
+            xinv_u = seg((size_t)std::max<int64_t>(1, P.xelems) * esz);
+        }
         W = seg((size_t)P.wrows * k * esz);
         Y = seg(n * k * esz);
         Xr = seg(n * k * 8);
@@ -510,11 +518,13 @@ struct Layout {
     }
 };
 
-size_t elem_size(wcs_precision p) { return p == WCS_FP64 ? 8 : 4; }
+size_t elem_size(wcs_precision p) { return p == WCS_FP32 ? 4 : 8; }
+bool is_lu(wcs_precision p) { return p == WCS_LU64; }
+bool valid_prec(wcs_precision p) { return p == WCS_FP64 || p == WCS_FP32 || p == WCS_LU64; }
 
 // Update kernel used before any autotuning: on large fronts the streamed form
 // is the faster one in FP64 and the register-staged one in FP32.
-int32_t default_update_variant(wcs_precision p) { return p == WCS_FP64 ? WCS_UPD_STREAM128 : WCS_UPD_REG128; }
+int32_t default_update_variant(wcs_precision p) { return p == WCS_FP32 ? WCS_UPD_REG128 : WCS_UPD_STREAM128; }
 
 int grid_for(int64_t work, int threads = 256)
 {
@@ -704,27 +714,43 @@ double update_flops(const Plan &P, const int4 &t, int32_t jbeg, int32_t ka, int3
     return 2.0 * K * cnt;
 }
 
+// Numeric factorization.  Cholesky: values = the stored lower entries.  LU
+// (f->prec == WCS_LU64, T = double): values = the entries on and below the
+// diagonal, upper = the entry above the diagonal of each stored lower entry;
+// every step runs on the L fronts and the U^T fronts alike (see k_lu_panel).
 template <typename T>
-int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof)
+int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof, const double *upper = nullptr)
 {
     const Layout &Lo = f->lay;
     const Plan &P = f->plan;
     const Symbolic &S = *f->S;
     const size_t esz = sizeof(T);
+    const bool lu = is_lu(f->prec);
     T *fronts = f->at<T>(Lo.fronts);
+    T *fronts_u = lu ? f->at<T>(Lo.fronts_u) : nullptr;
+    const int nbuf = lu ? 2 : 1;
+    auto buf = [&](int b) { return b ? fronts_u : fronts; };
     hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, st, f->at<int32_t>(Lo.bad), (int64_t)1, INT32_MAX);
     PROF_BEGIN(KC_FILL);
-    hipLaunchKernelGGL(k_zero_lower<T>, dim3((unsigned)std::min<int64_t>(P.zero_tasks.size(), 1 << 30)), dim3(256), 0,
-                       st, f->at<int2>(Lo.ztasks), f->at<int64_t>(Lo.front_off), f->at<int32_t>(Lo.mfront),
-                       f->at<int32_t>(Lo.pfront), fronts);
+    for (int b = 0; b < nbuf; b++)
+        hipLaunchKernelGGL(k_zero_lower<T>, dim3((unsigned)std::min<int64_t>(P.zero_tasks.size(), 1 << 30)), dim3(256),
+                           0, st, f->at<int2>(Lo.ztasks), f->at<int64_t>(Lo.front_off), f->at<int32_t>(Lo.mfront),
+                           f->at<int32_t>(Lo.pfront), buf(b));
     PROF_END(KC_FILL);
     PROF_BEGIN(KC_SCATTER);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(S.nnz)), dim3(256), 0, st, values, f->at<int64_t>(Lo.amap),
-                       S.nnz, fronts);
+    if constexpr (sizeof(T) == 8) {
+        if (lu)
+            hipLaunchKernelGGL(k_scatter_lu, dim3(grid_for(S.nnz)), dim3(256), 0, st, values, upper,
+                               f->at<int64_t>(Lo.amap), f->at<int32_t>(Lo.rowind), f->at<int32_t>(Lo.colof),
+                               f->at<int32_t>(Lo.iperm), S.nnz, fronts, fronts_u);
+    }
+    if (!lu)
+        hipLaunchKernelGGL(k_scatter<T>, dim3(grid_for(S.nnz)), dim3(256), 0, st, values, f->at<int64_t>(Lo.amap),
+                           S.nnz, fronts);
     PROF_END(KC_SCATTER);
     if (prof) {
-        prof->bytes[KC_FILL] += (double)P.lower_elems * esz;
-        prof->bytes[KC_SCATTER] += (double)S.nnz * (8 + 8 + esz);
+        prof->bytes[KC_FILL] += (double)P.lower_elems * esz * nbuf;
+        prof->bytes[KC_SCATTER] += (double)S.nnz * (8 + 8 + esz) * nbuf;
     }
     const int64_t *fo = f->at<int64_t>(Lo.front_off);
     const int32_t *mf = f->at<int32_t>(Lo.mfront);
@@ -750,15 +776,17 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
     auto extend_add = [&](const std::vector<std::pair<int64_t, int64_t>> &rounds, bool pre) -> int {
         for (auto &r : rounds) {
             PROF_BEGIN(KC_EXTEND_ADD);
-            hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)r.second), dim3(256), 0, st, ea + r.first, fo, mf,
-                               pf, sp, rp, rl, pre ? esp : nullptr, fronts);
+            for (int b = 0; b < nbuf; b++)
+                hipLaunchKernelGGL(k_extend_add<T>, dim3((unsigned)r.second), dim3(256), 0, st, ea + r.first, fo, mf,
+                                   pf, sp, rp, rl, pre ? esp : nullptr, buf(b));
             PROF_END(KC_EXTEND_ADD);
             if (prof)
                 for (int64_t t = r.first; t < r.first + r.second; t++) {
                     int2 task = P.ea_tasks[t];
                     double nu = P.mfront[task.x] - P.pfront[task.x];
                     double c1 = std::min<double>(task.y + EA_COLS, pre ? P.ea_split[task.x] : nu);
-                    for (double col = task.y; col < c1; col++) prof->bytes[KC_EXTEND_ADD] += (nu - col) * (3 * esz + 4);
+                    for (double col = task.y; col < c1; col++)
+                        prof->bytes[KC_EXTEND_ADD] += (nu - col) * (3 * esz + 4) * nbuf;
                 }
         }
         return WCS_OK;
@@ -793,18 +821,23 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                     us = side;
                 }
                 PROF_BEGIN(KC_UPDATE);
-                if (small)
-                    hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, us, upd + off, op.ka,
-                                       op.kw, fronts);
-                else if (L.upd_var == WCS_UPD_STREAM128)
-                    hipLaunchKernelGGL((k_update_dma<T, 4>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off, op.ka,
-                                       op.kw, fronts);
-                else if (L.upd_var == WCS_UPD_STREAM128_3)
-                    hipLaunchKernelGGL((k_update_dma<T, 3>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off, op.ka,
-                                       op.kw, fronts);
-                else
-                    hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, us, upd + off,
-                                       op.ka, op.kw, fronts);
+                for (int b = 0; b < nbuf; b++) {
+                    // LU: the L fronts take B from the U^T fronts and the other way round
+                    T *cf = buf(b);
+                    const int64_t bd = lu ? (int64_t)(buf(1 - b) - cf) : 0;
+                    if (small)
+                        hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, us, upd + off, op.ka,
+                                           op.kw, cf, bd);
+                    else if (L.upd_var == WCS_UPD_STREAM128)
+                        hipLaunchKernelGGL((k_update_dma<T, 4>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off,
+                                           op.ka, op.kw, cf, bd);
+                    else if (L.upd_var == WCS_UPD_STREAM128_3)
+                        hipLaunchKernelGGL((k_update_dma<T, 3>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off,
+                                           op.ka, op.kw, cf, bd);
+                    else
+                        hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, us,
+                                           upd + off, op.ka, op.kw, cf, bd);
+                }
                 PROF_END(KC_UPDATE);
                 if (us != st) {
                     HIP_TRY(hipEventRecord(f->ev_side, side));
@@ -812,12 +845,19 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                 }
                 if (prof)
                     for (int64_t q = off; q < off + cnt; q++)
-                        prof->flops[KC_UPDATE] += update_flops(P, P.upd_tasks[q], P.upd_jbeg[q], op.ka, op.kw,
-                                                                small ? 64 : UT);
+                        prof->flops[KC_UPDATE] += nbuf * update_flops(P, P.upd_tasks[q], P.upd_jbeg[q], op.ka, op.kw,
+                                                                       small ? 64 : UT);
             } else {
-                int c = op.kind == OP_PANEL ? KC_PANEL : KC_PANEL_FP64DIAG;
+                int c = (op.kind == OP_PANEL || lu) ? KC_PANEL : KC_PANEL_FP64DIAG;
                 PROF_BEGIN(c);
-                if (op.kind == OP_PANEL)
+                if constexpr (sizeof(T) == 8) {
+                    if (lu)
+                        hipLaunchKernelGGL(k_lu_panel<T>, dim3((unsigned)op.cnt), dim3(THREADS), 0, st, pan + op.off,
+                                           op.ka, fo, mf, pf, fi, dso, fronts, fronts_u, dscr, f->at<T>(Lo.dscr_u),
+                                           bad);
+                }
+                if (lu) {
+                } else if (op.kind == OP_PANEL)
                     hipLaunchKernelGGL((k_panel<T, T>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
                                        pan + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr, bad);
                 else
@@ -826,7 +866,7 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                 PROF_END(c);
                 if (prof)
                     for (int64_t q = op.off; q < op.off + op.cnt; q++)
-                        if (P.pan_tasks[q].y == 0) prof->flops[c] += panel_flops(P, P.pan_tasks[q].x, op.ka);
+                        if (P.pan_tasks[q].y == 0) prof->flops[c] += nbuf * panel_flops(P, P.pan_tasks[q].x, op.ka);
             }
         }
         if (pending) {   // the next level's extend-add reads this level's update matrices
@@ -841,8 +881,11 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
             PROF_BEGIN(KC_FILL);
             hipLaunchKernelGGL(k_diag_inv<T>, dim3((unsigned)L.dinv_cnt), dim3(64), 0, aux,
                                f->at<int2>(Lo.dinvt) + L.dinv_off, dso, dscr, dinv);
+            if (lu)
+                hipLaunchKernelGGL(k_diag_inv<T>, dim3((unsigned)L.dinv_cnt), dim3(64), 0, aux,
+                                   f->at<int2>(Lo.dinvt) + L.dinv_off, dso, f->at<T>(Lo.dscr_u), f->at<T>(Lo.dinv_u));
             PROF_END(KC_FILL);
-            if (prof) prof->bytes[KC_FILL] += (double)L.dinv_cnt * NB * NB * esz * 2;
+            if (prof) prof->bytes[KC_FILL] += (double)L.dinv_cnt * NB * NB * esz * 2 * nbuf;
         }
         r_ea = extend_add(L.ea_post, false);
         if (r_ea) return r_ea;
@@ -852,10 +895,11 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
         }
     }
     PROF_BEGIN(KC_FILL);
-    hipLaunchKernelGGL(k_diag_fixup<T>, dim3((unsigned)S.ns), dim3(256), 0, st, f->at<int32_t>(Lo.all_fronts), fo, mf,
-                       pf, dso, dscr, fronts);
+    for (int b = 0; b < nbuf; b++)
+        hipLaunchKernelGGL(k_diag_fixup<T>, dim3((unsigned)S.ns), dim3(256), 0, st, f->at<int32_t>(Lo.all_fronts), fo,
+                           mf, pf, dso, b ? f->at<T>(Lo.dscr_u) : dscr, buf(b));
     PROF_END(KC_FILL);
-    if (prof) prof->bytes[KC_FILL] += (double)P.dscr_elems * esz * 2;
+    if (prof) prof->bytes[KC_FILL] += (double)P.dscr_elems * esz * 2 * nbuf;
     if (aux != st) {   // the block inverses, then the super-block inverses built from them
         HIP_TRY(hipEventRecord(f->ev_aux, aux));
         HIP_TRY(hipStreamWaitEvent(st, f->ev_aux, 0));
@@ -865,6 +909,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
         hipLaunchKernelGGL(k_build_xinv<T>, dim3((unsigned)P.xinv_tasks.size()), dim3(THREADS), 0, st,
                            f->at<int4>(Lo.xinvt), fo, mf, pf, dso, f->at<int64_t>(Lo.xoff), fronts, dinv,
                            f->at<T>(Lo.xinv));
+        if (lu)
+            hipLaunchKernelGGL(k_build_xinv<T>, dim3((unsigned)P.xinv_tasks.size()), dim3(THREADS), 0, st,
+                               f->at<int4>(Lo.xinvt), fo, mf, pf, dso, f->at<int64_t>(Lo.xoff), fronts_u,
+                               f->at<T>(Lo.dinv_u), f->at<T>(Lo.xinv_u));
         PROF_END(KC_FILL);
     }
     HIP_TRY(hipGetLastError());
@@ -872,8 +920,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
 }
 
 // device pointers of the factor for the solve and product kernels
+// upper = true: the U^T fronts of an LU factor (the backward sweep solves
+// with U = (U^T)^T exactly as the Cholesky one solves with L^T)
 template <typename T>
-SolveArgs<T> solve_args(wcs_factor f, int k)
+SolveArgs<T> solve_args(wcs_factor f, int k, bool upper = false)
 {
     SolveArgs<T> a;
     const Layout &Lo = f->lay;
@@ -896,6 +946,11 @@ SolveArgs<T> solve_args(wcs_factor f, int k)
     a.W = f->at<T>(Lo.W);
     a.Y = f->at<T>(Lo.Y);
     a.k = k;
+    if (upper && is_lu(f->prec)) {
+        a.fronts = f->at<T>(Lo.fronts_u);
+        a.dinv = f->at<T>(Lo.dinv_u);
+        a.xinv = f->at<T>(Lo.xinv_u);
+    }
     return a;
 }
 
@@ -906,6 +961,7 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
     const Layout &Lo = f->lay;
     const Plan &P = f->plan;
     SolveArgs<T> a = solve_args<T>(f, k);
+    const SolveArgs<T> au = solve_args<T>(f, k, true);    // the backward sweep's factor (LU: U^T)
     const int32_t *sl = f->at<int32_t>(Lo.slist);
     const int2 *tf = f->at<int2>(Lo.sfwd);
     const int4 *tb = f->at<int4>(Lo.sbelow);
@@ -946,19 +1002,19 @@ int launch_sweeps(wcs_factor f, int part, int k, hipStream_t st)
             const SolveLevel &V = P.levels[h].sv;
             if (V.fused_cnt)
                 hipLaunchKernelGGL((k_bwd_fused<T, KT>), dim3((unsigned)V.fused_cnt), dim3(THREADS), 0, st,
-                                   sl + V.fused_off, a);
+                                   sl + V.fused_off, au);
             if (V.step_cnt) {
                 if (V.below.second)
                     hipLaunchKernelGGL((k_bwd_below_part<T, KT>), dim3((unsigned)V.below.second), dim3(THREADS), 0,
-                                       st, tb + V.below.first, a);
+                                       st, tb + V.below.first, au);
                 hipLaunchKernelGGL(k_bwd_below_sum<T>, dim3((unsigned)V.below_sum.second), dim3(THREADS), 0, st,
-                                   tbs + V.below_sum.first, a);
+                                   tbs + V.below_sum.first, au);
                 for (const SuperStep &s : V.bwd) {
                     hipLaunchKernelGGL((k_bwd_sx<T, KT>), dim3((unsigned)s.d_cnt), dim3(THREADS), 0, st,
-                                       sbk + s.d_off, s.s0, a);
+                                       sbk + s.d_off, s.s0, au);
                     if (s.t_cnt)
                         hipLaunchKernelGGL((k_bwd_scols<T, KT>), dim3((unsigned)s.t_cnt), dim3(THREADS), 0, st,
-                                           ts + s.t_off, s.s0, a);
+                                           ts + s.t_off, s.s0, au);
                 }
             }
         }
@@ -1395,7 +1451,7 @@ extern "C" {
 
 int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, size_t *bytes)
 {
-    if (!sym || !bytes || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32)) {
+    if (!sym || !bytes || max_nrhs < 1 || !valid_prec(prec)) {
         set_error("invalid argument to wcs_workspace_size");
         return WCS_EINVAL;
     }
@@ -1403,7 +1459,7 @@ int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, s
         Plan P;
         P.build(symbolic_of(sym));
         Layout L;
-        L.compute(symbolic_of(sym), P, elem_size(prec), max_nrhs);
+        L.compute(symbolic_of(sym), P, elem_size(prec), max_nrhs, is_lu(prec));
         *bytes = L.total;
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
@@ -1427,7 +1483,7 @@ int new_factor(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, wcs_facto
         f->max_nrhs = max_nrhs;
         f->plan.build(*f->S);
         for (Level &L : f->plan.levels) L.upd_var = default_update_variant(prec);
-        f->lay.compute(*f->S, f->plan, elem_size(prec), max_nrhs);
+        f->lay.compute(*f->S, f->plan, elem_size(prec), max_nrhs, is_lu(prec));
     } catch (const std::bad_alloc &) {
         delete f;
         set_error("host allocation failed");
@@ -1448,7 +1504,7 @@ extern "C" {
 int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, void *workspace, size_t bytes,
                       wcs_stream stream, wcs_factor *out)
 {
-    if (!sym || !out || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32) || !workspace) {
+    if (!sym || !out || max_nrhs < 1 || !valid_prec(prec) || !workspace) {
         set_error("invalid argument to wcs_factor_create");
         return WCS_EINVAL;
     }
@@ -1482,7 +1538,7 @@ int wcs_factor_create(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, vo
 int wcs_factor_create_static(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, wcs_stream stream,
                              wcs_factor *out)
 {
-    if (!sym || !out || max_nrhs < 1 || (prec != WCS_FP64 && prec != WCS_FP32)) {
+    if (!sym || !out || max_nrhs < 1 || !valid_prec(prec)) {
         set_error("invalid argument to wcs_factor_create_static");
         return WCS_EINVAL;
     }
@@ -1610,6 +1666,7 @@ extern "C" {
 int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *bad_col)
 {
     if (!f || !values_dev) { set_error("invalid argument to wcs_factor_numeric"); return WCS_EINVAL; }
+    if (is_lu(f->prec)) { set_error("an LU factor takes both triangles: wcs_factor_numeric_lu"); return WCS_EINVAL; }
     hipStream_t st = (hipStream_t)stream;
     int rc;
     auto eager = [&] {
@@ -1637,8 +1694,21 @@ int wcs_factor_numeric(wcs_factor f, const double *values_dev, wcs_stream stream
     return WCS_OK;
 }
 
+int wcs_factor_numeric_lu(wcs_factor f, const double *lower_dev, const double *upper_dev, wcs_stream stream,
+                          int32_t *bad_col)
+{
+    if (!f || !lower_dev || !upper_dev) { set_error("invalid argument to wcs_factor_numeric_lu"); return WCS_EINVAL; }
+    if (!is_lu(f->prec)) { set_error("wcs_factor_numeric_lu needs a factor created with WCS_LU64"); return WCS_EINVAL; }
+    int rc = launch_factor<double>(f, lower_dev, (hipStream_t)stream, nullptr, upper_dev);
+    if (rc) return rc;
+    f->have_values = true;
+    if (bad_col) return wcs_factor_check(f, stream, bad_col);
+    return WCS_OK;
+}
+
 int wcs_factor_profile(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *stats)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_factor_profile is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !values_dev || !stats) { set_error("invalid argument to wcs_factor_profile"); return WCS_EINVAL; }
     hipStream_t st = (hipStream_t)stream;
     Prof prof;
@@ -1659,6 +1729,11 @@ int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col)
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     if (h != INT32_MAX) {
         *bad_col = h;
+        if (is_lu(f->prec)) {
+            set_error("zero or non-finite pivot in the LU factorization: pivot " + std::to_string(h) +
+                      " (original index " + std::to_string(f->S->perm[h]) + ")");
+            return WCS_ESINGULAR;
+        }
         set_error("matrix is not positive definite: pivot " + std::to_string(h) + " (original index " +
                   std::to_string(f->S->perm[h]) + ")");
         return WCS_ENOTSPD;
@@ -1669,6 +1744,7 @@ int wcs_factor_check(wcs_factor f, wcs_stream stream, int32_t *bad_col)
 
 int wcs_factor_profile_levels(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *levels)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_factor_profile_levels is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !values_dev || !levels) { set_error("invalid argument to wcs_factor_profile_levels"); return WCS_EINVAL; }
     hipStream_t st = (hipStream_t)stream;
     Prof prof;
@@ -1685,6 +1761,7 @@ void wcs_factor_free(wcs_factor f) { delete f; }
 
 int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream stream, int32_t *tiles, double *ms)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_factor_autotune is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !values_dev) { set_error("invalid argument to wcs_factor_autotune"); return WCS_EINVAL; }
     hipStream_t st = (hipStream_t)stream;
     Plan &P = f->plan;
@@ -1778,7 +1855,32 @@ int wcs_factor_residuals(wcs_factor f, double *rel, int64_t count)
     return WCS_OK;
 }
 
+namespace wcs {
+namespace {
+// columns [j0, j1) of the L fronts (upper = false) or of the U^T fronts of an LU factor
+int export_columns(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t *Li, double *Lx, wcs_stream stream,
+                   bool upper);
+}  // namespace
+}  // namespace wcs
+
 int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t *Li, double *Lx, wcs_stream stream)
+{
+    return export_columns(f, j0, j1, Lp, Li, Lx, stream, false);
+}
+
+int wcs_factor_export_upper(wcs_factor f, int32_t j0, int32_t j1, int64_t *Up, int32_t *Ui, double *Ux,
+                            wcs_stream stream)
+{
+    if (f && !is_lu(f->prec)) { set_error("wcs_factor_export_upper needs an LU factor"); return WCS_EINVAL; }
+    return export_columns(f, j0, j1, Up, Ui, Ux, stream, true);
+}
+
+}  // extern "C"
+
+namespace wcs {
+namespace {
+int export_columns(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t *Li, double *Lx, wcs_stream stream,
+                   bool upper)
 {
     if (!f || !Lp || j0 < 0 || j1 < j0 || j1 > f->S->n || ((Li == nullptr) != (Lx == nullptr))) {
         set_error("invalid argument to wcs_factor_export");
@@ -1801,7 +1903,8 @@ int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t
         int32_t m = S.m_of(s), t = j - S.sptr[s];
         int32_t cnt = m - t;
         buf.resize((size_t)cnt * esz);
-        size_t off = f->lay.fronts + ((size_t)S.front_off[s] + (size_t)t * front_ld_host(m) + t) * esz;
+        size_t off = (upper ? f->lay.fronts_u : f->lay.fronts) +
+                     ((size_t)S.front_off[s] + (size_t)t * front_ld_host(m) + t) * esz;
         HIP_TRY(hipMemcpy(buf.data(), f->ws + off, (size_t)cnt * esz, hipMemcpyDeviceToHost));
         int64_t o = Lp[j - j0];
         for (int32_t r = 0; r < cnt; r++) {
@@ -1811,6 +1914,10 @@ int wcs_factor_export(wcs_factor f, int32_t j0, int32_t j1, int64_t *Lp, int32_t
     }
     return WCS_OK;
 }
+}  // namespace
+}  // namespace wcs
+
+extern "C" {
 
 int wcs_solve(wcs_factor f, wcs_part part, int32_t nrhs, double *B_dev, int64_t ld, wcs_stream stream)
 {
@@ -1820,12 +1927,13 @@ int wcs_solve(wcs_factor f, wcs_part part, int32_t nrhs, double *B_dev, int64_t 
     }
     if (!f->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
     hipStream_t st = (hipStream_t)stream;
-    return f->prec == WCS_FP64 ? launch_solve<double>(f, part, nrhs, B_dev, ld, st)
-                               : launch_solve<float>(f, part, nrhs, B_dev, ld, st);
+    return f->prec == WCS_FP32 ? launch_solve<float>(f, part, nrhs, B_dev, ld, st)
+                               : launch_solve<double>(f, part, nrhs, B_dev, ld, st);
 }
 
 int wcs_apply(wcs_factor f, wcs_apply_part part, int32_t nrhs, double *B_dev, int64_t ld, wcs_stream stream)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_apply is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !B_dev || nrhs < 1 || nrhs > f->max_nrhs || ld < f->S->n ||
         (part != WCS_APPLY_L && part != WCS_APPLY_LT)) {
         set_error("invalid argument to wcs_apply");
@@ -1840,6 +1948,7 @@ int wcs_apply(wcs_factor f, wcs_apply_part part, int32_t nrhs, double *B_dev, in
 int wcs_solve_refined(wcs_factor f, const double *values_dev, int32_t nrhs, const double *B_dev, double *X_dev,
                       int64_t ld, double tol, int32_t max_iter, wcs_ir_report *rep, wcs_stream stream)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_solve_refined is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !values_dev || !B_dev || !X_dev || !rep || nrhs < 1 || nrhs > f->max_nrhs || ld < f->S->n ||
         max_iter < 0 || !(tol >= 0)) {
         set_error("invalid argument to wcs_solve_refined");
@@ -1855,6 +1964,7 @@ int wcs_solve_refined(wcs_factor f, const double *values_dev, int32_t nrhs, cons
 int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double *X_dev, double *Y_dev, int64_t ld,
              wcs_stream stream)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_spmv is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !values_dev || !X_dev || !Y_dev || nrhs < 1 || ld < f->S->n) {
         set_error("invalid argument to wcs_spmv");
         return WCS_EINVAL;
@@ -1875,6 +1985,7 @@ int wcs_spmv(wcs_factor f, const double *values_dev, int32_t nrhs, const double 
 int wcs_theta_matrix(wcs_factor f, const double *K_values_dev, double theta, double dt, double *A_values_dev,
                      wcs_stream stream)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_theta_matrix is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !K_values_dev || !A_values_dev || !(theta > 0 && theta <= 1) || !(dt > 0)) {
         set_error("invalid argument to wcs_theta_matrix");
         return WCS_EINVAL;
@@ -1891,6 +2002,7 @@ int wcs_theta_steps(wcs_factor f, const double *A_values_dev, double theta, doub
                     const double *F_dev, int64_t ldf, double *U_dev, int64_t ldu, double tol, wcs_ir_report *rep,
                     wcs_stream stream)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_theta_steps is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !A_values_dev || !F_dev || !U_dev || !rep || nsteps < 1 || !(theta > 0 && theta <= 1) || !(dt > 0) ||
         ldf < f->S->n || ldu < f->S->n || !(tol >= 0)) {
         set_error("invalid argument to wcs_theta_steps");
@@ -1905,6 +2017,7 @@ int wcs_theta_steps(wcs_factor f, const double *A_values_dev, double theta, doub
 
 int wcs_grad_pattern(wcs_factor f, const double *lam_dev, const double *x_dev, double *gA_dev, wcs_stream stream)
 {
+    if (f && is_lu(f->prec)) { set_error("wcs_grad_pattern is not defined for an LU factor"); return WCS_EINVAL; }
     if (!f || !lam_dev || !x_dev || !gA_dev) { set_error("invalid argument to wcs_grad_pattern"); return WCS_EINVAL; }
     const Symbolic &S = *f->S;
     hipLaunchKernelGGL(k_grad_pattern, dim3(grid_for(S.nnz)), dim3(256), 0, (hipStream_t)stream,

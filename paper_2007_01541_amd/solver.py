@@ -18,6 +18,7 @@ from .capi import AnalyzeOpts, IRReport, SymbolicInfo, check, lib
 
 FP64 = 0
 FP32 = 1
+LU64 = 2          # nonsymmetric A = P^T L U P (FP64 fronts)
 SOLVE_FULL = 0
 SOLVE_L = 1
 SOLVE_LT = 2
@@ -177,6 +178,19 @@ class Factor:
             check(lib().wcs_factor_numeric(self.handle, _dptr(values), _stream_ptr(stream), None),
                   "wcs_factor_numeric")
 
+    def numeric_lu(self, lower, upper, check_pivots: bool = True, stream=None) -> None:
+        """LU factorization (factor created with LU64) of the nonsymmetric matrix
+        with device FP64 values on/below the diagonal (lower) and above it
+        (upper), both aligned with the analysed lower pattern."""
+        torch = _torch()
+        for v in (lower, upper):
+            assert v.dtype == torch.float64 and v.is_cuda and v.is_contiguous()
+        self.values = (lower, upper)
+        bad = C.c_int32(-1)
+        rc = lib().wcs_factor_numeric_lu(self.handle, _dptr(lower), _dptr(upper), _stream_ptr(stream),
+                                         C.byref(bad) if check_pivots else None)
+        check(rc, "wcs_factor_numeric_lu", bad.value)
+
     def use_graphs(self, enable: bool = True) -> None:
         """Record the factorization and the sweeps into HIP graphs and replay them."""
         check(lib().wcs_factor_use_graphs(self.handle, 1 if enable else 0), "wcs_factor_use_graphs")
@@ -329,14 +343,20 @@ class Factor:
 
     def export_L(self, j0: int = 0, j1: Optional[int] = None):
         """Columns [j0, j1) of L in pivot order as host CSC (stored pattern, explicit zeros kept)."""
+        return self._export("wcs_factor_export", j0, j1)
+
+    def export_U(self, j0: int = 0, j1: Optional[int] = None):
+        """LU factors: columns [j0, j1) of U^T (entry (i, j) = u(j, i)) in the format of export_L."""
+        return self._export("wcs_factor_export_upper", j0, j1)
+
+    def _export(self, call: str, j0: int, j1: Optional[int]):
         j1 = self.n if j1 is None else j1
+        fn = getattr(lib(), call)
         Lp = np.empty(j1 - j0 + 1, np.int64)
-        check(lib().wcs_factor_export(self.handle, j0, j1, Lp.ctypes.data, None, None, _stream_ptr()),
-              "wcs_factor_export")
+        check(fn(self.handle, j0, j1, Lp.ctypes.data, None, None, _stream_ptr()), call)
         Li = np.empty(int(Lp[-1]), np.int32)
         Lx = np.empty(int(Lp[-1]), np.float64)
-        check(lib().wcs_factor_export(self.handle, j0, j1, Lp.ctypes.data, Li.ctypes.data, Lx.ctypes.data,
-                                      _stream_ptr()), "wcs_factor_export")
+        check(fn(self.handle, j0, j1, Lp.ctypes.data, Li.ctypes.data, Lx.ctypes.data, _stream_ptr()), call)
         return Lp, Li, Lx
 
 
