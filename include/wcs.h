@@ -424,6 +424,30 @@ int wcs_theta_steps(wcs_factor f, const double *A_values_dev, double theta, doub
                     wcs_stream stream);
 
 /*
+ * Gaussian random field samples in covariance form (Section 5.3,
+ * eq:CholFastField): out = G^-1 (abar^G + L X), the wavelet coefficients of
+ * the field a_J = Psi_J G^-1 (abar^G + L X), where L L^T = C^G is the
+ * Cholesky decomposition of the Galerkin covariance matrix and G the mass
+ * matrix.  cov: a Cholesky factor of C^G (its own ordering P_C, so L =
+ * P_C^T L_C); mass: a Cholesky factor of G created from its own analysis
+ * (Section 6.3: the mass matrix gets an ordering of its own, with much less
+ * fill than the system matrix's), on the same index set (equal n).  Either
+ * may be FP64 or FP32 (FP32 products and solves round once to FP32 and back).
+ * X_dev: nrhs standard normal vectors, n x nrhs column-major with leading
+ * dimension ldx, read as coefficients in cov's pivot order (white noise: any
+ * fixed order gives the same distribution).  abar_dev: the mean term in the
+ * original order, n x nrhs with leading dimension lda, or one vector for all
+ * samples (lda = 0), or NULL (no mean).  out_dev: n x nrhs, leading dimension
+ * ld, original order; it may be X_dev when ldx == ld.  nrhs may not exceed
+ * either factor's max_nrhs.  Uses both factors' right-hand-side buffers, so
+ * calls on them are ordered by the stream.  Errors: WCS_EINVAL (bad arguments,
+ * LU factors, different n), WCS_ESTATE (a factor without numeric values).
+ * Asynchronous on the stream.
+ */
+int wcs_field_sample(wcs_factor cov, wcs_factor mass, int32_t nrhs, const double *abar_dev, int64_t lda,
+                     const double *X_dev, int64_t ldx, double *out_dev, int64_t ld, wcs_stream stream);
+
+/*
  * Gradient of a scalar loss through x = A^-1 b with respect to the stored
  * lower entries of A, given lam = A^-1 (dloss/dx): entry (i,j), i > j, gets
  * -(lam_i x_j + lam_j x_i); a diagonal entry gets -lam_i x_i.  Device arrays:

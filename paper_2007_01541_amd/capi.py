@@ -87,6 +87,7 @@ SIGNATURES = [
                                     C.POINTER(IRReport), c_p]),
     ("wcs_spmv", C.c_int, [c_p, c_p, c_i32, c_p, c_p, c_i64, c_p]),
     ("wcs_grad_pattern", C.c_int, [c_p, c_p, c_p, c_p, c_p]),
+    ("wcs_field_sample", C.c_int, [c_p, c_p, c_i32, c_p, c_i64, c_p, c_i64, c_p, c_i64, c_p]),
     ("wcs_theta_matrix", C.c_int, [c_p, c_p, C.c_double, C.c_double, c_p, c_p]),
     ("wcs_theta_steps", C.c_int, [c_p, c_p, C.c_double, C.c_double, c_i32, c_p, c_i64, c_p, c_i64, C.c_double,
                                   C.POINTER(IRReport), c_p]),

@@ -1178,6 +1178,18 @@ __global__ void k_perm_out(const T *__restrict__ Y, const int32_t *__restrict__ 
 
 // Plain copies between a caller column-major block and the internal
 // row-major layout without permutation (used by the half solves).
+// X[:, c] += a[:, c] (lda > 0) or a (lda == 0: one vector for every column);
+// column-major n x k with leading dimension ld
+__global__ void k_add_cols(double *__restrict__ X, int64_t ld, int n, int k, const double *__restrict__ a,
+                           int64_t lda)
+{
+    int64_t nk = (int64_t)n * k, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += stride) {
+        int64_t c = i / n, r = i % n;
+        X[c * ld + r] += a[c * lda + r];
+    }
+}
+
 template <typename T>
 __global__ void k_rows_in(const double *__restrict__ B, int64_t ld, int n, int k, T *__restrict__ Y)
 {

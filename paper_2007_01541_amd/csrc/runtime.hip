@@ -2015,6 +2015,36 @@ int wcs_theta_steps(wcs_factor f, const double *A_values_dev, double theta, doub
                : theta_steps<float>(f, A_values_dev, theta, dt, nsteps, F_dev, ldf, U_dev, ldu, tol, rep, st);
 }
 
+int wcs_field_sample(wcs_factor cov, wcs_factor mass, int32_t nrhs, const double *abar_dev, int64_t lda,
+                     const double *X_dev, int64_t ldx, double *out_dev, int64_t ld, wcs_stream stream)
+{
+    if (!cov || !mass || !X_dev || !out_dev || nrhs < 1 || is_lu(cov->prec) || is_lu(mass->prec) ||
+        cov->S->n != mass->S->n || nrhs > cov->max_nrhs || nrhs > mass->max_nrhs || lda < 0 ||
+        (lda > 0 && lda < cov->S->n) || ldx < cov->S->n || ld < cov->S->n) {
+        set_error("invalid argument to wcs_field_sample");
+        return WCS_EINVAL;
+    }
+    if (!cov->have_values || !mass->have_values) { set_error("no numeric factorization yet"); return WCS_ESTATE; }
+    hipStream_t st = (hipStream_t)stream;
+    const int n = cov->S->n;
+    if (X_dev != out_dev || ldx != ld)
+        HIP_TRY(hipMemcpy2DAsync(out_dev, (size_t)ld * 8, X_dev, (size_t)ldx * 8, (size_t)n * 8, (size_t)nrhs,
+                                 hipMemcpyDeviceToDevice, st));
+    // P_C^T L_C X with the noise in the covariance factor's pivot order
+    int rc = cov->prec == WCS_FP32 ? launch_apply<float>(cov, WCS_APPLY_L, nrhs, out_dev, ld, st)
+                                   : launch_apply<double>(cov, WCS_APPLY_L, nrhs, out_dev, ld, st);
+    if (rc) return rc;
+    if (abar_dev)
+        hipLaunchKernelGGL(k_add_cols, dim3(grid_for((int64_t)n * nrhs)), dim3(256), 0, st, out_dev, ld, n, nrhs,
+                           abar_dev, lda);
+    // G^-1 (abar + L X) with the mass matrix's own factor
+    rc = mass->prec == WCS_FP32 ? launch_solve<float>(mass, WCS_SOLVE_FULL, nrhs, out_dev, ld, st)
+                                : launch_solve<double>(mass, WCS_SOLVE_FULL, nrhs, out_dev, ld, st);
+    if (rc) return rc;
+    HIP_TRY(hipGetLastError());
+    return WCS_OK;
+}
+
 int wcs_grad_pattern(wcs_factor f, const double *lam_dev, const double *x_dev, double *gA_dev, wcs_stream stream)
 {
     if (f && is_lu(f->prec)) { set_error("wcs_grad_pattern is not defined for an LU factor"); return WCS_EINVAL; }

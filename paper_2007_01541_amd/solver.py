@@ -360,6 +360,30 @@ class Factor:
         return Lp, Li, Lx
 
 
+def field_sample(cov: Factor, mass: Factor, X, abar=None, stream=None):
+    """Random field coefficients G^-1 (abar + L X) (Section 5.3, eq:CholFastField)
+    from a Cholesky factor of the covariance matrix (cov) and one of the mass
+    matrix (mass, its own ordering); X: device FP64 (n,) or (n, k) standard
+    normal noise in cov's pivot order; abar: None, (n,) or (n, k).  Returns a
+    new (n,) or (n, k) tensor in the original order."""
+    torch = _torch()
+    n = cov.n
+    Xm = X if X.dim() == 2 else X.view(-1, 1)
+    k = Xm.shape[1]
+    xc = Xm.t().contiguous()                      # column-major n x k, ld = n
+    out = torch.empty_like(xc)
+    a = None
+    lda = 0
+    if abar is not None:
+        am = abar if abar.dim() == 2 else abar.view(-1, 1)
+        a = am.t().contiguous()
+        lda = n if am.shape[1] > 1 else 0
+    check(lib().wcs_field_sample(cov.handle, mass.handle, k, _dptr(a) if a is not None else None, lda, _dptr(xc), n,
+                                 _dptr(out), n, _stream_ptr(stream)), "wcs_field_sample")
+    res = out.t()
+    return res.contiguous() if X.dim() == 2 else res.reshape(-1)
+
+
 def _solve_op():
     torch = _torch()
 
