@@ -293,12 +293,179 @@ def bench_theta(args) -> int:
     return 0
 
 
+def lu_flops(colcount) -> float:
+    """Flops of LU without pivoting on the Cholesky pattern: column j (count
+    c_j, diagonal included) takes c_j - 1 divisions and a rank-one update of
+    the (c_j - 1)^2 entries below and right of its pivot (2 flops each)."""
+    import numpy as np
+    c = np.asarray(colcount, np.float64)
+    return float(np.sum((c - 1.0) * (2.0 * c - 1.0)))
+
+
+def lu_sample_flops(Lp, Li, ncols: int) -> float:
+    """Flops of the oracle's left-looking LU over its first ncols columns:
+    pivot t < ncols contributes its c_t - 1 divisions and, for every row j of
+    its column with j < ncols (a column of U it updates), 2 (c_t - 1) flops."""
+    import numpy as np
+    total = 0.0
+    for t in range(ncols):
+        rows = Li[Lp[t] + 1:Lp[t + 1]]
+        c1 = rows.size
+        total += c1 + 2.0 * c1 * int(np.searchsorted(rows, ncols))
+    return total
+
+
+def bench_lu(args) -> int:
+    """LU of the nonsymmetric PCM stand-in (Section 5.1, eq:PCM2) on the
+    nested dissection ordering of its symmetric pattern, FP64: value load and
+    factorization timed with HIP events, then the solve of the right-hand
+    sides; the oracle's left-looking LU timed on the leading pivot columns."""
+    import numpy as np
+    import torch
+    import oracle
+    import workloads
+    from paper_2007_01541_amd import LU64, Factor, Symbolic
+    w = workloads.pcm_lu(args.grid, 8)
+    t0 = time.perf_counter()
+    m = w.matrix()
+    n = m["n"]
+    B = w.rhs()
+    log(f"{w.name}: generated in {time.perf_counter() - t0:.1f}s, nnz_lower={m['colptr'][-1]}")
+    t0 = time.perf_counter()
+    sym = Symbolic(n, m["colptr"], m["rowind"], coords=m["coords"])
+    t_an = time.perf_counter() - t0
+    ex = sym.export()
+    F = lu_flops(ex["colcount"])
+    log(f"analyze {t_an:.1f}s: nnz(L) = nnz(U) = {sym.info['nnz_l']}, LU flops {F:.4e}")
+    lo = torch.as_tensor(m["values"], device="cuda")
+    up = torch.as_tensor(m["upper"], device="cuda")
+    Bd = torch.as_tensor(B, device="cuda")
+    f = Factor(sym, LU64, max_nrhs=w.nrhs)
+    log(f"LU workspace {f.workspace.numel() / 2**30:.1f} GiB")
+    for _ in range(args.warmup):
+        f.numeric_lu(lo, up)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    fact, sol = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        f.numeric_lu(lo, up, check_pivots=False)
+        e1.record(stream)
+        X = f.solve(Bd)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        fact.append(e0.elapsed_time(e1))
+        sol.append(e1.elapsed_time(e2))
+    t_step = (time.perf_counter() - t0) / args.steps
+    f.numeric_lu(lo, up)          # pivot check
+    fact_ms, sol_ms = float(np.median(fact)), float(np.median(sol))
+    log(f"  LU factor {fact_ms:.2f} ms ({F / fact_ms / 1e9:.1f} TFLOP/s), solve of {w.nrhs} RHS {sol_ms:.2f} ms")
+    cpu = None
+    Xh = X.cpu().numpy()
+    res = float(oracle.gemv_residual(n, m["colptr"], m["rowind"], m["values"], m["upper"], Xh, B).max())
+    log(f"  residual of the LU solution (oracle product): {res:.3e}")
+    if not args.no_cpu_baseline:
+        parent, cc, _, _ = oracle.symbolic(n, m["colptr"], m["rowind"], ex["perm"])
+        assert np.array_equal(parent, ex["parent"]) and np.array_equal(cc, ex["colcount"])
+        Lp, Li = oracle.pattern(n, m["colptr"], m["rowind"], ex["perm"], parent, cc)
+        cum = np.cumsum((cc.astype(np.float64) - 1) * (2 * cc.astype(np.float64) - 1))
+        k = min(int(np.searchsorted(cum, 3e9 * args.cpu_seconds / 20.0)) + 1, n)
+        t0 = time.perf_counter()
+        oracle.lu(n, m["colptr"], m["rowind"], m["values"], m["upper"], ex["perm"], Lp, Li, ncols=k)
+        t = time.perf_counter() - t0
+        fl = lu_sample_flops(Lp, Li, k)
+        cpu = {"value": fl / t / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+               "sample": f"left-looking FP64 LU of the first {k} of {n} pivot columns of the same matrix: "
+                         f"{fl:.4g} flops in {t:.2f} s, single thread"}
+        log(f"  oracle LU sample: {cpu['sample']}")
+    out = {
+        "metric": "LU factor TFLOP/s (FP64, nonsymmetric PCM stand-in on the nested dissection ordering)",
+        "value": F / fact_ms / 1e9, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_step * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "nnz_lower": int(m["colptr"][-1]), "nnz_l": int(sym.info["nnz_l"]),
+                   "lu_flops": F, "nrhs": w.nrhs, "analyze_s": round(t_an, 2)},
+        "pct_fp64_mfma_peak": 100 * F / fact_ms / 1e9 / PEAK["fp64_mfma_tflops"],
+        "factor_ms": fact_ms, "solve_ms": sol_ms, "residual": res, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_field(args) -> int:
+    """Random field samples in covariance form (Section 5.3,
+    eq:CholFastField): the covariance matrix and the mass matrix analysed
+    and factored separately, then batches of samples G^-1 (abar + L X); the
+    factors are set up once, the samples are the timed work (the paper times
+    one sample, averaged over 1000)."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2007_01541_amd import FP32, FP64, Factor, Symbolic, field_sample
+    w = workloads.covariance_field(args.grid + 1 if args.grid else 9)
+    t0 = time.perf_counter()
+    mc, mg = w.cov_matrix(), w.mass_matrix()
+    n = w.n
+    log(f"{w.name}: generated in {time.perf_counter() - t0:.1f}s; nnz_lower C {mc['colptr'][-1]}, G {mg['colptr'][-1]}")
+    t0 = time.perf_counter()
+    sc = Symbolic(n, mc["colptr"], mc["rowind"], coords=mc["coords"])
+    sg = Symbolic(n, mg["colptr"], mg["rowind"], coords=mg["coords"])
+    t_an = time.perf_counter() - t0
+    log(f"analyze {t_an:.1f}s: nnz(L_C) {sc.info['nnz_l']}, nnz(L_G) {sg.info['nnz_l']}")
+    vc = torch.as_tensor(mc["values"], device="cuda")
+    vg = torch.as_tensor(mg["values"], device="cuda")
+    abar = torch.as_tensor(w.mean(), device="cuda")
+    res = {}
+    for prec, nm in ((FP64, "fp64"), (FP32, "fp32")):
+        fc = Factor(sc, prec, max_nrhs=64)
+        fg = Factor(sg, prec, max_nrhs=64)
+        fc.numeric(vc)
+        fg.numeric(vg)
+        per = {}
+        for k in (1, 64):
+            X = torch.as_tensor(w.noise(k), device="cuda")
+            for _ in range(max(1, args.warmup)):
+                field_sample(fc, fg, X, abar)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = max(3, args.steps)
+            e0.record()
+            for _ in range(reps):
+                S = field_sample(fc, fg, X, abar)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            per[f"k{k}"] = {"ms_per_call": ms, "samples_per_s": k / ms * 1e3,
+                            "ms_per_sample": ms / k}
+            log(f"  {nm}: {k} sample(s) per call: {ms:.3f} ms ({k / ms * 1e3:.0f} samples/s)")
+        res[nm] = per
+        del fc, fg
+        torch.cuda.empty_cache()
+    out = {
+        "metric": "random field samples/s (covariance form G^-1 (abar + L X), FP64, one sample per call)",
+        "value": res["fp64"]["k1"]["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": max(3, args.steps),
+        "warmup": args.warmup, "ms_per_step": res["fp64"]["k1"]["ms_per_call"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "n": n, "nnz_lower_cov": int(mc["colptr"][-1]),
+                   "nnz_lower_mass": int(mg["colptr"][-1]), "nnz_l_cov": int(sc.info["nnz_l"]),
+                   "nnz_l_mass": int(sg.info["nnz_l"]), "analyze_s": round(t_an, 2)},
+        "fp64": res["fp64"], "fp32": res["fp32"], "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="headline", choices=["headline", "medium", "small", "batch", "theta"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "medium", "small", "batch", "theta", "lu", "field"])
+    ap.add_argument("--grid", type=int, default=8,
+                    help="lu workload: grid exponent (2^grid squared cells, N = 4^grid); field: grid + 1")
     ap.add_argument("--instances", type=int, default=256, help="batch workload: number of instances")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -320,6 +487,10 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "theta":
         return bench_theta(args)
+    if args.workload == "lu":
+        return bench_lu(args)
+    if args.workload == "field":
+        return bench_field(args)
 
     import numpy as np
     import torch
