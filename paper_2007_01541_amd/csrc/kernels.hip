@@ -56,6 +56,11 @@ template <int B, int E, int S, typename Fn> __device__ __forceinline__ void stat
     }
 }
 
+// four consecutive elements as one vector access (16 bytes FP32, 32 bytes FP64)
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float4 type; };
+template <> struct Vec4<double> { typedef double4 type; };
+
 // leading dimension of an m x m front (m rounded up to 8 elements)
 __device__ __forceinline__ int front_ld(int m) { return (m + 7) & ~7; }
 
@@ -532,6 +537,143 @@ __global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *_
     }
 }
 
+// ---------------------------------------------------------------- leaf fronts
+// Persistent factorization of the leaf fronts (no children) of one or many
+// assembly trees in a single launch: every workgroup takes the next front
+// from a queue (fronts listed largest first; *counter starts at 0 and is
+// advanced atomically) until the queue is empty, so every workgroup exits.
+// The front's pivot columns (m x p, zeroed and filled with A beforehand) are
+// staged in LDS, column-major with leading dimension sld (= 16 mod 32, so the
+// four k-columns a wave reads per matrix-core step fall in distinct bank
+// halves), and factored by right-looking column steps (l_jj = sqrt(a_jj),
+// l_ij = a_ij / l_jj below it, then the later pivot columns updated by the
+// rank-one product; each element by one thread in a fixed order).  The
+// factored panel goes back to the front and its diagonal block to the
+// diagonal-block scratch (as the panel kernel's block, identity-padded);
+// then the update matrix C = -L21 L21^T (lower triangle; a leaf has no
+// children, so it is assigned) is formed on the matrix cores straight from
+// the LDS copy, 64 x 64 tiles spread over the waves.  Fronts that fit:
+// p <= NB and sld * p <= LeafCfg<T>::ELEMS (the plan routes the others to the
+// level-synchronous kernels, which run beside this launch).  A non-positive pivot is reported as in the
+// panel kernel.
+// LDS of the staged panel: FP32 80 KB (two workgroups per compute unit),
+// FP64 156 KB (one); either holds the pivot columns of nearly every leaf
+// front of the benchmark matrices
+template <typename T> struct LeafCfg {
+    static constexpr int BYTES = sizeof(T) == 4 ? 81920 - 64 : 159744 - 64;
+    static constexpr int ELEMS = BYTES / (int)sizeof(T);
+    static constexpr int PER_CU = sizeof(T) == 4 ? 2 : 1;
+};
+__host__ __device__ inline int leaf_sld(int m) { return ((m + 15) / 32) * 32 + 16; }
+
+template <typename T>
+__global__ __launch_bounds__(THREADS, LeafCfg<T>::PER_CU) void k_leaf(const int32_t *__restrict__ queue, int nq,
+                                                     int32_t *__restrict__ counter,
+                                                     const int64_t *__restrict__ front_off,
+                                                     const int32_t *__restrict__ mfront,
+                                                     const int32_t *__restrict__ pfront,
+                                                     const int32_t *__restrict__ first,
+                                                     const int64_t *__restrict__ dscr_off, T *__restrict__ fronts,
+                                                     T *__restrict__ dscr, int32_t *__restrict__ bad)
+{
+    __shared__ __align__(16) T S[LeafCfg<T>::ELEMS];
+    __shared__ int s_task;
+    typedef typename Mfma<T>::V V;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int kq = lane / 16, ln = lane % 16;
+    for (;;) {
+        if (tid == 0) s_task = atomicAdd(counter, 1);
+        __syncthreads();
+        const int q = s_task;
+        __syncthreads();                  // every thread has read s_task (and the last front's LDS use is over)
+        if (q >= nq) break;
+        const int f = queue[q];
+        const int m = mfront[f], p = pfront[f], ld = front_ld(m), sld = leaf_sld(m);
+        T *F = fronts + front_off[f];
+        for (int c = 0; c < p; c++)
+            for (int r = c + tid; r < m; r += THREADS) S[c * sld + r] = F[(int64_t)c * ld + r];
+        for (int j = 0; j < p; j++) {
+            __syncthreads();              // column j is final
+            T d = S[j * sld + j];
+            if (!(d > (T)0)) {
+                if (tid == 0) atomicMin(bad, first[f] + j);
+                d = (T)1;
+            }
+            const T rp = rsqrt_refined(d);
+            __syncthreads();              // every thread has read the pivot
+            for (int i = j + tid; i < m; i += THREADS) S[j * sld + i] = i == j ? d * rp : S[j * sld + i] * rp;
+            __syncthreads();
+            for (int c = j + 1; c < p; c++) {
+                const T lc = S[j * sld + c];
+                for (int i = c + tid; i < m; i += THREADS) S[c * sld + i] -= S[j * sld + i] * lc;
+            }
+        }
+        __syncthreads();
+        for (int c = 0; c < p; c++)
+            for (int r = c + tid; r < m; r += THREADS) F[(int64_t)c * ld + r] = S[c * sld + r];
+        T *D = dscr + dscr_off[f];
+        for (int e = tid; e < NB * NB; e += THREADS) {
+            int c = e / NB, r = e % NB;
+            D[e] = (r < p && c < p && r >= c) ? S[c * sld + r] : (r == c ? (T)1 : (T)0);
+        }
+        // update matrix, 64 x 64 tiles of the lower triangle from row and column
+        // p rounded down to 4 (earlier rows and columns masked), round robin
+        // over the waves.  The A operand takes the tile rows in the order that
+        // leaves each lane the results of four consecutive rows of one column
+        // (MFMA row 4e + q of the FP64 form holds row 4q + e; the FP32 form
+        // already does), so each quad goes out as one 16- or 32-byte store.
+        const int p4 = p & ~3, nu = m - p4, nt = (nu + 63) / 64;
+        const int arow = sizeof(T) == 8 ? 4 * (ln % 4) + ln / 4 : ln;
+        int tile = 0;
+        for (int bj = 0; bj < nt; bj++)
+            for (int bi = bj; bi < nt; bi++, tile++) {
+                if (tile % (THREADS / 64) != wave) continue;
+                const int i0 = p4 + 64 * bi, j0 = p4 + 64 * bj;
+                V acc[4][4];
+#pragma unroll
+                for (int x = 0; x < 4; x++)
+#pragma unroll
+                    for (int y = 0; y < 4; y++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++) acc[x][y][e] = 0;
+                for (int kc = 0; kc < p; kc += 4) {
+                    const int k = kc + kq;
+                    T av[4], bv[4];
+#pragma unroll
+                    for (int x = 0; x < 4; x++) {
+                        int ra = i0 + 16 * x + arow, rb = j0 + 16 * x + ln;
+                        av[x] = (k < p && ra < m) ? S[k * sld + ra] : (T)0;
+                        bv[x] = (k < p && rb < m) ? S[k * sld + rb] : (T)0;
+                    }
+#pragma unroll
+                    for (int x = 0; x < 4; x++)
+#pragma unroll
+                        for (int y = 0; y < 4; y++) acc[x][y] = Mfma<T>::mma(av[x], bv[y], acc[x][y]);
+                }
+                typedef typename Vec4<T>::type V4;
+#pragma unroll
+                for (int x = 0; x < 4; x++)
+#pragma unroll
+                    for (int y = 0; y < 4; y++) {
+                        const int r0 = i0 + 16 * x + 4 * kq, col = j0 + 16 * y + ln;
+                        if (col < p || col >= m) continue;
+                        if (r0 >= col && r0 + 3 < m) {
+                            V4 v;
+                            v.x = -acc[x][y][0];
+                            v.y = -acc[x][y][1];
+                            v.z = -acc[x][y][2];
+                            v.w = -acc[x][y][3];
+                            *reinterpret_cast<V4 *>(F + (int64_t)col * ld + r0) = v;
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; e++)
+                                if (r0 + e < m && r0 + e >= col) F[(int64_t)col * ld + r0 + e] = -acc[x][y][e];
+                        }
+                    }
+            }
+    }
+}
+
 // ---------------------------------------------------------------- LU panel
 // LU without pivoting of a front with a symmetric pattern (the nonsymmetric
 // matrices of Section 5.1): two buffers with the same layout as the Cholesky
@@ -669,9 +811,6 @@ __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict_
 // before any store, a masked-off element loading a harmless in-bounds word
 // (F[0]) that is never stored, so the round trips to memory overlap instead
 // of being serialised element by element.
-template <typename T> struct Vec4;
-template <> struct Vec4<float> { typedef float4 type; };
-template <> struct Vec4<double> { typedef double4 type; };
 
 template <typename T, typename V, typename RowFn, typename ColFn>
 __device__ __forceinline__ void tile_sub(T *__restrict__ F, int ld, int m, int jbeg, int jend, int pa,

@@ -67,6 +67,15 @@ int32_t solve_step_min_rows()
 }
 constexpr int kPartBlocks = 512;             // blocks of the two-pass column reductions
 
+// Leaf fronts whose pivot columns fit in LDS are factored by one persistent
+// launch (k_leaf) instead of the level-synchronous panel and update launches
+// (environment WCS_LEAF_KERNEL, default 1; 0 = off).  Cholesky factors only.
+bool leaf_kernel_enabled()
+{
+    const char *e = std::getenv("WCS_LEAF_KERNEL");
+    return e ? std::atoi(e) != 0 : true;
+}
+
 // Static schedule derived from the symbolic structure only.  Inside every
 // front: for each outer block of NBO pivot columns, for each NB-wide panel in
 // it, factor the panel (diagonal block + rows below) and update the rest of
@@ -105,6 +114,7 @@ struct Level {
     std::vector<std::pair<int64_t, int64_t>> ea;   // extend-add rounds into the pivot columns (offset, count)
     std::vector<std::pair<int64_t, int64_t>> ea_post;   // ... into the update matrices, after the trailing updates
     int64_t dinv_off = 0, dinv_cnt = 0;            // diagonal blocks of this level's fronts (dinv_tasks)
+    int64_t leaf_off = 0, leaf_cnt = 0;            // fronts factored by the persistent leaf kernel (leaf_queue)
     int64_t fl_off = 0, fl_cnt = 0;                // fronts of this level in flist
 };
 
@@ -141,8 +151,11 @@ struct Plan {
     // adds in slot order
     std::vector<int4> spmv_chunks, spmv_long;
     int64_t spmv_slots = 0;
+    std::vector<int32_t> leaf_queue;              // leaf fronts of the persistent kernel, largest first
 
-    void build(const Symbolic &S)
+    // esz: element size of the fronts; leaf_ok: route leaf fronts that fit in
+    // LDS to the persistent leaf kernel
+    void build(const Symbolic &S, size_t esz = 8, bool leaf_ok = false)
     {
         int32_t ns = S.ns;
         const int32_t diag64 = fp64_diag_min_cols();
@@ -193,14 +206,29 @@ struct Plan {
         upd_tasks.clear();
         upd_jbeg.clear();
         ea_tasks.clear();
+        leaf_queue.clear();
+        const int leaf_elems = esz == 4 ? LeafCfg<float>::ELEMS : LeafCfg<double>::ELEMS;
         for (int32_t h = 0; h < H; h++) {
             Level &L = levels[h];
-            const std::vector<int32_t> &fr = bylev[h];
+            const std::vector<int32_t> &all = bylev[h];
+            // the fronts of this level that the level-synchronous launches factor
+            std::vector<int32_t> fr;
+            L.leaf_off = (int64_t)leaf_queue.size();
+            for (int32_t s : all) {
+                bool leaf = h == 0 && leaf_ok && pfront[s] <= NB &&
+                            (int64_t)leaf_sld(mfront[s]) * pfront[s] <= leaf_elems;
+                (leaf ? leaf_queue : fr).push_back(s);
+            }
+            L.leaf_cnt = (int64_t)leaf_queue.size() - L.leaf_off;
+            // largest fronts first (work per front ~ m^2 p)
+            std::stable_sort(leaf_queue.begin() + L.leaf_off, leaf_queue.end(), [&](int32_t a, int32_t b) {
+                return (double)mfront[a] * mfront[a] * pfront[a] > (double)mfront[b] * mfront[b] * pfront[b];
+            });
             L.fl_off = (int64_t)flist.size();
-            flist.insert(flist.end(), fr.begin(), fr.end());
-            L.fl_cnt = (int64_t)fr.size();
+            flist.insert(flist.end(), all.begin(), all.end());
+            L.fl_cnt = (int64_t)all.size();
             L.dinv_off = (int64_t)dinv_tasks.size();
-            for (int32_t s : fr)
+            for (int32_t s : all)
                 for (int32_t b = 0; b < (pfront[s] + NB - 1) / NB; b++) dinv_tasks.push_back(make_int2(s, b));
             L.dinv_cnt = (int64_t)dinv_tasks.size() - L.dinv_off;
             // extend-add rounds: round r adds the r-th child of every parent;
@@ -438,7 +466,7 @@ struct Layout {
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
-    size_t spchunk, splong, sppart, iperm;
+    size_t spchunk, splong, sppart, iperm, leafq, leafc;
     // LU factors only: the U^T fronts and their diagonal-block scratch, inverses and super-block inverses
     size_t fronts_u = 0, dscr_u = 0, dinv_u = 0, xinv_u = 0;
     size_t total;
@@ -514,6 +542,8 @@ struct Layout {
         splong = seg(std::max<size_t>(1, P.spmv_long.size()) * sizeof(int4));
         sppart = seg((size_t)std::max<int64_t>(1, P.spmv_slots) * k * 8);
         iperm = seg(n * 4);
+        leafq = seg(std::max<size_t>(1, P.leaf_queue.size()) * 4);
+        leafc = seg(4);
         total = o;
     }
 };
@@ -546,6 +576,7 @@ struct wcs_factor_s {
     bool have_values = false;
     std::vector<double> last_rel;              // last refinement residuals per (segment, column)
     int static_device = -1;                    // device whose static workspace this factor holds, or -1
+    int ncu = 256;                             // compute units of the device (grid of the persistent leaf kernel)
 
     // replay of recorded launch sequences (wcs_factor_use_graphs)
     bool graphs = false;
@@ -805,6 +836,34 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
         }
         int r_ea = extend_add(L.ea, true);
         if (r_ea) return r_ea;
+        if (L.leaf_cnt) {
+            // on the side stream when the level also has fronts for the
+            // level-synchronous launches (independent of these); the level's
+            // closing join waits for it
+            hipStream_t ls = st;
+            if (side != st && !L.ops.empty()) {
+                HIP_TRY(hipEventRecord(f->ev_main, st));
+                HIP_TRY(hipStreamWaitEvent(side, f->ev_main, 0));
+                ls = side;
+            }
+            int32_t *ctr = f->at<int32_t>(Lo.leafc);
+            PROF_BEGIN(KC_PANEL);
+            hipLaunchKernelGGL(k_fill<int32_t>, dim3(1), dim3(64), 0, ls, ctr, (int64_t)1, 0);
+            hipLaunchKernelGGL(k_leaf<T>, dim3((unsigned)std::min<int64_t>(L.leaf_cnt, LeafCfg<T>::PER_CU * f->ncu)),
+                               dim3(THREADS), 0, ls, f->at<int32_t>(Lo.leafq) + L.leaf_off, (int)L.leaf_cnt, ctr, fo,
+                               mf, pf, fi, dso, fronts, dscr, bad);
+            PROF_END(KC_PANEL);
+            if (ls != st) {
+                HIP_TRY(hipEventRecord(f->ev_side, ls));
+                pending = true;
+            }
+            if (prof)
+                for (int64_t q = L.leaf_off; q < L.leaf_off + L.leaf_cnt; q++) {
+                    int32_t s = P.leaf_queue[q];
+                    double m = P.mfront[s], pp = P.pfront[s];
+                    prof->flops[KC_PANEL] += pp * pp * pp / 3.0 + (m - pp) * pp * pp + (m - pp) * (m - pp + 1) * pp;
+                }
+        }
         for (const Op &op : L.ops) {
             if (op.kind == OP_UPDATE) {
                 bool small = L.upd_var == WCS_UPD_REG64;
@@ -1457,7 +1516,7 @@ int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, s
     }
     try {
         Plan P;
-        P.build(symbolic_of(sym));
+        P.build(symbolic_of(sym), elem_size(prec), prec != WCS_LU64 && leaf_kernel_enabled());
         Layout L;
         L.compute(symbolic_of(sym), P, elem_size(prec), max_nrhs, is_lu(prec));
         *bytes = L.total;
@@ -1481,7 +1540,7 @@ int new_factor(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, wcs_facto
         f->S = &symbolic_of(sym);
         f->prec = prec;
         f->max_nrhs = max_nrhs;
-        f->plan.build(*f->S);
+        f->plan.build(*f->S, elem_size(prec), prec != WCS_LU64 && leaf_kernel_enabled());
         for (Level &L : f->plan.levels) L.upd_var = default_update_variant(prec);
         f->lay.compute(*f->S, f->plan, elem_size(prec), max_nrhs, is_lu(prec));
     } catch (const std::bad_alloc &) {
@@ -1588,6 +1647,12 @@ namespace wcs {
 namespace {
 int upload_plan(wcs_factor f, hipStream_t st, wcs_factor *out)
 {
+    {
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+            f->ncu = ncu;
+    }
     const Symbolic &S = *f->S;
     const Plan &P = f->plan;
     const Layout &L = f->lay;
@@ -1645,6 +1710,7 @@ int upload_plan(wcs_factor f, hipStream_t st, wcs_factor *out)
     rc = rc ? rc : upload(f, L.xoff, P.xoff, st);
     rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
     rc = rc ? rc : upload(f, L.ztasks, P.zero_tasks, st);
+    rc = rc ? rc : upload(f, L.leafq, P.leaf_queue, st);
     std::vector<int32_t> segp = S.seg_ptr.size() >= 2 ? S.seg_ptr : std::vector<int32_t>{0, S.n};
     rc = rc ? rc : upload(f, L.segp, segp, st);
     if (rc == WCS_OK) {
