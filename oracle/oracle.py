@@ -45,12 +45,15 @@ def _ptr(a: np.ndarray):
 
 
 def load() -> C.CDLL:
+    """The compiled oracle; ORACLE_LIB names another build of oracle.c (the
+    sanitizer test runs the pins against an instrumented one)."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
+    path = os.environ.get("ORACLE_LIB", _LIB)
+    if path == _LIB and not os.path.exists(_LIB):
         build()
-    lib = C.CDLL(_LIB)
+    lib = C.CDLL(path)
     i32, i64 = C.c_int32, C.c_int64
     lib.orc_check_perm.argtypes = [i32, _P]
     lib.orc_symbolic.argtypes = [i32, _P, _P, _P, _P, _P, _P, _P]
