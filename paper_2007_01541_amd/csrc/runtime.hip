@@ -56,7 +56,15 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 // independent diagonal blocks of the matrix (1 unless it is a batch)
 size_t nseg_of(const Symbolic &S) { return S.seg_ptr.size() >= 2 ? S.seg_ptr.size() - 1 : 1; }
 
-constexpr int32_t NBO = 256;   // outer block: trailing updates use K = NBO columns at once
+// outer block: trailing updates use K = NBO columns at once (environment
+// WCS_OUTER_BLOCK, a multiple of the panel width, default 512; read when a
+// plan is built)
+int32_t outer_block()
+{
+    const char *e = std::getenv("WCS_OUTER_BLOCK");
+    int32_t v = e ? std::atoi(e) : 512;
+    return v >= 64 && v % 64 == 0 ? v : 512;
+}
 // fronts with more rows solve block by block over many workgroups (tuning knob WCS_SOLVE_STEP_ROWS)
 // Fronts of at most this many rows are solved one workgroup per front for the
 // whole sweep; by default none (the super-block path is faster for them too).
@@ -157,6 +165,7 @@ struct Plan {
     // LDS to the persistent leaf kernel
     void build(const Symbolic &S, size_t esz = 8, bool leaf_ok = false)
     {
+        const int32_t NBO = outer_block();
         int32_t ns = S.ns;
         const int32_t diag64 = fp64_diag_min_cols();
         mfront.resize(ns);
