@@ -275,15 +275,132 @@ __device__ __forceinline__ typename Mfma<TD>::V mm16(typename Mfma<TD>::V acc, F
     return acc;
 }
 
-// task = (front, tile).  Wave 0 of every workgroup factors the diagonal
-// block A = F[k0:k0+nb, k0:k0+nb] (still unfactored in the front), padded to
-// NB x NB with the identity, by 16-column blocks: the 16 x 16 diagonal
-// sub-block with one lane per row in registers (l_jj = sqrt(a_jj),
-// l_rj = a_rj / l_jj, a_rc -= l_rj l_cj, l_cj broadcast from lane c), its
-// inverse by forward substitution, the sub-panel below it as X = A L_kk^-T
-// and the trailing update A -= X X^T as 16x16x16 matrix-core products; wave 0
-// updates only the next diagonal sub-block and goes on factoring it while the
-// other waves take the other block pairs.  Waves 1..3 own 64-row
+// Broadcast of lane `src` (wave-uniform) of x to every lane, through a scalar
+// register (v_readlane).
+__device__ __forceinline__ double lane_bcast(double x, int src)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), src),
+                            __builtin_amdgcn_readlane(__double2loint(x), src));
+}
+__device__ __forceinline__ float lane_bcast(float x, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), src));
+}
+
+// Factorization of one NB x NB diagonal block held in LDS by all four waves
+// of a workgroup.  A: column-major (A[c][r] = block(r, c)), lower part
+// meaningful, upper part zero, padded past the block's nb columns with the
+// identity; on return it holds the factor L (upper part zero).  Iv (zeroed by
+// the caller) receives the inverses of the four 16 x 16 diagonal sub-blocks of
+// L, Rd the reciprocal pivots.  The caller synchronises the workgroup after
+// filling A and Iv; the helper ends synchronised, after which waves 1..3 run
+// slab(c) for c = 0..3 (work of the caller that needs L and the inverses).
+// Right-looking by 16-column blocks: wave 0 factors the block's columns for
+// all rows at once, one lane per row holding the 16 columns in registers
+// (pivot l_jj = sqrt(a_jj), column l_rj = a_rj / l_jj, then the block's later
+// columns a_rc -= l_rj l_cj, with a_jj and l_cj broadcast from their lanes),
+// so the pivot chain of the block is 16 short steps; the rows and columns
+// after the block are then updated by the panel's 16 x 16 x 16 matrix-core
+// products, spread over the four waves.  Last, wave w inverts diagonal
+// sub-block w by forward substitution (lane c forms column c).
+// A non-positive (or NaN) pivot is reported through atomicMin on *bad (pivot
+// number piv0 + column, if report) and replaced by 1 so the rest stays finite.
+template <typename TD, typename Slab>
+__device__ __forceinline__ void factor_diag_block(TD (&A)[NB][NB + 1], TD (&Iv)[NB][NB + 1], TD (&Rd)[NB], int nb,
+                                                  bool report, int32_t *bad, int32_t piv0, Slab slab)
+{
+    typedef typename Mfma<TD>::V VD;
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int kq = lane / 16, ln = lane % 16;
+    // A(ib.., jb..) -= L_i L_j^T with the 16 x 16 blocks L of column block kb
+    auto syrk_pair = [&](int kb, int ib, int jb) {
+        VD acc = {0, 0, 0, 0};
+        acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
+                       [&](int k, int n) { return A[kb + k][jb + n]; });
+#pragma unroll
+        for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<TD>::row(kq, e)] -= acc[e];
+    };
+    static_for<0, NB / 16, 1>([&](auto bc) {
+        constexpr int kb = 16 * decltype(bc)::value;
+        if (wave == 0) {
+            TD a[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) a[u] = A[kb + u][lane];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int j = kb + u;
+                TD d = lane_bcast(a[u], j);
+                if (!(d > (TD)0)) {
+                    if (lane == 0 && report && j < nb) atomicMin(bad, piv0 + j);
+                    d = (TD)1;
+                }
+                TD rp = rsqrt_refined(d);
+                TD l = (lane == j) ? d * rp : a[u] * rp;
+                a[u] = l;
+                if (lane == j) Rd[j] = rp;
+#pragma unroll
+                for (int v = u + 1; v < 16; v++) a[v] -= l * lane_bcast(l, kb + v);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++) A[kb + u][lane] = (lane >= kb + u) ? a[u] : (TD)0;
+        }
+        __syncthreads();
+        if constexpr (kb + 16 < NB) {
+            // the block pairs (ib >= jb) after the panel, round-robin over the waves
+            int q = 0;
+#pragma unroll
+            for (int ib = kb + 16; ib < NB; ib += 16)
+#pragma unroll
+                for (int jb = kb + 16; jb <= ib; jb += 16)
+                    if (q++ % 4 == wave) syrk_pair(kb, ib, jb);
+            __syncthreads();
+        }
+    });
+    // inverses of the diagonal sub-blocks: wave w, lane c < 16 solves
+    // L_ww y = e_c column by column (each y entry, once known, is taken out
+    // of all later right-hand sides)
+    if (lane < 16) {
+        const int kb = 16 * wave, c = lane;
+        TD y[16], s2[16];
+#pragma unroll
+        for (int rr = 0; rr < 16; rr++) s2[rr] = (rr == c) ? (TD)1 : (TD)0;
+#pragma unroll
+        for (int rr = 0; rr < 16; rr++) {
+            y[rr] = s2[rr] * Rd[kb + rr];
+#pragma unroll
+            for (int q = rr + 1; q < 16; q++) s2[q] -= A[kb + rr][kb + q] * y[rr];
+        }
+#pragma unroll
+        for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
+    }
+    __syncthreads();
+    if (wave != 0) static_for<0, NB / 16, 1>([&](auto cc) { slab(cc); });
+}
+
+// The factored block (rounded to T, full NB x NB column-major, padding and
+// upper part included) and the inverses of its 16 x 16 diagonal sub-blocks
+// (rounded to T, zero elsewhere) to global memory; wave w writes columns
+// 16 w .. 16 w + 15 (after factor_diag_block: A and Iv complete).
+template <typename T, typename TD>
+__device__ __forceinline__ void store_diag_block(const TD (&A)[NB][NB + 1], const TD (&Iv)[NB][NB + 1], T *D, T *Dinv)
+{
+    const int r = threadIdx.x % 64, cb = 16 * (threadIdx.x / 64);
+    T lv[16];
+#pragma unroll
+    for (int c = 0; c < 16; c++) lv[c] = (T)A[cb + c][r];
+#pragma unroll
+    for (int c = 0; c < 16; c++) D[(cb + c) * NB + r] = lv[c];
+    if (Dinv) {
+#pragma unroll
+        for (int c = 0; c < 16; c++) lv[c] = (T)Iv[cb + c][r];
+#pragma unroll
+        for (int c = 0; c < 16; c++) Dinv[(cb + c) * NB + r] = lv[c];
+    }
+}
+
+// task = (front, tile).  Every workgroup factors the diagonal block
+// A = F[k0:k0+nb, k0:k0+nb] (still unfactored in the front), padded to
+// NB x NB with the identity (factor_diag_block).  Waves 1..3 own 64-row
 // slabs of the panel below the block (rows [k0+nb+t*TRW, +TRW)) and solve
 // X L^T = B by 16-column blocks, X_c = (B_c - sum_{j<c} X_j L_cj^T) L_cc^-T,
 // as matrix-core products, each block as soon as its diagonal sub-block is
@@ -294,8 +411,6 @@ __device__ __forceinline__ typename Mfma<TD>::V mm16(typename Mfma<TD>::V acc, F
 // Tile 0 writes the factored block to `dscr` (the front must keep the
 // unfactored block readable for the other workgroups of this launch, and a
 // later launch copies it into place; another one inverts it for the solves).
-// A non-positive (or NaN) pivot is reported through atomicMin on *bad (global
-// pivot numbering) and replaced by 1 so the rest stays finite.
 constexpr int TRW = THREADS - 64;   // panel rows per workgroup (waves 1..3)
 
 template <typename T, typename TD>
@@ -307,7 +422,6 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_panel(const
                                                    const int64_t *__restrict__ dscr_off, T *__restrict__ fronts,
                                                    T *__restrict__ dscr, int32_t *__restrict__ bad)
 {
-    typedef typename Mfma<TD>::V VD;
     __shared__ TD A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L
     __shared__ TD Iv[NB][NB + 1];    // column-major: Iv[c][r] = L^-1(r, c)
     __shared__ TD Rd[NB];            // 1 / L(r, r)
@@ -377,108 +491,311 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_panel(const
         }
     };
     __syncthreads();
-    // the diagonal block, 16 columns at a time; the sub-block products of a
-    // step are spread over the four waves
-    // wave 0: the diagonal 16 x 16 sub-block kb, lanes 0..15 owning its rows,
-    // then its inverse
-    auto diag_step = [&](auto kbc) {
-        constexpr int kb = decltype(kbc)::value;
-        if (lane < 16) {
-            const int r = kb + lane;
-            TD a[16];
-#pragma unroll
-            for (int u = 0; u < 16; u++) a[u] = A[kb + u][r];
-#pragma unroll
-            for (int u = 0; u < 16; u++) {
-                TD d = row_bcast(a[u], u);
-                if (!(d > (TD)0)) {
-                    if (lane == 0 && t.y == 0 && kb + u < nb) atomicMin(bad, first[f] + k0 + kb + u);
-                    d = (TD)1;
-                }
-                TD rp = rsqrt_refined(d);
-                TD piv = d * rp;
-                TD l = (lane == u) ? piv : a[u] * rp;
-                a[u] = l;
-                if (lane == u) Rd[kb + u] = rp;
-#pragma unroll
-                for (int v = u + 1; v < 16; v++) a[v] -= l * row_bcast(l, v);
-            }
-#pragma unroll
-            for (int u = 0; u < 16; u++) A[kb + u][r] = (u <= lane) ? a[u] : (TD)0;
-        }
-        __builtin_amdgcn_wave_barrier();
-        // its inverse: lane c < 16 solves L_kk y = e_c, column by column (each y
-        // entry, once known, is taken out of all later right-hand sides: 15
-        // independent updates per step instead of one chain)
-        if (lane < 16) {
-            const int c = lane;
-            TD y[16], s2[16];
-#pragma unroll
-            for (int rr = 0; rr < 16; rr++) s2[rr] = (rr == c) ? (TD)1 : (TD)0;
-#pragma unroll
-            for (int rr = 0; rr < 16; rr++) {
-                y[rr] = s2[rr] * Rd[kb + rr];
-#pragma unroll
-                for (int q = rr + 1; q < 16; q++) s2[q] -= A[kb + rr][kb + q] * y[rr];
-            }
-#pragma unroll
-            for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
-        }
-    };
-    // A(ib.., jb..) -= X_i X_j^T with the sub-panel blocks X of column block kb
-    auto syrk_pair = [&](int kb, int ib, int jb) {
-        VD acc = {0, 0, 0, 0};
-        acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
-                       [&](int k, int n) { return A[kb + k][jb + n]; });
-#pragma unroll
-        for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<TD>::row(kq, e)] -= acc[e];
-    };
-    if (wave == 0) diag_step(std::integral_constant<int, 0>());
-    __syncthreads();
-    static_for<0, NB / 16 - 1, 1>([&](auto cc) {
-        constexpr int c = decltype(cc)::value, kb = 16 * c;
-        // sub-panel below, one 16-row block per wave: X(i, n) = sum_k A(i, kb+k) L_kk^-1(n, k)
-        {
-            int ib = kb + 16 * (wave + 1);
-            if (ib < NB) {
-                VD acc = {0, 0, 0, 0};
-                acc = mm16<TD>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
-                               [&](int k, int n) { return Iv[kb + k][kb + n]; });
-                __builtin_amdgcn_wave_barrier();
-#pragma unroll
-                for (int e = 0; e < 4; e++) A[kb + ln][ib + Mfma<TD>::row(kq, e)] = acc[e];
-            }
-        }
-        __syncthreads();
-        // trailing update of the block by X X^T: wave 0 takes the next diagonal
-        // sub-block and goes on to factor it; waves 1..3 share the other block
-        // pairs and then solve their slab block c (disjoint parts of A and Iv)
-        if (wave == 0) {
-            syrk_pair(kb, kb + 16, kb + 16);
-            __builtin_amdgcn_wave_barrier();
-            diag_step(std::integral_constant<int, kb + 16>());
-        } else {
-            int q = 0;
-            for (int ib = kb + 16; ib < NB; ib += 16)
-                for (int jb = kb + 16; jb <= ib; jb += 16) {
-                    if (ib == kb + 16) continue;   // the diagonal sub-block (wave 0)
-                    if (q++ % 3 == wave - 1) syrk_pair(kb, ib, jb);
-                }
-            if (slab) slab_block(cc);
-        }
-        __syncthreads();
+    factor_diag_block<TD>(A, Iv, Rd, nb, t.y == 0, bad, first[f] + k0, [&](auto cc) {
+        if (slab) slab_block(cc);
     });
-    if (slab) slab_block(std::integral_constant<int, NB / 16 - 1>());
-    // tile 0: the factored block (full, padding and upper part included) to the scratch
-    if (t.y == 0) {
-        const int r = lane, cb = 16 * wave;
-        T *D = dscr + dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
-        T lv[16];
+    // tile 0: the factored block to the scratch
+    if (t.y == 0) store_diag_block<T, TD>(A, Iv, dscr + dscr_off[f] + (int64_t)(k0 / NB) * NB * NB, (T *)nullptr);
+}
+
+// ---------------------------------------------------------------- fused panel steps
+// Large fronts (p at or above a threshold) are factored by a different
+// schedule of the same arithmetic: the diagonal block of every panel is
+// factored once, one step ahead, and each panel's triangular solve is fused
+// with the update of the rest of its outer block.  Per outer block [K0, kend):
+//   k_diag_factor   D_K0 (the block's first diagonal block), once per front;
+//   k_step, k0 = K0, K0 + NB, ...: rows below D_k solved against L_kk, the
+//                   outer block's later columns updated by the panel, and the
+//                   next diagonal block D_{k+1} factored as soon as its last
+//                   update lands (by the workgroup that applies it);
+// then the trailing updates with the whole outer block, as for other fronts.
+// The factored diagonal block sits in the diagonal-block scratch (as the
+// panel kernel leaves it) and the inverses of its 16 x 16 diagonal
+// sub-blocks in the block's slot of the inverses (replaced by the full block
+// inverse once the level is done): the step kernel solves with exactly the
+// values the panel kernel uses, so both schedules give the same factor bit
+// for bit.
+
+// task = front; factors the diagonal block of pivot columns [k0, k0 + nb) from
+// the front (all of its updates applied) into the scratch and the inverse slot.
+template <typename T, typename TD>
+__global__ __launch_bounds__(THREADS) void k_diag_factor(const int32_t *__restrict__ tasks, int k0,
+                                                         const int64_t *__restrict__ front_off,
+                                                         const int32_t *__restrict__ mfront,
+                                                         const int32_t *__restrict__ pfront,
+                                                         const int32_t *__restrict__ first,
+                                                         const int64_t *__restrict__ dscr_off,
+                                                         const T *__restrict__ fronts, T *__restrict__ dscr,
+                                                         T *__restrict__ dinv, int32_t *__restrict__ bad)
+{
+    __shared__ TD A[NB][NB + 1];
+    __shared__ TD Iv[NB][NB + 1];
+    __shared__ TD Rd[NB];
+    const int f = tasks[blockIdx.x];
+    const int m = mfront[f], p = pfront[f], ld = front_ld(m);
+    const int nb = min(NB, p - k0);
+    const T *F = fronts + front_off[f];
+    // thread (wave, lane) loads row lane of columns wave + 4 i: every load in
+    // flight at once (addresses clamped into the block, padding selected after)
+    const int r = threadIdx.x % 64, c0 = threadIdx.x / 64;
+    T raw[NB / 4];
 #pragma unroll
-        for (int c = 0; c < 16; c++) lv[c] = (T)A[cb + c][r];
+    for (int i = 0; i < NB / 4; i++)
+        raw[i] = F[(int64_t)(k0 + min(c0 + 4 * i, nb - 1)) * ld + k0 + min(r, nb - 1)];
 #pragma unroll
-        for (int c = 0; c < 16; c++) D[(cb + c) * NB + r] = lv[c];
+    for (int i = 0; i < NB / 4; i++) {
+        const int c = c0 + 4 * i;
+        A[c][r] = (r < nb && c < nb && c <= r) ? (TD)raw[i] : (c == r ? (TD)1 : (TD)0);
+        Iv[c][r] = 0;
     }
+    __syncthreads();
+    factor_diag_block<TD>(A, Iv, Rd, nb, true, bad, first[f] + k0, [](auto) {});
+    const int64_t o = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
+    store_diag_block<T, TD>(A, Iv, dscr + o, dinv + o);
+}
+
+// Task flags of k_step (int4 w); task z = -2 marks a pure copy task whose
+// w is the end of its row range.
+constexpr int STEP_WRITE = 1;    // write the tile's panel rows X_i
+constexpr int STEP_DIAG = 2;     // the tile is the next diagonal block: factor it
+constexpr int STEP_DIRECT = 4;   // X_i to its place (else to the transposed position)
+constexpr int STEP_COPY = 8;     // move the deferred panels [K0, k0) of the tile's rows into place
+constexpr int STEP_COPY_ONLY = -2;
+
+// Panel rows written to the transposed position F[R * ld + C] (R > C: the
+// front's upper triangle, never part of L) are moved to F[C * ld + R]: rows
+// [r0, r1), columns [c0, c1) (whole panels starting at multiples of NB from
+// c0), each panel only for its rows below its diagonal block (R >= panel + NB).
+template <typename T>
+__device__ __forceinline__ void move_deferred(T *F, int ld, int m, int r0, int r1, int c0, int c1,
+                                              T (*tile)[NB + 1])
+{
+    r1 = min(r1, m);
+    for (int cb = c0; cb < c1; cb += NB) {
+        const int rs = max(r0, cb + NB);
+        for (int rb = rs; rb < r1; rb += NB) {
+            const int nr = min(NB, r1 - rb), nc = min(NB, c1 - cb);
+            // thread (wave, lane): element lane of rows / columns wave + 4 i, all loads in flight
+            const int a = threadIdx.x % 64, b0 = threadIdx.x / 64;
+            T v[NB / 4];
+#pragma unroll
+            for (int i = 0; i < NB / 4; i++)
+                v[i] = F[(int64_t)(rb + min(b0 + 4 * i, nr - 1)) * ld + cb + min(a, nc - 1)];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NB / 4; i++) tile[b0 + 4 * i][a] = v[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NB / 4; i++) {
+                const int c = b0 + 4 * i;
+                if (a < nr && c < nc) F[(int64_t)(cb + c) * ld + rb + a] = tile[a][c];
+            }
+        }
+    }
+}
+
+// One panel step (see above): panel k = pivot columns [k0, k0 + nb) of the
+// outer block [K0, min(K0 + nbo, p)).  Task (front, i0, j0, w) owns the
+// 64-row tile [i0, i0 + 64) of the rows below D_k (i0 = k0 + nb + 64 t):
+//  - X_i = A_i L_kk^-T by 16-column block forward substitution on the matrix
+//    cores (the panel kernel's slab solve, from the stored L_kk and
+//    sub-block inverses), wave w taking rows 16 w.. of the tile;
+//  - j0 >= 0: X_j likewise for rows [j0, j0 + 64) of the panel (the update's
+//    B rows), then C(i0.., j0..) -= X_i X_j^T on the lower part of the
+//    64 x 64 tile, K = nb, accumulated in the order of the update kernels
+//    (wave w: tile columns 16 w.., four interleaved row blocks);
+//  - STEP_DIAG (i0 = j0 = k0 + nb): the updated tile is D_{k+1}; it is
+//    factored at once and stored like D_k;
+//  - STEP_WRITE: X_i goes to the front.  While strips of the outer block
+//    follow, other workgroups of the launch still read the panel's unfactored
+//    rows, so it goes to the transposed position; the outer block's last step
+//    (no strips) writes in place and moves the deferred panels (STEP_COPY,
+//    and copy-only tasks for the rows above its own).
+template <typename T, typename TD>
+__global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ tasks, int k0, int K0, int nbo,
+                                                     const int64_t *__restrict__ front_off,
+                                                     const int32_t *__restrict__ mfront,
+                                                     const int32_t *__restrict__ pfront,
+                                                     const int32_t *__restrict__ first,
+                                                     const int64_t *__restrict__ dscr_off, T *__restrict__ fronts,
+                                                     T *__restrict__ dscr, T *__restrict__ dinv,
+                                                     int32_t *__restrict__ bad)
+{
+    typedef typename Mfma<T>::V V;
+    typedef typename Vec4<T>::type V4;
+    constexpr int LSZ = NB * (NB + 1);
+    constexpr int XLD = NB + 16;   // operand rows padded: the B reads of the four lane groups hit distinct banks
+    constexpr size_t PH1 = 2 * (size_t)LSZ * sizeof(T);                 // L_kk, sub-block inverses
+    constexpr size_t PH2 = 2 * (size_t)NB * XLD * sizeof(T);            // X_i, X_j (k-major)
+    constexpr size_t PH3 = (2 * (size_t)LSZ + NB) * sizeof(TD);         // D_{k+1} being factored
+    constexpr size_t PH = PH1 > PH2 ? (PH1 > PH3 ? PH1 : PH3) : (PH2 > PH3 ? PH2 : PH3);
+    __shared__ __align__(16) char smem[PH];
+    T(*Ls)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(smem);
+    T(*Ivs)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(smem + (size_t)LSZ * sizeof(T));
+    T(*XA)[XLD] = reinterpret_cast<T(*)[XLD]>(smem);
+    T(*XB)[XLD] = reinterpret_cast<T(*)[XLD]>(smem + (size_t)NB * XLD * sizeof(T));
+    const int4 t = tasks[blockIdx.x];
+    const int f = t.x, i0 = t.y, j0 = t.z, w = t.w;
+    const int m = mfront[f], p = pfront[f], ld = front_ld(m);
+    const int nb = min(NB, p - k0);
+    const int kend = min(K0 + nbo, p);
+    T *F = fronts + front_off[f];
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const int kq = lane / 16, ln = lane % 16;
+    if (j0 == STEP_COPY_ONLY) {
+        move_deferred<T>(F, ld, m, i0, w, K0, k0, Ls);
+        return;
+    }
+    const int64_t ok = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
+    {
+        // thread (wave, lane): row lane of columns wave + 4 i, all loads in flight
+        T lv[NB / 4], iv[NB / 4];
+#pragma unroll
+        for (int i = 0; i < NB / 4; i++) {
+            lv[i] = dscr[ok + (wave + 4 * i) * NB + lane];
+            iv[i] = dinv[ok + (wave + 4 * i) * NB + lane];
+        }
+#pragma unroll
+        for (int i = 0; i < NB / 4; i++) {
+            Ls[wave + 4 * i][lane] = lv[i];
+            Ivs[wave + 4 * i][lane] = iv[i];
+        }
+    }
+    // xs[c][h]: transposed 16 x 16 block (rows 16 wave.. of the tile, panel
+    // columns 16 c..) of A_i (h = 0) or A_j (h = 1), later of X: element e of
+    // lane (kq, ln) is column 16 c + Mfma<T>::row(kq, e) of row 16 wave + ln
+    const bool two = j0 >= 0;
+    V xs[NB / 16][2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int row = (h ? j0 : i0) + 16 * wave + ln;
+        const bool rok = (h == 0 || two) && row < m;
+#pragma unroll
+        for (int c = 0; c < NB / 16; c++)
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                int k = 16 * c + Mfma<T>::row(kq, e);
+                xs[c][h][e] = (rok && k < nb) ? F[(int64_t)(k0 + k) * ld + row] : (T)0;
+            }
+    }
+    __syncthreads();
+    static_for<0, NB / 16, 1>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        const int kb = 16 * c;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            if (h == 1 && !two) break;
+            V acc = xs[c][h];
+#pragma unroll
+            for (int j = 0; j < c; j++)
+#pragma unroll
+                for (int st = 0; st < 4; st++)
+                    acc = Mfma<T>::mma(-Ls[16 * j + Mfma<T>::row(kq, st)][kb + ln], xs[j][h][st], acc);
+            V x = {0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < 4; st++) x = Mfma<T>::mma(Ivs[kb + Mfma<T>::row(kq, st)][kb + ln], acc[st], x);
+            xs[c][h] = x;
+        }
+    });
+    __syncthreads();   // L_kk and the inverses are no longer read (X_i, X_j take their place)
+#pragma unroll
+    for (int c = 0; c < NB / 16; c++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            int k = 16 * c + Mfma<T>::row(kq, e);
+            XA[k][16 * wave + ln] = xs[c][0][e];
+            if (two) XB[k][16 * wave + ln] = xs[c][1][e];
+        }
+    __syncthreads();
+    if (w & STEP_WRITE) {
+        if (w & STEP_DIRECT) {
+            for (int e = tid; e < NB * NB; e += THREADS) {
+                int k = e / NB, r = e % NB;
+                if (k < nb && i0 + r < m) F[(int64_t)(k0 + k) * ld + i0 + r] = XA[k][r];
+            }
+        } else {
+            for (int e = tid; e < NB * NB; e += THREADS) {
+                int r = e / NB, k = e % NB;
+                if (k < nb && i0 + r < m) F[(int64_t)(i0 + r) * ld + k0 + k] = XA[k][r];
+            }
+        }
+    }
+    if (two) {
+        V acc[4];
+#pragma unroll
+        for (int x = 0; x < 4; x++) acc[x] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NB; kk += 4) {
+            V4 a4 = *reinterpret_cast<const V4 *>(&XA[kk + kq][4 * ln]);
+            T b = XB[kk + kq][16 * wave + ln];
+            acc[0] = Mfma<T>::mma(a4.x, b, acc[0]);
+            acc[1] = Mfma<T>::mma(a4.y, b, acc[1]);
+            acc[2] = Mfma<T>::mma(a4.z, b, acc[2]);
+            acc[3] = Mfma<T>::mma(a4.w, b, acc[3]);
+        }
+        // element e of acc[x] is C(row 4 Mfma<T>::row(kq, e) + x, column 16 wave + ln) of the tile:
+        // rows come in aligned quads (i0 is a multiple of 4)
+        const int jend = min(j0 + NB, kend);
+        const int col = j0 + 16 * wave + ln;
+        T nv[4][4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int r0 = i0 + 4 * Mfma<T>::row(kq, e);
+            T *q = F + (int64_t)col * ld + r0;
+            if (col < jend && r0 >= col && r0 + 3 < m) {
+                V4 v = *reinterpret_cast<const V4 *>(q);
+                nv[e][0] = v.x - acc[0][e];
+                nv[e][1] = v.y - acc[1][e];
+                nv[e][2] = v.z - acc[2][e];
+                nv[e][3] = v.w - acc[3][e];
+                V4 o;
+                o.x = nv[e][0];
+                o.y = nv[e][1];
+                o.z = nv[e][2];
+                o.w = nv[e][3];
+                *reinterpret_cast<V4 *>(q) = o;
+            } else {
+#pragma unroll
+                for (int x = 0; x < 4; x++) {
+                    const int r = r0 + x;
+                    nv[e][x] = 0;
+                    if (col < jend && r >= col && r < m) {
+                        nv[e][x] = q[x] - acc[x][e];
+                        q[x] = nv[e][x];
+                    }
+                }
+            }
+        }
+        if (w & STEP_DIAG) {
+            // D_{k+1} = the updated tile (i0 = j0 = k0 + nb): factor it now
+            TD(*A)[NB + 1] = reinterpret_cast<TD(*)[NB + 1]>(smem);
+            TD(*Iv)[NB + 1] = reinterpret_cast<TD(*)[NB + 1]>(smem + (size_t)LSZ * sizeof(TD));
+            TD *Rd = reinterpret_cast<TD *>(smem + 2 * (size_t)LSZ * sizeof(TD));
+            const int nb2 = min(NB, p - j0);
+            __syncthreads();   // X_i, X_j no longer read
+            for (int e = tid; e < NB * NB; e += THREADS) {
+                int c = e / NB, r = e % NB;
+                A[c][r] = (c == r && r >= nb2) ? (TD)1 : (TD)0;
+                Iv[c][r] = 0;
+            }
+            __syncthreads();
+            const int c = 16 * wave + ln;
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+#pragma unroll
+                for (int x = 0; x < 4; x++) {
+                    const int r = 4 * Mfma<T>::row(kq, e) + x;
+                    if (r < nb2 && c < nb2 && c <= r) A[c][r] = (TD)nv[e][x];
+                }
+            __syncthreads();
+            factor_diag_block<TD>(*reinterpret_cast<TD(*)[NB][NB + 1]>(A), *reinterpret_cast<TD(*)[NB][NB + 1]>(Iv),
+                                  *reinterpret_cast<TD(*)[NB]>(Rd), nb2, true, bad, first[f] + j0, [](auto) {});
+            const int64_t o2 = dscr_off[f] + (int64_t)(j0 / NB) * NB * NB;
+            store_diag_block<T, TD>(*reinterpret_cast<TD(*)[NB][NB + 1]>(A),
+                                    *reinterpret_cast<TD(*)[NB][NB + 1]>(Iv), dscr + o2, dinv + o2);
+        }
+    }
+    if (w & STEP_COPY) move_deferred<T>(F, ld, m, i0, i0 + NB, K0, k0, Ls);
 }
 
 // Inverse of every factored NB x NB diagonal block (task = (front, block)),
@@ -497,7 +814,14 @@ __global__ __launch_bounds__(64) void k_diag_inv(const int2 *__restrict__ tasks,
     int64_t o = dscr_off[t.x] + (int64_t)t.y * NB * NB;
     const T *D = dscr + o;
     const int c = threadIdx.x;
-    for (int i = c; i < NB * NB; i += 64) L[i / NB][i % NB] = (double)D[i];
+    {
+        // lane c loads row c of every column (all loads in flight)
+        T v[NB];
+#pragma unroll
+        for (int j = 0; j < NB; j++) v[j] = D[j * NB + c];
+#pragma unroll
+        for (int j = 0; j < NB; j++) L[j][c] = (double)v[j];
+    }
     __syncthreads();
     double y[NB];
 #pragma unroll

@@ -84,12 +84,22 @@ bool leaf_kernel_enabled()
     return e ? std::atoi(e) != 0 : true;
 }
 
+// Cholesky fronts with at least this many pivots are factored by the fused
+// panel steps (k_diag_factor + k_step) instead of the panel kernel and a
+// separate update of the outer block's later columns (environment
+// WCS_STEP_MIN_COLS; read when a plan is built).  Same factor bit for bit.
+int32_t step_min_cols()
+{
+    const char *e = std::getenv("WCS_STEP_MIN_COLS");
+    return e ? std::atoi(e) : 1024;
+}
+
 // Static schedule derived from the symbolic structure only.  Inside every
 // front: for each outer block of NBO pivot columns, for each NB-wide panel in
 // it, factor the panel (diagonal block + rows below) and update the rest of
 // the outer block's columns; then update the trailing matrix with the whole
 // outer block (K = NBO).
-enum OpKind { OP_PANEL = 0, OP_PANEL_FP64DIAG = 1, OP_UPDATE = 2 };
+enum OpKind { OP_PANEL = 0, OP_PANEL_FP64DIAG = 1, OP_UPDATE = 2, OP_DIAG = 3, OP_STEP = 4 };
 struct Op {
     int32_t kind;
     int32_t ka, kw;      // panel: ka = k0; update: columns [ka, ka + min(kw, p - ka)) form K
@@ -99,6 +109,7 @@ struct Op {
     // outer block's pivot columns runs on the side stream (side); the update of
     // those next pivot columns by the following block first waits for it (join)
     bool side = false, join = false;
+    bool d64 = false;    // OP_DIAG / OP_STEP: diagonal blocks factored in FP64 (FP32 fronts)
 };
 struct SuperStep {
     int32_t s0;                  // first pivot of the super-block
@@ -160,12 +171,17 @@ struct Plan {
     std::vector<int4> spmv_chunks, spmv_long;
     int64_t spmv_slots = 0;
     std::vector<int32_t> leaf_queue;              // leaf fronts of the persistent kernel, largest first
+    std::vector<int32_t> diag_fronts;             // OP_DIAG tasks (fronts)
+    std::vector<int4> step_tasks;                 // OP_STEP tasks (front, i0, j0, flags)
+    int32_t nbo = 512;                            // outer block of this plan
 
     // esz: element size of the fronts; leaf_ok: route leaf fronts that fit in
     // LDS to the persistent leaf kernel
-    void build(const Symbolic &S, size_t esz = 8, bool leaf_ok = false)
+    void build(const Symbolic &S, size_t esz = 8, bool leaf_ok = false, bool step_ok = false)
     {
         const int32_t NBO = outer_block();
+        nbo = NBO;
+        const int32_t step_min = step_min_cols();
         int32_t ns = S.ns;
         const int32_t diag64 = fp64_diag_min_cols();
         mfront.resize(ns);
@@ -216,6 +232,8 @@ struct Plan {
         upd_jbeg.clear();
         ea_tasks.clear();
         leaf_queue.clear();
+        diag_fronts.clear();
+        step_tasks.clear();
         const int leaf_elems = esz == 4 ? LeafCfg<float>::ELEMS : LeafCfg<double>::ELEMS;
         for (int32_t h = 0; h < H; h++) {
             Level &L = levels[h];
@@ -262,6 +280,28 @@ struct Plan {
                 }
             int32_t maxp = 0;
             for (int32_t s : fr) maxp = std::max(maxp, pfront[s]);
+            // fronts of the fused panel steps, and the others
+            std::vector<int32_t> frs, fro;
+            for (int32_t s : fr) (step_ok && pfront[s] >= step_min && pfront[s] > NB ? frs : fro).push_back(s);
+            // tasks of one panel step of front s (see k_step): the tile holding the
+            // next diagonal block first, then the other tiles of the first strip
+            // (they write the panel rows), then the later strips
+            auto step_of = [&](int32_t s, int32_t K0, int32_t k0, std::vector<int4> &head, std::vector<int4> &rest) {
+                int32_t p = pfront[s], m = mfront[s];
+                int32_t nb = std::min(NB, p - k0), kend = std::min(K0 + NBO, p), rs = k0 + nb;
+                if (rs < kend) {
+                    head.push_back(make_int4(s, rs, rs, STEP_WRITE | STEP_DIAG));
+                    for (int32_t i0 = rs + NB; i0 < m; i0 += NB) rest.push_back(make_int4(s, i0, rs, STEP_WRITE));
+                    for (int32_t j0 = rs + NB; j0 < kend; j0 += NB)
+                        for (int32_t i0 = j0; i0 < m; i0 += NB) rest.push_back(make_int4(s, i0, j0, 0));
+                } else {
+                    int32_t fl = STEP_WRITE | STEP_DIRECT | (K0 < k0 ? STEP_COPY : 0);
+                    for (int32_t i0 = rs; i0 < m; i0 += NB) rest.push_back(make_int4(s, i0, -1, fl));
+                    if (K0 < k0)
+                        for (int32_t r0 = K0 + NB; r0 < rs; r0 += NB)
+                            rest.push_back(make_int4(s, r0, STEP_COPY_ONLY, std::min(r0 + NB, rs)));
+                }
+            };
             int32_t tw = UT;
             // tiles start at a multiple of 4 (the columns before clo masked):
             // every tile then holds whole aligned quads of rows
@@ -277,7 +317,7 @@ struct Plan {
                 for (int32_t k0 = K0; k0 < std::min(K0 + NBO, maxp); k0 += NB) {
                     for (int pass = 0; pass < 2; pass++) {
                         Op op{pass ? OP_PANEL_FP64DIAG : OP_PANEL, k0, NB, (int64_t)pan_tasks.size(), 0};
-                        for (int32_t s : fr) {
+                        for (int32_t s : fro) {
                             int32_t p = pfront[s], m = mfront[s];
                             if (p <= k0 || (p >= diag64) != (pass == 1)) continue;
                             int32_t nb = std::min(NB, p - k0);
@@ -287,11 +327,30 @@ struct Plan {
                         op.cnt = (int64_t)pan_tasks.size() - op.off;
                         if (op.cnt) L.ops.push_back(op);
                     }
+                    for (int pass = 0; pass < 2; pass++) {
+                        if (k0 == K0) {
+                            Op dg{OP_DIAG, k0, NB, (int64_t)diag_fronts.size(), 0};
+                            dg.d64 = pass == 1;
+                            for (int32_t s : frs)
+                                if (pfront[s] > k0 && (pfront[s] >= diag64) == (pass == 1)) diag_fronts.push_back(s);
+                            dg.cnt = (int64_t)diag_fronts.size() - dg.off;
+                            if (dg.cnt) L.ops.push_back(dg);
+                        }
+                        std::vector<int4> head, rest;
+                        for (int32_t s : frs)
+                            if (pfront[s] > k0 && (pfront[s] >= diag64) == (pass == 1)) step_of(s, K0, k0, head, rest);
+                        Op st{OP_STEP, k0, K0, (int64_t)step_tasks.size(), 0};
+                        st.d64 = pass == 1;
+                        step_tasks.insert(step_tasks.end(), head.begin(), head.end());
+                        step_tasks.insert(step_tasks.end(), rest.begin(), rest.end());
+                        st.cnt = (int64_t)step_tasks.size() - st.off;
+                        if (st.cnt) L.ops.push_back(st);
+                    }
                     Op up{OP_UPDATE, k0, NB, 0, 0};
                     for (int v = 0; v < 2; v++) {
                         tw = v == 0 ? UT : 64;
                         int64_t o = (int64_t)upd_tasks.size();
-                        for (int32_t s : fr) {
+                        for (int32_t s : fro) {
                             int32_t p = pfront[s];
                             if (p <= k0) continue;
                             int32_t nb = std::min(NB, p - k0);
@@ -475,7 +534,7 @@ struct Layout {
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
-    size_t spchunk, splong, sppart, iperm, leafq, leafc;
+    size_t spchunk, splong, sppart, iperm, leafq, leafc, diagf, stept;
     // LU factors only: the U^T fronts and their diagonal-block scratch, inverses and super-block inverses
     size_t fronts_u = 0, dscr_u = 0, dinv_u = 0, xinv_u = 0;
     size_t total;
@@ -553,6 +612,8 @@ struct Layout {
         iperm = seg(n * 4);
         leafq = seg(std::max<size_t>(1, P.leaf_queue.size()) * 4);
         leafc = seg(4);
+        diagf = seg(std::max<size_t>(1, P.diag_fronts.size()) * 4);
+        stept = seg(std::max<size_t>(1, P.step_tasks.size()) * sizeof(int4));
         total = o;
     }
 };
@@ -744,6 +805,28 @@ double panel_flops(const Plan &P, int32_t s, int32_t k0)
     double below = P.mfront[s] - k0 - nb;
     return nb * nb * nb / 3.0 + below * nb * nb;
 }
+// one k_step task: the panel rows it solves (if it writes them), its share of
+// the outer block's update, and the next diagonal block it factors
+double step_flops(const Plan &P, const int4 &t, int32_t k0, int32_t K0)
+{
+    if (t.z == STEP_COPY_ONLY) return 0;
+    double m = P.mfront[t.x], p = P.pfront[t.x];
+    double nb = std::min<double>(NB, p - k0);
+    double fl = 0;
+    if (t.w & STEP_WRITE) fl += nb * nb * std::min<double>(NB, m - t.y);
+    if (t.z >= 0) {
+        double cnt = 0;
+        int32_t jend = std::min(t.z + NB, std::min(K0 + P.nbo, P.pfront[t.x]));
+        for (int32_t col = t.z; col < jend; col++)
+            cnt += std::max<double>(0, std::min<double>(t.y + NB, m) - std::max<double>(t.y, col));
+        fl += 2.0 * nb * cnt;
+    }
+    if (t.w & STEP_DIAG) {
+        double nb2 = std::min<double>(NB, p - t.z);
+        fl += nb2 * nb2 * nb2 / 3.0;
+    }
+    return fl;
+}
 double update_flops(const Plan &P, const int4 &t, int32_t jbeg, int32_t ka, int32_t kw, int32_t tw)
 {
     int32_t m = P.mfront[t.x], p = P.pfront[t.x];
@@ -915,6 +998,39 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                     for (int64_t q = off; q < off + cnt; q++)
                         prof->flops[KC_UPDATE] += nbuf * update_flops(P, P.upd_tasks[q], P.upd_jbeg[q], op.ka, op.kw,
                                                                        small ? 64 : UT);
+            } else if (op.kind == OP_DIAG || op.kind == OP_STEP) {
+                int c = op.d64 ? KC_PANEL_FP64DIAG : KC_PANEL;
+                PROF_BEGIN(c);
+                if (op.kind == OP_DIAG) {
+                    if (op.d64)
+                        hipLaunchKernelGGL((k_diag_factor<T, double>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
+                                           f->at<int32_t>(Lo.diagf) + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr,
+                                           dinv, bad);
+                    else
+                        hipLaunchKernelGGL((k_diag_factor<T, T>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
+                                           f->at<int32_t>(Lo.diagf) + op.off, op.ka, fo, mf, pf, fi, dso, fronts, dscr,
+                                           dinv, bad);
+                } else {
+                    const int nbo = P.nbo;
+                    if (op.d64)
+                        hipLaunchKernelGGL((k_step<T, double>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
+                                           f->at<int4>(Lo.stept) + op.off, op.ka, op.kw, nbo, fo, mf, pf, fi, dso,
+                                           fronts, dscr, dinv, bad);
+                    else
+                        hipLaunchKernelGGL((k_step<T, T>), dim3((unsigned)op.cnt), dim3(THREADS), 0, st,
+                                           f->at<int4>(Lo.stept) + op.off, op.ka, op.kw, nbo, fo, mf, pf, fi, dso,
+                                           fronts, dscr, dinv, bad);
+                }
+                PROF_END(c);
+                if (prof) {
+                    if (op.kind == OP_DIAG)
+                        for (int64_t q = op.off; q < op.off + op.cnt; q++) {
+                            double nb = std::min(NB, P.pfront[P.diag_fronts[q]] - op.ka);
+                            prof->flops[c] += nb * nb * nb / 3.0;
+                        }
+                    else
+                        for (int64_t q = op.off; q < op.off + op.cnt; q++) prof->flops[c] += step_flops(P, P.step_tasks[q], op.ka, op.kw);
+                }
             } else {
                 int c = (op.kind == OP_PANEL || lu) ? KC_PANEL : KC_PANEL_FP64DIAG;
                 PROF_BEGIN(c);
@@ -1525,7 +1641,7 @@ int wcs_workspace_size(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, s
     }
     try {
         Plan P;
-        P.build(symbolic_of(sym), elem_size(prec), prec != WCS_LU64 && leaf_kernel_enabled());
+        P.build(symbolic_of(sym), elem_size(prec), prec != WCS_LU64 && leaf_kernel_enabled(), prec != WCS_LU64);
         Layout L;
         L.compute(symbolic_of(sym), P, elem_size(prec), max_nrhs, is_lu(prec));
         *bytes = L.total;
@@ -1549,7 +1665,7 @@ int new_factor(wcs_symbolic sym, wcs_precision prec, int32_t max_nrhs, wcs_facto
         f->S = &symbolic_of(sym);
         f->prec = prec;
         f->max_nrhs = max_nrhs;
-        f->plan.build(*f->S, elem_size(prec), prec != WCS_LU64 && leaf_kernel_enabled());
+        f->plan.build(*f->S, elem_size(prec), prec != WCS_LU64 && leaf_kernel_enabled(), prec != WCS_LU64);
         for (Level &L : f->plan.levels) L.upd_var = default_update_variant(prec);
         f->lay.compute(*f->S, f->plan, elem_size(prec), max_nrhs, is_lu(prec));
     } catch (const std::bad_alloc &) {
@@ -1720,6 +1836,8 @@ int upload_plan(wcs_factor f, hipStream_t st, wcs_factor *out)
     rc = rc ? rc : upload(f, L.sasm, P.sasm_tasks, st);
     rc = rc ? rc : upload(f, L.ztasks, P.zero_tasks, st);
     rc = rc ? rc : upload(f, L.leafq, P.leaf_queue, st);
+    rc = rc ? rc : upload(f, L.diagf, P.diag_fronts, st);
+    rc = rc ? rc : upload(f, L.stept, P.step_tasks, st);
     std::vector<int32_t> segp = S.seg_ptr.size() >= 2 ? S.seg_ptr : std::vector<int32_t>{0, S.n};
     rc = rc ? rc : upload(f, L.segp, segp, st);
     if (rc == WCS_OK) {
