@@ -305,6 +305,16 @@ __device__ __forceinline__ float lane_bcast(float x, int src)
 // sub-block w by forward substitution (lane c forms column c).
 // A non-positive (or NaN) pivot is reported through atomicMin on *bad (pivot
 // number piv0 + column, if report) and replaced by 1 so the rest stays finite.
+// 1 / sqrt(d) for a pivot of the diagonal-block factorization: the hardware
+// estimate (relative error below 2^-24 in FP64) and one Newton step, which
+// leaves a few units in the last place (FP64: about 1e-15 relative; FP32: the
+// estimate refined once as well).
+template <typename TD> __device__ __forceinline__ TD rsqrt_pivot(TD d)
+{
+    TD r = sizeof(TD) == 8 ? (TD)__builtin_amdgcn_rsq((double)d) : (TD)__builtin_amdgcn_rsqf((float)d);
+    return r * ((TD)1.5 - (TD)0.5 * d * r * r);
+}
+
 template <typename TD, typename Slab>
 __device__ __forceinline__ void factor_diag_block(TD (&A)[NB][NB + 1], TD (&Iv)[NB][NB + 1], TD (&Rd)[NB], int nb,
                                                   bool report, int32_t *bad, int32_t piv0, Slab slab)
@@ -320,60 +330,108 @@ __device__ __forceinline__ void factor_diag_block(TD (&A)[NB][NB + 1], TD (&Iv)[
 #pragma unroll
         for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<TD>::row(kq, e)] -= acc[e];
     };
-    static_for<0, NB / 16, 1>([&](auto bc) {
-        constexpr int kb = 16 * decltype(bc)::value;
-        if (wave == 0) {
-            TD a[16];
+    // inverse of diagonal sub-block kb: lane c < 16 solves L y = e_c column by
+    // column, each y entry taken out of all later right-hand sides at once;
+    // the next column of L is read from LDS while the current one is applied
+    auto invert = [&](int kb) {
+        if (lane < 16) {
+            const int c = lane;
+            TD y[16], s2[16], rd[16], cur[16], nxt[16];
 #pragma unroll
-            for (int u = 0; u < 16; u++) a[u] = A[kb + u][lane];
-#pragma unroll
-            for (int u = 0; u < 16; u++) {
-                const int j = kb + u;
-                TD d = lane_bcast(a[u], j);
-                if (!(d > (TD)0)) {
-                    if (lane == 0 && report && j < nb) atomicMin(bad, piv0 + j);
-                    d = (TD)1;
-                }
-                TD rp = rsqrt_refined(d);
-                TD l = (lane == j) ? d * rp : a[u] * rp;
-                a[u] = l;
-                if (lane == j) Rd[j] = rp;
-#pragma unroll
-                for (int v = u + 1; v < 16; v++) a[v] -= l * lane_bcast(l, kb + v);
+            for (int rr = 0; rr < 16; rr++) {
+                s2[rr] = (rr == c) ? (TD)1 : (TD)0;
+                rd[rr] = Rd[kb + rr];
+                cur[rr] = A[kb][kb + rr];
             }
 #pragma unroll
-            for (int u = 0; u < 16; u++) A[kb + u][lane] = (lane >= kb + u) ? a[u] : (TD)0;
+            for (int rr = 0; rr < 16; rr++) {
+                if (rr + 1 < 16)
+#pragma unroll
+                    for (int q = rr + 2; q < 16; q++) nxt[q] = A[kb + rr + 1][kb + q];
+                y[rr] = s2[rr] * rd[rr];
+#pragma unroll
+                for (int q = rr + 1; q < 16; q++) s2[q] -= cur[q] * y[rr];
+#pragma unroll
+                for (int q = rr + 2; q < 16; q++) cur[q] = nxt[q];
+            }
+#pragma unroll
+            for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
         }
-        __syncthreads();
+    };
+    // wave 0: the 16 columns of block kb for all 64 rows (lane = row), two
+    // pivots at a time: l_j = a_j / sqrt(a_jj), l_{j+1} = (a_{j+1} - l_j
+    // l_{j+1,j}) / sqrt(a_{j+1,j+1} - l_{j+1,j}^2), then the block's later
+    // columns a_v -= l_j l_vj + l_{j+1} l_v,j+1; pivot values broadcast from
+    // their lanes.  A non-positive pivot is replaced by 1 and the first one
+    // reported after the block.
+    auto pivots = [&](auto bc_) {
+        constexpr int kb = 16 * decltype(bc_)::value;
+        TD a[16];
+#pragma unroll
+        for (int u = 0; u < 16; u++) a[u] = A[kb + u][lane];
+        int first_bad = INT32_MAX;
+        TD rd_own = 0;
+#pragma unroll
+        for (int u = 0; u < 16; u += 2) {
+            const int j = kb + u;
+            TD d0 = lane_bcast(a[u], j);
+            TD d01 = lane_bcast(a[u], j + 1);
+            TD d1 = lane_bcast(a[u + 1], j + 1);
+            if (!(d0 > (TD)0)) {
+                first_bad = min(first_bad, j);
+                d0 = (TD)1;
+            }
+            TD r0 = rsqrt_pivot(d0);
+            TD l10 = d01 * r0;
+            TD e1 = d1 - l10 * l10;
+            if (!(e1 > (TD)0)) {
+                first_bad = min(first_bad, j + 1);
+                e1 = (TD)1;
+            }
+            TD r1 = rsqrt_pivot(e1);
+            TD l0 = (lane == j) ? d0 * r0 : a[u] * r0;
+            TD l1 = (lane == j + 1) ? e1 * r1 : (a[u + 1] - l0 * l10) * r1;
+            rd_own = (lane == j) ? r0 : (lane == j + 1 ? r1 : rd_own);
+            a[u] = l0;
+            a[u + 1] = l1;
+#pragma unroll
+            for (int v = u + 2; v < 16; v++)
+                a[v] -= l0 * lane_bcast(l0, kb + v) + l1 * lane_bcast(l1, kb + v);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; u++) A[kb + u][lane] = (lane >= kb + u) ? a[u] : (TD)0;
+        if (lane >= kb && lane < kb + 16) Rd[lane] = rd_own;
+        if (report && first_bad < nb && lane == 0) atomicMin(bad, piv0 + first_bad);
+    };
+    // Right-looking over the four column blocks with the next block's updates
+    // first: after block b's pivots, waves 1..3 update the column block b + 1
+    // (its block pairs), then wave 0 factors it while the others apply block
+    // b's remaining pairs and invert block b.
+    if (wave == 0) pivots(std::integral_constant<int, 0>());
+    __syncthreads();
+    static_for<0, NB / 16, 1>([&](auto bc_) {
+        constexpr int b = decltype(bc_)::value, kb = 16 * b;
         if constexpr (kb + 16 < NB) {
-            // the block pairs (ib >= jb) after the panel, round-robin over the waves
-            int q = 0;
+            // pairs (ib, kb + 16): the next column block, one per wave 1..3
+            if (wave > 0 && kb + 16 * wave < NB) syrk_pair(kb, kb + 16 * wave, kb + 16);
+            __syncthreads();
+            if (wave == 0) {
+                pivots(std::integral_constant<int, b + 1>());
+            } else {
+                int q = 0;
 #pragma unroll
-            for (int ib = kb + 16; ib < NB; ib += 16)
+                for (int ib = kb + 32; ib < NB; ib += 16)
 #pragma unroll
-                for (int jb = kb + 16; jb <= ib; jb += 16)
-                    if (q++ % 4 == wave) syrk_pair(kb, ib, jb);
+                    for (int jb = kb + 32; jb <= ib; jb += 16)
+                        if (q++ % 3 == wave - 1) syrk_pair(kb, ib, jb);
+                if (wave == 3 - (b % 3)) invert(kb);
+            }
+            __syncthreads();
+        } else {
+            if (wave == 0) invert(kb);   // the last block
             __syncthreads();
         }
     });
-    // inverses of the diagonal sub-blocks: wave w, lane c < 16 solves
-    // L_ww y = e_c column by column (each y entry, once known, is taken out
-    // of all later right-hand sides)
-    if (lane < 16) {
-        const int kb = 16 * wave, c = lane;
-        TD y[16], s2[16];
-#pragma unroll
-        for (int rr = 0; rr < 16; rr++) s2[rr] = (rr == c) ? (TD)1 : (TD)0;
-#pragma unroll
-        for (int rr = 0; rr < 16; rr++) {
-            y[rr] = s2[rr] * Rd[kb + rr];
-#pragma unroll
-            for (int q = rr + 1; q < 16; q++) s2[q] -= A[kb + rr][kb + q] * y[rr];
-        }
-#pragma unroll
-        for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
-    }
-    __syncthreads();
     if (wave != 0) static_for<0, NB / 16, 1>([&](auto cc) { slab(cc); });
 }
 
@@ -663,13 +721,14 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
     }
     // xs[c][h]: transposed 16 x 16 block (rows 16 wave.. of the tile, panel
     // columns 16 c..) of A_i (h = 0) or A_j (h = 1), later of X: element e of
-    // lane (kq, ln) is column 16 c + Mfma<T>::row(kq, e) of row 16 wave + ln
-    const bool two = j0 >= 0;
+    // lane (kq, ln) is column 16 c + Mfma<T>::row(kq, e) of row 16 wave + ln.
+    // A tile on the diagonal (i0 = j0) has X_j = X_i: solved once.
+    const bool two = j0 >= 0, dtile = j0 == i0;
     V xs[NB / 16][2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const int row = (h ? j0 : i0) + 16 * wave + ln;
-        const bool rok = (h == 0 || two) && row < m;
+        const bool rok = (h == 0 || (two && !dtile)) && row < m;
 #pragma unroll
         for (int c = 0; c < NB / 16; c++)
 #pragma unroll
@@ -678,13 +737,41 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
                 xs[c][h][e] = (rok && k < nb) ? F[(int64_t)(k0 + k) * ld + row] : (T)0;
             }
     }
+    // the tile's earlier values, read now (they do not depend on the solve):
+    // element e of quad cq[e] is row i0 + 4 Mfma<T>::row(kq, e) + x of column
+    // j0 + 16 wave + ln; a quad reaching past the stored lower part is read
+    // element by element (masked elements read as 0 and are not stored)
+    const int jend = min(j0 + NB, kend);
+    const int col = j0 + 16 * wave + ln;
+    V4 cq[4];
+    if (two) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int r0 = i0 + 4 * Mfma<T>::row(kq, e);
+            const T *q = F + (int64_t)col * ld + r0;
+            if (col < jend && r0 >= col && r0 + 3 < m) {
+                cq[e] = *reinterpret_cast<const V4 *>(q);
+            } else {
+                T v[4];
+#pragma unroll
+                for (int x = 0; x < 4; x++) {
+                    const int r = r0 + x;
+                    v[x] = (col < jend && r >= col && r < m) ? q[x] : (T)0;
+                }
+                cq[e].x = v[0];
+                cq[e].y = v[1];
+                cq[e].z = v[2];
+                cq[e].w = v[3];
+            }
+        }
+    }
     __syncthreads();
     static_for<0, NB / 16, 1>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         const int kb = 16 * c;
 #pragma unroll
         for (int h = 0; h < 2; h++) {
-            if (h == 1 && !two) break;
+            if (h == 1 && (!two || dtile)) break;
             V acc = xs[c][h];
 #pragma unroll
             for (int j = 0; j < c; j++)
@@ -704,7 +791,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
         for (int e = 0; e < 4; e++) {
             int k = 16 * c + Mfma<T>::row(kq, e);
             XA[k][16 * wave + ln] = xs[c][0][e];
-            if (two) XB[k][16 * wave + ln] = xs[c][1][e];
+            if (two) XB[k][16 * wave + ln] = xs[c][dtile ? 0 : 1][e];
         }
     __syncthreads();
     if (w & STEP_WRITE) {
@@ -735,19 +822,16 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
         }
         // element e of acc[x] is C(row 4 Mfma<T>::row(kq, e) + x, column 16 wave + ln) of the tile:
         // rows come in aligned quads (i0 is a multiple of 4)
-        const int jend = min(j0 + NB, kend);
-        const int col = j0 + 16 * wave + ln;
         T nv[4][4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             const int r0 = i0 + 4 * Mfma<T>::row(kq, e);
             T *q = F + (int64_t)col * ld + r0;
+            nv[e][0] = cq[e].x - acc[0][e];
+            nv[e][1] = cq[e].y - acc[1][e];
+            nv[e][2] = cq[e].z - acc[2][e];
+            nv[e][3] = cq[e].w - acc[3][e];
             if (col < jend && r0 >= col && r0 + 3 < m) {
-                V4 v = *reinterpret_cast<const V4 *>(q);
-                nv[e][0] = v.x - acc[0][e];
-                nv[e][1] = v.y - acc[1][e];
-                nv[e][2] = v.z - acc[2][e];
-                nv[e][3] = v.w - acc[3][e];
                 V4 o;
                 o.x = nv[e][0];
                 o.y = nv[e][1];
@@ -758,11 +842,8 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
 #pragma unroll
                 for (int x = 0; x < 4; x++) {
                     const int r = r0 + x;
-                    nv[e][x] = 0;
-                    if (col < jend && r >= col && r < m) {
-                        nv[e][x] = q[x] - acc[x][e];
-                        q[x] = nv[e][x];
-                    }
+                    if (col < jend && r >= col && r < m) q[x] = nv[e][x];
+                    else nv[e][x] = 0;
                 }
             }
         }
@@ -1295,8 +1376,7 @@ template <> struct UpdCfg<double> { static constexpr int KC = 16; };
 __device__ __forceinline__ int frag_pos(int r) { return (r & ~63) + (r & 15) * 4 + ((r >> 4) & 3); }
 
 template <typename T, int TW>
-__global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__restrict__ tasks, int ka, int kw,
-                                                    T *__restrict__ fronts, int64_t bdelta)
+__device__ __forceinline__ void update_tile(const UpdTask t, int ka, int kw, T *__restrict__ fronts, int64_t bdelta)
 {
     constexpr int KC = UpdCfg<T>::KC;
     constexpr int NTH = TW * TW / 64;          // one wave per 64 x 64 quarter
@@ -1305,7 +1385,6 @@ __global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__res
     __shared__ __align__(16) T Bs[2][KC][LD];
     constexpr int KSTEP = NTH / TW;            // k rows covered by one pass of the block
     constexpr int PER = KC / KSTEP;            // elements of each operand per thread per chunk
-    const UpdTask t = tasks[blockIdx.x];
     int i0 = t.b.x, j0 = t.b.y, jend = t.b.z, jbeg = t.b.w;
     int m = t.a.z, p = t.a.w, ld = front_ld(m);
     int K = min(kw, p - ka);
@@ -1461,9 +1540,9 @@ __device__ __forceinline__ void dma_to_lds16(const void *g, uint32_t lds)
 // deeper pipeline pays on long contractions, the third workgroup on short
 // ones; the autotuner picks per level.  The launch bound keeps the
 // accumulators within the register budget of that many waves.
-template <typename T, int NS, int KC = DmaCfg<T>::KC>
-__global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_update_dma(const UpdTask *__restrict__ tasks, int ka, int kw,
-                                                                   T *__restrict__ fronts, int64_t bdelta)
+template <typename T, int NS, int KC>
+__device__ __forceinline__ void update_tile_dma(const UpdTask t, int ka, int kw, T *__restrict__ fronts,
+                                                int64_t bdelta)
 {
     static_assert(NS >= 2 && NS <= 4, "the stage arrays below hold two to four stages");
     constexpr int VEC = 16 / (int)sizeof(T);       // elements per lane per DMA instruction
@@ -1485,7 +1564,6 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
         else if constexpr (st == 2) return reinterpret_cast<T(*)[KC][128]>(&S2[0][0][0]);   // (three or more)
         else return reinterpret_cast<T(*)[KC][128]>(&S3[0][0][0]);   // (four stages only)
     };
-    const UpdTask t = tasks[blockIdx.x];
     int i0 = t.b.x, j0 = t.b.y, jend = t.b.z, jbeg = t.b.w;
     int m = t.a.z, p = t.a.w, ld = front_ld(m);
     int K = min(kw, p - ka);
@@ -1601,6 +1679,30 @@ __global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_up
     epi.store(0, c0v, av);
     if constexpr (!early2) epi.load(2, c1v);
     epi.store(2, c1v, av);
+}
+
+// The trailing-update kernels: workgroup b takes tasks b, b + grid, ... (a
+// launch may use fewer workgroups than tasks: the look-ahead updates on the
+// side stream do, so that the panel-step kernels on the main stream always
+// find room on the compute units).
+template <typename T, int TW>
+__global__ __launch_bounds__(TW * TW / 64, 2) void k_update(const UpdTask *__restrict__ tasks, int ntask, int ka,
+                                                            int kw, T *__restrict__ fronts, int64_t bdelta)
+{
+    for (int i = blockIdx.x; i < ntask; i += gridDim.x) {
+        if (i != (int)blockIdx.x) __syncthreads();   // the previous tile's LDS reads are done
+        update_tile<T, TW>(tasks[i], ka, kw, fronts, bdelta);
+    }
+}
+
+template <typename T, int NS, int KC = DmaCfg<T>::KC>
+__global__ __launch_bounds__(256, (NS == 3 && sizeof(T) == 4) ? 3 : 2) void k_update_dma(
+    const UpdTask *__restrict__ tasks, int ntask, int ka, int kw, T *__restrict__ fronts, int64_t bdelta)
+{
+    for (int i = blockIdx.x; i < ntask; i += gridDim.x) {
+        if (i != (int)blockIdx.x) __syncthreads();   // the previous tile's LDS reads are done
+        update_tile_dma<T, NS, KC>(tasks[i], ka, kw, fronts, bdelta);
+    }
 }
 
 // ---------------------------------------------------------------- solves

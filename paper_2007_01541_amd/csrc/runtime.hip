@@ -88,6 +88,20 @@ bool leaf_kernel_enabled()
 // panel steps (k_diag_factor + k_step) instead of the panel kernel and a
 // separate update of the outer block's later columns (environment
 // WCS_STEP_MIN_COLS; read when a plan is built).  Same factor bit for bit.
+// Workgroups of a look-ahead trailing update on the side stream, as a
+// multiple of the compute units (environment WCS_SIDE_GRID, workgroups per
+// compute unit in quarters; default 0 = one workgroup per tile): the tiles
+// are shared out over that many workgroups, which leaves room on every unit
+// for the panel steps on the main stream.  Measured at N = 2^18: 4, 6 and 8
+// quarters slow the factorization (FP32 47.3 -> 48.6-49.9 ms, FP64 81.6 ->
+// 82-92 ms).
+int side_grid(int ncu)
+{
+    const char *e = std::getenv("WCS_SIDE_GRID");
+    int q = e ? std::atoi(e) : 0;
+    return q > 0 ? q * ncu / 4 : 0;
+}
+
 int32_t step_min_cols()
 {
     const char *e = std::getenv("WCS_STEP_MIN_COLS");
@@ -966,7 +980,10 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                 }
                 if (cnt == 0) continue;
                 hipStream_t us = st;
+                unsigned grid = (unsigned)cnt;
                 if (op.side && side != st) {
+                    const int cap = side_grid(f->ncu) * (small ? 4 : 1);   // 64-tiles: one-wave workgroups
+                    if (cap > 0 && cnt > cap) grid = (unsigned)cap;
                     HIP_TRY(hipEventRecord(f->ev_main, st));
                     HIP_TRY(hipStreamWaitEvent(side, f->ev_main, 0));
                     us = side;
@@ -977,17 +994,17 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                     T *cf = buf(b);
                     const int64_t bd = lu ? (int64_t)(buf(1 - b) - cf) : 0;
                     if (small)
-                        hipLaunchKernelGGL((k_update<T, 64>), dim3((unsigned)cnt), dim3(64), 0, us, upd + off, op.ka,
+                        hipLaunchKernelGGL((k_update<T, 64>), dim3(grid), dim3(64), 0, us, upd + off, (int)cnt, op.ka,
                                            op.kw, cf, bd);
                     else if (L.upd_var == WCS_UPD_STREAM128)
-                        hipLaunchKernelGGL((k_update_dma<T, 4>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off,
+                        hipLaunchKernelGGL((k_update_dma<T, 4>), dim3(grid), dim3(256), 0, us, upd + off, (int)cnt,
                                            op.ka, op.kw, cf, bd);
                     else if (L.upd_var == WCS_UPD_STREAM128_3)
-                        hipLaunchKernelGGL((k_update_dma<T, 3>), dim3((unsigned)cnt), dim3(256), 0, us, upd + off,
+                        hipLaunchKernelGGL((k_update_dma<T, 3>), dim3(grid), dim3(256), 0, us, upd + off, (int)cnt,
                                            op.ka, op.kw, cf, bd);
                     else
-                        hipLaunchKernelGGL((k_update<T, UT>), dim3((unsigned)cnt), dim3(UT * UT / 64), 0, us,
-                                           upd + off, op.ka, op.kw, cf, bd);
+                        hipLaunchKernelGGL((k_update<T, UT>), dim3(grid), dim3(UT * UT / 64), 0, us,
+                                           upd + off, (int)cnt, op.ka, op.kw, cf, bd);
                 }
                 PROF_END(KC_UPDATE);
                 if (us != st) {
