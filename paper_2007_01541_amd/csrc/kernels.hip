@@ -1118,12 +1118,24 @@ __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict_
     T *L = FL + front_off[f];
     T *U = FU + front_off[f];
     const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += THREADS) {
-        int c = e / NB, r = e % NB;
-        double v = r == c ? 1.0 : 0.0;
-        if (r < nb && c < nb)
-            v = r >= c ? (double)L[(int64_t)(k0 + c) * ld + k0 + r] : (double)U[(int64_t)(k0 + r) * ld + k0 + c];
-        A[c][r] = v;
+    {
+        // thread (wave, lane): row lane of columns wave + 4 i, every load in flight
+        // (addresses clamped into the block): L below the diagonal, U^T above it
+        const int r = tid % 64, c0 = tid / 64, rc = min(r, nb - 1);
+        T lv[NB / 4], uv[NB / 4];
+#pragma unroll
+        for (int i = 0; i < NB / 4; i++) {
+            const int cc = min(c0 + 4 * i, nb - 1);
+            lv[i] = L[(int64_t)(k0 + cc) * ld + k0 + rc];
+            uv[i] = U[(int64_t)(k0 + rc) * ld + k0 + cc];
+        }
+#pragma unroll
+        for (int i = 0; i < NB / 4; i++) {
+            const int c = c0 + 4 * i;
+            double v = r == c ? 1.0 : 0.0;
+            if (r < nb && c < nb) v = r >= c ? (double)lv[i] : (double)uv[i];
+            A[c][r] = v;
+        }
     }
     __syncthreads();
     for (int kk = 0; kk < NB; kk++) {
@@ -1183,29 +1195,53 @@ __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict_
             DU[e] = (T)(r >= c ? A[r][c] : 0.0);        // U11^T: (r, c) = u(c, r)
         }
     }
-    const int row = k0 + nb + t.y * TRW + tid;
-    if (tid < TRW && row < m) {
-        // L21 row: out_c = sum_{t <= c} a_t (U11^-1)(t, c)
-        double x[NB];
+    // the rows below the block, TRW per workgroup, on the FP64 matrix cores:
+    // L21 = A21 U11^-1 (out(r, c) = sum_t a(r, t) U11^-1(t, c)) and
+    // U12^T = A12^T L11^-T (out(r, c) = sum_t a(r, t) L11^-1(c, t)); wave w
+    // takes the 16-row blocks 3 w .. 3 w + 2 and all 64 output columns
+    typedef typename Mfma<double>::V VD;
+    const int wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+    constexpr int RB = TRW / 64;     // 16-row blocks per wave
+    const int row0 = k0 + nb + t.y * TRW + wave * 16 * RB;
 #pragma unroll
-        for (int tt = 0; tt < NB; tt++) x[tt] = tt < nb ? (double)L[(int64_t)(k0 + tt) * ld + row] : 0.0;
-        for (int c = 0; c < nb; c++) {
-            double s = 0.0;
+    for (int side = 0; side < 2; side++) {
+        T *X = side ? U : L;
+        // operands of this wave: a(row0 + 16 rb + ln, 4 s + kq) for s = 0..15
+        double av[RB][NB / 4];
 #pragma unroll
-            for (int tt = 0; tt < NB; tt++)
-                if (tt <= c) s += x[tt] * Ui[c][tt];
-            L[(int64_t)(k0 + c) * ld + row] = (T)s;
+        for (int rb = 0; rb < RB; rb++) {
+            const int row = row0 + 16 * rb + ln;
+#pragma unroll
+            for (int sidx = 0; sidx < NB / 4; sidx++) {
+                const int tt = 4 * sidx + kq;
+                av[rb][sidx] = (row < m && tt < nb) ? (double)X[(int64_t)(k0 + tt) * ld + min(row, m - 1)] : 0.0;
+            }
         }
-        // U12^T row: out_c = sum_{t <= c} a_t (L11^-1)(c, t)
+        VD acc[RB][NB / 16];
 #pragma unroll
-        for (int tt = 0; tt < NB; tt++) x[tt] = tt < nb ? (double)U[(int64_t)(k0 + tt) * ld + row] : 0.0;
-        for (int c = 0; c < nb; c++) {
-            double s = 0.0;
+        for (int rb = 0; rb < RB; rb++)
 #pragma unroll
-            for (int tt = 0; tt < NB; tt++)
-                if (tt <= c) s += x[tt] * Li[tt][c];
-            U[(int64_t)(k0 + c) * ld + row] = (T)s;
+            for (int cb = 0; cb < NB / 16; cb++) acc[rb][cb] = VD{0, 0, 0, 0};
+#pragma unroll
+        for (int sidx = 0; sidx < NB / 4; sidx++) {
+            const int tt = 4 * sidx + kq;
+#pragma unroll
+            for (int cb = 0; cb < NB / 16; cb++) {
+                const int c = 16 * cb + ln;
+                const double bv = side ? Li[tt][c] : Ui[c][tt];
+#pragma unroll
+                for (int rb = 0; rb < RB; rb++) acc[rb][cb] = Mfma<double>::mma(av[rb][sidx], bv, acc[rb][cb]);
+            }
         }
+#pragma unroll
+        for (int rb = 0; rb < RB; rb++)
+#pragma unroll
+            for (int cb = 0; cb < NB / 16; cb++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int row = row0 + 16 * rb + Mfma<double>::row(kq, e), c = 16 * cb + ln;
+                    if (row < m && c < nb) X[(int64_t)(k0 + c) * ld + row] = (T)acc[rb][cb][e];
+                }
     }
 }
 
