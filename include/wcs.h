@@ -280,12 +280,14 @@ typedef enum {
     WCS_UPD_REG128 = 0,     /* 128 x 128 tiles, operands staged through registers into LDS */
     WCS_UPD_REG64 = 1,      /* 64 x 64 tiles (one wave per tile), same staging */
     WCS_UPD_STREAM128 = 2,  /* 128 x 128 tiles, operands streamed global -> LDS, four chunks in flight */
-    WCS_UPD_STREAM128_3 = 3 /* the same with three chunks in flight: less LDS, one more workgroup per CU */
+    WCS_UPD_STREAM128_3 = 3,/* the same with three chunks in flight: less LDS, one more workgroup per CU */
+    WCS_UPD_STREAM128_K32 = 4 /* 128 x 128 tiles streamed in two chunks of 32 (FP32) / 16 (FP64) k-columns:
+                                 half the barriers per product */
 } wcs_update_variant;
 
 /*
  * Autotuner for the trailing-update kernel.  Factors values_dev (which leaves
- * a valid factor, as wcs_factor_numeric does) eight times on the stream: a
+ * a valid factor, as wcs_factor_numeric does) ten times on the stream: a
  * warm-up and a timed run with each wcs_update_variant on every level, timing
  * each level of the assembly tree with HIP events; then keeps, per level, the
  * fastest variant.  All variants compute bitwise the same factor (same

@@ -1002,6 +1002,9 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
                     else if (L.upd_var == WCS_UPD_STREAM128_3)
                         hipLaunchKernelGGL((k_update_dma<T, 3>), dim3(grid), dim3(256), 0, us, upd + off, (int)cnt,
                                            op.ka, op.kw, cf, bd);
+                    else if (L.upd_var == WCS_UPD_STREAM128_K32)
+                        hipLaunchKernelGGL((k_update_dma<T, 2, 2 * DmaCfg<T>::KC>), dim3(grid), dim3(256), 0, us,
+                                           upd + off, (int)cnt, op.ka, op.kw, cf, bd);
                     else
                         hipLaunchKernelGGL((k_update<T, UT>), dim3(grid), dim3(UT * UT / 64), 0, us,
                                            upd + off, (int)cnt, op.ka, op.kw, cf, bd);
@@ -1991,7 +1994,7 @@ int wcs_factor_autotune(wcs_factor f, const double *values_dev, wcs_stream strea
         return WCS_OK;
     };
     // each candidate kernel on every level: a warm-up factorization, then a timed one
-    constexpr int NV = 4;
+    constexpr int NV = 5;
     std::vector<double> t[NV];
     const int32_t dflt = default_update_variant(f->prec);
     for (int v = 0; v < NV; v++) {
@@ -2031,9 +2034,9 @@ int wcs_factor_set_tiles(wcs_factor f, const int32_t *tiles)
 {
     if (!f || !tiles) { set_error("invalid argument to wcs_factor_set_tiles"); return WCS_EINVAL; }
     for (size_t h = 0; h < f->plan.levels.size(); h++)
-        if (tiles[h] < WCS_UPD_REG128 || tiles[h] > WCS_UPD_STREAM128_3) {
-            set_error("update kernel variant must be WCS_UPD_REG128, WCS_UPD_REG64, WCS_UPD_STREAM128 or "
-                      "WCS_UPD_STREAM128_3");
+        if (tiles[h] < WCS_UPD_REG128 || tiles[h] > WCS_UPD_STREAM128_K32) {
+            set_error("update kernel variant must be WCS_UPD_REG128, WCS_UPD_REG64, WCS_UPD_STREAM128, "
+                      "WCS_UPD_STREAM128_3 or WCS_UPD_STREAM128_K32");
             return WCS_EINVAL;
         }
     for (size_t h = 0; h < f->plan.levels.size(); h++) f->plan.levels[h].upd_var = tiles[h];

@@ -188,10 +188,10 @@ def test_autotune_keeps_factor_exact(prec):
     L0 = f.export_L()[2]
     res = f.autotune(vals)
     print(f"autotune {res}", flush=True)
-    assert set(res["tiles"].tolist()) <= {0, 1, 2, 3}
+    assert set(res["tiles"].tolist()) <= {0, 1, 2, 3, 4}
     assert res["ms_tuned"] <= res["ms_default"] + 1e-9
     assert np.array_equal(f.export_L()[2], L0)
-    for v in (0, 1, 2, 3):
+    for v in (0, 1, 2, 3, 4):
         f.set_tiles(np.full(bs.info["nlevels"], v, np.int32))
         f.numeric(vals)
         assert np.array_equal(f.export_L()[2], L0), v

@@ -368,18 +368,19 @@ def test_solve_fused_fronts(kind, leaf, coords, k, rows, monkeypatch):
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_update_variants_bitwise(kind, prec):
     """Every trailing-update kernel (128 x 128 register-staged, 64 x 64,
-    128 x 128 streamed with four or three chunks in flight) sums the same
+    128 x 128 streamed with four or three chunks in flight or two chunks of
+    twice the depth) sums the same
     products in the same order: the factor is bitwise the same on fronts with
     many tiles and ragged edges."""
     m, sym, orc = prepared(kind)
     vals = dev(m["values"])
     out = []
-    for v in range(4):
+    for v in range(5):
         f = Factor(sym, prec)
         f.set_tiles(np.full(sym.info["nlevels"], v, np.int32))
         f.numeric(vals)
         out.append(f.export_L()[2])
-    for v in range(1, 4):
+    for v in range(1, 5):
         assert np.array_equal(out[v], out[0]), v
     Lp, Li, _ = f.export_L()
     worst, scale = compare_columns(Lp, Li, out[3], orc)
