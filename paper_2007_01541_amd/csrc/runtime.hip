@@ -102,6 +102,17 @@ int side_grid(int ncu)
     return q > 0 ? q * ncu / 4 : 0;
 }
 
+// Right-hand-side counts from 5 up to this one run the 16-column sweep
+// kernels, larger ones the 64-column ones (environment WCS_SOLVE_KT16_MAX,
+// read by every solve; default 4: none).  Measured at N = 2^18, one solve:
+// 8 RHS FP32 11.7 ms with the 16-column kernels, 7.0 ms with the 64-column
+// ones; 16 RHS 12.2 / 7.1 ms; FP64 16 RHS 22.1 / 14.4 ms.
+int kt16_max_rhs()
+{
+    const char *e = std::getenv("WCS_SOLVE_KT16_MAX");
+    return e ? std::atoi(e) : 4;
+}
+
 int32_t step_min_cols()
 {
     const char *e = std::getenv("WCS_STEP_MIN_COLS");
@@ -1231,7 +1242,7 @@ template <typename T>
 int launch_solve_internal(wcs_factor f, int part, int k, hipStream_t st)
 {
     if (k <= 4) return launch_sweeps<T, 4>(f, part, k, st);
-    if (k <= 16) return launch_sweeps<T, 16>(f, part, k, st);
+    if (k <= kt16_max_rhs()) return launch_sweeps<T, 16>(f, part, k, st);
     return launch_sweeps<T, 64>(f, part, k, st);
 }
 

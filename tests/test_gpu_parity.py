@@ -80,6 +80,26 @@ def test_fp64_solve(kind, leaf, coords, k):
     assert np.abs(X - Xo).max() <= tol * np.abs(Xo).max()
 
 
+@pytest.mark.parametrize("kind,leaf,coords", CASES)
+@pytest.mark.parametrize("k", [5, 9, 16])
+def test_solve_sixteen_column_kernels(kind, leaf, coords, k, monkeypatch):
+    """5..16 right-hand sides through the 16-column sweep kernels (routed
+    there by WCS_SOLVE_KT16_MAX, read by every solve; by default they take the
+    64-column ones): oracle residual and agreement with the default route."""
+    m, sym, orc = prepared(kind, leaf, coords)
+    n = m["n"]
+    B = normal_rhs(n, k, 79)
+    f = Factor(sym, FP64, max_nrhs=k)
+    f.numeric(dev(m["values"]))
+    X64 = f.solve(dev(B)).cpu().numpy()
+    monkeypatch.setenv("WCS_SOLVE_KT16_MAX", "16")
+    X16 = f.solve(dev(B)).cpu().numpy()
+    res = oracle.residual(n, m["colptr"], m["rowind"], m["values"], X16, B)
+    assert res.max() <= 1e-12
+    tol = factor_tol(m, int(orc.colcount.max()), EPS64)
+    assert np.abs(X16 - X64).max() <= tol * np.abs(X64).max()
+
+
 @pytest.mark.parametrize("part", [SOLVE_L, SOLVE_LT])
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_half_solves(part, prec):
