@@ -1089,15 +1089,20 @@ __global__ __launch_bounds__(THREADS, LeafCfg<T>::PER_CU) void k_leaf(const int3
 //
 // task = (front, tile), k0 = the panel's first column.  Every workgroup
 // assembles the panel's diagonal block A11 (lower part from FL, strict upper
-// from FU, padded to NB x NB with the identity), factors it as L11 U11
-// (Doolittle: unit lower L11, right-looking in LDS, FP64), forms L11^-1 and
-// U11^-1 by substitution (one column per thread), and then solves its TRW
-// rows below the block: L21 = A21 U11^-1 in FL and U12^T = A12^T L11^-T in
-// FU, one row per thread.  Tile 0 writes the factored block to the
-// diagonal-block scratch of both factors (L11 with its unit diagonal, U11^T),
-// which a later launch copies into place, as for the Cholesky panel.  A
-// zero or non-finite pivot is reported through atomicMin on *bad (global
-// pivot numbering) and replaced by 1.
+// from FU, padded to NB x NB with the identity) and factors it as L11 U11
+// (Doolittle: unit lower L11, FP64) by 16-column blocks: wave 0 eliminates a
+// block's columns for all 64 rows at once (lane = row, pivot row values
+// broadcast from the pivot's lane), wave 1 forms the block rows of U to its
+// right (U12 = L_bb^-1 A12, a column per lane), waves 2 and 3 invert the
+// block's 16 x 16 diagonal parts of L and U, and the rest of the block is
+// updated by the 16 x 16 x 16 matrix-core products L21 U12.  The TRW rows of
+// the workgroup below the block are then solved by 16-column block
+// substitution on the matrix cores: L21 = A21 U11^-1 in FL (X U11 = A21) and
+// U12^T = A12^T L11^-T in FU (X L11^T = A12^T), wave w taking 48 rows.  Tile
+// 0 writes the factored block to the diagonal-block scratch of both factors
+// (L11 with its unit diagonal, U11^T), which a later launch copies into
+// place, as for the Cholesky panel.  A zero or non-finite pivot is reported
+// through atomicMin on *bad (global pivot numbering) and replaced by 1.
 template <typename T>
 __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict__ tasks, int k0,
                                                          const int64_t *__restrict__ front_off,
@@ -1108,9 +1113,11 @@ __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict_
                                                          T *__restrict__ FU, T *__restrict__ dscrL,
                                                          T *__restrict__ dscrU, int32_t *__restrict__ bad)
 {
+    static_assert(sizeof(T) == 8, "the LU factors are FP64");
+    typedef typename Mfma<double>::V VD;
     __shared__ double A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L11 \ U11
-    __shared__ double Li[NB][NB + 1];    // L11^-1, Li[c][r] = (r, c)
-    __shared__ double Ui[NB][NB + 1];    // U11^-1, Ui[c][r] = (r, c)
+    __shared__ double Li[NB][NB + 1];    // inverses of the 16 x 16 diagonal blocks of L11, Li[c][r] = (r, c)
+    __shared__ double Ui[NB][NB + 1];    // ... and of U11
     const int2 t = tasks[blockIdx.x];
     const int f = t.x;
     const int m = mfront[f], p = pfront[f], ld = front_ld(m);
@@ -1118,10 +1125,11 @@ __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict_
     T *L = FL + front_off[f];
     T *U = FU + front_off[f];
     const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
     {
         // thread (wave, lane): row lane of columns wave + 4 i, every load in flight
         // (addresses clamped into the block): L below the diagonal, U^T above it
-        const int r = tid % 64, c0 = tid / 64, rc = min(r, nb - 1);
+        const int r = lane, c0 = wave, rc = min(r, nb - 1);
         T lv[NB / 4], uv[NB / 4];
 #pragma unroll
         for (int i = 0; i < NB / 4; i++) {
@@ -1135,57 +1143,102 @@ __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict_
             double v = r == c ? 1.0 : 0.0;
             if (r < nb && c < nb) v = r >= c ? (double)lv[i] : (double)uv[i];
             A[c][r] = v;
+            Li[c][r] = 0.0;
+            Ui[c][r] = 0.0;
         }
     }
     __syncthreads();
-    for (int kk = 0; kk < NB; kk++) {
-        double piv = A[kk][kk];
-        const bool badp = piv == 0.0 || !(fabs(piv) <= __builtin_huge_val());
-        if (badp) piv = 1.0;
-        __syncthreads();                   // every thread has read the pivot
-        if (tid == 0 && badp) {
-            A[kk][kk] = 1.0;
-            if (t.y == 0 && kk < nb) atomicMin(bad, first[f] + k0 + kk);
+    static_for<0, NB / 16, 1>([&](auto bc_) {
+        constexpr int kb = 16 * decltype(bc_)::value;
+        if (wave == 0) {
+            // the block's 16 columns, all rows: pivot d = a_jj, l_rj = a_rj / d
+            // below it, a_rv -= l_rj u_jv for the block's later columns
+            double a[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) a[u] = A[kb + u][lane];
+            int first_bad = INT32_MAX;
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int j = kb + u;
+                double d = lane_bcast(a[u], j);
+                if (!(d != 0.0 && fabs(d) <= __builtin_huge_val())) {
+                    first_bad = min(first_bad, j);
+                    d = 1.0;
+                    if (lane == j) a[u] = 1.0;
+                }
+                const double l = a[u] * (1.0 / d);
+                const bool below = lane > j;
+                if (below) a[u] = l;
+#pragma unroll
+                for (int v = u + 1; v < 16; v++) {
+                    const double ujv = lane_bcast(a[v], j);
+                    if (below) a[v] -= l * ujv;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++) A[kb + u][lane] = a[u];
+            if (t.y == 0 && first_bad < nb && lane == 0) atomicMin(bad, first[f] + k0 + first_bad);
         }
-        const double rp = 1.0 / piv;
-        for (int i = kk + 1 + tid; i < NB; i += THREADS) A[kk][i] *= rp;
         __syncthreads();
-        const int w = NB - kk - 1;
-        for (int e = tid; e < w * w; e += THREADS) {
-            int j = kk + 1 + e / w, i = kk + 1 + e % w;
-            A[j][i] -= A[kk][i] * A[j][kk];
+        if (wave == 1) {
+            // rows of U to the right of the block: U12 = L_bb^-1 A12, column kb + 16 + lane
+            const int col = kb + 16 + lane;
+            if (col < NB) {
+                double x[16];
+#pragma unroll
+                for (int tt = 0; tt < 16; tt++) x[tt] = A[col][kb + tt];
+#pragma unroll
+                for (int tt = 0; tt < 16; tt++)
+#pragma unroll
+                    for (int q = tt + 1; q < 16; q++) x[q] -= A[kb + tt][kb + q] * x[tt];
+#pragma unroll
+                for (int tt = 0; tt < 16; tt++) A[col][kb + tt] = x[tt];
+            }
+        } else if (wave == 2 && lane < 16) {
+            // column c of L_bb^-1 (unit diagonal)
+            const int c = lane;
+            double y[16];
+#pragma unroll
+            for (int r = 0; r < 16; r++) y[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int tt = 0; tt < 16; tt++)
+#pragma unroll
+                for (int q = tt + 1; q < 16; q++) y[q] -= A[kb + tt][kb + q] * y[tt];
+#pragma unroll
+            for (int r = 0; r < 16; r++) Li[kb + c][kb + r] = y[r];
+        } else if (wave == 3 && lane < 16) {
+            // column c of U_bb^-1, from the last row up
+            const int c = lane;
+            double y[16];
+#pragma unroll
+            for (int r = 0; r < 16; r++) y[r] = r == c ? 1.0 : 0.0;
+#pragma unroll
+            for (int tt = 15; tt >= 0; tt--) {
+                y[tt] /= A[kb + tt][kb + tt];
+#pragma unroll
+                for (int r = 0; r < tt; r++) y[r] -= A[kb + tt][kb + r] * y[tt];
+            }
+#pragma unroll
+            for (int r = 0; r < 16; r++) Ui[kb + c][kb + r] = y[r];
         }
         __syncthreads();
-    }
-    if (tid < NB) {
-        // column c of L11^-1: y = e_c, then y_r -= l_rt y_t for r > t (unit diagonal)
-        const int c = tid;
-        double y[NB];
+        if constexpr (kb + 16 < NB) {
+            // the rest of the block: A22 -= L21 U12, block pairs round-robin over the waves
+            int q = 0;
 #pragma unroll
-        for (int r = 0; r < NB; r++) y[r] = r == c ? 1.0 : 0.0;
+            for (int ib = kb + 16; ib < NB; ib += 16)
 #pragma unroll
-        for (int tt = 0; tt < NB; tt++)
+                for (int jb = kb + 16; jb < NB; jb += 16)
+                    if (q++ % 4 == wave) {
+                        VD acc = {0, 0, 0, 0};
+                        acc = mm16<double>(acc, [&](int r, int k) { return A[kb + k][ib + r]; },
+                                           [&](int k, int n) { return A[jb + n][kb + k]; });
 #pragma unroll
-            for (int r = tt + 1; r < NB; r++) y[r] -= A[tt][r] * y[tt];
-#pragma unroll
-        for (int r = 0; r < NB; r++) Li[c][r] = y[r];
-    } else if (tid < 2 * NB) {
-        // column c of U11^-1: y = e_c, then from the last row up y_t /= u_tt and
-        // y_r -= u_rt y_t for r < t
-        const int c = tid - NB;
-        double y[NB];
-#pragma unroll
-        for (int r = 0; r < NB; r++) y[r] = r == c ? 1.0 : 0.0;
-#pragma unroll
-        for (int tt = NB - 1; tt >= 0; tt--) {
-            y[tt] /= A[tt][tt];
-#pragma unroll
-            for (int r = 0; r < tt; r++) y[r] -= A[tt][r] * y[tt];
+                        for (int e = 0; e < 4; e++) A[jb + ln][ib + Mfma<double>::row(kq, e)] -= acc[e];
+                    }
+            __syncthreads();
         }
-#pragma unroll
-        for (int r = 0; r < NB; r++) Ui[c][r] = y[r];
-    }
-    __syncthreads();
+    });
     if (t.y == 0) {
         T *DL = dscrL + dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
         T *DU = dscrU + dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
@@ -1195,53 +1248,58 @@ __global__ __launch_bounds__(THREADS, 1) void k_lu_panel(const int2 *__restrict_
             DU[e] = (T)(r >= c ? A[r][c] : 0.0);        // U11^T: (r, c) = u(c, r)
         }
     }
-    // the rows below the block, TRW per workgroup, on the FP64 matrix cores:
-    // L21 = A21 U11^-1 (out(r, c) = sum_t a(r, t) U11^-1(t, c)) and
-    // U12^T = A12^T L11^-T (out(r, c) = sum_t a(r, t) L11^-1(c, t)); wave w
-    // takes the 16-row blocks 3 w .. 3 w + 2 and all 64 output columns
-    typedef typename Mfma<double>::V VD;
-    const int wave = tid / 64, lane = tid % 64, kq = lane / 16, ln = lane % 16;
+    // the rows below the block by 16-column block substitution on transposed
+    // 16 x 16 blocks (as the Cholesky panel's slab): xs[c][rb] element e of
+    // lane (kq, ln) is column 16 c + Mfma::row(kq, e) of row row0 + 16 rb + ln
     constexpr int RB = TRW / 64;     // 16-row blocks per wave
     const int row0 = k0 + nb + t.y * TRW + wave * 16 * RB;
 #pragma unroll
     for (int side = 0; side < 2; side++) {
+        // side 0: X U11 = A21 in FL; side 1: X L11^T = A12^T in FU
         T *X = side ? U : L;
-        // operands of this wave: a(row0 + 16 rb + ln, 4 s + kq) for s = 0..15
-        double av[RB][NB / 4];
+        VD xs[NB / 16][RB];
 #pragma unroll
-        for (int rb = 0; rb < RB; rb++) {
-            const int row = row0 + 16 * rb + ln;
+        for (int c = 0; c < NB / 16; c++)
 #pragma unroll
-            for (int sidx = 0; sidx < NB / 4; sidx++) {
-                const int tt = 4 * sidx + kq;
-                av[rb][sidx] = (row < m && tt < nb) ? (double)X[(int64_t)(k0 + tt) * ld + min(row, m - 1)] : 0.0;
-            }
-        }
-        VD acc[RB][NB / 16];
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int cb = 0; cb < NB / 16; cb++) acc[rb][cb] = VD{0, 0, 0, 0};
-#pragma unroll
-        for (int sidx = 0; sidx < NB / 4; sidx++) {
-            const int tt = 4 * sidx + kq;
-#pragma unroll
-            for (int cb = 0; cb < NB / 16; cb++) {
-                const int c = 16 * cb + ln;
-                const double bv = side ? Li[tt][c] : Ui[c][tt];
-#pragma unroll
-                for (int rb = 0; rb < RB; rb++) acc[rb][cb] = Mfma<double>::mma(av[rb][sidx], bv, acc[rb][cb]);
-            }
-        }
-#pragma unroll
-        for (int rb = 0; rb < RB; rb++)
-#pragma unroll
-            for (int cb = 0; cb < NB / 16; cb++)
+            for (int rb = 0; rb < RB; rb++)
 #pragma unroll
                 for (int e = 0; e < 4; e++) {
-                    const int row = row0 + 16 * rb + Mfma<double>::row(kq, e), c = 16 * cb + ln;
-                    if (row < m && c < nb) X[(int64_t)(k0 + c) * ld + row] = (T)acc[rb][cb][e];
+                    const int row = row0 + 16 * rb + ln, k = 16 * c + Mfma<double>::row(kq, e);
+                    xs[c][rb][e] = (row < m && k < nb) ? (double)X[(int64_t)(k0 + k) * ld + row] : 0.0;
                 }
+        static_for<0, NB / 16, 1>([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            constexpr int kb = 16 * c;
+#pragma unroll
+            for (int rb = 0; rb < RB; rb++) {
+                VD acc = xs[c][rb];
+#pragma unroll
+                for (int j = 0; j < c; j++)
+#pragma unroll
+                    for (int st = 0; st < 4; st++) {
+                        const int kk = 16 * j + Mfma<double>::row(kq, st);
+                        // side 0: (U^T)_cj(ln, kk) = U(kk, kb + ln); side 1: L_cj(ln, kk) = L(kb + ln, kk)
+                        const double mv = side ? A[kk][kb + ln] : A[kb + ln][kk];
+                        acc = Mfma<double>::mma(-mv, xs[j][rb][st], acc);
+                    }
+                VD x = {0, 0, 0, 0};
+#pragma unroll
+                for (int st = 0; st < 4; st++) {
+                    const int kk = kb + Mfma<double>::row(kq, st);
+                    // side 0: (U_cc^-1)^T(ln, kk); side 1: L_cc^-1(ln, kk)
+                    const double dv = side ? Li[kk][kb + ln] : Ui[kb + ln][kk];
+                    x = Mfma<double>::mma(dv, acc[st], x);
+                }
+                xs[c][rb] = x;
+                const int row = row0 + 16 * rb + ln;
+                if (row < m)
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const int n = kb + Mfma<double>::row(kq, e);
+                        if (n < nb) X[(int64_t)(k0 + n) * ld + row] = (T)x[e];
+                    }
+            }
+        });
     }
 }
 
