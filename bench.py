@@ -30,19 +30,27 @@ METRIC = "factor TFLOP/s + % MFMA peak, N=2^18: FP32+IR vs FP64 at resid 1e-10"
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "update_fp32_headline_hbm_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2007_01541_amd", "csrc", "kernels.hip")
+# the update kernels' source: their own file and the definitions it includes
+KERNEL_SRC = [os.path.join(ROOT, "paper_2007_01541_amd", "csrc", f) for f in ("common.h", "update.h")]
+
+
+def update_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic():
     """HBM bytes per launch of the FP32 update kernel class from the committed
-    counter summary, or None when the kernel source changed since then."""
-    import hashlib
+    counter summary, or None when the update kernels' source changed since."""
     try:
         fields = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines() if ": " in l)
-        src = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        src = update_source_sha256()
     except OSError:
         return None
-    if fields.get("kernels_hip_sha256", "").strip() != src:
+    if fields.get("update_source_sha256", "").strip() != src:
         return None
     return float(fields["traffic_bytes_per_launch"])
 
