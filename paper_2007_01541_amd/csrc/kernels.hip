@@ -632,16 +632,25 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
     typedef typename Mfma<T>::V V;
     typedef typename Vec4<T>::type V4;
     constexpr int LSZ = NB * (NB + 1);
-    constexpr int XLD = NB + 16;   // operand rows padded: the B reads of the four lane groups hit distinct banks
-    constexpr size_t PH1 = 2 * (size_t)LSZ * sizeof(T);                 // L_kk, sub-block inverses
-    constexpr size_t PH2 = 2 * (size_t)NB * XLD * sizeof(T);            // X_i, X_j (k-major)
+    // L_kk and the sub-block inverses: rows of LST elements, so that the solve's
+    // operand reads (lane group kq reading row 4 kq + s in FP32, row 4 s + kq
+    // in FP64) of the four lane groups fall in distinct banks
+    constexpr int LST = sizeof(T) == 4 ? NB + 4 : NB + 16;
+    // X_i, X_j (k-major): FP64 rows padded to 80 elements; FP32 rows unpadded
+    // with columns swizzled by xcol, which keeps the row-block stores (rows
+    // 4 kq + e) and the update's reads (rows kk + kq) both free of conflicts
+    constexpr int XLD = sizeof(T) == 4 ? NB : NB + 16;
+    constexpr size_t PH1 = 2 * (size_t)NB * LST * sizeof(T);            // L_kk, sub-block inverses
+    constexpr size_t PH2 = 2 * (size_t)NB * XLD * sizeof(T);            // X_i, X_j
     constexpr size_t PH3 = (2 * (size_t)LSZ + NB) * sizeof(TD);         // D_{k+1} being factored
     constexpr size_t PH = PH1 > PH2 ? (PH1 > PH3 ? PH1 : PH3) : (PH2 > PH3 ? PH2 : PH3);
     __shared__ __align__(16) char smem[PH];
-    T(*Ls)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(smem);
-    T(*Ivs)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(smem + (size_t)LSZ * sizeof(T));
+    T(*Ls)[LST] = reinterpret_cast<T(*)[LST]>(smem);
+    T(*Ivs)[LST] = reinterpret_cast<T(*)[LST]>(smem + (size_t)NB * LST * sizeof(T));
+    T(*Lt)[NB + 1] = reinterpret_cast<T(*)[NB + 1]>(smem);   // transpose tile of the deferred-panel moves
     T(*XA)[XLD] = reinterpret_cast<T(*)[XLD]>(smem);
     T(*XB)[XLD] = reinterpret_cast<T(*)[XLD]>(smem + (size_t)NB * XLD * sizeof(T));
+    auto xcol = [](int k, int c) { return sizeof(T) == 4 ? c ^ ((((k >> 2) ^ k) & 3) << 4) : c; };
     const int4 t = tasks[blockIdx.x];
     const int f = t.x, i0 = t.y, j0 = t.z, w = t.w;
     const int m = mfront[f], p = pfront[f], ld = front_ld(m);
@@ -651,7 +660,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
     const int kq = lane / 16, ln = lane % 16;
     if (j0 == STEP_COPY_ONLY) {
-        move_deferred<T>(F, ld, m, i0, w, K0, k0, Ls);
+        move_deferred<T>(F, ld, m, i0, w, K0, k0, Lt);
         return;
     }
     const int64_t ok = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
@@ -734,26 +743,52 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
             xs[c][h] = x;
         }
     });
+    // FP32, panel rows to the transposed position: straight from the
+    // registers, where a lane holds four consecutive columns 16 c + 4 kq.. of
+    // its row (one 16-byte store each)
+    constexpr bool reg_park = sizeof(T) == 4;
+    if (reg_park && (w & STEP_WRITE) && !(w & STEP_DIRECT)) {
+        const int row = i0 + 16 * wave + ln;
+        if (row < m) {
+            T *q = F + (int64_t)row * ld + k0;
+#pragma unroll
+            for (int c = 0; c < NB / 16; c++) {
+                const int kb = 16 * c + 4 * kq;
+                if (kb + 3 < nb) {
+                    V4 o;
+                    o.x = xs[c][0][0];
+                    o.y = xs[c][0][1];
+                    o.z = xs[c][0][2];
+                    o.w = xs[c][0][3];
+                    *reinterpret_cast<V4 *>(q + kb) = o;
+                } else {
+#pragma unroll
+                    for (int x = 0; x < 4; x++)
+                        if (kb + x < nb) q[kb + x] = xs[c][0][x];
+                }
+            }
+        }
+    }
     __syncthreads();   // L_kk and the inverses are no longer read (X_i, X_j take their place)
 #pragma unroll
     for (int c = 0; c < NB / 16; c++)
 #pragma unroll
         for (int e = 0; e < 4; e++) {
             int k = 16 * c + Mfma<T>::row(kq, e);
-            XA[k][16 * wave + ln] = xs[c][0][e];
-            if (two) XB[k][16 * wave + ln] = xs[c][dtile ? 0 : 1][e];
+            XA[k][xcol(k, 16 * wave + ln)] = xs[c][0][e];
+            if (two) XB[k][xcol(k, 16 * wave + ln)] = xs[c][dtile ? 0 : 1][e];
         }
     __syncthreads();
     if (w & STEP_WRITE) {
         if (w & STEP_DIRECT) {
             for (int e = tid; e < NB * NB; e += THREADS) {
                 int k = e / NB, r = e % NB;
-                if (k < nb && i0 + r < m) F[(int64_t)(k0 + k) * ld + i0 + r] = XA[k][r];
+                if (k < nb && i0 + r < m) F[(int64_t)(k0 + k) * ld + i0 + r] = XA[k][xcol(k, r)];
             }
-        } else {
+        } else if (!reg_park) {
             for (int e = tid; e < NB * NB; e += THREADS) {
                 int r = e / NB, k = e % NB;
-                if (k < nb && i0 + r < m) F[(int64_t)(i0 + r) * ld + k0 + k] = XA[k][r];
+                if (k < nb && i0 + r < m) F[(int64_t)(i0 + r) * ld + k0 + k] = XA[k][xcol(k, r)];
             }
         }
     }
@@ -763,8 +798,8 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
         for (int x = 0; x < 4; x++) acc[x] = V{0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < NB; kk += 4) {
-            V4 a4 = *reinterpret_cast<const V4 *>(&XA[kk + kq][4 * ln]);
-            T b = XB[kk + kq][16 * wave + ln];
+            V4 a4 = *reinterpret_cast<const V4 *>(&XA[kk + kq][xcol(kk + kq, 4 * ln)]);
+            T b = XB[kk + kq][xcol(kk + kq, 16 * wave + ln)];
             acc[0] = Mfma<T>::mma(a4.x, b, acc[0]);
             acc[1] = Mfma<T>::mma(a4.y, b, acc[1]);
             acc[2] = Mfma<T>::mma(a4.z, b, acc[2]);
@@ -826,19 +861,23 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
                                     *reinterpret_cast<TD(*)[NB][NB + 1]>(Iv), dscr + o2, dinv + o2);
         }
     }
-    if (w & STEP_COPY) move_deferred<T>(F, ld, m, i0, i0 + NB, K0, k0, Ls);
+    if (w & STEP_COPY) move_deferred<T>(F, ld, m, i0, i0 + NB, K0, k0, Lt);
 }
 
-// Inverse of every factored NB x NB diagonal block (task = (front, block)),
-// from its copy in dscr, formed in FP64 and rounded to T into dinv (column
-// major, same offsets): one wave per block, lane c forms column c of L^-1 by
-// forward substitution, right-looking (15 and more independent updates per
-// step).  The triangular solves use these inverses; nothing in the
-// factorization does, so this runs once at its end, off the panel chain.
+// Every factored NB x NB diagonal block of a level's fronts (task = (front,
+// block)), from its copy in dscr: copied into the lower triangle of its place
+// in the front, and inverted in FP64 and rounded to T into dinv (column major,
+// same offsets).  One wave per block; lane c forms column c of L^-1 by forward
+// substitution, right-looking (15 and more independent updates per step).
+// The triangular solves use these; nothing in the factorization reads them,
+// so each level's blocks are handled beside the levels above it, off the
+// panel chain.
 template <typename T>
 __global__ __launch_bounds__(64) void k_diag_inv(const int2 *__restrict__ tasks,
                                                  const int64_t *__restrict__ dscr_off, const T *__restrict__ dscr,
-                                                 T *__restrict__ dinv)
+                                                 T *__restrict__ dinv, const int64_t *__restrict__ front_off,
+                                                 const int32_t *__restrict__ mfront,
+                                                 const int32_t *__restrict__ pfront, T *__restrict__ fronts)
 {
     __shared__ double L[NB][NB + 1];   // column-major: L[c][r] = L(r, c)
     int2 t = tasks[blockIdx.x];
@@ -850,6 +889,11 @@ __global__ __launch_bounds__(64) void k_diag_inv(const int2 *__restrict__ tasks,
         T v[NB];
 #pragma unroll
         for (int j = 0; j < NB; j++) v[j] = D[j * NB + c];
+        const int k0 = t.y * NB, nb = min(NB, pfront[t.x] - k0), ld = front_ld(mfront[t.x]);
+        T *F = fronts + front_off[t.x] + (int64_t)k0 * ld + k0;
+#pragma unroll
+        for (int j = 0; j < NB; j++)
+            if (c < nb && c >= j) F[(int64_t)j * ld + c] = v[j];
 #pragma unroll
         for (int j = 0; j < NB; j++) L[j][c] = (double)v[j];
     }
@@ -868,28 +912,6 @@ __global__ __launch_bounds__(64) void k_diag_inv(const int2 *__restrict__ tasks,
     for (int r = 0; r < NB; r++) L[c][r] = y[r];
     __syncthreads();
     for (int i = c; i < NB * NB; i += 64) dinv[o + i] = (T)L[i / NB][i % NB];
-}
-
-// Copies the factored diagonal blocks of every listed front from the scratch
-// area into the lower triangle of the front's pivot columns.
-template <typename T>
-__global__ void k_diag_fixup(const int32_t *__restrict__ flist, const int64_t *__restrict__ front_off,
-                             const int32_t *__restrict__ mfront, const int32_t *__restrict__ pfront,
-                             const int64_t *__restrict__ dscr_off, const T *__restrict__ dscr,
-                             T *__restrict__ fronts)
-{
-    int f = flist[blockIdx.x];
-    int m = mfront[f], p = pfront[f], ld = front_ld(m);
-    T *F = fronts + front_off[f];
-    const T *D = dscr + dscr_off[f];
-    int nblk = (p + NB - 1) / NB;
-    for (int64_t idx = threadIdx.x; idx < (int64_t)nblk * NB * NB; idx += blockDim.x) {
-        int b = (int)(idx / (NB * NB)), e = (int)(idx % (NB * NB));
-        int c = e / NB, r = e % NB;
-        int k0 = b * NB;
-        int nb = min(NB, p - k0);
-        if (c < nb && r < nb && r >= c) F[(int64_t)(k0 + c) * ld + k0 + r] = D[idx];
-    }
 }
 
 // ---------------------------------------------------------------- leaf fronts

@@ -150,6 +150,7 @@ struct SolveLevel {
     std::pair<int64_t, int64_t> below{0, 0};       // backward update-row partial tasks (sbelow_tasks)
     std::pair<int64_t, int64_t> below_sum{0, 0};   // ... and their sums (sbsum_tasks)
     std::vector<SuperStep> bwd;                    // s0 descending
+    std::pair<int64_t, int64_t> xinv{0, 0};        // super-block inverse tasks of this level (xinv_tasks)
 };
 struct Level {
     SolveLevel sv;
@@ -175,7 +176,6 @@ struct Plan {
     std::vector<int64_t> dscr_off;                // per front: element offset of its diagonal-block scratch
     std::vector<int2> dinv_tasks;                 // (front, diagonal block) of every NB x NB block
     int64_t dscr_elems = 0;
-    std::vector<int32_t> all_fronts;
     std::vector<int2> zero_tasks;                 // (front, first column) chunks of ZCOLS columns
     int64_t lower_elems = 0;
     std::vector<int32_t> child_ptr, child_list;
@@ -214,7 +214,6 @@ struct Plan {
         first.resize(ns);
         woff.resize(ns);
         dscr_off.resize(ns);
-        all_fronts.resize(ns);
         wrows = 0;
         dscr_elems = 0;
         dinv_tasks.clear();
@@ -226,7 +225,6 @@ struct Plan {
             wrows += mfront[s];
             dscr_off[s] = dscr_elems;
             dscr_elems += (int64_t)((pfront[s] + NB - 1) / NB) * NB * NB;
-            all_fronts[s] = s;
         }
         child_ptr.assign((size_t)ns + 1, 0);
         for (int32_t s = 0; s < ns; s++)
@@ -443,6 +441,7 @@ struct Plan {
             for (int32_t s : big)
                 for (int32_t t = 0; t < (mfront[s] + SROWS - 1) / SROWS; t++) sasm_tasks.push_back(make_int2(s, t));
             V.assemble.second = (int64_t)sasm_tasks.size() - V.assemble.first;
+            V.xinv.first = (int64_t)xinv_tasks.size();
             for (int32_t s : big) {
                 int32_t nsup = (pfront[s] + SS - 1) / SS;
                 xoff[s] = xelems;
@@ -455,6 +454,7 @@ struct Plan {
                     for (int32_t jb = 0; jb < nb; jb++) xinv_tasks.push_back(make_int4(s, si, jb, 0));
                 }
             }
+            V.xinv.second = (int64_t)xinv_tasks.size() - V.xinv.first;
             auto blk_tasks = [&](int32_t s0) {
                 int64_t off = (int64_t)sblk_tasks.size();
                 for (int32_t s : big) {
@@ -557,7 +557,7 @@ struct Layout {
     size_t fronts, W, Y, Xr, Rr, Br, vec, bad;
     size_t front_off, mfront, pfront, first, sparent, rptr, rows, rel, amap, woff, child_ptr, child_list, easplit;
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
-    size_t pan, upd, ea, flist, dscr, dinv, dscr_off, all_fronts, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
+    size_t pan, upd, ea, flist, dscr, dinv, dscr_off, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
     size_t spchunk, splong, sppart, iperm, leafq, leafc, diagf, stept;
     // LU factors only: the U^T fronts and their diagonal-block scratch, inverses and super-block inverses
@@ -630,7 +630,6 @@ struct Layout {
         segp = seg((nseg + 1) * 4);
         ztasks = seg(std::max<size_t>(1, P.zero_tasks.size()) * sizeof(int2));
         dscr_off = seg(ns * 8);
-        all_fronts = seg(ns * 4);
         spchunk = seg(std::max<size_t>(1, P.spmv_chunks.size()) * sizeof(int4));
         splong = seg(std::max<size_t>(1, P.spmv_long.size()) * sizeof(int4));
         sppart = seg((size_t)std::max<int64_t>(1, P.spmv_slots) * k * 8);
@@ -1088,19 +1087,28 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
             HIP_TRY(hipStreamWaitEvent(st, f->ev_side, 0));
             pending = false;
         }
-        if (L.dinv_cnt) {   // this level's diagonal blocks are final: invert them beside the next levels
+        if (L.dinv_cnt) {
+            // this level's fronts are final: beside the levels above, copy their
+            // diagonal blocks into place and invert them, then build the solve's
+            // super-block inverses from them
             if (aux != st) {
                 HIP_TRY(hipEventRecord(f->ev_main, st));
                 HIP_TRY(hipStreamWaitEvent(aux, f->ev_main, 0));
             }
             PROF_BEGIN(KC_FILL);
-            hipLaunchKernelGGL(k_diag_inv<T>, dim3((unsigned)L.dinv_cnt), dim3(64), 0, aux,
-                               f->at<int2>(Lo.dinvt) + L.dinv_off, dso, dscr, dinv);
-            if (lu)
+            for (int b = 0; b < nbuf; b++)
                 hipLaunchKernelGGL(k_diag_inv<T>, dim3((unsigned)L.dinv_cnt), dim3(64), 0, aux,
-                                   f->at<int2>(Lo.dinvt) + L.dinv_off, dso, f->at<T>(Lo.dscr_u), f->at<T>(Lo.dinv_u));
+                                   f->at<int2>(Lo.dinvt) + L.dinv_off, dso, b ? f->at<T>(Lo.dscr_u) : dscr,
+                                   b ? f->at<T>(Lo.dinv_u) : dinv, fo, mf, pf, buf(b));
+            const std::pair<int64_t, int64_t> &xt = L.sv.xinv;
+            for (int b = 0; b < nbuf && xt.second; b++)
+                hipLaunchKernelGGL(k_build_xinv<T>, dim3((unsigned)xt.second), dim3(THREADS), 0, aux,
+                                   f->at<int4>(Lo.xinvt) + xt.first, fo, mf, pf, dso, f->at<int64_t>(Lo.xoff),
+                                   buf(b), b ? f->at<T>(Lo.dinv_u) : dinv,
+                                   b ? f->at<T>(Lo.xinv_u) : f->at<T>(Lo.xinv));
             PROF_END(KC_FILL);
-            if (prof) prof->bytes[KC_FILL] += (double)L.dinv_cnt * NB * NB * esz * 2 * nbuf;
+            // read the block, write its inverse and the lower half of its place
+            if (prof) prof->bytes[KC_FILL] += (double)L.dinv_cnt * NB * NB * esz * 2.5 * nbuf;
         }
         r_ea = extend_add(L.ea_post, false);
         if (r_ea) return r_ea;
@@ -1109,26 +1117,9 @@ int launch_factor(wcs_factor f, const double *values, hipStream_t st, Prof *prof
             if (r_) return r_;
         }
     }
-    PROF_BEGIN(KC_FILL);
-    for (int b = 0; b < nbuf; b++)
-        hipLaunchKernelGGL(k_diag_fixup<T>, dim3((unsigned)S.ns), dim3(256), 0, st, f->at<int32_t>(Lo.all_fronts), fo,
-                           mf, pf, dso, b ? f->at<T>(Lo.dscr_u) : dscr, buf(b));
-    PROF_END(KC_FILL);
-    if (prof) prof->bytes[KC_FILL] += (double)P.dscr_elems * esz * 2 * nbuf;
-    if (aux != st) {   // the block inverses, then the super-block inverses built from them
+    if (aux != st) {   // the diagonal blocks and the solve's inverses
         HIP_TRY(hipEventRecord(f->ev_aux, aux));
         HIP_TRY(hipStreamWaitEvent(st, f->ev_aux, 0));
-    }
-    if (!P.xinv_tasks.empty()) {
-        PROF_BEGIN(KC_FILL);
-        hipLaunchKernelGGL(k_build_xinv<T>, dim3((unsigned)P.xinv_tasks.size()), dim3(THREADS), 0, st,
-                           f->at<int4>(Lo.xinvt), fo, mf, pf, dso, f->at<int64_t>(Lo.xoff), fronts, dinv,
-                           f->at<T>(Lo.xinv));
-        if (lu)
-            hipLaunchKernelGGL(k_build_xinv<T>, dim3((unsigned)P.xinv_tasks.size()), dim3(THREADS), 0, st,
-                               f->at<int4>(Lo.xinvt), fo, mf, pf, dso, f->at<int64_t>(Lo.xoff), fronts_u,
-                               f->at<T>(Lo.dinv_u), f->at<T>(Lo.xinv_u));
-        PROF_END(KC_FILL);
     }
     HIP_TRY(hipGetLastError());
     return WCS_OK;
@@ -1850,7 +1841,6 @@ int upload_plan(wcs_factor f, hipStream_t st, wcs_factor *out)
     rc = rc ? rc : upload(f, L.ea, P.ea_tasks, st);
     rc = rc ? rc : upload(f, L.flist, P.flist, st);
     rc = rc ? rc : upload(f, L.dscr_off, P.dscr_off, st);
-    rc = rc ? rc : upload(f, L.all_fronts, P.all_fronts, st);
     rc = rc ? rc : upload(f, L.slist, P.slist, st);
     rc = rc ? rc : upload(f, L.sfwd, P.sfwd_tasks, st);
     rc = rc ? rc : upload(f, L.sbelow, P.sbelow_tasks, st);
