@@ -240,10 +240,10 @@ __device__ __forceinline__ float lane_bcast(float x, int src)
 // Factorization of one NB x NB diagonal block held in LDS by all four waves
 // of a workgroup.  A: column-major (A[c][r] = block(r, c)), lower part
 // meaningful, upper part zero, padded past the block's nb columns with the
-// identity; on return it holds the factor L (upper part zero).  Iv (zeroed by
-// the caller) receives the inverses of the four 16 x 16 diagonal sub-blocks of
-// L, Rd the reciprocal pivots.  The caller synchronises the workgroup after
-// filling A and Iv; the helper ends synchronised, after which waves 1..3 run
+// identity; on return it holds the factor L (upper part zero).  Iv receives
+// the inverses of the four 16 x 16 diagonal sub-blocks of L (Iv[b][c][r] =
+// L_bb^-1(r, c), upper parts zero), Rd the reciprocal pivots.  The caller synchronises the workgroup after
+// filling A; the helper ends synchronised, after which waves 1..3 run
 // slab(c) for c = 0..3 (work of the caller that needs L and the inverses).
 // Right-looking by 16-column blocks: wave 0 factors the block's columns for
 // all rows at once, one lane per row holding the 16 columns in registers
@@ -265,8 +265,13 @@ template <typename TD> __device__ __forceinline__ TD rsqrt_pivot(TD d)
     return r * ((TD)1.5 - (TD)0.5 * d * r * r);
 }
 
+// the inverses of the four 16 x 16 diagonal sub-blocks of a diagonal block:
+// DiagInv<TD>[b][c][r] = L_bb^-1(r, c) (rows padded to 17: lane c's column
+// writes fall in distinct banks)
+template <typename TD> using DiagInv = TD[NB / 16][16][17];
+
 template <typename TD, typename Slab>
-__device__ __forceinline__ void factor_diag_block(TD (&A)[NB][NB + 1], TD (&Iv)[NB][NB + 1], TD (&Rd)[NB], int nb,
+__device__ __forceinline__ void factor_diag_block(TD (&A)[NB][NB + 1], DiagInv<TD> &Iv, TD (&Rd)[NB], int nb,
                                                   bool report, int32_t *bad, int32_t piv0, Slab slab)
 {
     typedef typename Mfma<TD>::V VD;
@@ -305,7 +310,7 @@ __device__ __forceinline__ void factor_diag_block(TD (&A)[NB][NB + 1], TD (&Iv)[
                 for (int q = rr + 2; q < 16; q++) cur[q] = nxt[q];
             }
 #pragma unroll
-            for (int rr = 0; rr < 16; rr++) Iv[kb + c][kb + rr] = y[rr];
+            for (int rr = 0; rr < 16; rr++) Iv[kb / 16][c][rr] = y[rr];
         }
     };
     // wave 0: the 16 columns of block kb for all 64 rows (lane = row), two
@@ -390,7 +395,7 @@ __device__ __forceinline__ void factor_diag_block(TD (&A)[NB][NB + 1], TD (&Iv)[
 // (rounded to T, zero elsewhere) to global memory; wave w writes columns
 // 16 w .. 16 w + 15 (after factor_diag_block: A and Iv complete).
 template <typename T, typename TD>
-__device__ __forceinline__ void store_diag_block(const TD (&A)[NB][NB + 1], const TD (&Iv)[NB][NB + 1], T *D, T *Dinv)
+__device__ __forceinline__ void store_diag_block(const TD (&A)[NB][NB + 1], const DiagInv<TD> &Iv, T *D, T *Dinv)
 {
     const int r = threadIdx.x % 64, cb = 16 * (threadIdx.x / 64);
     T lv[16];
@@ -400,7 +405,7 @@ __device__ __forceinline__ void store_diag_block(const TD (&A)[NB][NB + 1], cons
     for (int c = 0; c < 16; c++) D[(cb + c) * NB + r] = lv[c];
     if (Dinv) {
 #pragma unroll
-        for (int c = 0; c < 16; c++) lv[c] = (T)Iv[cb + c][r];
+        for (int c = 0; c < 16; c++) lv[c] = r / 16 == cb / 16 ? (T)Iv[cb / 16][c][r % 16] : (T)0;
 #pragma unroll
         for (int c = 0; c < 16; c++) Dinv[(cb + c) * NB + r] = lv[c];
     }
@@ -431,7 +436,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_panel(const
                                                    T *__restrict__ dscr, int32_t *__restrict__ bad)
 {
     __shared__ TD A[NB][NB + 1];     // column-major: A[c][r] = block(r, c); becomes L
-    __shared__ TD Iv[NB][NB + 1];    // column-major: Iv[c][r] = L^-1(r, c)
+    __shared__ DiagInv<TD> Iv;       // inverses of the 16 x 16 diagonal sub-blocks
     __shared__ TD Rd[NB];            // 1 / L(r, r)
     int2 t = tasks[blockIdx.x];
     int f = t.x;
@@ -457,10 +462,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_panel(const
 #pragma unroll
         for (int c = 0; c < NB; c++) raw[c] = F[(int64_t)(k0 + min(c, nb - 1)) * ld + k0 + rc];
 #pragma unroll
-        for (int c = 0; c < NB; c++) {
-            A[c][r] = (r < nb && c < nb && c <= r) ? (TD)raw[c] : (c == r ? (TD)1 : (TD)0);
-            Iv[c][r] = 0;
-        }
+        for (int c = 0; c < NB; c++) A[c][r] = (r < nb && c < nb && c <= r) ? (TD)raw[c] : (c == r ? (TD)1 : (TD)0);
     } else if (row0 < m) {
 #pragma unroll
         for (int c = 0; c < NB / 16; c++)
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(THREADS, sizeof(T) == 4 ? 2 : 1) void k_panel(const
             V x = {0, 0, 0, 0};
 #pragma unroll
             for (int st = 0; st < 4; st++)
-                x = Mfma<T>::mma((T)Iv[kb + Mfma<T>::row(kq, st)][kb + ln], acc[st], x);
+                x = Mfma<T>::mma((T)Iv[c][Mfma<T>::row(kq, st)][ln], acc[st], x);
             xs[c][rb] = x;
             int row = row0 + rb * 16 + ln;
             if (row < m)
@@ -537,7 +539,7 @@ __global__ __launch_bounds__(THREADS) void k_diag_factor(const int32_t *__restri
                                                          T *__restrict__ dinv, int32_t *__restrict__ bad)
 {
     __shared__ TD A[NB][NB + 1];
-    __shared__ TD Iv[NB][NB + 1];
+    __shared__ DiagInv<TD> Iv;
     __shared__ TD Rd[NB];
     const int f = tasks[blockIdx.x];
     const int m = mfront[f], p = pfront[f], ld = front_ld(m);
@@ -554,7 +556,6 @@ __global__ __launch_bounds__(THREADS) void k_diag_factor(const int32_t *__restri
     for (int i = 0; i < NB / 4; i++) {
         const int c = c0 + 4 * i;
         A[c][r] = (r < nb && c < nb && c <= r) ? (TD)raw[i] : (c == r ? (TD)1 : (TD)0);
-        Iv[c][r] = 0;
     }
     __syncthreads();
     factor_diag_block<TD>(A, Iv, Rd, nb, true, bad, first[f] + k0, [](auto) {});
@@ -642,7 +643,7 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
     constexpr int XLD = sizeof(T) == 4 ? NB : NB + 16;
     constexpr size_t PH1 = 2 * (size_t)NB * LST * sizeof(T);            // L_kk, sub-block inverses
     constexpr size_t PH2 = 2 * (size_t)NB * XLD * sizeof(T);            // X_i, X_j
-    constexpr size_t PH3 = (2 * (size_t)LSZ + NB) * sizeof(TD);         // D_{k+1} being factored
+    constexpr size_t PH3 = ((size_t)LSZ + sizeof(DiagInv<TD>) / sizeof(TD) + NB) * sizeof(TD);   // D_{k+1} being factored
     constexpr size_t PH = PH1 > PH2 ? (PH1 > PH3 ? PH1 : PH3) : (PH2 > PH3 ? PH2 : PH3);
     __shared__ __align__(16) char smem[PH];
     T(*Ls)[LST] = reinterpret_cast<T(*)[LST]>(smem);
@@ -665,12 +666,16 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
     }
     const int64_t ok = dscr_off[f] + (int64_t)(k0 / NB) * NB * NB;
     {
-        // thread (wave, lane): row lane of columns wave + 4 i, all loads in flight
+        // thread (wave, lane): row lane of columns wave + 4 i, all loads in
+        // flight; the solve reads only the 16 x 16 blocks of L_kk below its
+        // diagonal blocks and the diagonal blocks' inverses, so only those
+        // are fetched (whole 64-byte lines of a column each)
         T lv[NB / 4], iv[NB / 4];
 #pragma unroll
         for (int i = 0; i < NB / 4; i++) {
-            lv[i] = dscr[ok + (wave + 4 * i) * NB + lane];
-            iv[i] = dinv[ok + (wave + 4 * i) * NB + lane];
+            const int c = wave + 4 * i;
+            lv[i] = lane >= 16 * (c / 16 + 1) ? dscr[ok + c * NB + lane] : (T)0;
+            iv[i] = lane / 16 == c / 16 ? dinv[ok + c * NB + lane] : (T)0;
         }
 #pragma unroll
         for (int i = 0; i < NB / 4; i++) {
@@ -835,14 +840,13 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
         if (w & STEP_DIAG) {
             // D_{k+1} = the updated tile (i0 = j0 = k0 + nb): factor it now
             TD(*A)[NB + 1] = reinterpret_cast<TD(*)[NB + 1]>(smem);
-            TD(*Iv)[NB + 1] = reinterpret_cast<TD(*)[NB + 1]>(smem + (size_t)LSZ * sizeof(TD));
-            TD *Rd = reinterpret_cast<TD *>(smem + 2 * (size_t)LSZ * sizeof(TD));
+            DiagInv<TD> &Iv = *reinterpret_cast<DiagInv<TD> *>(smem + (size_t)LSZ * sizeof(TD));
+            TD *Rd = reinterpret_cast<TD *>(smem + (size_t)LSZ * sizeof(TD) + sizeof(DiagInv<TD>));
             const int nb2 = min(NB, p - j0);
             __syncthreads();   // X_i, X_j no longer read
             for (int e = tid; e < NB * NB; e += THREADS) {
                 int c = e / NB, r = e % NB;
                 A[c][r] = (c == r && r >= nb2) ? (TD)1 : (TD)0;
-                Iv[c][r] = 0;
             }
             __syncthreads();
             const int c = 16 * wave + ln;
@@ -854,11 +858,10 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
                     if (r < nb2 && c < nb2 && c <= r) A[c][r] = (TD)nv[e][x];
                 }
             __syncthreads();
-            factor_diag_block<TD>(*reinterpret_cast<TD(*)[NB][NB + 1]>(A), *reinterpret_cast<TD(*)[NB][NB + 1]>(Iv),
-                                  *reinterpret_cast<TD(*)[NB]>(Rd), nb2, true, bad, first[f] + j0, [](auto) {});
+            factor_diag_block<TD>(*reinterpret_cast<TD(*)[NB][NB + 1]>(A), Iv, *reinterpret_cast<TD(*)[NB]>(Rd), nb2,
+                                  true, bad, first[f] + j0, [](auto) {});
             const int64_t o2 = dscr_off[f] + (int64_t)(j0 / NB) * NB * NB;
-            store_diag_block<T, TD>(*reinterpret_cast<TD(*)[NB][NB + 1]>(A),
-                                    *reinterpret_cast<TD(*)[NB][NB + 1]>(Iv), dscr + o2, dinv + o2);
+            store_diag_block<T, TD>(*reinterpret_cast<TD(*)[NB][NB + 1]>(A), Iv, dscr + o2, dinv + o2);
         }
     }
     if (w & STEP_COPY) move_deferred<T>(F, ld, m, i0, i0 + NB, K0, k0, Lt);
