@@ -702,16 +702,22 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
             }
     }
     // the tile's earlier values, read now (they do not depend on the solve):
-    // element e of quad cq[e] is row i0 + 4 Mfma<T>::row(kq, e) + x of column
-    // j0 + 16 wave + ln; a quad reaching past the stored lower part is read
-    // element by element (masked elements read as 0 and are not stored)
+    // element x of quad cq[e] is row r0(e) + x of column cl(e) (wave w's
+    // columns j0 + 16 w ..): FP64 r0 = i0 + 4 Mfma<T>::row(kq, e), cl = j0 +
+    // 16 w + ln, the accumulator's own layout, whose four lane groups cover
+    // 16 consecutive rows; FP32 (coalesced order, see the epilogue) r0 = i0 +
+    // 4 (lane % 16), cl = j0 + 16 w + 4 e + lane / 16.  A quad reaching past
+    // the stored lower part is read element by element (masked elements read
+    // as 0 and are not stored)
+    constexpr bool colepi = sizeof(T) == 4;
     const int jend = min(j0 + NB, kend);
-    const int col = j0 + 16 * wave + ln;
+    auto qrow = [&](int e) { return i0 + 4 * (colepi ? lane % 16 : Mfma<T>::row(kq, e)); };
+    auto qcol = [&](int e) { return j0 + 16 * wave + (colepi ? 4 * e + lane / 16 : ln); };
     V4 cq[4];
     if (two) {
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const int r0 = i0 + 4 * Mfma<T>::row(kq, e);
+            const int r0 = qrow(e), col = qcol(e);
             const T *q = F + (int64_t)col * ld + r0;
             if (col < jend && r0 >= col && r0 + 3 < m) {
                 cq[e] = *reinterpret_cast<const V4 *>(q);
@@ -811,16 +817,51 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
             acc[3] = Mfma<T>::mma(a4.w, b, acc[3]);
         }
         // element e of acc[x] is C(row 4 Mfma<T>::row(kq, e) + x, column 16 wave + ln) of the tile:
-        // rows come in aligned quads (i0 is a multiple of 4)
+        // rows come in aligned quads (i0 is a multiple of 4).  FP32: a lane's
+        // quads (rows 16 kq + 4 e, e = 0..3) would be stored as 16-byte
+        // pieces of 64 cache lines per instruction; they go through LDS
+        // (quad rq of the wave's column cl at cl * 64 + 4 (rq ^ cl): distinct
+        // banks both ways) and come back as the quads of four whole columns
+        T av[4][4];
+        if constexpr (colepi) {
+            __syncthreads();   // every wave is done with X_i, X_j
+            T *Q = reinterpret_cast<T *>(smem) + wave * 16 * 64;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                V4 v;
+                v.x = acc[0][e];
+                v.y = acc[1][e];
+                v.z = acc[2][e];
+                v.w = acc[3][e];
+                *reinterpret_cast<V4 *>(Q + ln * 64 + 4 * ((4 * kq + e) ^ ln)) = v;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int cl = 4 * e + lane / 16, rq = lane % 16;
+                const V4 v = *reinterpret_cast<const V4 *>(Q + cl * 64 + 4 * (rq ^ cl));
+                av[e][0] = v.x;
+                av[e][1] = v.y;
+                av[e][2] = v.z;
+                av[e][3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+#pragma unroll
+                for (int x = 0; x < 4; x++) av[e][x] = acc[x][e];
+        }
         T nv[4][4];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            const int r0 = i0 + 4 * Mfma<T>::row(kq, e);
+            const int r0 = qrow(e), col = qcol(e);
             T *q = F + (int64_t)col * ld + r0;
-            nv[e][0] = cq[e].x - acc[0][e];
-            nv[e][1] = cq[e].y - acc[1][e];
-            nv[e][2] = cq[e].z - acc[2][e];
-            nv[e][3] = cq[e].w - acc[3][e];
+            nv[e][0] = cq[e].x - av[e][0];
+            nv[e][1] = cq[e].y - av[e][1];
+            nv[e][2] = cq[e].z - av[e][2];
+            nv[e][3] = cq[e].w - av[e][3];
             if (col < jend && r0 >= col && r0 + 3 < m) {
                 V4 o;
                 o.x = nv[e][0];
@@ -849,12 +890,11 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
                 A[c][r] = (c == r && r >= nb2) ? (TD)1 : (TD)0;
             }
             __syncthreads();
-            const int c = 16 * wave + ln;
 #pragma unroll
             for (int e = 0; e < 4; e++)
 #pragma unroll
                 for (int x = 0; x < 4; x++) {
-                    const int r = 4 * Mfma<T>::row(kq, e) + x;
+                    const int c = qcol(e) - j0, r = qrow(e) - i0 + x;
                     if (r < nb2 && c < nb2 && c <= r) A[c][r] = (TD)nv[e][x];
                 }
             __syncthreads();
