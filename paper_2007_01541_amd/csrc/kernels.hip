@@ -1558,6 +1558,7 @@ __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ r
 // in P[slot] for k_spmv_long_sum (a single wave would otherwise walk a row of
 // all N entries alone, after everything else).
 constexpr int SPMV_CHUNK = 4096;
+constexpr int SPMV_GROUP = 4;   // rows of one column pattern per work item (k_spmv_grp)
 template <typename TX> struct SpmvVec;
 template <> struct SpmvVec<double> {
     using V = double2;
@@ -1659,6 +1660,122 @@ __global__ __launch_bounds__(256) void k_spmv_vec(const int4 *__restrict__ items
     }
 }
 
+// The same product by groups of up to SPMV_GROUP rows with one column
+// pattern (g = group rows, -1 past its end): every gathered X row serves
+// every row of the group, whose values are read side by side, so a pattern
+// shared by three rows (the wavelets of a cell) costs a third of the
+// gathers.  Item (group, first entry, chunks of a split group or -1, partial
+// slot): a chunk of a split group leaves row r's partial sums in slot
+// slot + r * chunks (for k_spmv_long_sum); otherwise R is written as above.
+template <int LPE, typename TX, typename SV = SpmvVec<TX>>
+__global__ __launch_bounds__(256) void k_spmv_grp(const int4 *__restrict__ items, int nitems,
+                                                  const int4 *__restrict__ groups, const int64_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci, const double *__restrict__ v,
+                                                  const TX *__restrict__ X, const double *B,
+                                                  const double *__restrict__ mul, double *R, double *__restrict__ P)
+{
+    using V = typename SV::V;
+    constexpr int G = SPMV_GROUP;
+    constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
+    constexpr int U = EPI >= 16 ? 1 : 16 / EPI;   // about 16 entries in flight per wave
+    int it = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (it >= nitems) return;
+    const int4 w4 = items[it];
+    const int4 g4 = groups[w4.x];
+    const int rows[G] = {g4.x, g4.y, g4.z, g4.w};
+    int ng = 1;
+#pragma unroll
+    for (int g = 1; g < G; g++) ng += rows[g] >= 0;
+    const int64_t len = rp[rows[0] + 1] - rp[rows[0]];
+    const int64_t a = w4.y, b = min(len, a + (int64_t)SPMV_CHUNK);
+    int64_t base[G];
+#pragma unroll
+    for (int g = 0; g < G; g++) base[g] = g < ng ? rp[rows[g]] : rp[rows[0]];
+    int q = lane / LPE, ql = lane % LPE;
+    const V *xc = reinterpret_cast<const V *>(X) + 2 * ql;   // a row is 2 LPE vectors V
+    double s[G][EL];
+#pragma unroll
+    for (int g = 0; g < G; g++)
+#pragma unroll
+        for (int j = 0; j < EL; j++) s[g][j] = 0;
+    for (int64_t q0 = a; q0 < b; q0 += 64) {
+        int cnt = (int)min((int64_t)64, b - q0);
+        int myc = lane < cnt ? __builtin_nontemporal_load(ci + base[0] + q0 + lane) : 0;
+        double myv[G];
+#pragma unroll
+        for (int g = 0; g < G; g++)
+            myv[g] = lane < cnt && g < ng ? __builtin_nontemporal_load(v + base[g] + q0 + lane) : 0.0;
+        int t = 0;
+        for (; t + U * EPI <= cnt; t += U * EPI) {
+            V x0[U], x1[U];
+            double w[U][G];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                int e = t + EPI * u + q;
+                const V *pr = xc + (int64_t)__shfl(myc, e) * (2 * LPE);
+                x0[u] = pr[0];
+                x1[u] = pr[1];
+#pragma unroll
+                for (int g = 0; g < G; g++) w[u][g] = __shfl(myv[g], e);
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++)
+#pragma unroll
+                for (int j = 0; j < H; j++) {
+                    const double x0j = SV::at(x0[u], j), x1j = SV::at(x1[u], j);
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        s[g][j] += w[u][g] * x0j;
+                        s[g][H + j] += w[u][g] * x1j;
+                    }
+                }
+        }
+        for (; t < cnt; t += EPI) {
+            int e = t + q;
+            bool ok = e < cnt;
+            int cc = __shfl(myc, ok ? e : t);
+            double ww[G];
+#pragma unroll
+            for (int g = 0; g < G; g++) ww[g] = __shfl(myv[g], ok ? e : t);
+            if (ok) {
+                const V *pr = xc + (int64_t)cc * (2 * LPE);
+                V a0 = pr[0], a1 = pr[1];
+#pragma unroll
+                for (int j = 0; j < H; j++)
+#pragma unroll
+                    for (int g = 0; g < G; g++) {
+                        s[g][j] += ww[g] * SV::at(a0, j);
+                        s[g][H + j] += ww[g] * SV::at(a1, j);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= LPE; off >>= 1)
+#pragma unroll
+        for (int g = 0; g < G; g++)
+#pragma unroll
+            for (int j = 0; j < EL; j++) s[g][j] += __shfl_down(s[g][j], off, 64);
+    if (q == 0) {
+#pragma unroll
+        for (int g = 0; g < G; g++) {
+            if (g >= ng) break;
+            if (w4.z >= 0) {      // a chunk of a split group: its partial sums
+#pragma unroll
+                for (int j = 0; j < EL; j++) P[(int64_t)(w4.w + g * w4.z) * K + EL * ql + j] = s[g][j];
+                continue;
+            }
+            int64_t o = (int64_t)rows[g] * K + EL * ql;
+#pragma unroll
+            for (int j = 0; j < EL; j++) {
+                double r = s[g][j];
+                if (mul) r *= mul[EL * ql + j];
+                R[o + j] = B ? B[o + j] - r : r;
+            }
+        }
+    }
+}
+
 // Long rows: R = B - mul[c] (sum of the row's chunk partials in slot order),
 // element (row, c) at row * sx + c; one workgroup per long row (row, first
 // slot, slots), threads over the k columns.
@@ -1742,28 +1859,32 @@ __global__ void k_scatter_rows(const double *__restrict__ Xp, const int32_t *__r
     }
 }
 
-// Y = (T)(R * scale[c])  (same row-major layout)
+// Y = (T)(R * scale[c])  (same row-major layout).  The grid stride is
+// rounded down to a multiple of k, so that every thread stays on one column
+// (no division per element; fewer than k threads idle).
 template <typename T>
 __global__ void k_cast_scaled(const double *__restrict__ R, int64_t total, int k, const double *__restrict__ scale,
                               T *__restrict__ Y)
 {
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        double x = R[idx];
-        if (scale) x *= scale[idx % k];
-        Y[idx] = (T)x;
-    }
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / k * k;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= stride) return;
+    const double s = scale ? scale[idx % k] : 1.0;
+    for (; idx < total; idx += stride) Y[idx] = (T)(R[idx] * s);
 }
 
-// X (+)= Y / scale[c]
+// X (+)= Y / scale[c], scale a power of two (the product with its inverse is
+// the same number); one column per thread as above
 template <typename T>
 __global__ void k_add_unscaled(const T *__restrict__ Y, int64_t total, int k, const double *__restrict__ scale,
                                int accumulate, double *__restrict__ X)
 {
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        double y = (double)Y[idx];
-        if (scale) y /= scale[idx % k];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x / k * k;
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= stride) return;
+    const double inv = scale ? 1.0 / scale[idx % k] : 1.0;
+    for (; idx < total; idx += stride) {
+        const double y = (double)Y[idx] * inv;
         X[idx] = accumulate ? X[idx] + y : y;
     }
 }
@@ -1786,7 +1907,9 @@ __global__ void k_colred_part(const double *__restrict__ A, int n, int k, int op
     for (int c0 = 0; c0 < k; c0 += kc) {
         int c = c0 + threadIdx.x % kc, g = threadIdx.x / kc;
         double s = 0;
+        // unrolled so that eight loads are in flight ahead of the (ordered) sum
         if (g < groups && c < k)
+#pragma unroll 8
             for (int64_t r = r0 + g; r < r1; r += groups) {
                 double x = A[r * k + c];
                 s = op == 0 ? s + x * x : fmax(s, fabs(x));

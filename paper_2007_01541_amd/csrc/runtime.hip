@@ -195,6 +195,15 @@ struct Plan {
     // adds in slot order
     std::vector<int4> spmv_chunks, spmv_long;
     int64_t spmv_slots = 0;
+    // the same product by groups of up to SPMV_GROUP rows with one column
+    // pattern (a wavelet matrix has three rows per pattern, one per wavelet
+    // of a cell): spmv_grp (rows, -1 past the group's end); items (group,
+    // first entry, chunks of a split group or -1, partial slot of its first
+    // row's chunk); row g of a split group with nc chunks keeps its partial
+    // for chunk c at slot first + g nc + c, which spmv_glong (row, first slot,
+    // slots) adds in slot order
+    std::vector<int4> spmv_grp, spmv_gitems, spmv_glong;
+    int64_t spmv_gslots = 0;
     std::vector<int32_t> leaf_queue;              // leaf fronts of the persistent kernel, largest first
     std::vector<int32_t> diag_fronts;             // OP_DIAG tasks (fronts)
     std::vector<int4> step_tasks;                 // OP_STEP tasks (front, i0, j0, flags)
@@ -522,6 +531,72 @@ struct Plan {
             int64_t len = S.csr_ptr[i + 1] - S.csr_ptr[i];
             if (len <= SPMV_CHUNK) spmv_chunks.push_back(make_int4(i, 0, (int32_t)len, -1));
         }
+        // row groups: rows with equal column lists (hash, then an exact
+        // comparison with the group's first row), in order of their first row
+        {
+            std::vector<uint64_t> hsh((size_t)S.n);
+            for (int32_t i = 0; i < S.n; i++) {
+                uint64_t h = 1469598103934665603ull ^ (uint64_t)(S.csr_ptr[i + 1] - S.csr_ptr[i]);
+                for (int64_t q = S.csr_ptr[i]; q < S.csr_ptr[i + 1]; q++)
+                    h = (h ^ (uint64_t)(uint32_t)S.csr_col[q]) * 1099511628211ull;
+                hsh[i] = h;
+            }
+            auto same = [&](int32_t a, int32_t b) {
+                int64_t la = S.csr_ptr[a + 1] - S.csr_ptr[a];
+                return la == S.csr_ptr[b + 1] - S.csr_ptr[b] &&
+                       std::equal(S.csr_col.begin() + S.csr_ptr[a], S.csr_col.begin() + S.csr_ptr[a + 1],
+                                  S.csr_col.begin() + S.csr_ptr[b]);
+            };
+            std::vector<int32_t> order((size_t)S.n);
+            for (int32_t i = 0; i < S.n; i++) order[i] = i;
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return hsh[a] < hsh[b]; });
+            std::vector<std::vector<int32_t>> groups;
+            std::vector<int32_t> first_of((size_t)S.n, -1);   // group index by its first row
+            for (size_t q = 0; q < order.size();) {
+                size_t q1 = q;
+                while (q1 < order.size() && hsh[order[q1]] == hsh[order[q]]) q1++;
+                // equal hashes: split into classes of equal lists (ascending rows)
+                std::vector<int32_t> rest(order.begin() + q, order.begin() + q1);
+                std::sort(rest.begin(), rest.end());
+                while (!rest.empty()) {
+                    std::vector<int32_t> cls, other;
+                    for (int32_t r : rest) (same(rest[0], r) ? cls : other).push_back(r);
+                    for (size_t g0 = 0; g0 < cls.size(); g0 += SPMV_GROUP) {
+                        first_of[cls[g0]] = (int32_t)groups.size();
+                        groups.emplace_back(cls.begin() + g0, cls.begin() + std::min(cls.size(), g0 + SPMV_GROUP));
+                    }
+                    rest.swap(other);
+                }
+                q = q1;
+            }
+            spmv_grp.clear();
+            spmv_gitems.clear();
+            spmv_glong.clear();
+            spmv_gslots = 0;
+            std::vector<int32_t> gid;   // groups in order of their first row
+            for (int32_t i = 0; i < S.n; i++)
+                if (first_of[i] >= 0) gid.push_back(first_of[i]);
+            std::vector<int4> shortit;
+            for (int32_t g : gid) {
+                const std::vector<int32_t> &rs = groups[g];
+                int32_t gi = (int32_t)spmv_grp.size();
+                spmv_grp.push_back(make_int4(rs[0], rs.size() > 1 ? rs[1] : -1, rs.size() > 2 ? rs[2] : -1,
+                                             rs.size() > 3 ? rs[3] : -1));
+                int64_t len = S.csr_ptr[rs[0] + 1] - S.csr_ptr[rs[0]];
+                if (len <= SPMV_CHUNK) {
+                    shortit.push_back(make_int4(gi, 0, -1, -1));
+                    continue;
+                }
+                int32_t nc = (int32_t)((len + SPMV_CHUNK - 1) / SPMV_CHUNK);
+                for (size_t r = 0; r < rs.size(); r++)
+                    spmv_glong.push_back(make_int4(rs[r], (int32_t)(spmv_gslots + (int64_t)r * nc), nc, 0));
+                for (int32_t c = 0; c < nc; c++)
+                    spmv_gitems.push_back(make_int4(gi, c * SPMV_CHUNK, nc, (int32_t)(spmv_gslots + c)));
+                spmv_gslots += (int64_t)rs.size() * nc;
+            }
+            // split groups first (their chunks are the longest items)
+            spmv_gitems.insert(spmv_gitems.end(), shortit.begin(), shortit.end());
+        }
         // products with the factor
         alt_tasks.clear();
         al_tasks.clear();
@@ -559,7 +634,7 @@ struct Layout {
     size_t perm, csr_ptr, csr_col, csr_src, csr_val, rowind, colof, segp;
     size_t pan, upd, ea, flist, dscr, dinv, dscr_off, slist, sfwd, sbelow, sbwd, sasm, part, ztasks;
     size_t sblk, sbsum, xinvt, xoff, xinv, part2, dinvt, altt, alt2, gptr, glist;
-    size_t spchunk, splong, sppart, iperm, leafq, leafc, diagf, stept;
+    size_t spchunk, splong, sppart, iperm, leafq, leafc, diagf, stept, spgrp, spgit, spglong;
     // LU factors only: the U^T fronts and their diagonal-block scratch, inverses and super-block inverses
     size_t fronts_u = 0, dscr_u = 0, dinv_u = 0, xinv_u = 0;
     size_t total;
@@ -632,7 +707,10 @@ struct Layout {
         dscr_off = seg(ns * 8);
         spchunk = seg(std::max<size_t>(1, P.spmv_chunks.size()) * sizeof(int4));
         splong = seg(std::max<size_t>(1, P.spmv_long.size()) * sizeof(int4));
-        sppart = seg((size_t)std::max<int64_t>(1, P.spmv_slots) * k * 8);
+        sppart = seg((size_t)std::max<int64_t>(1, std::max(P.spmv_slots, P.spmv_gslots)) * k * 8);
+        spgrp = seg(std::max<size_t>(1, P.spmv_grp.size()) * sizeof(int4));
+        spgit = seg(std::max<size_t>(1, P.spmv_gitems.size()) * sizeof(int4));
+        spglong = seg(std::max<size_t>(1, P.spmv_glong.size()) * sizeof(int4));
         iperm = seg(n * 4);
         leafq = seg(std::max<size_t>(1, P.leaf_queue.size()) * 4);
         leafc = seg(4);
@@ -1387,36 +1465,37 @@ template <typename TX> bool spmv_vec_fits(int k)
 template <typename TX>
 void launch_spmv_vec(wcs_factor f, int k, const TX *X, const double *B, const double *mul, double *R, hipStream_t st)
 {
+    // work items by groups of rows with one column pattern (k_spmv_grp)
     const Plan &P = f->plan;
     const int64_t *rp = f->at<int64_t>(f->lay.csr_ptr);
     const int32_t *ci = f->at<int32_t>(f->lay.csr_col);
     const double *v = f->at<double>(f->lay.csr_val);
-    const int4 *items = f->at<int4>(f->lay.spchunk);
+    const int4 *items = f->at<int4>(f->lay.spgit);
+    const int4 *grp = f->at<int4>(f->lay.spgrp);
     double *part = f->at<double>(f->lay.sppart);
-    int ni = (int)P.spmv_chunks.size();
+    int ni = (int)P.spmv_gitems.size();
     dim3 g((unsigned)((ni + 3) / 4)), b(256);
+    bool done = false;
     if constexpr (sizeof(TX) == 4) {
         if (k == 4) {
-            hipLaunchKernelGGL((k_spmv_vec<1, TX, SpmvVecF4>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part);
-            if (!P.spmv_long.empty())
-                hipLaunchKernelGGL(k_spmv_long_sum, dim3((unsigned)P.spmv_long.size()), dim3(64), 0, st,
-                                   f->at<int4>(f->lay.splong), k, (int64_t)k, part, B, mul, R);
-            return;
+            hipLaunchKernelGGL((k_spmv_grp<1, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R,
+                               part);
+            done = true;
         }
     }
-    switch (k / (sizeof(TX) == 8 ? 4 : 8)) {
-    case 1: hipLaunchKernelGGL((k_spmv_vec<1, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
-    case 2: hipLaunchKernelGGL((k_spmv_vec<2, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
-    case 4: hipLaunchKernelGGL((k_spmv_vec<4, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
-    case 8: hipLaunchKernelGGL((k_spmv_vec<8, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part); break;
+    if (!done) switch (k / (sizeof(TX) == 8 ? 4 : 8)) {
+    case 1: hipLaunchKernelGGL((k_spmv_grp<1, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
+    case 2: hipLaunchKernelGGL((k_spmv_grp<2, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
+    case 4: hipLaunchKernelGGL((k_spmv_grp<4, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
+    case 8: hipLaunchKernelGGL((k_spmv_grp<8, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
     default:
         if constexpr (sizeof(TX) == 8)
-            hipLaunchKernelGGL((k_spmv_vec<16, TX>), g, b, 0, st, items, ni, rp, ci, v, X, B, mul, R, part);
+            hipLaunchKernelGGL((k_spmv_grp<16, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part);
         break;
     }
-    if (!P.spmv_long.empty())
-        hipLaunchKernelGGL(k_spmv_long_sum, dim3((unsigned)P.spmv_long.size()), dim3(64), 0, st,
-                           f->at<int4>(f->lay.splong), k, (int64_t)k, part, B, mul, R);
+    if (!P.spmv_glong.empty())
+        hipLaunchKernelGGL(k_spmv_long_sum, dim3((unsigned)P.spmv_glong.size()), dim3(64), 0, st,
+                           f->at<int4>(f->lay.spglong), k, (int64_t)k, part, B, mul, R);
 }
 
 // R = B - C X or Y = C X (B null) with C = P A P^T in pivot order; element
@@ -1823,6 +1902,9 @@ int upload_plan(wcs_factor f, hipStream_t st, wcs_factor *out)
     rc = rc ? rc : upload(f, L.csr_src, S.csr_src, st);
     rc = rc ? rc : upload(f, L.spchunk, f->plan.spmv_chunks, st);
     rc = rc ? rc : upload(f, L.splong, f->plan.spmv_long, st);
+    rc = rc ? rc : upload(f, L.spgrp, f->plan.spmv_grp, st);
+    rc = rc ? rc : upload(f, L.spgit, f->plan.spmv_gitems, st);
+    rc = rc ? rc : upload(f, L.spglong, f->plan.spmv_glong, st);
     rc = rc ? rc : upload(f, L.iperm, S.iperm, st);
     rc = rc ? rc : upload(f, L.rowind, S.rowind, st);
     rc = rc ? rc : upload(f, L.colof, P.colof, st);
