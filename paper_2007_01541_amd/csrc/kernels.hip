@@ -1558,7 +1558,7 @@ __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ r
 // in P[slot] for k_spmv_long_sum (a single wave would otherwise walk a row of
 // all N entries alone, after everything else).
 constexpr int SPMV_CHUNK = 4096;
-constexpr int SPMV_GROUP = 4;   // rows of one column pattern per work item (k_spmv_grp)
+constexpr int SPMV_GROUP = 3;   // rows of one column pattern per work item (k_spmv_grp)
 template <typename TX> struct SpmvVec;
 template <> struct SpmvVec<double> {
     using V = double2;
@@ -1677,12 +1677,13 @@ __global__ __launch_bounds__(256) void k_spmv_grp(const int4 *__restrict__ items
     using V = typename SV::V;
     constexpr int G = SPMV_GROUP;
     constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
-    constexpr int U = EPI >= 16 ? 1 : 16 / EPI;   // about 16 entries in flight per wave
+    constexpr int U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
     int it = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
     if (it >= nitems) return;
     const int4 w4 = items[it];
     const int4 g4 = groups[w4.x];
-    const int rows[G] = {g4.x, g4.y, g4.z, g4.w};
+    static_assert(G >= 2 && G <= 4, "a group is one int4 of rows");
+    const int rows[4] = {g4.x, g4.y, g4.z, g4.w};
     int ng = 1;
 #pragma unroll
     for (int g = 1; g < G; g++) ng += rows[g] >= 0;

@@ -1475,23 +1475,23 @@ void launch_spmv_vec(wcs_factor f, int k, const TX *X, const double *B, const do
     double *part = f->at<double>(f->lay.sppart);
     int ni = (int)P.spmv_gitems.size();
     dim3 g((unsigned)((ni + 3) / 4)), b(256);
-    bool done = false;
     if constexpr (sizeof(TX) == 4) {
-        if (k == 4) {
-            hipLaunchKernelGGL((k_spmv_grp<1, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R,
-                               part);
-            done = true;
+        // FP32 rows: four columns per lane (two 8-byte halves), so that the
+        // FP64 sums of a group's rows stay within the register budget of
+        // four waves per SIMD
+        switch (k / 4) {
+        case 1: hipLaunchKernelGGL((k_spmv_grp<1, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
+        case 2: hipLaunchKernelGGL((k_spmv_grp<2, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
+        case 4: hipLaunchKernelGGL((k_spmv_grp<4, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
+        case 8: hipLaunchKernelGGL((k_spmv_grp<8, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
+        default: hipLaunchKernelGGL((k_spmv_grp<16, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
         }
-    }
-    if (!done) switch (k / (sizeof(TX) == 8 ? 4 : 8)) {
+    } else switch (k / 4) {
     case 1: hipLaunchKernelGGL((k_spmv_grp<1, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
     case 2: hipLaunchKernelGGL((k_spmv_grp<2, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
     case 4: hipLaunchKernelGGL((k_spmv_grp<4, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
     case 8: hipLaunchKernelGGL((k_spmv_grp<8, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
-    default:
-        if constexpr (sizeof(TX) == 8)
-            hipLaunchKernelGGL((k_spmv_grp<16, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part);
-        break;
+    default: hipLaunchKernelGGL((k_spmv_grp<16, TX>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
     }
     if (!P.spmv_glong.empty())
         hipLaunchKernelGGL(k_spmv_long_sum, dim3((unsigned)P.spmv_glong.size()), dim3(64), 0, st,
