@@ -1589,7 +1589,7 @@ __global__ __launch_bounds__(256) void k_spmv_vec(const int4 *__restrict__ items
 {
     using V = typename SV::V;
     constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
-    constexpr int U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
+    constexpr int U = EPI >= 16 ? 1 : 16 / EPI;   // about 16 entries in flight per wave
     int it = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
     if (it >= nitems) return;
     int4 w4 = items[it];
@@ -1677,7 +1677,7 @@ __global__ __launch_bounds__(256) void k_spmv_grp(const int4 *__restrict__ items
     using V = typename SV::V;
     constexpr int G = SPMV_GROUP;
     constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
-    constexpr int U = EPI >= 32 ? 1 : 32 / EPI;   // about 32 entries in flight per wave
+    constexpr int U = EPI >= 16 ? 1 : 16 / EPI;   // about 16 entries in flight per wave
     int it = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
     if (it >= nitems) return;
     const int4 w4 = items[it];
