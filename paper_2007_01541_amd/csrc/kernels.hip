@@ -1544,19 +1544,17 @@ __global__ __launch_bounds__(256) void k_spmv_wide(const int64_t *__restrict__ r
     }
 }
 
-// Vector form for row-major X with k = EL * LPE columns, EL = 4 for FP64 X
-// and 8 for FP32 X (LPE = 1, 2, 4, 8, 16): one wave per row; a group of LPE
-// lanes takes one matrix entry and EL columns per lane (two 16-byte loads of
-// the X row), so one wave instruction gathers the X rows of 64 / LPE entries
-// at once.  Products and sums are FP64 whatever the type of X.  Partial sums
-// of the groups are added with shuffles (fixed order).  Rows go to blocks in
-// plain order: consecutive rows of the dissection order share their X rows in
-// L2.  Output R = B - mul[c] (A X), or R = A X when B is null (null mul means
-// 1); B may be R itself (each element is read and written by one lane).
-// Waves take work items (row, first, end entry within the row, slot): rows
-// longer than SPMV_CHUNK entries come in several items that leave partial sums
-// in P[slot] for k_spmv_long_sum (a single wave would otherwise walk a row of
-// all N entries alone, after everything else).
+// Vector form for row-major X with k = EL * LPE columns (EL = 4, LPE = 1, 2,
+// 4, 8, 16): a group of LPE lanes takes one matrix entry and EL columns per
+// lane (two 8-byte (FP32 X) or 16-byte (FP64 X) loads of the X row), so one
+// wave instruction gathers the X rows of 64 / LPE entries at once.  Products
+// and sums are FP64 whatever the type of X.  Partial sums of the lane groups
+// are added with shuffles (fixed order).  Output R = B - mul[c] (A X), or R =
+// A X when B is null (null mul means 1); B may be R itself (each element is
+// read and written by one lane).  Rows longer than SPMV_CHUNK entries come in
+// several work items that leave partial sums for k_spmv_long_sum (a single
+// wave would otherwise walk a row of all N entries alone, after everything
+// else).
 constexpr int SPMV_CHUNK = 4096;
 constexpr int SPMV_GROUP = 3;   // rows of one column pattern per work item (k_spmv_grp)
 template <typename TX> struct SpmvVec;
@@ -1565,103 +1563,16 @@ template <> struct SpmvVec<double> {
     static constexpr int EL = 4;
     __device__ static double at(const V &x, int j) { return j == 0 ? x.x : x.y; }
 };
-template <> struct SpmvVec<float> {
-    using V = float4;
-    static constexpr int EL = 8;
-    __device__ static double at(const V &x, int j)
-    {
-        return (double)(j == 0 ? x.x : j == 1 ? x.y : j == 2 ? x.z : x.w);
-    }
-};
-// FP32 rows of exactly four columns (k = 4): two 8-byte halves per lane
+// FP32 rows: four columns per lane, two 8-byte halves (the FP64 sums of a
+// group's rows then fit the register budget of three waves per SIMD)
 struct SpmvVecF4 {
     using V = float2;
     static constexpr int EL = 4;
     __device__ static double at(const V &x, int j) { return (double)(j == 0 ? x.x : x.y); }
 };
 
-template <int LPE, typename TX, typename SV = SpmvVec<TX>>
-__global__ __launch_bounds__(256) void k_spmv_vec(const int4 *__restrict__ items, int nitems,
-                                                  const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                                  const double *__restrict__ v, const TX *__restrict__ X,
-                                                  const double *B, const double *__restrict__ mul, double *R,
-                                                  double *__restrict__ P)
-{
-    using V = typename SV::V;
-    constexpr int EL = SV::EL, H = EL / 2, K = EL * LPE, EPI = 64 / LPE;
-    constexpr int U = EPI >= 16 ? 1 : 16 / EPI;   // about 16 entries in flight per wave
-    int it = blockIdx.x * 4 + (int)threadIdx.x / 64, lane = threadIdx.x % 64;
-    if (it >= nitems) return;
-    int4 w4 = items[it];
-    int row = w4.x;
-    int q = lane / LPE, ql = lane % LPE;
-    int64_t a = rp[row] + w4.y, b = rp[row] + w4.z;
-    const V *xc = reinterpret_cast<const V *>(X) + 2 * ql;   // a row is 2 LPE vectors V
-    double s[EL];
-#pragma unroll
-    for (int j = 0; j < EL; j++) s[j] = 0;
-    for (int64_t q0 = a; q0 < b; q0 += 64) {
-        int cnt = (int)min((int64_t)64, b - q0);
-        int myc = lane < cnt ? __builtin_nontemporal_load(ci + q0 + lane) : 0;
-        double myv = lane < cnt ? __builtin_nontemporal_load(v + q0 + lane) : 0.0;
-        int t = 0;
-        for (; t + U * EPI <= cnt; t += U * EPI) {
-            V x0[U], x1[U];
-            double w[U];
-#pragma unroll
-            for (int u = 0; u < U; u++) {
-                int e = t + EPI * u + q;
-                const V *pr = xc + (int64_t)__shfl(myc, e) * (2 * LPE);
-                x0[u] = pr[0];
-                x1[u] = pr[1];
-                w[u] = __shfl(myv, e);
-            }
-#pragma unroll
-            for (int u = 0; u < U; u++)
-#pragma unroll
-                for (int j = 0; j < H; j++) {
-                    s[j] += w[u] * SV::at(x0[u], j);
-                    s[H + j] += w[u] * SV::at(x1[u], j);
-                }
-        }
-        for (; t < cnt; t += EPI) {
-            int e = t + q;
-            bool ok = e < cnt;
-            int cc = __shfl(myc, ok ? e : t);
-            double ww = __shfl(myv, ok ? e : t);
-            if (ok) {
-                const V *pr = xc + (int64_t)cc * (2 * LPE);
-                V a0 = pr[0], a1 = pr[1];
-#pragma unroll
-                for (int j = 0; j < H; j++) {
-                    s[j] += ww * SV::at(a0, j);
-                    s[H + j] += ww * SV::at(a1, j);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int off = 32; off >= LPE; off >>= 1)
-#pragma unroll
-        for (int j = 0; j < EL; j++) s[j] += __shfl_down(s[j], off, 64);
-    if (q == 0) {
-        if (w4.w >= 0) {      // a chunk of a long row: its partial sums
-#pragma unroll
-            for (int j = 0; j < EL; j++) P[(int64_t)w4.w * K + EL * ql + j] = s[j];
-            return;
-        }
-        int64_t o = (int64_t)row * K + EL * ql;
-#pragma unroll
-        for (int j = 0; j < EL; j++) {
-            double r = s[j];
-            if (mul) r *= mul[EL * ql + j];
-            R[o + j] = B ? B[o + j] - r : r;
-        }
-    }
-}
-
-// The same product by groups of up to SPMV_GROUP rows with one column
-// pattern (g = group rows, -1 past its end): every gathered X row serves
+// The product by groups of up to SPMV_GROUP rows with one column pattern
+// (g = group rows, -1 past its end): every gathered X row serves
 // every row of the group, whose values are read side by side, so a pattern
 // shared by three rows (the wavelets of a cell) costs a third of the
 // gathers.  Item (group, first entry, chunks of a split group or -1, partial

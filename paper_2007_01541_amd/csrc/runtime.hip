@@ -1451,13 +1451,11 @@ void scatter_rows(wcs_factor f, const double *Xp, int k, double *X, int64_t ld, 
                            f->at<int32_t>(f->lay.perm), n, k, X, ld);
 }
 
-// Row-major X of k = 4 LPE (FP64) or 8 LPE (FP32) columns, LPE a power of
-// two up to 16 (FP64) or 8 (FP32): the vector SpMM form
+// Row-major X of k = 4 LPE columns, LPE a power of two up to 16: the vector
+// SpMM form (both types)
 template <typename TX> bool spmv_vec_fits(int k)
 {
-    constexpr int EL = sizeof(TX) == 8 ? 4 : 8, maxl = sizeof(TX) == 8 ? 16 : 8;
-    if (sizeof(TX) == 4 && k == 4) return true;     // the four-column FP32 form
-    return k % EL == 0 && k / EL <= maxl && ((k / EL) & (k / EL - 1)) == 0;
+    return k % 4 == 0 && k / 4 <= 16 && ((k / 4) & (k / 4 - 1)) == 0;
 }
 
 // R = B - mul[c] (C X), or R = C X when B is null; C = P A P^T in pivot order,
@@ -1476,9 +1474,7 @@ void launch_spmv_vec(wcs_factor f, int k, const TX *X, const double *B, const do
     int ni = (int)P.spmv_gitems.size();
     dim3 g((unsigned)((ni + 3) / 4)), b(256);
     if constexpr (sizeof(TX) == 4) {
-        // FP32 rows: four columns per lane (two 8-byte halves), so that the
-        // FP64 sums of a group's rows stay within the register budget of
-        // four waves per SIMD
+        // FP32 rows: four columns per lane (SpmvVecF4)
         switch (k / 4) {
         case 1: hipLaunchKernelGGL((k_spmv_grp<1, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
         case 2: hipLaunchKernelGGL((k_spmv_grp<2, TX, SpmvVecF4>), g, b, 0, st, items, ni, grp, rp, ci, v, X, B, mul, R, part); break;
