@@ -123,3 +123,25 @@ def test_step_path_reports_first_bad_pivot(prec, monkeypatch):
             f.numeric(dev(v))
         print(f"pivot {piv}: reported {e.value.bad_col}", flush=True)
         assert e.value.code == -4 and e.value.bad_col == piv
+
+
+@pytest.mark.parametrize("kind,leaf,coords", CASES)
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_late_levels_bitwise(kind, leaf, coords, prec, monkeypatch):
+    """Large fronts factored one level below their parent (WCS_LATE_MIN_PIVOTS)
+    share other launches but keep every front's arithmetic and the order of
+    the extend-add rounds: the factor and the solves are the same bit for bit."""
+    m, sym, orc = prepared(kind, leaf, coords)
+    vals = dev(m["values"])
+    B = normal_rhs(m["n"], 3, 73)
+    out = []
+    for late in ("0", "64", "200", "1024"):
+        monkeypatch.setenv("WCS_LATE_MIN_PIVOTS", late)
+        f = Factor(sym, prec, max_nrhs=3)
+        f.numeric(vals)
+        out.append((f.export_L(), f.solve(dev(B)).cpu().numpy()))
+    print(f"case {kind} prec={prec} n={m['n']}", flush=True)
+    for L, X in out[1:]:
+        for a, b in zip(out[0][0], L):
+            assert np.array_equal(a, b)
+        assert np.array_equal(out[0][1], X)
