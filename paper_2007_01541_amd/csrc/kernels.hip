@@ -885,17 +885,14 @@ __global__ __launch_bounds__(THREADS, 2) void k_step(const int4 *__restrict__ ta
             TD *Rd = reinterpret_cast<TD *>(smem + (size_t)LSZ * sizeof(TD) + sizeof(DiagInv<TD>));
             const int nb2 = min(NB, p - j0);
             __syncthreads();   // X_i, X_j no longer read
-            for (int e = tid; e < NB * NB; e += THREADS) {
-                int c = e / NB, r = e % NB;
-                A[c][r] = (c == r && r >= nb2) ? (TD)1 : (TD)0;
-            }
-            __syncthreads();
+            // the lanes' 16 elements each cover the tile once: the block's
+            // lower part, the identity past nb2, zero elsewhere
 #pragma unroll
             for (int e = 0; e < 4; e++)
 #pragma unroll
                 for (int x = 0; x < 4; x++) {
                     const int c = qcol(e) - j0, r = qrow(e) - i0 + x;
-                    if (r < nb2 && c < nb2 && c <= r) A[c][r] = (TD)nv[e][x];
+                    A[c][r] = (r < nb2 && c < nb2 && c <= r) ? (TD)nv[e][x] : (c == r && r >= nb2) ? (TD)1 : (TD)0;
                 }
             __syncthreads();
             factor_diag_block<TD>(*reinterpret_cast<TD(*)[NB][NB + 1]>(A), Iv, *reinterpret_cast<TD(*)[NB]>(Rd), nb2,
