@@ -651,11 +651,12 @@ def main() -> int:
     top = levels[-3:]
     root_ms = sum(l["ms"] for l in top)
     root_flops = sum(l["flops"] for l in top)
-    root = {"levels": len(top), "ms": root_ms, "tflops": root_flops / root_ms / 1e9,
+    root = {"levels": len(top), "schedule": "height in the assembly tree; fronts of >= 1024 pivots one level below "
+                                            "their parent", "ms": root_ms, "tflops": root_flops / root_ms / 1e9,
             "pct_fp32_mfma_peak": 100 * root_flops / root_ms / 1e9 / PEAK["fp32_mfma_tflops"],
             "per_level": [{"ms": round(l["ms"], 3), "tflops": round(l["flops"] / max(l["ms"], 1e-9) / 1e9, 2)}
                           for l in levels]}
-    log(f"  root-level fronts (top 3 levels): {root_ms:.2f} ms, {root['tflops']:.1f} TFLOP/s "
+    log(f"  root-level fronts (top 3 schedule levels): {root_ms:.2f} ms, {root['tflops']:.1f} TFLOP/s "
         f"({root['pct_fp32_mfma_peak']:.1f}% of FP32 MFMA peak)")
     dom = max(prof, key=lambda k: prof[k]["ms"])
     d = prof[dom]

@@ -322,11 +322,14 @@ typedef struct {
 int wcs_factor_profile(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *stats);
 
 /*
- * Diagnostic: as wcs_factor_profile, but timing whole levels of the assembly
- * tree (level 0 = leaves, nlevels-1 = root) with one event pair around all
- * launches of a level (extend-add and dense steps).  levels[h] gets the
- * level's time and the algorithmic flops of its fronts (sum over pivots of
- * the squared column length of the factored front).  nlevels entries.
+ * Diagnostic: as wcs_factor_profile, but timing whole levels of the schedule
+ * (level 0 = leaves, nlevels-1 = root; a front's level is its height in the
+ * assembly tree, or for fronts with at least WCS_LATE_MIN_PIVOTS pivots
+ * (environment, default 1024) one below its parent's level) with one event
+ * pair around all launches of a level (extend-add and dense steps).
+ * levels[h] gets the level's time and the algorithmic flops of its fronts
+ * (sum over pivots of the squared column length of the factored front).
+ * nlevels entries.
  */
 int wcs_factor_profile_levels(wcs_factor f, const double *values_dev, wcs_stream stream, wcs_kernel_stat *levels);
 
